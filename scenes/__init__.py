@@ -1,0 +1,426 @@
+"""Seeded synthetic scene descriptions for the coupled-LBM hot path.
+
+This module is pure input data: lattice choices, domain extents, relaxation
+times, forcing, and the boundary objects (flat walls, open planes, cylinders)
+with the boundary-condition kind and the wall data each lattice uses there.  It
+holds none of the method's arithmetic: no equilibria, no link geometry, no
+collision.  Both the FP64 oracle and the HIP library build their node masks
+and boundary-link tables from a ``Scene`` independently.
+
+Random draws (wall offsets q, Hartmann numbers, conductance ratios, per-position
+reaction rates, item sizes) come from SplitMix64 (Steele, Lea & Flood, 2014),
+implemented here from its published definition.
+
+Units are lattice units (dx = dt = 1).  The paper's parameter sets are stated in
+SI units with c = dx/dt (Section 2.1); ``paper_case_to_lattice`` converts.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# SplitMix64
+# ---------------------------------------------------------------------------
+_M64 = (1 << 64) - 1
+BASE_SEED = 2506009070
+
+
+class SplitMix64:
+    """64-bit SplitMix generator: add the golden-ratio increment, then mix."""
+
+    def __init__(self, seed: int):
+        self.state = seed & _M64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & _M64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+        return z ^ (z >> 31)
+
+    def uniform(self, lo: float = 0.0, hi: float = 1.0) -> float:
+        return lo + (hi - lo) * ((self.next_u64() >> 11) * (1.0 / 9007199254740992.0))
+
+    def log_uniform(self, lo: float, hi: float) -> float:
+        return math.exp(self.uniform(math.log(lo), math.log(hi)))
+
+    def randint(self, lo: int, hi: int) -> int:
+        """Integer uniform on [lo, hi] inclusive."""
+        return lo + int(self.uniform() * (hi - lo + 1)) if hi > lo else lo
+
+    def normal_array(self, n: int) -> np.ndarray:
+        """Box-Muller normals (used only to draw perturbed initial states)."""
+        out = np.empty(n)
+        for i in range(0, n, 2):
+            u1 = max(self.uniform(), 1e-300)
+            u2 = self.uniform()
+            r = math.sqrt(-2.0 * math.log(u1))
+            out[i] = r * math.cos(2 * math.pi * u2)
+            if i + 1 < n:
+                out[i + 1] = r * math.sin(2 * math.pi * u2)
+        return out
+
+
+# ---------------------------------------------------------------------------
+# Scene description
+# ---------------------------------------------------------------------------
+# lattice names
+D2Q9, D3Q19, D2Q5, D3Q7 = "D2Q9", "D3Q19", "D2Q5", "D3Q7"
+# boundary-condition kinds (per lattice, per boundary)
+VEL, PRES, CONC, FLUX, BB0, MAG_DIR, MAG_FLUX = (
+    "VEL", "PRES", "CONC", "FLUX", "BB0", "MAG_DIR", "MAG_FLUX")
+KIND_CODES = {VEL: 1, PRES: 2, CONC: 3, FLUX: 4, BB0: 5, MAG_DIR: 6, MAG_FLUX: 7}
+LATTICE_CODES = {D2Q9: 1, D3Q19: 2, D2Q5: 3, D3Q7: 4}
+STORAGE_CODES = {"f64": 1, "f32": 2, "f16": 3, "bf16": 4}
+
+
+@dataclass
+class BC:
+    """Boundary condition of one lattice (or one magnetic component) on a boundary.
+
+    kind   : one of VEL, PRES, CONC, FLUX, BB0, MAG_DIR, MAG_FLUX
+    value  : given rho (PRES), C (CONC) or B_k (MAG_DIR)
+    a1, a3 : flux law F(phi) = a1*phi_X - a3 (FLUX, MAG_FLUX), lattice units
+    u_given: the wall velocity is used in the moving-wall terms; False means the
+             velocity at the boundary point is extrapolated from the fluid
+    a1_profile: optional per-position a1 along ``profile_axis`` (indexed by
+             the first fluid node's coordinate on that axis)
+    """
+    kind: str
+    value: float = 0.0
+    a1: float = 0.0
+    a3: float = 0.0
+    u_given: bool = True
+    a1_profile: Optional[np.ndarray] = None
+    profile_axis: int = 0
+
+
+@dataclass
+class Boundary:
+    """A flat plane (wall or open inlet/outlet) or a cylinder.
+
+    plane   : ``axis`` is the wall normal axis, ``side`` 0 = below node 0,
+              1 = above node n-1; the wall sits ``q`` lattice units outside the
+              first/last node row (q in (0, 1]).
+    cylinder: ``axis`` is the cylinder axis; nodes are fluid strictly inside
+              radius ``radius`` about ``center`` (the axis coordinate of
+              ``center`` is ignored).
+    """
+    type: str                    # "plane" | "cylinder"
+    axis: int
+    side: int = 0
+    q: float = 0.5
+    center: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    radius: float = 0.0
+    is_open: bool = False
+    u_w: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    f: Optional[BC] = None
+    h: Optional[BC] = None
+    g: List[Optional[BC]] = field(default_factory=list)   # one per evolved component
+
+
+@dataclass
+class Scene:
+    name: str
+    dim: int
+    n: Tuple[int, int, int]               # node counts (nx, ny, nz); nz = 1 in 2D
+    periodic: Tuple[bool, bool, bool]
+    fluid_lattice: str
+    scalar_lattice: Optional[str] = None
+    mag_lattice: Optional[str] = None
+    mag_comps: Tuple[int, ...] = ()       # evolved Cartesian components of B
+    tau_f: float = 0.8
+    tau_c: float = 1.0
+    tau_m: float = 1.0
+    rho0: float = 1.0
+    C0: float = 0.0                       # rest (reference) concentration
+    mu: float = 1.0                       # magnetic permeability
+    B_ext: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    accel: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # body force per unit mass
+    boundaries: List[Boundary] = field(default_factory=list)
+    storage: str = "f64"
+    store_scale: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    steps: int = 1000
+    init_C: float = 0.0                   # initial uniform concentration
+    # optional initial fields (fluid-domain arrays, shape (nz, ny, nx[, 3]))
+    init_rho: Optional[np.ndarray] = None
+    init_u: Optional[np.ndarray] = None
+    init_Cf: Optional[np.ndarray] = None
+    init_B: Optional[np.ndarray] = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nodes(self) -> int:
+        return self.n[0] * self.n[1] * self.n[2]
+
+    def with_(self, **kw) -> "Scene":
+        return dataclasses.replace(self, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Helpers for the configurations
+# ---------------------------------------------------------------------------
+def _nu(tau: float) -> float:
+    return (tau - 0.5) / 3.0
+
+
+def _diff(tau: float) -> float:
+    """Diffusivity of the 5/7-velocity lattices (c^2 = 1/4 in lattice units)."""
+    return (tau - 0.5) / 4.0
+
+
+def hartmann_B0(Ha: float, H: float, rho: float, nu: float, eta: float, mu: float) -> float:
+    """B0 from Ha^2 = B0^2 H^2 sigma/(rho nu), sigma = 1/(mu eta)."""
+    return Ha * math.sqrt(rho * nu * eta * mu) / H
+
+
+def poiseuille(nx: int = 64, ny: int = 32, tau: float = 0.8, g: float = 1e-6,
+               q: float = 0.5, storage: str = "f64", steps: int = 20000,
+               u_top: float = 0.0) -> Scene:
+    """Plane channel between static (or sliding) walls, body-force driven."""
+    wall = lambda side, u: Boundary("plane", axis=1, side=side, q=q, u_w=(u, 0.0, 0.0),
+                                    f=BC(VEL))
+    return Scene(name=f"poiseuille_{nx}x{ny}", dim=2, n=(nx, ny, 1),
+                 periodic=(True, False, True), fluid_lattice=D2Q9, tau_f=tau,
+                 accel=(g, 0.0, 0.0), boundaries=[wall(0, 0.0), wall(1, u_top)],
+                 storage=storage, steps=steps)
+
+
+def reactive_channel(nx: int = 512, ny: int = 256, k: float = 1e-2, q: float = 0.3,
+                     rho_in: float = 1.001, rho_out: float = 1.0, tau_f: float = 0.8,
+                     tau_c: float = 0.6, storage: str = "f32", steps: int = 2000,
+                     k_range: Optional[Tuple[float, float]] = None, seed: int = BASE_SEED + 2,
+                     q_io: float = 0.5) -> Scene:
+    """Pressure-driven D2Q9 channel with a D2Q5 solute and Robin walls dC/dn = k C.
+
+    With n pointing into the fluid, -D dC/dn = F(C) = -k D C (consumption), so
+    a1 = -k D and a3 = 0.  When ``k_range`` is given, k is drawn per wall
+    position, log-uniform in that range.
+    """
+    D = _diff(tau_c)
+    rng = SplitMix64(seed)
+    walls = []
+    for side in (0, 1):
+        prof = None
+        if k_range is not None:
+            prof = np.array([-D * rng.log_uniform(*k_range) for _ in range(nx)])
+        walls.append(Boundary("plane", axis=1, side=side, q=q, f=BC(VEL),
+                              h=BC(FLUX, a1=-k * D, a3=0.0, a1_profile=prof, profile_axis=0)))
+    inlet = Boundary("plane", axis=0, side=0, q=q_io, is_open=True,
+                     f=BC(PRES, value=rho_in), h=BC(CONC, value=1.0, u_given=False))
+    outlet = Boundary("plane", axis=0, side=1, q=q_io, is_open=True,
+                      f=BC(PRES, value=rho_out), h=BC(FLUX, a1=0.0, a3=0.0, u_given=False))
+    return Scene(name=f"reactive_{nx}x{ny}", dim=2, n=(nx, ny, 1), periodic=(False, False, True),
+                 fluid_lattice=D2Q9, scalar_lattice=D2Q5, tau_f=tau_f, tau_c=tau_c,
+                 rho0=1.0, C0=0.0, init_C=0.0, boundaries=walls + [inlet, outlet],
+                 storage=storage, store_scale=(1024.0, 1024.0, 1.0), steps=steps)
+
+
+def hartmann_couette(nx: int = 1024, ny: int = 512, Ha: float = 5.0, c_top: float = 0.1,
+                     u_top: float = 0.01, v0: float = 0.002, qb: Optional[float] = None,
+                     qt: Optional[float] = None, tau_f: float = 0.8, tau_m: float = 0.9,
+                     storage: str = "f32", steps: int = 2000, seed: int = BASE_SEED + 3,
+                     accel: float = 0.0) -> Scene:
+    """Sheared MHD channel with transverse field B_ext = (0, B0).
+
+    Bottom wall: insulating (B1 = 0), velocity (0, v0).  Top wall: velocity
+    (u_top, v0), conductance ratio ``c_top``: 0 -> given B1 = 0,
+    inf -> perfectly conducting (zero flux), otherwise the Shercliff flux
+    F(B1) = -eta B1/(c H).  B2 = B0 is given on both walls.  With v0 != 0 both
+    walls transpire uniformly, which keeps the flow x-invariant.
+    """
+    rng = SplitMix64(seed)
+    qb = rng.uniform(0.1, 0.9) if qb is None else qb
+    qt = rng.uniform(0.1, 0.9) if qt is None else qt
+    H = (ny - 1 + qb + qt) / 2.0
+    nu, eta, rho, mu = _nu(tau_f), _diff(tau_m), 1.0, 1.0
+    B0 = hartmann_B0(Ha, H, rho, nu, eta, mu)
+    if c_top == 0.0:
+        top_b1 = BC(MAG_DIR, value=0.0)
+    elif math.isinf(c_top):
+        top_b1 = BC(MAG_FLUX, a1=0.0, a3=0.0)
+    else:
+        a1 = -eta / (c_top * H)
+        top_b1 = BC(MAG_FLUX, a1=a1, a3=a1 * 0.0)
+    bottom = Boundary("plane", axis=1, side=0, q=qb, u_w=(0.0, v0, 0.0), f=BC(VEL),
+                      g=[BC(MAG_DIR, value=0.0), BC(MAG_DIR, value=B0)])
+    top = Boundary("plane", axis=1, side=1, q=qt, u_w=(u_top, v0, 0.0), f=BC(VEL),
+                   g=[top_b1, BC(MAG_DIR, value=B0)])
+    sc = Scene(name=f"hartmann_{nx}x{ny}", dim=2, n=(nx, ny, 1), periodic=(True, False, True),
+               fluid_lattice=D2Q9, mag_lattice=D2Q5, mag_comps=(0, 1), tau_f=tau_f, tau_m=tau_m,
+               rho0=rho, mu=mu, B_ext=(0.0, B0, 0.0), accel=(accel, 0.0, 0.0),
+               boundaries=[bottom, top], storage=storage, store_scale=(1024.0, 1.0, 1024.0),
+               steps=steps)
+    sc.meta = dict(H=H, qb=qb, qt=qt, B0=B0, Ha=Ha, c_top=c_top, nu=nu, eta=eta)
+    return sc
+
+
+def mhd_pipe(nx: int = 64, side: int = 128, R: float = 60.0, wall: str = "insulating",
+             c_w: float = 0.05, Ha: float = 10.0, g: float = 1e-6, tau_f: float = 0.8,
+             tau_m: float = 0.9, storage: str = "f32", steps: int = 2000,
+             ncomp: int = 1) -> Scene:
+    """Pipe along x (periodic), circular cross-section in (y, z), B_ext along y.
+
+    ``wall``: "insulating" (given B1 = 0), "conducting" (zero flux) or
+    "shercliff" (F(B1) = -eta B1/(c_w R)).  With ``ncomp`` = 3 the transverse
+    components are also evolved with given-B walls (B2 = B0, B3 = 0).
+    """
+    nu, eta, rho, mu = _nu(tau_f), _diff(tau_m), 1.0, 1.0
+    B0 = hartmann_B0(Ha, R, rho, nu, eta, mu)
+    c = (side - 1) / 2.0
+    if wall == "insulating":
+        b1 = BC(MAG_DIR, value=0.0)
+    elif wall == "conducting":
+        b1 = BC(MAG_FLUX, a1=0.0, a3=0.0)
+    elif wall == "shercliff":
+        b1 = BC(MAG_FLUX, a1=-eta / (c_w * R), a3=0.0)
+    else:
+        raise ValueError(wall)
+    gbc = [b1] + ([BC(MAG_DIR, value=B0), BC(MAG_DIR, value=0.0)] if ncomp == 3 else [])
+    cyl = Boundary("cylinder", axis=0, center=(0.0, c, c), radius=R, f=BC(VEL), g=gbc)
+    comps = (0,) if ncomp == 1 else (0, 1, 2)
+    sc = Scene(name=f"pipe_{nx}x{side}x{side}_{wall}", dim=3, n=(nx, side, side),
+               periodic=(True, False, False), fluid_lattice=D3Q19, mag_lattice=D3Q7,
+               mag_comps=comps, tau_f=tau_f, tau_m=tau_m, rho0=rho, mu=mu,
+               B_ext=(0.0, B0, 0.0), accel=(g, 0.0, 0.0), boundaries=[cyl], storage=storage,
+               store_scale=(1024.0, 1.0, 1024.0), steps=steps)
+    sc.meta = dict(R=R, B0=B0, Ha=Ha, wall=wall, c_w=c_w, nu=nu, eta=eta, center=c)
+    return sc
+
+
+def diffusion_reaction(layout: str = "half", Da: float = 4.8, tau_D: float = 0.9,
+                       W_nodes: Optional[int] = None, steps: int = 20000) -> Scene:
+    """Pure diffusion (u = 0) with C given on the left, zero normal gradient on
+    the bottom and right, and a first-order surface reaction on the top.
+
+    Half-grid layout: walls half-way between nodes (d = 0.5).  Full-grid
+    layout: first and last node rows on the walls (d = 1).  Lattice sizes
+    follow the paper's 102 x 82 / 101 x 81 node case (W = 0.01, L = 0.0125,
+    dx = 1.25e-4, outer layers included) unless ``W_nodes`` rescales it.  C_BC = 10, C_eq = 1.
+    Reaction F(C) = -k_r (C - C_eq) with k_r = Da D / W.
+    """
+    D = _diff(tau_D)
+    if W_nodes is None:
+        W_cells = 80             # W / dx
+    else:
+        W_cells = W_nodes
+    L_cells = W_cells * 1.25   # L / W = 1.25
+    # half-grid: walls half-way between the outer node layers and the first
+    # fluid layers; full-grid: the outer node layers lie on the walls, so the
+    # fluid nodes start one spacing inside (d = 1).  Node j sits at j + q from
+    # the lower wall in both layouts.
+    if layout == "half":
+        nx, ny, q = int(round(L_cells)), int(W_cells), 0.5
+    else:
+        nx, ny, q = int(round(L_cells)) - 1, int(W_cells) - 1, 1.0
+    kr = Da * D / W_cells
+    left = Boundary("plane", axis=0, side=0, q=q, h=BC(CONC, value=10.0), f=BC(VEL))
+    right = Boundary("plane", axis=0, side=1, q=q, h=BC(BB0), f=BC(VEL))
+    bottom = Boundary("plane", axis=1, side=0, q=q, h=BC(BB0), f=BC(VEL))
+    top = Boundary("plane", axis=1, side=1, q=q, h=BC(FLUX, a1=-kr, a3=-kr * 1.0), f=BC(VEL))
+    # the bottom/right walls use the d >= 0.5 bounce-back (Eq. 22 form); with
+    # q = 0.5 both forms coincide.  Walls win ties against each other by order.
+    sc = Scene(name=f"diffreact_{layout}_Da{Da}", dim=2, n=(nx, ny, 1),
+               periodic=(False, False, True), fluid_lattice=D2Q9, scalar_lattice=D2Q5,
+               tau_f=1.0, tau_c=tau_D, C0=0.0, init_C=1.0,
+               boundaries=[bottom, top, left, right], storage="f64", steps=steps)
+    sc.meta = dict(W=float(W_cells), L=float(L_cells), D=D, kr=kr, Da=Da, layout=layout)
+    return sc
+
+
+# ---------------------------------------------------------------------------
+# The five workloads
+# ---------------------------------------------------------------------------
+def config(index: int, **kw) -> Scene:
+    """Workload ``index`` (1..4) at its full size; keyword overrides apply."""
+    if index == 1:
+        return poiseuille(**kw)
+    if index == 2:
+        return reactive_channel(**kw)
+    if index == 3:
+        return hartmann_couette(**kw)
+    if index == 4:
+        return mhd_pipe(**kw)
+    raise ValueError(index)
+
+
+@dataclass
+class BatchItem:
+    shape: str            # "duct" | "pipe"
+    ny: int
+    nz: int
+    q: Tuple[float, ...]  # duct: (y-lo, y-hi, z-lo, z-hi); pipe: (q,)
+    Ha: float
+    c_w: float
+    scene: Scene
+
+
+def batch_items(n_items: int = 256, seed: int = BASE_SEED + 5, side_lo: int = 64,
+                side_hi: int = 256, Ha_hi: float = 50.0, c_lo: float = 1e-3, c_hi: float = 10.0,
+                tau_f: float = 0.8, tau_m: float = 0.9, u_target: float = 0.01,
+                storage: str = "f16") -> List[BatchItem]:
+    """Uneven duct / pipe cross-sections (axial extent 1, periodic) for the
+    batched solver: D3Q19 fluid + D3Q7 magnetic lattice evolving B1 only,
+    B_ext along y, Shercliff walls with conductance ratio c_w everywhere."""
+    rng = SplitMix64(seed)
+    nu, eta = _nu(tau_f), _diff(tau_m)
+    items = []
+    for i in range(n_items):
+        shape = "duct" if rng.uniform() < 0.5 else "pipe"
+        Ha = rng.uniform(0.0, Ha_hi)
+        c_w = rng.log_uniform(c_lo, c_hi)
+        if shape == "duct":
+            a = rng.randint(side_lo, side_hi)
+            b = rng.randint(side_lo, side_hi)
+            qs = tuple(rng.uniform(0.1, 0.9) for _ in range(4))
+            Hy = (a - 1 + qs[0] + qs[1]) / 2.0
+            Hz = (b - 1 + qs[2] + qs[3]) / 2.0
+            Hmin = min(Hy, Hz)
+            B0 = hartmann_B0(Ha, Hy, 1.0, nu, eta, 1.0)
+            # Poiseuille-duct centre speed ~ g h^2/(2 nu) * 0.59 (h = short half side)
+            g = u_target * 2.0 * nu / (0.59 * Hmin * Hmin * (1.0 + 0.0 * Hy))
+            bnds = []
+            for ax, (side, qq) in [(1, (0, qs[0])), (1, (1, qs[1])), (2, (0, qs[2])), (2, (1, qs[3]))]:
+                H = Hy if ax == 1 else Hz
+                bnds.append(Boundary("plane", axis=ax, side=side, q=qq, f=BC(VEL),
+                                     g=[BC(MAG_FLUX, a1=-eta / (c_w * H), a3=0.0)]))
+            ny, nz = a, b
+        else:
+            s = rng.randint(side_lo, side_hi)
+            qq = rng.uniform(0.1, 0.9)
+            R = s / 2.0 - 2.0 + qq
+            B0 = hartmann_B0(Ha, R, 1.0, nu, eta, 1.0)
+            g = u_target * 4.0 * nu / (R * R)
+            c = (s - 1) / 2.0
+            bnds = [Boundary("cylinder", axis=0, center=(0.0, c, c), radius=R, f=BC(VEL),
+                             g=[BC(MAG_FLUX, a1=-eta / (c_w * R), a3=0.0)])]
+            ny = nz = s
+            qs = (qq,)
+        sc = Scene(name=f"item{i}_{shape}", dim=3, n=(1, ny, nz), periodic=(True, False, False),
+                   fluid_lattice=D3Q19, mag_lattice=D3Q7, mag_comps=(0,), tau_f=tau_f,
+                   tau_m=tau_m, B_ext=(0.0, B0, 0.0), accel=(g, 0.0, 0.0), boundaries=bnds,
+                   storage=storage, store_scale=(1024.0, 1.0, 1024.0))
+        items.append(BatchItem(shape, ny, nz, qs, Ha, c_w, sc))
+    return items
+
+
+def paper_case_to_lattice(dx: float, c: float, nu: float = None, D: float = None,
+                          eta: float = None) -> dict:
+    """Convert an SI parameter set (dx, c = dx/dt) into relaxation times.
+
+    nu = dt c^2/3 (tau_nu - 1/2); D, eta = dt c^2/4 (tau - 1/2).
+    """
+    dt = dx / c
+    out = {"dt": dt}
+    if nu is not None:
+        out["tau_f"] = 0.5 + nu / (dt * c * c / 3.0)
+    if D is not None:
+        out["tau_c"] = 0.5 + D / (dt * c * c / 4.0)
+    if eta is not None:
+        out["tau_m"] = 0.5 + eta / (dt * c * c / 4.0)
+    return out

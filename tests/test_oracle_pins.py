@@ -1,0 +1,582 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints, closed forms, exact special cases of the general link formulas,
+invariants, or brute force on small inputs.  None of these tests needs a GPU.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from oracle import analytic as an
+from scenes import BC, Boundary, Scene
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# lattices and equilibria (Section 2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D2Q5", "D3Q7"])
+def test_lattice_moments(name):
+    e, w, c2, opp = oracle.lattice_table(name)
+    assert np.isclose(w.sum(), 1.0, atol=1e-15)
+    assert np.allclose(w @ e, 0.0, atol=1e-15)
+    assert np.allclose((w[:, None, None] * e[:, :, None] * e[:, None, :]).sum(0)[:len(set(
+        [i for i in range(3) if e[:, i].any()])), :len(set([i for i in range(3) if e[:, i].any()]))],
+        c2 * np.eye(len([i for i in range(3) if e[:, i].any()])), atol=1e-15)
+    for a in range(len(w)):
+        assert np.array_equal(e[opp[a]], -e[a])
+        assert w[opp[a]] == w[a]
+    if name in ("D2Q9", "D3Q19"):
+        # fourth-order isotropy needed for the Navier-Stokes stress
+        d = 2 if name == "D2Q9" else 3
+        T = np.einsum("a,ai,aj,ak,al->ijkl", w, e[:, :d], e[:, :d], e[:, :d], e[:, :d])
+        I = np.eye(d)
+        iso = c2 * c2 * (np.einsum("ij,kl->ijkl", I, I) + np.einsum("ik,jl->ijkl", I, I)
+                         + np.einsum("il,jk->ijkl", I, I))
+        assert np.allclose(T, iso, atol=1e-15)
+
+
+def test_d2q9_ordering_pairs():
+    """The paper's D2Q9 indices pair 1-3, 2-4, 5-7, 6-8 (Section 3.1 text)."""
+    e, w, c2, opp = oracle.lattice_table("D2Q9")
+    assert list(opp) == [0, 3, 4, 1, 2, 7, 8, 5, 6]
+    assert tuple(e[1, :2]) == (1, 0) and tuple(e[5, :2]) == (1, 1)
+
+
+def test_paper_parameter_sets_fix_lattice_speeds():
+    """The paper's SI parameter sets imply c_s^2 = c^2/3 and c_h^2 = c_g^2 = c^2/4."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_parameter_sets.json")))
+    for case in g["cases"]:
+        dt = case["dx"] / case["c"]
+        c2_lattice = case["coef"] / (dt * case["c"] ** 2 * (case["tau"] - 0.5))
+        _, _, c2, _ = oracle.lattice_table(case["lattice"])
+        assert np.isclose(c2_lattice, c2, rtol=1e-12), case
+    st = g["stokes_second_problem"]
+    for tau, dt in zip(st["tau"], st["dt"]):
+        # nu = dx^2 (tau - 1/2) / (3 dt)
+        assert np.isclose(st["dx"] ** 2 * (tau - 0.5) / (3 * dt), st["nu"], rtol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
+def test_feq_moments_eq8(name):
+    rng = np.random.default_rng(1)
+    e, w, c2, _ = oracle.lattice_table(name)
+    d = 2 if name == "D2Q9" else 3
+    for _ in range(5):
+        rho = 1 + 0.1 * rng.standard_normal()
+        u = np.zeros(3)
+        u[:d] = 0.05 * rng.standard_normal(d)
+        f, _, _ = oracle.equilibria(name, rho, u)
+        assert np.isclose(f.sum(), rho, rtol=1e-14)
+        assert np.allclose(f @ e, rho * u, atol=1e-15)
+        Pi = np.einsum("a,ai,aj->ij", f, e, e)[:d, :d]
+        assert np.allclose(Pi, rho * np.outer(u, u)[:d, :d] + rho * c2 * np.eye(d), atol=1e-15)
+
+
+@pytest.mark.parametrize("name", ["D2Q5", "D3Q7"])
+def test_heq_geq_moments_eq9_eq10(name):
+    rng = np.random.default_rng(2)
+    e, w, c2, _ = oracle.lattice_table(name)
+    d = 2 if name == "D2Q5" else 3
+    for _ in range(5):
+        u = np.zeros(3)
+        u[:d] = 0.05 * rng.standard_normal(d)
+        B = np.zeros(3)
+        B[:d] = rng.standard_normal(d)
+        Cc = 1 + rng.random()
+        _, h, g = oracle.equilibria(name, 1.0, u, Cc, B)
+        assert np.isclose(h.sum(), Cc, rtol=1e-14)
+        assert np.allclose(h @ e, Cc * u, atol=1e-15)                          # Eq. 9
+        assert np.allclose(g.sum(0), B, atol=1e-15)
+        Lam = np.einsum("ai,ak->ik", e, g)                                    # sum e g
+        assert np.allclose(Lam, np.outer(u, B) - np.outer(B, u), atol=1e-15)  # Eq. 10
+
+
+def test_moving_increment_identity():
+    """f^eq_a(u) - f^eq_a'(u) = f^eq_a'(-u) - f^eq_a(-u) = 2 rho w_a (e_a.u)/c_s^2
+    (Sections 3.1 and 4.2.2)."""
+    e, w, c2, opp = oracle.lattice_table("D2Q9")
+    rho, u = 1.03, np.array([0.02, -0.013, 0.0])
+    fp, _, _ = oracle.equilibria("D2Q9", rho, u)
+    fm, _, _ = oracle.equilibria("D2Q9", rho, -u)
+    for a in range(9):
+        lhs = fp[a] - fp[opp[a]]
+        assert np.isclose(lhs, fm[opp[a]] - fm[a], rtol=1e-13, atol=1e-17)
+        assert np.isclose(lhs, 2 * rho * w[a] * (e[a] @ u) / c2, rtol=1e-13, atol=1e-17)
+
+
+# ---------------------------------------------------------------------------
+# single-link formulas against the paper's special cases (Eqs. 11-12, 28-29,
+# 32, 36-38, 41-42)
+# ---------------------------------------------------------------------------
+def _rand_inputs(rng):
+    return dict(x_ap_E=rng.random(), x_ap_A=rng.random(), x_a_A=rng.random())
+
+
+def test_vel_static_is_bouzidi_eq11_eq12():
+    rng = np.random.default_rng(3)
+    for d in (0.1, 0.3, 0.49, 0.5, 0.7, 1.0):
+        x = _rand_inputs(rng)
+        v = oracle.link_eval(kind="VEL", dir=3, d=d, u_w=(0, 0, 0), **x)
+        if d < 0.5:
+            ref = (1 - 2 * d) * x["x_ap_E"] + 2 * d * x["x_ap_A"]
+        else:
+            ref = ((2 * d - 1) * x["x_a_A"] + x["x_ap_A"]) / (2 * d)
+        assert np.isclose(v, ref, rtol=1e-14)
+
+
+def test_vel_pres_half_grid_eq41_eq42():
+    rng = np.random.default_rng(4)
+    e, w, c2, opp = oracle.lattice_table("D2Q9")
+    for a in range(1, 9):
+        x = _rand_inputs(rng)
+        rA, rE = 1 + 0.01 * rng.random(), 1 + 0.01 * rng.random()
+        uw = np.array([0.01 * rng.standard_normal(), 0.01 * rng.standard_normal(), 0.0])
+        mA = [rA, 0, 0, 0, 0, 0, 0, 0]
+        mE = [rE, 0, 0, 0, 0, 0, 0, 0]
+        v = oracle.link_eval(kind="VEL", dir=a, d=0.5, u_w=uw, mA=mA, mE=mE, **x)
+        rhoX = -0.5 * rE + 1.5 * rA
+        assert np.isclose(v, x["x_ap_A"] + 2 * rhoX * w[a] * (e[a] @ uw) / c2, rtol=1e-13)
+        # pressure: given rho_w, u_X extrapolated from u_A, u_E
+        uA = np.array([0.01, -0.003, 0.0])
+        uE = np.array([0.012, 0.001, 0.0])
+        mA = [rA, *uA, 0, 0, 0, 0]
+        mE = [rE, *uE, 0, 0, 0, 0]
+        v = oracle.link_eval(kind="PRES", dir=a, d=0.5, value=1.001, mA=mA, mE=mE, **x)
+        uX = -0.5 * uE + 1.5 * uA
+        eu = e[a] @ uX
+        s = 2 * 1.001 * w[a] * (1 + eu * eu / (2 * c2 * c2) - uX @ uX / (2 * c2))
+        assert np.isclose(v, -x["x_ap_A"] + s, rtol=1e-13)
+
+
+def test_flux_m_scheme_special_cases_eq28_eq29():
+    rng = np.random.default_rng(5)
+    e, w, c2, opp = oracle.lattice_table("D2Q5")
+    for a in range(1, 5):
+        x = _rand_inputs(rng)
+        CA, CE = 1 + rng.random(), 1 + rng.random()
+        uw = np.array([0.01, 0.004, 0.0])
+        a1, a3 = -0.02, -0.01
+        kw = dict(lattice="D2Q5", kind="FLUX", dir=a, a1=a1, a3=a3, u_w=uw,
+                  mA=[1, 0, 0, 0, CA, 0, 0, 0], mE=[1, 0, 0, 0, CE, 0, 0, 0], **x)
+        for d in (0.5, 1.0):
+            CX = -d * CE + (d + 1) * CA
+            dflux = a1 * CX - a3
+            dmove = 2 * w[a] * CX * (e[a] @ uw) / c2
+            v = oracle.link_eval(d=d, **kw)
+            if d == 0.5:
+                ref = x["x_ap_A"] + dflux + dmove                                   # Eq. 28
+            else:
+                ref = (0.5 * x["x_a_A"] - 0.5 * x["x_ap_E"] + 1.5 * x["x_ap_A"]
+                       + dflux + dmove) / 1.5                                       # Eq. 29
+            assert np.isclose(v, ref, rtol=1e-13)
+
+
+def test_conc_any_d_eq19_eq20():
+    rng = np.random.default_rng(6)
+    e, w, c2, opp = oracle.lattice_table("D2Q5")
+    for d in (0.2, 0.5, 0.77, 1.0):
+        for a in range(1, 5):
+            x = _rand_inputs(rng)
+            v = oracle.link_eval(lattice="D2Q5", kind="CONC", dir=a, d=d, value=2.5,
+                                 u_w=(0.01, 0.02, 0), **x)
+            ref = 2 * w[a] * 2.5 - ((1 - 2 * d) * x["x_ap_E"] + 2 * d * x["x_ap_A"])
+            assert np.isclose(v, ref, rtol=1e-13)
+
+
+def test_magnetic_special_cases_eq36_eq37_eq38_eq32():
+    """At U = (U1, 0) and d = 0.5: conducting wall -> Eq. 36; insulating B1 = 0 ->
+    Eq. 37; normal component B2 = B_ext -> Eq. 38.  At d = 1 the M scheme gives
+    Eq. 32 for the Shercliff wall."""
+    rng = np.random.default_rng(7)
+    e, w, c2, opp = oracle.lattice_table("D2Q5")
+    U1, Bext = 0.01, 0.02
+    for a in range(1, 5):
+        x = _rand_inputs(rng)
+        BA = np.array([0.003, Bext, 0.0])
+        BE = np.array([0.002, Bext, 0.0])
+        mA = [1, 0, 0, 0, 0, *BA]
+        mE = [1, 0, 0, 0, 0, *BE]
+        BX = -0.5 * BE + 1.5 * BA
+        # Eq. 36: conducting (zero flux), moving wall, component x1
+        v = oracle.link_eval(lattice="D2Q5", kind="MAG_FLUX", dir=a, d=0.5, comp_axis=0,
+                             a1=0.0, a3=0.0, u_w=(U1, 0, 0), mA=mA, mE=mE, **x)
+        if e[a] @ np.array([U1, 0, 0]) == 0:
+            ref = x["x_ap_A"] - 2 * w[a] * (e[a] @ BX) * U1 / c2
+            assert np.isclose(v, ref, rtol=1e-13)
+        # Eq. 37: insulating, B1 = 0
+        v = oracle.link_eval(lattice="D2Q5", kind="MAG_DIR", dir=a, d=0.5, comp_axis=0, value=0.0,
+                             u_w=(U1, 0, 0), mA=mA, mE=mE, **x)
+        assert np.isclose(v, -x["x_ap_A"], rtol=1e-13, atol=1e-18)
+        # Eq. 38: B2 = B_ext
+        v = oracle.link_eval(lattice="D2Q5", kind="MAG_DIR", dir=a, d=0.5, comp_axis=1,
+                             value=Bext, u_w=(U1, 0, 0), mA=mA, mE=mE, **x)
+        assert np.isclose(v, 2 * w[a] * Bext - x["x_ap_A"], rtol=1e-13)
+        # Eq. 32: Shercliff wall at d = 1 via the point M
+        a1 = -0.05
+        v = oracle.link_eval(lattice="D2Q5", kind="MAG_FLUX", dir=a, d=1.0, comp_axis=0,
+                             a1=a1, a3=0.0, u_w=(U1, 0, 0), mA=mA, mE=mE, **x)
+        BX1 = -1.0 * BE + 2.0 * BA
+        dflux = a1 * BX1[0]
+        dmove = 2 * w[a] * ((e[a] @ np.array([U1, 0, 0])) * BX1[0] - (e[a] @ BX1) * U1) / c2
+        gM = 1.5 * x["x_ap_A"] - 0.5 * x["x_ap_E"]
+        ref = (0.5 * x["x_a_A"] + gM + dflux + dmove) / 1.5
+        assert np.isclose(v, ref, rtol=1e-13)
+
+
+def test_halfway_limit_of_both_branches():
+    """As d -> 0.5 the d < 0.5 and d >= 0.5 forms meet (halfway bounce-back)."""
+    x = dict(x_ap_E=0.3, x_ap_A=0.7, x_a_A=0.1)
+    for kind in ("VEL", "BB0"):
+        lo = oracle.link_eval(kind=kind, dir=1, d=0.5 - 1e-12, **x)
+        hi = oracle.link_eval(kind=kind, dir=1, d=0.5, **x)
+        assert abs(lo - hi) < 1e-11 and abs(hi - 0.7) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# flow closed forms (P1-P3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tau", [0.8, 0.5 + math.sqrt(3) / 4, 1.3])
+def test_poiseuille_exact_discrete(tau):
+    N, g = 24, 1e-6
+    nu = (tau - 0.5) / 3
+    sc = scenes.poiseuille(nx=2, ny=N, tau=tau, g=g)
+    o = oracle.OracleSim(sc)
+    o.step(int(20 * N * N / (nu * math.pi ** 2)))
+    u = o.moments()[0, :, 0, 1]
+    ex = an.poiseuille_discrete(N, tau, g)
+    assert np.abs(u - ex).max() / ex.max() < 1e-7
+    if abs(tau - (0.5 + math.sqrt(3) / 4)) < 1e-12:
+        y = np.arange(N)
+        assert np.abs(u - an.poiseuille_continuum(y, -0.5, N - 0.5, g, nu)).max() / ex.max() < 1e-7
+
+
+@pytest.mark.parametrize("q", [0.5, 0.3, 0.7, 1.0, 0.15])
+def test_couette_exact_any_d(q):
+    N, U = 14, 1e-3
+    sc = scenes.poiseuille(nx=2, ny=N, g=0.0, q=q, u_top=U, tau=0.8)
+    o = oracle.OracleSim(sc)
+    o.step(25000)
+    m = o.moments()
+    u = m[0, :, 0, 1]
+    ex = an.couette(np.arange(N), -q, N - 1 + q, 0.0, U)
+    assert np.abs(u - ex).max() / U < 1e-9
+
+
+def test_mass_invariant_halfway_walls():
+    """Static or tangentially moving walls at d = 0.5 conserve mass exactly
+    (round-off only: < 1e-16 per node per step)."""
+    sc = scenes.poiseuille(nx=8, ny=10, g=1e-5, q=0.5, u_top=0.02, tau=0.7)
+    o = oracle.OracleSim(sc)
+    m0 = o.moments()[..., 0].sum()
+    for _ in range(20):
+        o.step(50)
+        assert abs(o.moments()[..., 0].sum() - m0) / m0 < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# scalar and magnetic walls: exact linear profiles for any d (Eqs. 19-22, 25-27)
+# ---------------------------------------------------------------------------
+def _chan_scalar(qb, qt, hb, ht, ny=12, tau_c=0.8):
+    bot = Boundary("plane", axis=1, side=0, q=qb, f=BC("VEL"), h=hb)
+    top = Boundary("plane", axis=1, side=1, q=qt, f=BC("VEL"), h=ht)
+    return Scene(name="c1d", dim=2, n=(1, ny, 1), periodic=(True, False, True),
+                 fluid_lattice="D2Q9", scalar_lattice="D2Q5", tau_c=tau_c, init_C=1.0,
+                 boundaries=[bot, top])
+
+
+@pytest.mark.parametrize("qb,qt", [(0.5, 0.5), (0.3, 0.8), (1.0, 0.2), (0.9, 1.0)])
+def test_scalar_linear_profiles_exact(qb, qt):
+    ny, D = 12, (0.8 - 0.5) / 4
+    y = np.arange(ny) + qb
+    W = ny - 1 + qb + qt
+    # given C on both walls -> linear
+    o = oracle.OracleSim(_chan_scalar(qb, qt, BC("CONC", value=1.0), BC("CONC", value=2.0)))
+    o.step(40000)
+    assert np.abs(o.moments()[0, :, 0, 4] - (1 + y / W)).max() < 1e-11
+    # given C below, Robin flux above: D C'(W) = a1 C(W) - a3  (n into the fluid)
+    a1, a3 = -0.01, -0.03
+    o = oracle.OracleSim(_chan_scalar(qb, qt, BC("CONC", value=1.0), BC("FLUX", a1=a1, a3=a3)))
+    o.step(60000)
+    s = (a1 - a3) / (D - a1 * W)
+    assert np.abs(o.moments()[0, :, 0, 4] - (1 + s * y)).max() < 1e-11
+    # zero normal gradient below, given C above -> uniform
+    o = oracle.OracleSim(_chan_scalar(qb, qt, BC("BB0"), BC("CONC", value=2.0)))
+    o.step(60000)
+    assert np.abs(o.moments()[0, :, 0, 4] - 2.0).max() < 1e-11
+
+
+@pytest.mark.parametrize("qb,qt", [(0.5, 0.5), (0.25, 1.0)])
+def test_magnetic_linear_profile_exact(qb, qt):
+    """Pure magnetic diffusion (u = 0, B2 = 0, Lorentz force switched off by a
+    huge permeability): given B1 below, Shercliff flux above -> linear B1 for
+    any d."""
+    ny, eta, a1 = 12, (0.9 - 0.5) / 4, -0.02
+    bot = Boundary("plane", axis=1, side=0, q=qb, f=BC("VEL"), g=[BC("MAG_DIR", value=0.01)])
+    top = Boundary("plane", axis=1, side=1, q=qt, f=BC("VEL"), g=[BC("MAG_FLUX", a1=a1, a3=0.0)])
+    sc = Scene(name="m1d", dim=2, n=(1, ny, 1), periodic=(True, False, True), fluid_lattice="D2Q9",
+               mag_lattice="D2Q5", mag_comps=(0,), tau_m=0.9, mu=1e15, boundaries=[bot, top])
+    o = oracle.OracleSim(sc)
+    o.step(60000)
+    y = np.arange(ny) + qb
+    W = ny - 1 + qb + qt
+    s = a1 * 0.01 / (eta - a1 * W)
+    assert np.abs(o.moments()[0, :, 0, 5] - (0.01 + s * y)).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Hartmann-Couette flow (Section 5.4): second-order convergence to the closed form
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("q", [0.5, 1.0, 0.3])
+@pytest.mark.parametrize("c", [0.0, 0.1, math.inf])
+def test_hartmann_couette_converges(q, c):
+    errs = []
+    for ny in (24, 48):
+        sc = scenes.hartmann_couette(nx=1, ny=ny, Ha=5.0, c_top=c, u_top=1e-3, v0=0.0, qb=q, qt=q,
+                                     storage="f64")
+        H, B0 = sc.meta["H"], sc.meta["B0"]
+        o = oracle.OracleSim(sc)
+        o.step(int(8 * H * H / 0.1))
+        m = o.moments()
+        y = np.arange(ny) - (ny - 1) / 2
+        u_ex, b_ex = an.hartmann_couette(y, H, B0, 0.1, 0.1, U_top=1e-3, c_top=c)
+        eu = np.linalg.norm(m[0, :, 0, 1] - u_ex) / np.linalg.norm(u_ex)
+        eb = np.linalg.norm(m[0, :, 0, 5] - b_ex) / np.linalg.norm(b_ex)
+        assert np.abs(m[0, :, 0, 6] - B0).max() < 1e-15        # B2 stays B_ext (Section 4.3)
+        errs.append((eu, eb))
+    (eu1, eb1), (eu2, eb2) = errs
+    assert eu2 < 5e-3 and eb2 < 2e-2, errs
+    assert eu1 / eu2 > 3.0 and eb1 / eb2 > 3.0, errs
+
+
+def test_hartmann_closed_form_matches_fd():
+    """The 4x4 closed form and the finite-difference channel solver agree."""
+    H, B0 = 20.0, 0.01
+    y = np.linspace(-H, H, 9)
+    for c in (0.0, 0.1, math.inf):
+        u1, b1 = an.hartmann_couette(y, H, B0, 0.1, 0.1, U_top=1e-3, c_top=c, g=1e-6)
+        u2, b2 = an.hartmann_channel_fd(y, H, B0, 0.1, 0.1, U_top=1e-3, c_top=c, g=1e-6, m=400)
+        assert np.allclose(u1, u2, rtol=1e-6, atol=1e-10)
+        assert np.allclose(b1, b2, rtol=1e-6, atol=1e-10)
+
+
+def test_transpiring_hartmann_couette():
+    """Walls moving with a normal speed v0 as well (uniform transpiration):
+    the oracle converges to the finite-difference solution of the channel
+    equations with the -v0 d/dy terms."""
+    errs = []
+    for ny in (24, 48):
+        sc = scenes.hartmann_couette(nx=1, ny=ny, Ha=5.0, c_top=0.1, u_top=1e-3, v0=2e-4,
+                                     qb=0.5, qt=0.5, storage="f64")
+        H, B0 = sc.meta["H"], sc.meta["B0"]
+        o = oracle.OracleSim(sc)
+        o.step(int(8 * H * H / 0.1))
+        m = o.moments()
+        y = np.arange(ny) - (ny - 1) / 2
+        u_ex, b_ex = an.hartmann_channel_fd(y, H, B0, 0.1, 0.1, U_top=1e-3, c_top=0.1, v0=2e-4)
+        errs.append((np.linalg.norm(m[0, :, 0, 1] - u_ex) / np.linalg.norm(u_ex),
+                     np.linalg.norm(m[0, :, 0, 5] - b_ex) / np.linalg.norm(b_ex)))
+        assert np.abs(m[0, :, 0, 2] - 2e-4).max() < 2e-6      # normal velocity carried through
+    assert errs[1][0] < 1e-2 and errs[1][1] < 2e-2, errs
+    assert errs[0][0] / errs[1][0] > 2.5, errs
+
+
+# ---------------------------------------------------------------------------
+# diffusion with a surface reaction (Section 5.3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("layout", ["half", "full"])
+@pytest.mark.parametrize("Da", [4.8, 48.0])
+def test_diffusion_reaction_converges(layout, Da):
+    errs = []
+    for W in (16, 32):
+        sc = scenes.diffusion_reaction(layout=layout, Da=Da, W_nodes=W)
+        o = oracle.OracleSim(sc)
+        Wc, Lc, D = sc.meta["W"], sc.meta["L"], sc.meta["D"]
+        o.step(int(3 * Lc * Lc / D))
+        C = o.moments()[0, :, :, 4]
+        ny, nx = C.shape
+        q = 0.5 if layout == "half" else 1.0
+        X, Y = np.meshgrid(np.arange(nx) + q, np.arange(ny) + q)
+        Cex = an.diffusion_reaction(X, Y, Wc, Lc, Da)
+        # the corner where the given-C and reacting walls meet is singular;
+        # compare away from it
+        errs.append(np.abs(C - Cex)[:, nx // 4:].max())
+    assert errs[1] < 0.07, errs                       # < 0.8 % of C_BC - C_eq
+    assert errs[0] / errs[1] > 1.8, errs
+
+
+# ---------------------------------------------------------------------------
+# curved walls (Section 6): geometry, segmentation, flux split, pipe flows
+# ---------------------------------------------------------------------------
+def _pipe(R, side, wall="shercliff", nx=1, **kw):
+    return scenes.mhd_pipe(nx=nx, side=side, R=R, wall=wall, storage="f64", **kw)
+
+
+def test_cylinder_link_distances_bruteforce():
+    sc = _pipe(7.3, 19)
+    o = oracle.OracleSim(sc)
+    c = sc.meta["center"]
+    R = sc.meta["R"]
+    e19, _, _, _ = oracle.lattice_table("D3Q19")
+    e7, _, _, _ = oracle.lattice_table("D3Q7")
+    nx, ny, nz = sc.n
+    L = o.links()
+    assert len(L) > 0
+    for lk in L:
+        A = lk["A"]
+        ax, ay, az = A % nx, (A // nx) % ny, A // (nx * ny)
+        e = (e19 if lk["field"] == 0 else e7)[lk["dir"]]
+        inside = lambda s: (ay - s * e[1] - c) ** 2 + (az - s * e[2] - c) ** 2 < R * R
+        lo, hi = 0.0, 1.0
+        assert inside(0.0) and not inside(1.0)
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            lo, hi = (mid, hi) if inside(mid) else (lo, mid)
+        assert abs(lk["d"] - 0.5 * (lo + hi)) < 1e-12
+        assert 0.0 < lk["d"] <= 1.0
+
+
+@pytest.mark.parametrize("R,side", [(7.3, 19), (20.5, 45), (60.0, 128)])
+def test_segmentation_total_area_and_split(R, side):
+    """Sum of S_i is 2 pi R (telescoping theta differences), and the split of
+    each B_i's flux over its links (Eq. 48) conserves S_i."""
+    sc = _pipe(R, side, nx=1)
+    o = oracle.OracleSim(sc)
+    S_sum, n_outer = o.segment_sum()
+    assert n_outer > 0
+    assert abs(S_sum - 2 * math.pi * R) < 1e-9 * R
+    L = o.links()
+    g = L[(L["field"] == 2)]
+    assert np.all(g["weight"] >= 0.0)
+    assert abs(g["weight"].sum() - 2 * math.pi * R) < 1e-9 * R
+
+
+def test_link_builder_corner_priority():
+    """A link leaving through a corner where a wall and an open boundary meet
+    takes the wall; among walls the smaller d wins."""
+    sc = scenes.reactive_channel(nx=6, ny=5, q=0.3, q_io=0.5)
+    o = oracle.OracleSim(sc)
+    L = o.links()
+    f = L[(L["field"] == 0) & (L["A"] == 0)]            # node (0, 0)
+    dirs = {int(r["dir"]): r for r in f}
+    # e5 = (1, 1) arrives from (-1, -1): wall (d = 0.3) beats the inlet (d = 0.5)
+    assert dirs[5]["kind"] == 1 and abs(dirs[5]["d"] - 0.3) < 1e-15
+    assert dirs[1]["kind"] == 2 and abs(dirs[1]["d"] - 0.5) < 1e-15   # inlet, pressure
+    assert dirs[2]["kind"] == 1                                         # wall, velocity
+    # the wall wins even when the open boundary is crossed first
+    sc = scenes.reactive_channel(nx=6, ny=5, q=0.8, q_io=0.5)
+    sc = sc.with_(boundaries=sc.boundaries[::-1])       # open planes listed first
+    o = oracle.OracleSim(sc)
+    L = o.links()
+    dirs = {int(r["dir"]): r for r in L[(L["field"] == 0) & (L["A"] == 0)]}
+    assert dirs[5]["kind"] == 1 and abs(dirs[5]["d"] - 0.8) < 1e-15
+
+
+def test_hagen_poiseuille_converges():
+    errs = []
+    for R in (6.3, 12.6):
+        side = int(2 * R + 5)
+        sc = _pipe(R, side, wall="insulating", Ha=0.0, g=1e-5).with_(mag_lattice=None, mag_comps=())
+        o = oracle.OracleSim(sc)
+        o.step(int(6 * R * R / 0.1))
+        m = o.moments()
+        u = m[:, :, 0, 1]
+        mask = o.mask()[:, :, 0] == 1
+        c = (side - 1) / 2
+        Y, Z = np.meshgrid(np.arange(side) - c, np.arange(side) - c, indexing="xy")
+        uex = an.hagen_poiseuille(np.hypot(Y, Z), R, 1e-5, 0.1)
+        errs.append(np.linalg.norm((u - uex)[mask]) / np.linalg.norm(uex[mask]))
+    assert errs[1] < 3e-3 and errs[0] / errs[1] > 3.0, errs
+
+
+def _mhd_pipe_error(R, wall, c_w=0.1):
+    side = int(2 * R + 5)
+    g = 1e-5
+    sc = _pipe(R, side, wall=wall, c_w=c_w, Ha=10.0, g=g)
+    B0 = sc.meta["B0"]
+    rg, tg, U, Bf = an.pipe_mhd_polar(R, B0, 0.1, 0.1, g, wall, c_w=c_w, nr=48, nt=192)
+    o = oracle.OracleSim(sc)
+    o.step(int(5 * R * R / 0.1))
+    m = o.moments()
+    u, b = m[:, :, 0, 1], m[:, :, 0, 5]
+    mask = o.mask()[:, :, 0] == 1
+    c = (side - 1) / 2
+    Y, Z = np.meshgrid(np.arange(side) - c, np.arange(side) - c, indexing="xy")
+    uex, bex = an.polar_sample(rg, tg, U, Y, Z), an.polar_sample(rg, tg, Bf, Y, Z)
+    if wall == "conducting":      # B1 is fixed only up to a constant by zero-flux walls
+        b, bex = b - b[mask].mean(), bex - bex[mask].mean()
+    eu = np.linalg.norm((u - uex)[mask]) / np.linalg.norm(uex[mask])
+    eb = np.linalg.norm((b - bex)[mask]) / np.linalg.norm(bex[mask])
+    return eu, eb
+
+
+@pytest.mark.parametrize("wall", ["insulating", "conducting", "shercliff"])
+def test_mhd_pipe_against_polar_solver(wall):
+    eu, eb = _mhd_pipe_error(10.3, wall)
+    assert eu < 4e-2 and eb < 6e-2, (eu, eb)
+
+
+@pytest.mark.slow
+def test_mhd_pipe_shercliff_converges():
+    e1 = _mhd_pipe_error(8.3, "shercliff")
+    e2 = _mhd_pipe_error(16.6, "shercliff")
+    assert e1[0] / e2[0] > 1.8 and e1[1] / e2[1] > 1.8, (e1, e2)
+
+
+def test_polar_solver_hagen_limit():
+    """With B0 -> 0 the polar solver returns the Hagen-Poiseuille profile."""
+    rg, tg, U, Bf = an.pipe_mhd_polar(1.0, 1e-9, 1.0, 1.0, 1.0, "insulating", nr=32, nt=64)
+    ex = an.hagen_poiseuille(rg, 1.0, 1.0, 1.0)
+    assert np.abs(U[:, 0] - ex).max() < 1e-3 * ex.max()
+
+
+def test_pipe_three_components_keep_transverse_field():
+    """Evolving all three B components keeps B2 = B_ext and B3 = 0 (Section
+    4.3 argument for a unidirectional flow; the compressible transient leaves a
+    tiny residue).  B1 and u then differ from the B1-only run by the
+    explicit-current reading's O(B0^2/(rho mu tau c^2)) term, which shrinks
+    as dx^2 at fixed Ha."""
+    gaps = []
+    for R, side in ((6.3, 17), (12.6, 31)):
+        res = {}
+        for ncomp in (1, 3):
+            sc = scenes.mhd_pipe(nx=1, side=side, R=R, Ha=10.0, g=1e-5, wall="insulating",
+                                 ncomp=ncomp, storage="f64")
+            o = oracle.OracleSim(sc)
+            o.step(int(4 * R * R / 0.1))
+            res[ncomp] = (o.moments(), o.mask() == 1, sc.meta["B0"])
+        (m1, mask, B0), (m3, _, _) = res[1], res[3]
+        assert np.abs(m3[..., 6][mask] - B0).max() < 1e-6 * B0
+        assert np.abs(m3[..., 7][mask]).max() < 1e-6 * B0
+        b1, u1 = m1[..., 5][mask], m1[..., 1][mask]
+        gaps.append((np.abs(m3[..., 5][mask] - b1).max() / np.abs(b1).max(),
+                     np.abs(m3[..., 1][mask] - u1).max() / np.abs(u1).max()))
+    assert gaps[0][0] / gaps[1][0] > 3.0 and gaps[0][1] / gaps[1][1] > 3.0, gaps
+
+
+@pytest.mark.parametrize("qi,qo", [(0.5, 0.5), (0.3, 0.8), (1.0, 0.2), (0.7, 1.0)])
+def test_open_boundaries_keep_uniform_flow(qi, qo):
+    """A given-velocity inlet and a given-pressure outlet (Eqs. 15-16, 43 and the
+    zeroth-moment pair, Eq. 44) hold the uniform state (rho_out, u_in) fixed
+    for any boundary offsets, in both d branches."""
+    nx = 20
+    u_in, rho_out = (0.01, 0.002, 0.0), 1.002
+    inl = Boundary("plane", axis=0, side=0, q=qi, is_open=True, f=BC("VEL"), u_w=u_in)
+    out = Boundary("plane", axis=0, side=1, q=qo, is_open=True, f=BC("PRES", value=rho_out))
+    sc = Scene(name="open1d", dim=2, n=(nx, 3, 1), periodic=(False, True, True),
+               fluid_lattice="D2Q9", tau_f=0.8, boundaries=[inl, out],
+               init_rho=np.full((1, 3, nx), rho_out),
+               init_u=np.broadcast_to(np.array(u_in), (1, 3, nx, 3)).copy())
+    o = oracle.OracleSim(sc)
+    o.step(500)
+    m = o.moments()
+    assert np.abs(m[..., 0] - rho_out).max() < 1e-14
+    assert np.abs(m[..., 1] - u_in[0]).max() < 1e-14
+    assert np.abs(m[..., 2] - u_in[1]).max() < 1e-14
