@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused coupled lattice Boltzmann sweep on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--storage f32]
+
+Default workload: the coupled D2Q9 flow + D2Q5 convection-diffusion channel,
+512 x 256 nodes, Robin-reacting walls at d = 0.3 with a per-position rate
+k ~ log-uniform[1e-3, 1e-1], pressure-driven (rho_in/rho_out = 1.001),
+tau_f = 0.8, tau_c = 0.6, FP32 storage.  One step = one fused sweep over
+every fluid node of both lattices with all boundary links.  Prints ONE JSON
+line: MLUPS (fluid nodes x steps / s / 1e6) with inputs resident in HBM, the
+roofline of the step kernel (algorithmic bytes per launch / mean launch
+duration from HIP events on the launch stream, against 8 TB/s) and the FP64
+oracle's throughput on the host cores on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # bytes/s, MI355X
+
+
+def make_scene(name: str, storage: str):
+    import scenes
+    if name == "reactive":
+        return scenes.config(2, storage=storage, k_range=(1e-3, 1e-1)), "reactive channel 512x256 (D2Q9 + D2Q5)"
+    if name == "hartmann":
+        return scenes.config(3, storage=storage), "Hartmann-Couette 1024x512 (D2Q9 + D2Q5 x2)"
+    if name == "pipe":
+        return scenes.config(4, storage=storage, wall="shercliff"), "MHD pipe 64x128x128 (D3Q19 + D3Q7)"
+    if name == "poiseuille":
+        return scenes.config(1, storage=storage), "plane Poiseuille 64x32 (D2Q9)"
+    if name == "hartmann_wide":
+        return scenes.config(3, storage=storage, nx=32768), "Hartmann-Couette 32768x512 (D2Q9 + D2Q5 x2)"
+    if name == "pipe_long":
+        return scenes.config(4, storage=storage, nx=1024, wall="shercliff"), "MHD pipe 1024x128x128 (D3Q19 + D3Q7)"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def algorithmic_bytes(lat) -> dict:
+    """Bytes one step must move at least once, by the kernel's design:
+    populations read + written once per fluid node, one flag byte per padded
+    node, each link record, its two stashed values read and written, two link
+    offsets per link node, and one store + one load of the eight moments of
+    every node some link extrapolates from."""
+    sc = lat.scene
+    s = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[sc.storage]
+    cb = 8 if sc.storage == "f64" else 4
+    rec = 96 if sc.storage == "f64" else 64
+    q = {"D2Q9": 9, "D3Q19": 19, "D2Q5": 5, "D3Q7": 7}
+    QT = q[sc.fluid_lattice] + (q[sc.scalar_lattice] if sc.scalar_lattice else 0) + \
+        (len(sc.mag_comps) * q[sc.mag_lattice] if sc.mag_lattice else 0)
+    n_fluid = int(lat.mask.sum())
+    padded = 1
+    for k in range(3):
+        padded *= sc.n[k] + (0 if sc.periodic[k] else 2)
+    links = lat.links
+    link_nodes = np.unique(links["node"]).size
+    e_valid = (links["flags"] & 2) == 0
+    mom_nodes = np.unique(np.concatenate([links["node"], links["enode"][e_valid]])).size
+    per_node = 2 * QT * s
+    total = n_fluid * per_node + padded + len(links) * (rec + 4 * cb) + link_nodes * 8 + mom_nodes * 16 * cb
+    return dict(total=int(total), per_fluid_node_populations=per_node, fluid_nodes=n_fluid, links=int(len(links)),
+                link_nodes=int(link_nodes), moment_nodes=int(mom_nodes), planes=QT)
+
+
+def time_gpu(lat, steps: int, warmup: int):
+    import torch
+    stream = lat.stream
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    lat.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1)  # ms
+
+
+def time_launches(lat, n: int = 200):
+    """Mean duration of single step launches: HIP events recorded right
+    before and after each launch on the stream the kernel runs on."""
+    import torch
+    stream = lat.stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        lat.step(1)
+        b.record(stream)
+    torch.cuda.synchronize()
+    d = np.array([a.elapsed_time(b) for a, b in ev])
+    return float(np.mean(d)), float(np.median(d))
+
+
+def cpu_baseline(sc, budget_s: float = 12.0):
+    import oracle
+    o = oracle.OracleSim(sc)
+    n_fluid = int(o.mask().sum())
+    o.step(1)
+    t = time.perf_counter()
+    o.step(2)
+    per = (time.perf_counter() - t) / 2
+    k = max(2, int(budget_s / max(per, 1e-6)))
+    t = time.perf_counter()
+    o.step(k)
+    el = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=n_fluid * k / el / 1e6, unit="MLUPS", cores=cores, kind="oracle",
+                sample=f"{k} steps of the full {sc.n[0]}x{sc.n[1]}x{sc.n[2]} workload, FP64, OpenMP over nodes")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="reactive")
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extra", action="store_true", help="add throughput of the other workloads")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sweep shards by "
+              "slab or by item; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2506_00907_amd import lbm
+
+    torch.cuda.set_device(0)
+    sc, desc = make_scene(args.workload, args.storage)
+    lat = lbm.Lattice(sc)
+    ab = algorithmic_bytes(lat)
+    ms = time_gpu(lat, args.steps, args.warmup)
+    mlups = ab["fluid_nodes"] * args.steps / (ms / 1e3) / 1e6
+    mean_ms, med_ms = time_launches(lat)
+    achieved = ab["total"] / (mean_ms / 1e3)
+    res = lat.reduce()
+    if not np.isfinite(res[1:6]).all():
+        raise SystemExit("non-finite state")
+    out = {
+        "metric": "MLUPS + HBM GB/s fraction; time-to-steady (fp16-store+warm-start vs plain)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32"}[args.storage],
+        "data": "synthetic (seeded scene, SplitMix64)",
+        "config": {"workload": desc, "storage": args.storage, "fluid_nodes": ab["fluid_nodes"],
+                   "links": ab["links"], "launch": "hipGraph of 64 fused steps, 256 threads/block"},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK, "traffic": None,
+                     "bytes_per_launch": ab["total"], "mean_launch_ms": mean_ms, "median_launch_ms": med_ms,
+                     "kernel": "k_step (fused stream-collide + links), both parities"},
+    }
+    if args.extra:
+        extra = {}
+        for w, st in (("reactive", "f16"), ("hartmann", "f32"), ("hartmann", "f16"), ("pipe", "f32"),
+                      ("pipe", "bf16"), ("hartmann_wide", "f32"), ("pipe_long", "f32")):
+            s2, d2 = make_scene(w, st)
+            l2 = lbm.Lattice(s2)
+            a2 = algorithmic_bytes(l2)
+            m2 = time_gpu(l2, 1000, 100)
+            mean2, _ = time_launches(l2, 50)
+            extra[f"{w}_{st}"] = dict(mlups=round(a2["fluid_nodes"] * 1000 / (m2 / 1e3) / 1e6, 1),
+                                      roofline_frac=a2["total"] / (mean2 / 1e3) / HBM_PEAK,
+                                      bytes_per_launch=a2["total"], mean_launch_ms=mean2)
+            del l2
+            torch.cuda.empty_cache()
+        out["extra"] = extra
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

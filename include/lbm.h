@@ -1,0 +1,228 @@
+/*
+ * lbm.h - C ABI of the fused coupled lattice Boltzmann sweep for MI355X (gfx950).
+ *
+ * One step advances three coupled lattices on a regular grid:
+ *   f  flow, BGK (Eqs. 1-2), D2Q9 or D3Q19, with a body force and the Lorentz
+ *      force J x B;
+ *   h  convection-diffusion scalar C (Eqs. 3-4), D2Q5 or D3Q7;
+ *   g  vector-valued magnetic distributions for B (Eqs. 5-6), D2Q5 or D3Q7,
+ *      one distribution per evolved Cartesian component of B;
+ * and, in the same sweep, the boundary-link updates of Sections 3-4:
+ * pair-wise moment conservation for a given velocity, pressure, concentration
+ * or magnetic component (Eqs. 15-16, 19-20, 34-35, 43-44), the flux-increment
+ * M scheme for Robin reactions and Shercliff thin walls (Eqs. 17, 23, 25-27,
+ * 30-32), the moving-wall correction (Eq. 24), zero-gradient bounce-back
+ * (Eqs. 21-22) and the extrapolation of unknown moments (Eq. 13), for any
+ * boundary-to-node distance d in (0, 1].
+ *
+ * Units: lattice units, dx = dt = 1.  nu = (tau_f - 1/2)/3,
+ * D = (tau_c - 1/2)/4, eta = (tau_m - 1/2)/4.
+ *
+ * Conventions for every entry point:
+ *  - Return value: LBM_OK (0) or a negative lbm_status.  Inputs are validated
+ *    before any work is queued, so a call that fails has no effect.  The text
+ *    of the last error of a context is lbm_last_error(ctx).
+ *  - Memory: every device buffer is allocated and owned by the caller (the
+ *    library never allocates device memory, never frees caller memory); the
+ *    library owns only its host-side context.  "dev" pointers are device
+ *    pointers, "host" pointers are host pointers.
+ *  - Streams: all device work of a context is queued on the hipStream_t given
+ *    at creation (or lbm_set_stream).  lbm_reduce and lbm_save synchronise
+ *    that stream; everything else is asynchronous.  Asynchronous device errors
+ *    are reported by the next synchronising call.
+ *  - Threads: a context is not thread-safe; use one context per stream.
+ *  - Node indices: a node of the fluid domain (n[0] x n[1] x n[2] nodes) has
+ *    the linear index x + n[0]*(y + n[1]*z); 2D domains have n[2] = 1.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument */
+    LBM_ESIZE = -2,      /* a buffer or table is too small */
+    LBM_EDEVICE = -3,    /* HIP runtime error */
+    LBM_EUNSTABLE = -4,  /* non-finite values found by lbm_reduce */
+    LBM_ESTATE = -5      /* call out of order (e.g. lbm_step before lbm_init) */
+} lbm_status;
+
+typedef enum { LBM_NONE = 0, LBM_D2Q9 = 1, LBM_D3Q19 = 2, LBM_D2Q5 = 3, LBM_D3Q7 = 4 } lbm_lattice;
+
+/* Storage of the populations.  F16 and BF16 hold the deviation from the rest
+ * equilibrium (w_a rho0, w_a C0, w_a B_ext,k) times store_scale; arithmetic is
+ * then FP32.  F32 also stores deviations.  F64 stores deviations and computes
+ * in FP64. */
+typedef enum { LBM_F64 = 1, LBM_F32 = 2, LBM_F16 = 3, LBM_BF16 = 4 } lbm_storage;
+
+/* Boundary-link kinds (Sections 3-4). */
+typedef enum {
+    LBM_LK_VEL = 1,      /* given velocity u_w: Eqs. 15-16 (d < 0.5), Eq. 43 (d >= 0.5) */
+    LBM_LK_PRES = 2,     /* given density: zeroth-moment pair (d < 0.5), Eq. 44 (d >= 0.5) */
+    LBM_LK_CONC = 3,     /* given concentration: Eqs. 19-20 */
+    LBM_LK_FLUX = 4,     /* scalar flux F(C) = a1 C_X - a3, M scheme: Eqs. 23-27 */
+    LBM_LK_BB0 = 5,      /* zero normal gradient, static: Eqs. 21-22 */
+    LBM_LK_MAG_DIR = 6,  /* given magnetic component B_k: Eqs. 34-35 */
+    LBM_LK_MAG_FLUX = 7  /* magnetic flux F(B_k) = a1 B_X,k - a3 (Shercliff, Eq. 30), M scheme */
+} lbm_link_kind;
+
+#define LBM_NBUF 8
+
+typedef struct {
+    int32_t dim;          /* 2 or 3 */
+    int32_t n[3];         /* fluid-domain node counts (n[2] = 1 in 2D) */
+    int32_t periodic[3];  /* 1 = periodic axis (2D: periodic[2] must be 1) */
+    int32_t fluid;        /* LBM_D2Q9 (2D) or LBM_D3Q19 (3D) */
+    int32_t scalar;       /* LBM_NONE, LBM_D2Q5 (2D) or LBM_D3Q7 (3D) */
+    int32_t magnetic;     /* LBM_NONE, LBM_D2Q5 (2D) or LBM_D3Q7 (3D) */
+    int32_t mag_ncomp;    /* evolved B components: 0 (no magnetic lattice), 1..3 */
+    int32_t mag_comp[3];  /* Cartesian axis (0..2) of each evolved component */
+    int32_t storage;      /* lbm_storage */
+    int32_t reserved;
+    double tau_f, tau_c, tau_m;  /* relaxation times (> 1/2) */
+    double rho0, C0, mu;         /* rest density, rest concentration, permeability */
+    double B_ext[3];             /* applied field; non-evolved components stay at B_ext */
+    double accel[3];             /* body force per unit mass */
+    double store_scale[3];       /* F16/BF16: power-of-two scale of f, h, g deviations */
+} lbm_params;
+
+/* One boundary link: the population entering fluid node A along e_alpha, whose
+ * source node A - e_alpha lies beyond a boundary.  For a magnetic link, comp is
+ * the slot (0..mag_ncomp-1) of the evolved component. */
+typedef struct {
+    uint32_t node;   /* fluid node A (domain linear index) */
+    uint32_t enode;  /* second fluid node E = A + e_alpha; ignored when flags bit 1 is set */
+    uint8_t field;   /* 0 = f, 1 = h, 2 = g */
+    uint8_t dir;     /* unknown direction alpha (lattice numbering, see lbm_lattice_table) */
+    uint8_t kind;    /* lbm_link_kind */
+    uint8_t comp;    /* magnetic slot */
+    uint8_t flags;   /* bit 0: u_w is the boundary velocity (else extrapolated, Eq. 13);
+                        bit 1: E is not fluid, A stands in for E */
+    uint8_t pad[3];
+    double d;        /* boundary-to-node distance |AX| / |AE| in (0, 1] */
+    double value;    /* PRES: rho_w; CONC: C_w; MAG_DIR: B_k */
+    double a1, a3;   /* FLUX / MAG_FLUX: F(phi) = a1 phi_X - a3 (lattice units) */
+    double weight;   /* flux share of this link: 1 on flat walls, S_i e.n / sum e.n on curved walls (Eq. 48) */
+    double u_w[3];   /* boundary velocity */
+} lbm_link;
+
+/* Boundary description consumed by lbm_build_links. */
+typedef struct {
+    int32_t kind;          /* lbm_link_kind, 0 = no condition for this lattice */
+    int32_t u_given;       /* 1: use the boundary velocity; 0: extrapolate u (Eq. 13) */
+    int32_t profile_axis;  /* axis of a1_profile */
+    int32_t profile_len;   /* 0 = no profile */
+    double value, a1, a3;
+    const double* a1_profile; /* host: a1 per coordinate of A along profile_axis, or NULL */
+} lbm_bc;
+
+typedef struct {
+    int32_t type;     /* 0 = plane, 1 = cylinder */
+    int32_t axis;     /* plane: normal axis; cylinder: its axis */
+    int32_t side;     /* plane: 0 below node 0, 1 above node n-1 */
+    int32_t is_open;  /* open boundary (inlet/outlet): loses corner ties to walls */
+    double q;         /* plane: distance of the plane outside the first/last node layer */
+    double center[3]; /* cylinder centre (axis coordinate ignored) */
+    double radius;    /* cylinder radius; nodes strictly inside are fluid */
+    double u_w[3];    /* boundary velocity */
+    lbm_bc f, h, g[3];
+} lbm_boundary;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Library version string. */
+const char* lbm_version(void);
+
+/* Lattice tables of the library: Q, e (Q x 3, row-major), w (Q), c^2 and the
+ * opposite direction of each direction.  e, w, opp hold at least 19 entries. */
+lbm_status lbm_lattice_table(int32_t lattice, int32_t* Q, int32_t* e, double* w, double* c2,
+                             int32_t* opp);
+
+/* Host-side geometry and link-table builder (Sections 3, 4 and 6).
+ * Node classification: a node is fluid iff it lies strictly inside every
+ * cylinder; planes lie outside the node range.  For every fluid node A and
+ * every direction alpha of every lattice whose source A - e_alpha is not a
+ * fluid node of the domain, one link (one per magnetic component) is made
+ * with the crossed boundary's condition: d is q for a plane and the exact
+ * ray-circle intersection for a cylinder (Section 6, per node and per
+ * direction).  A link crossing several boundaries takes a wall before an open
+ * boundary, then the smaller d, then the lower boundary index.  Flux links on
+ * a cylinder get the surface-segment split weights of Section 6.2 / Eq. 48.
+ *   p, bnds[nb]: host inputs; mask_out: host, n[0]*n[1]*n[2] bytes (1 = fluid)
+ *   or NULL; links_out: host array of cap links or NULL (then only *n_out is
+ *   set); n_out: number of links.  Links are ordered by node, field, comp, dir.
+ * Errors: LBM_EINVAL (bad parameters, a link with no boundary condition),
+ *   LBM_ESIZE (cap too small; *n_out holds the size needed). */
+lbm_status lbm_build_links(const lbm_params* p, const lbm_boundary* bnds, int32_t nb,
+                           uint8_t* mask_out, lbm_link* links_out, size_t cap, size_t* n_out);
+
+/* Sizes (bytes) of the LBM_NBUF device buffers a context needs for n_links
+ * links; returns their sum, 0 on invalid parameters.  Buffer roles:
+ *  0 populations (AA layout, in place), 1 node flags, 2 link offsets per node,
+ *  3 link records, 4 per-link post-collision stash, 5 moment planes (two
+ *  parities), 6 residual snapshot and FP64 accumulators, 7 reserved (may be 0). */
+size_t lbm_required_bytes(const lbm_params* p, size_t n_links, size_t sizes_out[LBM_NBUF]);
+
+/* Creates a context over caller-allocated device buffers dev_bufs[i] of at
+ * least sizes_out[i] bytes (256-byte aligned), working on hip_stream (a
+ * hipStream_t, NULL = default stream).  The device is the current HIP device. */
+lbm_status lbm_create(const lbm_params* p, size_t n_links, void* const dev_bufs[LBM_NBUF],
+                      void* hip_stream, lbm_ctx** out);
+
+/* Node classification, host array of n[0]*n[1]*n[2] bytes (nonzero = fluid). */
+lbm_status lbm_set_geometry(lbm_ctx* ctx, const uint8_t* host_mask);
+
+/* Validates the host link table against the geometry (every unknown
+ * population of every fluid node has exactly one link; d in (0,1]; kinds
+ * allowed for the field) and uploads it.  n must not exceed the n_links of
+ * lbm_create.  Resets the time to 0 and requires lbm_init again. */
+lbm_status lbm_set_links(lbm_ctx* ctx, const lbm_link* host_links, size_t n);
+
+/* Equilibrium initialisation (Eqs. 2, 4, 6) from device FP64 fields in domain
+ * layout: rho [N], u [3][N], C [N], B [3][N] (N = domain nodes); any may be
+ * NULL for the uniform rest value (rho0, 0, C0, B_ext).  Sets time 0. */
+lbm_status lbm_init(lbm_ctx* ctx, const double* dev_rho, const double* dev_u, const double* dev_C,
+                    const double* dev_B);
+
+/* Advances n >= 0 steps (asynchronous). */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Moments at the current time into dev_out, SoA [8][N] of rho, u_x, u_y, u_z,
+ * C, B_x, B_y, B_z (0 at solid nodes); out_type LBM_F64 or LBM_F32. */
+lbm_status lbm_read_moments(lbm_ctx* ctx, void* dev_out, int32_t out_type);
+
+/* Populations of one field at the current time (after the boundary links),
+ * FP64 into dev_out as [slots][N]: f: Q planes; h: Q planes; g: ncomp*Q
+ * planes (component-major).  Solid nodes hold 0. */
+lbm_status lbm_read_populations(lbm_ctx* ctx, int32_t field, double* dev_out);
+
+/* FP64 reductions at the current time, synchronising the stream:
+ * out[0] steady-state residual: max over u, C - C0 and B - B_ext of
+ *        ||phi(t) - phi(t0)||_2 / ((t - t0) max(||phi(t)||_2, 1e-30)), where t0
+ *        is the time of the previous lbm_reduce (-1 on the first call);
+ * out[1] total mass sum(rho); out[2] sum(C); out[3..5] sum(B);
+ * out[6] t - t0; out[7] number of non-finite moments.
+ * Returns LBM_EUNSTABLE when out[7] > 0. */
+lbm_status lbm_reduce(lbm_ctx* ctx, double out[8]);
+
+/* Checkpoint: lbm_state_bytes() bytes of host memory hold the populations,
+ * stash, moment planes and time.  lbm_save synchronises the stream. */
+size_t lbm_state_bytes(const lbm_ctx* ctx);
+lbm_status lbm_save(lbm_ctx* ctx, void* host);
+lbm_status lbm_load(lbm_ctx* ctx, const void* host);
+
+int64_t lbm_time(const lbm_ctx* ctx);
+lbm_status lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
+const char* lbm_last_error(const lbm_ctx* ctx);
+void lbm_destroy(lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

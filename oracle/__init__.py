@@ -19,15 +19,21 @@ import scenes as S
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source in extended precision (x87 long double): a tighter
+# reference for FP64 parity, whose error is below double rounding
+_LIB_LD = os.path.join(_HERE, "liboracle_ld.so")
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c with gcc (plain -O2, IEEE arithmetic, OpenMP loops)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC",
-                               "-shared", "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile oracle.c with gcc (plain -O2, IEEE arithmetic, OpenMP loops),
+    once in double precision and once in long double."""
+    for out, extra in ((_LIB, []), (_LIB_LD, ["-DOR_REAL=long double"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            tmp = out + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC",
+                                   "-shared", "-Wall", "-Wno-unused-function", *extra, _SRC, "-o", tmp,
+                                   "-lm"])
+            os.replace(tmp, out)
     return _LIB
 
 
@@ -70,14 +76,14 @@ class LinkIn(C.Structure):
                 ("mE", C.c_double * 8)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        _lib = C.CDLL(build())
-        L = _lib
+def lib(precision: str = "f64"):
+    """The oracle library: precision "f64" (default) or "ld" (long double)."""
+    if precision not in _libs:
+        build()
+        L = C.CDLL(_LIB if precision == "f64" else _LIB_LD)
         L.or_create.restype = C.c_void_p
         L.or_create.argtypes = [C.POINTER(_Scene)]
         L.or_destroy.argtypes = [C.c_void_p]
@@ -103,7 +109,9 @@ def lib():
         assert L.or_sizeof_link_in() == C.sizeof(LinkIn)
         assert L.or_sizeof_scene() == C.sizeof(_Scene)
         assert L.or_sizeof_boundary() == C.sizeof(_Boundary)
-    return _lib
+        assert L.or_real_bytes() == (8 if precision == "f64" else 16)
+        _libs[precision] = L
+    return _libs[precision]
 
 
 def _ptr(a: np.ndarray):
@@ -221,10 +229,12 @@ class OracleSim:
 
     FIELDS = ("rho", "ux", "uy", "uz", "C", "Bx", "By", "Bz")
 
-    def __init__(self, sc: S.Scene):
+    def __init__(self, sc: S.Scene, precision: str = "f64"):
         self.scene = sc
+        self.precision = precision
+        self._L = lib(precision)
         self._h = _SceneHolder(sc)
-        p = lib().or_create(C.byref(self._h.cs))
+        p = self._L.or_create(C.byref(self._h.cs))
         if not p:
             raise ValueError("oracle: scene has a boundary link with no boundary condition")
         self._p = C.c_void_p(p)
@@ -235,7 +245,7 @@ class OracleSim:
 
     def __del__(self):
         try:
-            lib().or_destroy(self._p)
+            self._L.or_destroy(self._p)
         except Exception:
             pass
 
@@ -244,19 +254,19 @@ class OracleSim:
             np.asarray(a, np.float64).reshape(self.N * k))
         arrs = [conv(rho, 1), conv(u, 3), conv(C_, 1), conv(B, 3)]
         ptrs = [None if a is None else _ptr(a) for a in arrs]
-        lib().or_init_fields(self._p, *ptrs)
+        self._L.or_init_fields(self._p, *ptrs)
 
     def step(self, n: int = 1):
-        lib().or_step(self._p, int(n))
+        self._L.or_step(self._p, int(n))
 
     @property
     def t(self) -> int:
-        return lib().or_time(self._p)
+        return self._L.or_time(self._p)
 
     def moments(self) -> np.ndarray:
         """[nz, ny, nx, 8] array of rho, u(3), C, B(3); zeros at solid nodes."""
         out = np.zeros((self.N, 8))
-        lib().or_moments(self._p, _ptr(out))
+        self._L.or_moments(self._p, _ptr(out))
         return out.reshape(self.shape + (8,))
 
     def populations(self, field: int) -> np.ndarray:
@@ -265,18 +275,18 @@ class OracleSim:
         q = len(lattice_table(Q)[1])
         nc = len(sc.mag_comps) if field == 2 else 1
         out = np.zeros(nc * q * self.N)
-        if lib().or_populations(self._p, field, _ptr(out)) != 0:
+        if self._L.or_populations(self._p, field, _ptr(out)) != 0:
             raise ValueError(field)
         return out.reshape((nc, q) + self.shape) if field == 2 else out.reshape((q,) + self.shape)
 
     def set_populations(self, field: int, arr: np.ndarray):
         a = np.ascontiguousarray(arr, np.float64)
-        lib().or_set_populations(self._p, field, _ptr(a))
+        self._L.or_set_populations(self._p, field, _ptr(a))
 
     def links(self) -> np.ndarray:
-        n = lib().or_num_links(self._p)
+        n = self._L.or_num_links(self._p)
         out = (Link * max(n, 1))()
-        lib().or_get_links(self._p, out)
+        self._L.or_get_links(self._p, out)
         dt = np.dtype([("A", "i4"), ("E", "i4"), ("field", "i4"), ("comp", "i4"), ("dir", "i4"),
                        ("kind", "i4"), ("bnd", "i4"), ("u_given", "i4"), ("d", "f8"),
                        ("value", "f8"), ("a1", "f8"), ("a3", "f8"), ("weight", "f8"),
@@ -286,10 +296,10 @@ class OracleSim:
 
     def mask(self) -> np.ndarray:
         out = np.zeros(self.N, np.uint8)
-        lib().or_get_mask(self._p, _ptr(out))
+        self._L.or_get_mask(self._p, _ptr(out))
         return out.reshape(self.shape)
 
     def segment_sum(self):
         n = C.c_int()
-        s = lib().or_segment_sum(self._p, C.byref(n))
+        s = self._L.or_segment_sum(self._p, C.byref(n))
         return s, n.value

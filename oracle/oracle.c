@@ -28,6 +28,14 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Arithmetic type of the state and of every update.  The default build is
+ * double precision; the same source compiled with -DOR_REAL="long double"
+ * gives an extended-precision build used as a tighter FP64 reference. */
+#ifndef OR_REAL
+#define OR_REAL double
+#endif
+typedef OR_REAL real;
+
 /* ------------------------------------------------------------------------- */
 /* lattices (Section 2): D2Q9 / D3Q19 for f, D2Q5 / D3Q7 for h and g          */
 /* ------------------------------------------------------------------------- */
@@ -36,8 +44,8 @@ enum { OR_D2Q9 = 1, OR_D3Q19 = 2, OR_D2Q5 = 3, OR_D3Q7 = 4 };
 typedef struct {
     int Q;
     int e[19][3];
-    double w[19];
-    double c2; /* squared lattice sound speed c_s^2, c_h^2 or c_g^2 */
+    real w[19];
+    real c2; /* squared lattice sound speed c_s^2, c_h^2 or c_g^2 */
     int opp[19];
 } or_lattice;
 
@@ -48,11 +56,11 @@ static void lattice_fill(or_lattice* L, int code) {
         static const int e[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1},
                                     {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
         L->Q = 9;
-        L->c2 = 1.0 / 3.0;
+        L->c2 = (real)1 / 3;
         for (int a = 0; a < 9; ++a) {
             L->e[a][0] = e[a][0];
             L->e[a][1] = e[a][1];
-            L->w[a] = a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+            L->w[a] = a == 0 ? (real)4 / 9 : (a < 5 ? (real)1 / 9 : (real)1 / 36);
         }
     } else if (code == OR_D3Q19) {
         static const int e[19][3] = {
@@ -60,10 +68,10 @@ static void lattice_fill(or_lattice* L, int code) {
             {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
             {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
         L->Q = 19;
-        L->c2 = 1.0 / 3.0;
+        L->c2 = (real)1 / 3;
         for (int a = 0; a < 19; ++a) {
             for (int k = 0; k < 3; ++k) L->e[a][k] = e[a][k];
-            L->w[a] = a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+            L->w[a] = a == 0 ? (real)1 / 3 : (a < 7 ? (real)1 / 18 : (real)1 / 36);
         }
     } else if (code == OR_D2Q5) {
         static const int e[5][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1}};
@@ -96,43 +104,70 @@ int or_lattice_table(int code, int* Q, int* e /* Q x 3 */, double* w, double* c2
     if (code < 1 || code > 4) return -1;
     lattice_fill(&L, code);
     *Q = L.Q;
-    *c2 = L.c2;
+    *c2 = (double)L.c2;
     for (int a = 0; a < L.Q; ++a) {
         for (int k = 0; k < 3; ++k) e[3 * a + k] = L.e[a][k];
-        w[a] = L.w[a];
+        w[a] = (double)L.w[a];
         opp[a] = L.opp[a];
     }
     return 0;
 }
 
-static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
-static double edot(const int* e, const double* v) { return e[0] * v[0] + e[1] * v[1] + e[2] * v[2]; }
+static real dot3(const real* a, const real* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static real edot(const int* e, const real* v) { return e[0] * v[0] + e[1] * v[1] + e[2] * v[2]; }
 
 /* Eq. 2 */
-static double feq(const or_lattice* L, int a, double rho, const double* u) {
-    double eu = edot(L->e[a], u), cs2 = L->c2;
-    return rho * L->w[a] * (1.0 + eu / cs2 + eu * eu / (2.0 * cs2 * cs2) - dot3(u, u) / (2.0 * cs2));
+static real feq(const or_lattice* L, int a, real rho, const real* u) {
+    real eu = edot(L->e[a], u), cs2 = L->c2;
+    return rho * L->w[a] * (1 + eu / cs2 + eu * eu / (2 * cs2 * cs2) - dot3(u, u) / (2 * cs2));
 }
 /* Eq. 4 */
-static double heq(const or_lattice* L, int a, double C, const double* u) {
-    return C * L->w[a] * (1.0 + edot(L->e[a], u) / L->c2);
+static real heq(const or_lattice* L, int a, real C, const real* u) {
+    return C * L->w[a] * (1 + edot(L->e[a], u) / L->c2);
 }
 /* Eq. 6, Cartesian component k of the vector equilibrium */
-static double geq(const or_lattice* L, int a, int k, const double* B, const double* u) {
-    double s = 0.0; /* e_alpha . (u B - B u), component k */
+static real geq(const or_lattice* L, int a, int k, const real* B, const real* u) {
+    real s = 0; /* e_alpha . (u B - B u), component k */
     for (int i = 0; i < 3; ++i) s += L->e[a][i] * (u[i] * B[k] - B[i] * u[k]);
     return L->w[a] * (B[k] + s / L->c2);
+}
+
+/* equilibrium vectors whose rest entry closes the zeroth moment exactly */
+static void eq_closed_f(const or_lattice* L, real rho, const real* u, real* out) {
+    real s = 0;
+    for (int a = 1; a < L->Q; ++a) {
+        out[a] = feq(L, a, rho, u);
+        s += out[a];
+    }
+    out[0] = rho - s;
+}
+static void eq_closed_h(const or_lattice* L, real C, const real* u, real* out) {
+    real s = 0;
+    for (int a = 1; a < L->Q; ++a) {
+        out[a] = heq(L, a, C, u);
+        s += out[a];
+    }
+    out[0] = C - s;
+}
+static void eq_closed_g(const or_lattice* L, int k, const real* B, const real* u, real* out) {
+    real s = 0;
+    for (int a = 1; a < L->Q; ++a) {
+        out[a] = geq(L, a, k, B, u);
+        s += out[a];
+    }
+    out[0] = B[k] - s;
 }
 
 void or_equilibria(int code, double rho, const double* u, double C, const double* B,
                    double* f_out, double* h_out, double* g_out /* Q x 3 */) {
     or_lattice L;
     lattice_fill(&L, code);
+    real ur[3] = {u[0], u[1], u[2]}, Br[3] = {B[0], B[1], B[2]};
     for (int a = 0; a < L.Q; ++a) {
-        if (f_out) f_out[a] = feq(&L, a, rho, u);
-        if (h_out) h_out[a] = heq(&L, a, C, u);
+        if (f_out) f_out[a] = (double)feq(&L, a, rho, ur);
+        if (h_out) h_out[a] = (double)heq(&L, a, C, ur);
         if (g_out)
-            for (int k = 0; k < 3; ++k) g_out[3 * a + k] = geq(&L, a, k, B, u);
+            for (int k = 0; k < 3; ++k) g_out[3 * a + k] = (double)geq(&L, a, k, Br, ur);
     }
 }
 
@@ -355,8 +390,8 @@ typedef struct {
     or_lattice Lf, Lh, Lg;
     int N;
     uint8_t* fluid;
-    double *f, *fs, *h, *hs, *g, *gs; /* [Q][N] (g: [ncomp][Q][N]) */
-    double* mom;                     /* [N][8]: rho, ux, uy, uz, C, Bx, By, Bz */
+    real *f, *fs, *h, *hs, *g, *gs; /* [Q][N] (g: [ncomp][Q][N]) */
+    real* mom;                     /* [N][8]: rho, ux, uy, uz, C, Bx, By, Bz */
     or_link* links;
     int nlinks;
     long t;
@@ -489,45 +524,45 @@ static int build_links(or_sim* S) {
 
 /* moments at node n from the pre-collision populations: rho, u, C, B.
  * Also returns the total force F (body + Lorentz). */
-static void node_moments(const or_sim* S, int n, double* rho_o, double* u, double* C_o, double* B,
-                         double* F) {
+static void node_moments(const or_sim* S, int n, real* rho_o, real* u, real* C_o, real* B,
+                         real* F) {
     const or_scene* s = &S->sc;
     const or_lattice* Lf = &S->Lf;
-    double rho = 0.0, m[3] = {0.0, 0.0, 0.0};
+    real rho = 0.0, m[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < Lf->Q; ++a) {
-        double fa = S->f[IDX(a, n)];
+        real fa = S->f[IDX(a, n)];
         rho += fa;
         for (int k = 0; k < 3; ++k) m[k] += Lf->e[a][k] * fa;
     }
-    double C = 0.0;
+    real C = 0.0;
     if (s->sl)
         for (int a = 0; a < S->Lh.Q; ++a) C += S->h[IDX(a, n)];
     for (int k = 0; k < 3; ++k) B[k] = s->B_ext[k];
-    double Fl[3] = {0.0, 0.0, 0.0};
+    real Fl[3] = {0.0, 0.0, 0.0};
     if (s->ml) {
         const or_lattice* Lg = &S->Lg;
         for (int c = 0; c < s->ncomp; ++c) {
-            double sum = 0.0;
+            real sum = 0.0;
             for (int a = 0; a < Lg->Q; ++a) sum += S->g[GIDX(c, a, n)];
             B[s->comps[c]] = sum;
         }
         /* velocity with half the body force only (explicit Lorentz reading) */
-        double u0[3];
+        real u0[3];
         for (int k = 0; k < 3; ++k) u0[k] = (m[k] + 0.5 * rho * s->accel[k]) / rho;
         /* gradient of B from the non-equilibrium first moment of g:
          * d_i B_j = -(Lambda_ij - Lambda^eq_ij) / (tau_m c_g^2), Lambda^eq = u B - B u */
-        double dB[3][3] = {{0}};
+        real dB[3][3] = {{0}};
         for (int c = 0; c < s->ncomp; ++c) {
             int j = s->comps[c];
             for (int i = 0; i < 3; ++i) {
-                double lam = 0.0;
+                real lam = 0.0;
                 for (int a = 0; a < Lg->Q; ++a) lam += Lg->e[a][i] * S->g[GIDX(c, a, n)];
-                double lam_eq = u0[i] * B[j] - B[i] * u0[j];
+                real lam_eq = u0[i] * B[j] - B[i] * u0[j];
                 dB[i][j] = -(lam - lam_eq) / (s->tau_m * Lg->c2);
             }
         }
         /* J = curl(B) / mu; F_L = J x B */
-        double J[3];
+        real J[3];
         J[0] = (dB[1][2] - dB[2][1]) / s->mu;
         J[1] = (dB[2][0] - dB[0][2]) / s->mu;
         J[2] = (dB[0][1] - dB[1][0]) / s->mu;
@@ -545,9 +580,9 @@ static void node_moments(const or_sim* S, int n, double* rho_o, double* u, doubl
 
 static void collide_node(or_sim* S, int n) {
     const or_scene* s = &S->sc;
-    double rho, u[3], C, B[3], F[3];
+    real rho, u[3], C, B[3], F[3];
     node_moments(S, n, &rho, u, &C, B, F);
-    double* mo = &S->mom[(size_t)n * 8];
+    real* mo = &S->mom[(size_t)n * 8];
     mo[0] = rho;
     mo[1] = u[0];
     mo[2] = u[1];
@@ -556,31 +591,45 @@ static void collide_node(or_sim* S, int n) {
     mo[5] = B[0];
     mo[6] = B[1];
     mo[7] = B[2];
-    /* Eq. 1 with the Guo source term */
+    /* Eq. 1 with the Guo source term.  The equilibria conserve the zeroth
+     * moments (Section 2.4) and the force adds no mass; with weights rounded
+     * to real precision that holds only if the rest entry closes the sum,
+     * so the rest entries are taken as the moment minus the moving ones. */
     const or_lattice* Lf = &S->Lf;
-    double tf = s->tau_f, cs2 = Lf->c2;
-    for (int a = 0; a < Lf->Q; ++a) {
-        double fa = S->f[IDX(a, n)];
-        double eu = edot(Lf->e[a], u);
-        double src = 0.0;
+    real tf = s->tau_f, cs2 = Lf->c2;
+    real eqv[19], srcv[19];
+    eq_closed_f(Lf, rho, u, eqv);
+    real ssum = 0.0;
+    for (int a = 1; a < Lf->Q; ++a) {
+        real eu = edot(Lf->e[a], u);
+        real src = 0.0;
         for (int k = 0; k < 3; ++k)
             src += ((Lf->e[a][k] - u[k]) / cs2 + eu * Lf->e[a][k] / (cs2 * cs2)) * F[k];
-        src *= (1.0 - 0.5 / tf) * Lf->w[a];
-        S->fs[IDX(a, n)] = fa + (feq(Lf, a, rho, u) - fa) / tf + src;
+        srcv[a] = src * (1.0 - 0.5 / tf) * Lf->w[a];
+        ssum += srcv[a];
+    }
+    srcv[0] = -ssum;
+    for (int a = 0; a < Lf->Q; ++a) {
+        real fa = S->f[IDX(a, n)];
+        S->fs[IDX(a, n)] = fa + (eqv[a] - fa) / tf + srcv[a];
     }
     /* Eq. 3 */
-    if (s->sl)
+    if (s->sl) {
+        eq_closed_h(&S->Lh, C, u, eqv);
         for (int a = 0; a < S->Lh.Q; ++a) {
-            double ha = S->h[IDX(a, n)];
-            S->hs[IDX(a, n)] = ha + (heq(&S->Lh, a, C, u) - ha) / s->tau_c;
+            real ha = S->h[IDX(a, n)];
+            S->hs[IDX(a, n)] = ha + (eqv[a] - ha) / s->tau_c;
         }
+    }
     /* Eq. 5 */
     if (s->ml)
-        for (int c = 0; c < s->ncomp; ++c)
+        for (int c = 0; c < s->ncomp; ++c) {
+            eq_closed_g(&S->Lg, s->comps[c], B, u, eqv);
             for (int a = 0; a < S->Lg.Q; ++a) {
-                double ga = S->g[GIDX(c, a, n)];
-                S->gs[GIDX(c, a, n)] = ga + (geq(&S->Lg, a, s->comps[c], B, u) - ga) / s->tau_m;
+                real ga = S->g[GIDX(c, a, n)];
+                S->gs[GIDX(c, a, n)] = ga + (eqv[a] - ga) / s->tau_m;
             }
+        }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -597,48 +646,57 @@ typedef struct {
 } or_link_in;
 
 /* Eq. 13: phi(X) = -d phi(E) + (d+1) phi(A) */
-static double extrap(double d, double pE, double pA) { return -d * pE + (d + 1.0) * pA; }
+static real extrap(real d, real pE, real pA) { return -d * pE + (d + 1) * pA; }
 
-double or_link_eval(const or_link_in* in) {
+/* the same inputs in the arithmetic type of the build */
+typedef struct {
+    int32_t lattice, kind, dir, comp_axis, u_given;
+    real d, value, a1, a3, weight;
+    real u_w[3];
+    real x_ap_E, x_ap_A, x_a_A;
+    real mA[8], mE[8];
+} or_link_in_r;
+
+static real link_eval_r(const or_link_in_r* in) {
     or_lattice L;
     lattice_fill(&L, in->lattice);
     int a = in->dir, ap = L.opp[a];
-    double d = in->d;
-    double uX[3], BX[3];
+    real d = in->d;
+    real uX[3], BX[3];
     for (int k = 0; k < 3; ++k) {
         uX[k] = in->u_given ? in->u_w[k] : extrap(d, in->mE[1 + k], in->mA[1 + k]);
         BX[k] = extrap(d, in->mE[5 + k], in->mA[5 + k]);
     }
     /* Y interpolation / extrapolation (Eqs. 16, 20, 35) */
-    double xY = (1.0 - 2.0 * d) * in->x_ap_E + 2.0 * d * in->x_ap_A;
+    real xY = (1 - 2 * d) * in->x_ap_E + 2 * d * in->x_ap_A;
     switch (in->kind) {
         case K_VEL: {
-            double rhoX = extrap(d, in->mE[0], in->mA[0]);
-            double inc = feq(&L, a, rhoX, in->u_w) - feq(&L, ap, rhoX, in->u_w);
-            if (d < 0.5) return xY + inc;                                         /* Eq. 15 */
-            return ((2.0 * d - 1.0) * in->x_a_A + in->x_ap_A + inc) / (2.0 * d); /* Eq. 43 */
+            real rhoX = extrap(d, in->mE[0], in->mA[0]);
+            real inc = feq(&L, a, rhoX, in->u_w) - feq(&L, ap, rhoX, in->u_w);
+            if (d < (real)0.5) return xY + inc;                                         /* Eq. 15 */
+            return ((2 * d - 1) * in->x_a_A + in->x_ap_A + inc) / (2 * d); /* Eq. 43 */
         }
         case K_PRES: {
-            double uXp[3];
+            real uXp[3];
             for (int k = 0; k < 3; ++k) uXp[k] = extrap(d, in->mE[1 + k], in->mA[1 + k]);
-            double sum = feq(&L, a, in->value, uXp) + feq(&L, ap, in->value, uXp);
-            if (d < 0.5) return sum - xY;                                         /* zeroth-moment pair */
-            return ((2.0 * d - 1.0) * in->x_a_A - in->x_ap_A + sum) / (2.0 * d); /* Eq. 44 */
+            real sum = feq(&L, a, in->value, uXp) + feq(&L, ap, in->value, uXp);
+            if (d < (real)0.5) return sum - xY;                                         /* zeroth-moment pair */
+            return ((2 * d - 1) * in->x_a_A - in->x_ap_A + sum) / (2 * d); /* Eq. 44 */
         }
         case K_CONC: /* Eqs. 19-20 */
             return heq(&L, a, in->value, uX) + heq(&L, ap, in->value, uX) - xY;
         case K_MAG_DIR: { /* Eqs. 34-35 */
-            double Bg[3] = {BX[0], BX[1], BX[2]};
+            real Bg[3] = {BX[0], BX[1], BX[2]};
             Bg[in->comp_axis] = in->value;
             return geq(&L, a, in->comp_axis, Bg, uX) + geq(&L, ap, in->comp_axis, Bg, uX) - xY;
         }
         case K_BB0: /* Eqs. 21-22 */
-            if (d < 0.5) return xY;
-            return ((2.0 * d - 1.0) * in->x_a_A + in->x_ap_A) / (2.0 * d);
+            if (d < (real)0.5) return xY;
+            return ((2 * d - 1) * in->x_a_A + in->x_ap_A) / (2 * d);
         case K_FLUX:
         case K_MAG_FLUX: {
-            double phiX, dmove;
-            double mu_[3] = {-uX[0], -uX[1], -uX[2]};
+            real phiX, dmove;
+            real mu_[3] = {-uX[0], -uX[1], -uX[2]};
             if (in->kind == K_FLUX) {
                 phiX = extrap(d, in->mE[4], in->mA[4]);
                 dmove = heq(&L, ap, phiX, mu_) - heq(&L, a, phiX, mu_); /* Eq. 24 */
@@ -646,14 +704,37 @@ double or_link_eval(const or_link_in* in) {
                 phiX = BX[in->comp_axis];
                 dmove = geq(&L, ap, in->comp_axis, BX, mu_) - geq(&L, a, in->comp_axis, BX, mu_);
             }
-            double dflux = (in->a1 * phiX - in->a3) * in->weight;              /* Eq. 23, Eq. 48 */
-            double xM = (0.5 - d) * in->x_ap_E + (0.5 + d) * in->x_ap_A;      /* Eq. 25 */
-            double xM1 = xM + dflux + dmove;                                    /* Eq. 26 */
-            return ((d - 0.5) * in->x_a_A + xM1) / (d + 0.5);                  /* Eq. 27 */
+            real dflux = (in->a1 * phiX - in->a3) * in->weight;              /* Eq. 23, Eq. 48 */
+            real xM = ((real)0.5 - d) * in->x_ap_E + ((real)0.5 + d) * in->x_ap_A;      /* Eq. 25 */
+            real xM1 = xM + dflux + dmove;                                    /* Eq. 26 */
+            return ((d - (real)0.5) * in->x_a_A + xM1) / (d + (real)0.5);                  /* Eq. 27 */
         }
         default:
             return NAN;
     }
+}
+
+double or_link_eval(const or_link_in* in) {
+    or_link_in_r r;
+    r.lattice = in->lattice;
+    r.kind = in->kind;
+    r.dir = in->dir;
+    r.comp_axis = in->comp_axis;
+    r.u_given = in->u_given;
+    r.d = in->d;
+    r.value = in->value;
+    r.a1 = in->a1;
+    r.a3 = in->a3;
+    r.weight = in->weight;
+    r.x_ap_E = in->x_ap_E;
+    r.x_ap_A = in->x_ap_A;
+    r.x_a_A = in->x_a_A;
+    for (int k = 0; k < 3; ++k) r.u_w[k] = in->u_w[k];
+    for (int k = 0; k < 8; ++k) {
+        r.mA[k] = in->mA[k];
+        r.mE[k] = in->mE[k];
+    }
+    return (double)link_eval_r(&r);
 }
 
 static void apply_links(or_sim* S) {
@@ -661,12 +742,12 @@ static void apply_links(or_sim* S) {
     for (int i = 0; i < S->nlinks; ++i) {
         const or_link* lk = &S->links[i];
         const or_lattice* L = lk->field == 0 ? &S->Lf : (lk->field == 1 ? &S->Lh : &S->Lg);
-        const double* xs = lk->field == 0 ? S->fs : (lk->field == 1 ? S->hs : S->gs);
-        double* x = lk->field == 0 ? S->f : (lk->field == 1 ? S->h : S->g);
+        const real* xs = lk->field == 0 ? S->fs : (lk->field == 1 ? S->hs : S->gs);
+        real* x = lk->field == 0 ? S->f : (lk->field == 1 ? S->h : S->g);
         size_t base = lk->field == 2 ? (size_t)lk->comp * (size_t)L->Q * (size_t)S->N : 0;
         int a = lk->dir, ap = L->opp[a];
         int E = lk->E >= 0 ? lk->E : lk->A;
-        or_link_in in;
+        or_link_in_r in;
         memset(&in, 0, sizeof(in));
         in.lattice = lk->field == 0 ? s->fl : (lk->field == 1 ? s->sl : s->ml);
         in.kind = lk->kind;
@@ -682,9 +763,9 @@ static void apply_links(or_sim* S) {
         in.x_ap_E = xs[base + (size_t)ap * S->N + E];
         in.x_ap_A = xs[base + (size_t)ap * S->N + lk->A];
         in.x_a_A = xs[base + (size_t)a * S->N + lk->A];
-        memcpy(in.mA, &S->mom[(size_t)lk->A * 8], sizeof(double) * 8);
-        memcpy(in.mE, &S->mom[(size_t)E * 8], sizeof(double) * 8);
-        x[base + (size_t)a * S->N + lk->A] = or_link_eval(&in);
+        for (int k = 0; k < 8; ++k) in.mA[k] = S->mom[(size_t)lk->A * 8 + k];
+        for (int k = 0; k < 8; ++k) in.mE[k] = S->mom[(size_t)E * 8 + k];
+        x[base + (size_t)a * S->N + lk->A] = link_eval_r(&in);
     }
 }
 
@@ -717,17 +798,17 @@ or_sim* or_create(const or_scene* sc) {
     S->fluid = (uint8_t*)malloc((size_t)S->N);
     or_fluid_mask(sc, S->fluid);
     size_t N = (size_t)S->N;
-    S->f = (double*)calloc(N * S->Lf.Q, sizeof(double));
-    S->fs = (double*)calloc(N * S->Lf.Q, sizeof(double));
+    S->f = (real*)calloc(N * S->Lf.Q, sizeof(real));
+    S->fs = (real*)calloc(N * S->Lf.Q, sizeof(real));
     if (sc->sl) {
-        S->h = (double*)calloc(N * S->Lh.Q, sizeof(double));
-        S->hs = (double*)calloc(N * S->Lh.Q, sizeof(double));
+        S->h = (real*)calloc(N * S->Lh.Q, sizeof(real));
+        S->hs = (real*)calloc(N * S->Lh.Q, sizeof(real));
     }
     if (sc->ml) {
-        S->g = (double*)calloc(N * S->Lg.Q * sc->ncomp, sizeof(double));
-        S->gs = (double*)calloc(N * S->Lg.Q * sc->ncomp, sizeof(double));
+        S->g = (real*)calloc(N * S->Lg.Q * sc->ncomp, sizeof(real));
+        S->gs = (real*)calloc(N * S->Lg.Q * sc->ncomp, sizeof(real));
     }
-    S->mom = (double*)calloc(N * 8, sizeof(double));
+    S->mom = (real*)calloc(N * 8, sizeof(real));
     if (build_links(S) != 0) {
         or_destroy(S);
         return NULL;
@@ -741,20 +822,25 @@ or_sim* or_create(const or_scene* sc) {
 int or_init_fields(or_sim* S, const double* rho, const double* u, const double* C, const double* B) {
     const or_scene* s = &S->sc;
     for (int n = 0; n < S->N; ++n) {
-        double r = rho ? rho[n] : s->rho0;
-        double uu[3] = {0.0, 0.0, 0.0}, BB[3] = {s->B_ext[0], s->B_ext[1], s->B_ext[2]};
+        real r = rho ? rho[n] : s->rho0;
+        real uu[3] = {0, 0, 0}, BB[3] = {s->B_ext[0], s->B_ext[1], s->B_ext[2]};
         if (u)
             for (int k = 0; k < 3; ++k) uu[k] = u[3 * (size_t)n + k];
         if (B)
             for (int k = 0; k < 3; ++k) BB[k] = B[3 * (size_t)n + k];
-        double cc = C ? C[n] : s->init_C;
-        for (int a = 0; a < S->Lf.Q; ++a) S->f[IDX(a, n)] = feq(&S->Lf, a, r, uu);
-        if (s->sl)
-            for (int a = 0; a < S->Lh.Q; ++a) S->h[IDX(a, n)] = heq(&S->Lh, a, cc, uu);
+        real cc = C ? C[n] : s->init_C;
+        real eqv[19];
+        eq_closed_f(&S->Lf, r, uu, eqv);
+        for (int a = 0; a < S->Lf.Q; ++a) S->f[IDX(a, n)] = eqv[a];
+        if (s->sl) {
+            eq_closed_h(&S->Lh, cc, uu, eqv);
+            for (int a = 0; a < S->Lh.Q; ++a) S->h[IDX(a, n)] = eqv[a];
+        }
         if (s->ml)
-            for (int c = 0; c < s->ncomp; ++c)
-                for (int a = 0; a < S->Lg.Q; ++a)
-                    S->g[GIDX(c, a, n)] = geq(&S->Lg, a, s->comps[c], BB, uu);
+            for (int c = 0; c < s->ncomp; ++c) {
+                eq_closed_g(&S->Lg, s->comps[c], BB, uu, eqv);
+                for (int a = 0; a < S->Lg.Q; ++a) S->g[GIDX(c, a, n)] = eqv[a];
+            }
     }
     S->t = 0;
     return 0;
@@ -808,7 +894,7 @@ void or_moments(const or_sim* S, double* out) {
             memset(o, 0, sizeof(double) * 8);
             continue;
         }
-        double rho, u[3], C, B[3], F[3];
+        real rho, u[3], C, B[3], F[3];
         node_moments(S, n, &rho, u, &C, B, F);
         o[0] = rho;
         o[1] = u[0];
@@ -822,24 +908,32 @@ void or_moments(const or_sim* S, double* out) {
 }
 
 /* populations of one field at the current time, [Q][N] (g: [ncomp][Q][N]) */
+static void copy_out(const real* src, double* dst, size_t n) {
+    for (size_t i = 0; i < n; ++i) dst[i] = (double)src[i];
+}
+static void copy_in(const double* src, real* dst, size_t n) {
+    for (size_t i = 0; i < n; ++i) dst[i] = src[i];
+}
+
 int or_populations(const or_sim* S, int field, double* out) {
     size_t N = (size_t)S->N;
-    if (field == 0) memcpy(out, S->f, sizeof(double) * N * S->Lf.Q);
-    else if (field == 1 && S->sc.sl) memcpy(out, S->h, sizeof(double) * N * S->Lh.Q);
-    else if (field == 2 && S->sc.ml) memcpy(out, S->g, sizeof(double) * N * S->Lg.Q * S->sc.ncomp);
+    if (field == 0) copy_out(S->f, out, N * S->Lf.Q);
+    else if (field == 1 && S->sc.sl) copy_out(S->h, out, N * S->Lh.Q);
+    else if (field == 2 && S->sc.ml) copy_out(S->g, out, N * S->Lg.Q * S->sc.ncomp);
     else return -1;
     return 0;
 }
 
 int or_set_populations(or_sim* S, int field, const double* in) {
     size_t N = (size_t)S->N;
-    if (field == 0) memcpy(S->f, in, sizeof(double) * N * S->Lf.Q);
-    else if (field == 1 && S->sc.sl) memcpy(S->h, in, sizeof(double) * N * S->Lh.Q);
-    else if (field == 2 && S->sc.ml) memcpy(S->g, in, sizeof(double) * N * S->Lg.Q * S->sc.ncomp);
+    if (field == 0) copy_in(in, S->f, N * S->Lf.Q);
+    else if (field == 1 && S->sc.sl) copy_in(in, S->h, N * S->Lh.Q);
+    else if (field == 2 && S->sc.ml) copy_in(in, S->g, N * S->Lg.Q * S->sc.ncomp);
     else return -1;
     return 0;
 }
 
+int or_real_bytes(void) { return (int)sizeof(real); }
 int or_num_links(const or_sim* S) { return S->nlinks; }
 void or_get_links(const or_sim* S, or_link* out) { memcpy(out, S->links, sizeof(or_link) * (size_t)S->nlinks); }
 void or_get_mask(const or_sim* S, uint8_t* out) { memcpy(out, S->fluid, (size_t)S->N); }

@@ -1,0 +1,101 @@
+"""ctypes declarations of include/lbm.h and loading of the in-tree liblbm.so.
+
+Argument marshalling only: every step of the sweep runs in the HIP library.
+Importing this module never falls back to anything else; if the library is
+missing it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+LBM_NBUF = 8
+STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ESIZE", -3: "LBM_EDEVICE", -4: "LBM_EUNSTABLE",
+          -5: "LBM_ESTATE"}
+LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = 1, 2, 3, 4
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class lbm_params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
+                ("fluid", C.c_int32), ("scalar", C.c_int32), ("magnetic", C.c_int32),
+                ("mag_ncomp", C.c_int32), ("mag_comp", C.c_int32 * 3), ("storage", C.c_int32),
+                ("reserved", C.c_int32), ("tau_f", C.c_double), ("tau_c", C.c_double),
+                ("tau_m", C.c_double), ("rho0", C.c_double), ("C0", C.c_double), ("mu", C.c_double),
+                ("B_ext", C.c_double * 3), ("accel", C.c_double * 3), ("store_scale", C.c_double * 3)]
+
+
+class lbm_link(C.Structure):
+    _fields_ = [("node", C.c_uint32), ("enode", C.c_uint32), ("field", C.c_uint8), ("dir", C.c_uint8),
+                ("kind", C.c_uint8), ("comp", C.c_uint8), ("flags", C.c_uint8), ("pad", C.c_uint8 * 3),
+                ("d", C.c_double), ("value", C.c_double), ("a1", C.c_double), ("a3", C.c_double),
+                ("weight", C.c_double), ("u_w", C.c_double * 3)]
+
+
+class lbm_bc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("u_given", C.c_int32), ("profile_axis", C.c_int32),
+                ("profile_len", C.c_int32), ("value", C.c_double), ("a1", C.c_double),
+                ("a3", C.c_double), ("a1_profile", C.POINTER(C.c_double))]
+
+
+class lbm_boundary(C.Structure):
+    _fields_ = [("type", C.c_int32), ("axis", C.c_int32), ("side", C.c_int32), ("is_open", C.c_int32),
+                ("q", C.c_double), ("center", C.c_double * 3), ("radius", C.c_double),
+                ("u_w", C.c_double * 3), ("f", lbm_bc), ("h", lbm_bc), ("g", lbm_bc * 3)]
+
+
+# every entry point declared in include/lbm.h: name -> (restype, argtypes)
+_VP = C.c_void_p
+SIGNATURES = {
+    "lbm_version": (C.c_char_p, []),
+    "lbm_lattice_table": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), _VP, _VP, C.POINTER(C.c_double), _VP]),
+    "lbm_build_links": (C.c_int, [C.POINTER(lbm_params), C.POINTER(lbm_boundary), C.c_int32, _VP, _VP,
+                                  C.c_size_t, C.POINTER(C.c_size_t)]),
+    "lbm_required_bytes": (C.c_size_t, [C.POINTER(lbm_params), C.c_size_t, C.POINTER(C.c_size_t)]),
+    "lbm_create": (C.c_int, [C.POINTER(lbm_params), C.c_size_t, C.POINTER(_VP), _VP, C.POINTER(_VP)]),
+    "lbm_set_geometry": (C.c_int, [_VP, _VP]),
+    "lbm_set_links": (C.c_int, [_VP, _VP, C.c_size_t]),
+    "lbm_init": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "lbm_step": (C.c_int, [_VP, C.c_int64]),
+    "lbm_read_moments": (C.c_int, [_VP, _VP, C.c_int32]),
+    "lbm_read_populations": (C.c_int, [_VP, C.c_int32, _VP]),
+    "lbm_reduce": (C.c_int, [_VP, C.POINTER(C.c_double)]),
+    "lbm_state_bytes": (C.c_size_t, [_VP]),
+    "lbm_save": (C.c_int, [_VP, _VP]),
+    "lbm_load": (C.c_int, [_VP, _VP]),
+    "lbm_time": (C.c_int64, [_VP]),
+    "lbm_set_stream": (C.c_int, [_VP, _VP]),
+    "lbm_last_error": (C.c_char_p, [_VP]),
+    "lbm_destroy": (None, [_VP]),
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2506_00907_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code: int, ctx=None, what: str = ""):
+    if code != 0:
+        msg = lib().lbm_last_error(ctx).decode() if ctx else what
+        raise LbmError(code, msg or what)

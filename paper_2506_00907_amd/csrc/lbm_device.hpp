@@ -1,0 +1,829 @@
+// Fused stream-collide node update for gfx950: BGK flow f (Eqs. 1-2, Guo
+// forcing, Lorentz force), convection-diffusion h (Eqs. 3-4) and the vector
+// magnetic distributions g (Eqs. 5-6), with the boundary links of Sections 3-4
+// applied in the same sweep.
+//
+// Layout: structure of arrays, one plane of `plane` nodes per population,
+// padded grid with a one-node halo on non-periodic axes.  Streaming is the AA
+// pattern, in place:
+//   even step: node x reads slot i at x and writes its post-collision value
+//              of direction i into slot opp(i) at x;
+//   odd step:  node x reads slot opp(i) at x - e_i and writes its
+//              post-collision value of direction i into slot i at x + e_i.
+// Each location is read and written by one thread only, so one array holds
+// the state.  Populations are stored as deviations from the rest
+// equilibrium (w rho0, w C0, w B_ext,k), scaled by a power of two for the
+// 16-bit formats.
+//
+// Boundary links.  The unknown population f_alpha(A, t+1) needs, from time t,
+// the post-collision values f*_alpha'(A), f*_alpha(A), f*_alpha'(E) and the
+// moments at A and E (Eq. 13).  f*_alpha'(E) is exactly what A receives along
+// alpha' by ordinary streaming, so it is already in a register.  The two
+// values of A itself are written by A after its collision into a per-link
+// stash and read back by A on the next step (A owns them, no race).  Moments
+// of the link nodes are written to one of two moment planes by parity, so the
+// plane read during a step is never written during it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbm_internal.hpp"
+
+namespace lbmi {
+
+// ---------------------------------------------------------------------------
+// lattices
+// ---------------------------------------------------------------------------
+struct NoLat {
+    static constexpr int Q = 0;
+    __host__ __device__ static constexpr int ex(int) { return 0; }
+    __host__ __device__ static constexpr int ey(int) { return 0; }
+    __host__ __device__ static constexpr int ez(int) { return 0; }
+    __host__ __device__ static constexpr int opp(int a) { return a; }
+    __host__ __device__ static constexpr double w(int) { return 0.0; }
+    static constexpr double c2 = 1.0;
+};
+
+// D2Q9: 0 rest, 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1), 5 (1,1), 6 (-1,1),
+// 7 (-1,-1), 8 (1,-1); opposite pairs 1-3, 2-4, 5-7, 6-8.
+struct LD2Q9 {
+    static constexpr int Q = 9;
+    __host__ __device__ static constexpr int ex(int a) {
+        return (a == 1 || a == 5 || a == 8) ? 1 : ((a == 3 || a == 6 || a == 7) ? -1 : 0);
+    }
+    __host__ __device__ static constexpr int ey(int a) {
+        return (a == 2 || a == 5 || a == 6) ? 1 : ((a == 4 || a == 7 || a == 8) ? -1 : 0);
+    }
+    __host__ __device__ static constexpr int ez(int) { return 0; }
+    __host__ __device__ static constexpr int opp(int a) {
+        return a == 0 ? 0 : (a < 5 ? ((a + 1) & 3) + 1 : ((a - 3) & 3) + 5);
+    }
+    __host__ __device__ static constexpr double w(int a) {
+        return a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+    static constexpr double c2 = 1.0 / 3.0;
+};
+
+// D3Q19: rest, the six axis directions in +/- pairs, then the twelve edge
+// directions in +/- pairs; opp(a) = a + 1 for odd a, a - 1 for even a > 0.
+struct LD3Q19 {
+    static constexpr int Q = 19;
+    __host__ __device__ static constexpr int e(int a, int k) {
+        constexpr signed char t[19][3] = {
+            {0, 0, 0},   {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+            {1, 1, 0},   {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+            {-1, 0, 1},  {0, 1, 1},   {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+        return t[a][k];
+    }
+    __host__ __device__ static constexpr int ex(int a) { return e(a, 0); }
+    __host__ __device__ static constexpr int ey(int a) { return e(a, 1); }
+    __host__ __device__ static constexpr int ez(int a) { return e(a, 2); }
+    __host__ __device__ static constexpr int opp(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
+    __host__ __device__ static constexpr double w(int a) {
+        return a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+    static constexpr double c2 = 1.0 / 3.0;
+};
+
+// D2Q5: rest, (1,0), (-1,0), (0,1), (0,-1); weights 1/2 and 1/8, c^2 = 1/4.
+struct LD2Q5 {
+    static constexpr int Q = 5;
+    __host__ __device__ static constexpr int ex(int a) { return a == 1 ? 1 : (a == 2 ? -1 : 0); }
+    __host__ __device__ static constexpr int ey(int a) { return a == 3 ? 1 : (a == 4 ? -1 : 0); }
+    __host__ __device__ static constexpr int ez(int) { return 0; }
+    __host__ __device__ static constexpr int opp(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
+    __host__ __device__ static constexpr double w(int a) { return a == 0 ? 0.5 : 0.125; }
+    static constexpr double c2 = 0.25;
+};
+
+// D3Q7: rest, (+-1,0,0), (0,+-1,0), (0,0,+-1); weights 1/4 and 1/8, c^2 = 1/4.
+struct LD3Q7 {
+    static constexpr int Q = 7;
+    __host__ __device__ static constexpr int ex(int a) { return a == 1 ? 1 : (a == 2 ? -1 : 0); }
+    __host__ __device__ static constexpr int ey(int a) { return a == 3 ? 1 : (a == 4 ? -1 : 0); }
+    __host__ __device__ static constexpr int ez(int a) { return a == 5 ? 1 : (a == 6 ? -1 : 0); }
+    __host__ __device__ static constexpr int opp(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
+    __host__ __device__ static constexpr double w(int a) { return a == 0 ? 0.25 : 0.125; }
+    static constexpr double c2 = 0.25;
+};
+
+template <int CODE> struct LatOf { using T = NoLat; };
+template <> struct LatOf<1> { using T = LD2Q9; };
+template <> struct LatOf<2> { using T = LD3Q19; };
+template <> struct LatOf<3> { using T = LD2Q5; };
+template <> struct LatOf<4> { using T = LD3Q7; };
+
+// ---------------------------------------------------------------------------
+// storage formats
+// ---------------------------------------------------------------------------
+struct F64S { using T = double; using R = double; };
+struct F32S { using T = float; using R = float; };
+struct F16S { using T = uint16_t; using R = float; };
+struct BF16S { using T = uint16_t; using R = float; };
+
+template <class SF> __device__ __forceinline__ typename SF::R ld(const typename SF::T* p, size_t i);
+template <> __device__ __forceinline__ double ld<F64S>(const double* p, size_t i) { return p[i]; }
+template <> __device__ __forceinline__ float ld<F32S>(const float* p, size_t i) { return p[i]; }
+template <> __device__ __forceinline__ float ld<F16S>(const uint16_t* p, size_t i) {
+    return (float)__builtin_bit_cast(_Float16, p[i]);
+}
+template <> __device__ __forceinline__ float ld<BF16S>(const uint16_t* p, size_t i) {
+    return __builtin_bit_cast(float, (uint32_t)p[i] << 16);
+}
+
+template <class SF> __device__ __forceinline__ void st(typename SF::T* p, size_t i, typename SF::R v);
+template <> __device__ __forceinline__ void st<F64S>(double* p, size_t i, double v) { p[i] = v; }
+template <> __device__ __forceinline__ void st<F32S>(float* p, size_t i, float v) { p[i] = v; }
+template <> __device__ __forceinline__ void st<F16S>(uint16_t* p, size_t i, float v) {
+    p[i] = __builtin_bit_cast(uint16_t, (_Float16)v);  // round to nearest even
+}
+template <> __device__ __forceinline__ void st<BF16S>(uint16_t* p, size_t i, float v) {
+    // round to nearest even on the upper 16 bits (finite inputs)
+    uint32_t b = __builtin_bit_cast(uint32_t, v);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    p[i] = (uint16_t)(b >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// configuration bundle
+// ---------------------------------------------------------------------------
+template <int FLC, int SLC, int MLC, int NC, class SF>
+struct Cfg {
+    using FL = typename LatOf<FLC>::T;
+    using HL = typename LatOf<SLC>::T;
+    using GL = typename LatOf<MLC>::T;
+    using S = SF;
+    using T = typename SF::T;
+    using R = typename SF::R;
+    static constexpr int QF = FL::Q;
+    static constexpr int QH = HL::Q;
+    static constexpr int QG = GL::Q;
+    static constexpr int NCOMP = (MLC == 0) ? 0 : NC;
+    static constexpr int QT = QF + QH + NCOMP * QG;
+    static constexpr int H0 = QF;          // first h plane
+    static constexpr int G0 = QF + QH;     // first g plane
+};
+
+// physical parameters in the compute type
+template <class R>
+struct Phys {
+    R omf, omc, omm, guo;          // 1/tau_f, 1/tau_c, 1/tau_m, 1 - 1/(2 tau_f)
+    R rho0, C0, inv_mu, grad_c;    // grad_c = 1/(tau_m c_g^2)
+    R Bext[3], acc[3];
+    R sc[3], isc[3];               // storage scale and inverse (f, h, g)
+    int comp[3];
+};
+
+template <class R>
+__host__ Phys<R> make_phys(const KArgs& a, double cg2) {
+    Phys<R> p;
+    p.omf = (R)(1.0 / a.tau_f);
+    p.omc = (R)(1.0 / a.tau_c);
+    p.omm = (R)(1.0 / a.tau_m);
+    p.guo = (R)(1.0 - 0.5 / a.tau_f);
+    p.rho0 = (R)a.rho0;
+    p.C0 = (R)a.C0;
+    p.inv_mu = (R)(1.0 / a.mu);
+    p.grad_c = (R)(1.0 / (a.tau_m * cg2));
+    for (int k = 0; k < 3; ++k) {
+        p.Bext[k] = (R)a.Bext[k];
+        p.acc[k] = (R)a.accel[k];
+        p.sc[k] = (R)a.scale[k];
+        p.isc[k] = (R)(1.0 / a.scale[k]);
+        p.comp[k] = a.comp[k];
+    }
+    return p;
+}
+
+// Grid geometry of one launch.
+struct Geo {
+    int NX, NY, NZ;
+    int hx, hy, hz, n0, n1, n2;
+    uint32_t plane;
+};
+
+// logical workgroup index: consecutive blocks are dispatched round-robin over
+// the 8 XCDs; give each XCD a contiguous range of the grid so that the rows a
+// block streams from are mostly in its own L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
+    uint32_t G8 = G & ~7u;
+    if (b >= G8) return b;
+    return (b & 7u) * (G8 >> 3) + (b >> 3);
+}
+
+// moments of one node (compute type)
+template <class R>
+struct Mom {
+    R drho, u[3], dC, dB[3];  // deviations from rho0, C0 and B_ext (all three axes)
+};
+
+// ---------------------------------------------------------------------------
+// boundary link value (deviation form; Sections 3-4)
+// ---------------------------------------------------------------------------
+// x_a:   post-collision deviation of A along alpha (stash)
+// x_apA: post-collision deviation of A along alpha' (stash)
+// x_apE: post-collision deviation of E along alpha' (streamed value)
+// mA, mE: moments at A and E at the previous time (deviations + u)
+template <class R>
+__device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R x_a, R x_apA,
+                                        R x_apE, const R* mA, const R* mE, R w, R c2) {
+    const R d = L.d;
+    const R one = (R)1, two = (R)2, half = (R)0.5;
+    const R cE = -d, cA = d + one;  // Eq. 13 coefficients
+    const R ex = (R)L.ex, ey = (R)L.ey, ez = (R)L.ez;
+    // boundary velocity: given, or extrapolated (Eq. 13)
+    R ux, uy, uz;
+    if (L.flags & 1) {
+        ux = L.uw0;
+        uy = L.uw1;
+        uz = L.uw2;
+    } else {
+        ux = cE * mE[1] + cA * mA[1];
+        uy = cE * mE[2] + cA * mA[2];
+        uz = cE * mE[3] + cA * mA[3];
+    }
+    const R Y = (one - two * d) * x_apE + two * d * x_apA;  // Eqs. 16, 20, 35
+    const bool lo = d < half;
+    switch (L.kind) {
+        case 1: {  // VEL
+            R rhoX = P.rho0 + cE * mE[0] + cA * mA[0];
+            R inc = two * w * rhoX * (ex * ux + ey * uy + ez * uz) / c2;
+            return lo ? Y + inc : ((two * d - one) * x_a + x_apA + inc) / (two * d);  // Eq. 15 / 43
+        }
+        case 2: {  // PRES: u_X always extrapolated
+            R vx = cE * mE[1] + cA * mA[1], vy = cE * mE[2] + cA * mA[2], vz = cE * mE[3] + cA * mA[3];
+            R eu = ex * vx + ey * vy + ez * vz;
+            R rw = P.rho0 + L.value;  // value holds rho_w - rho0
+            R sdev = two * w * (L.value + rw * (eu * eu / (two * c2 * c2) - (vx * vx + vy * vy + vz * vz) / (two * c2)));
+            return lo ? sdev - Y : ((two * d - one) * x_a - x_apA + sdev) / (two * d);  // pair form / Eq. 44
+        }
+        case 3:  // CONC (Eqs. 19-20); the velocity terms of the pair cancel; value = C_w - C0
+        case 6:  // MAG_DIR (Eqs. 34-35); value = B_k - B_ext,k
+            return two * w * L.value - Y;
+        case 5:  // BB0 (Eqs. 21-22)
+            return lo ? Y : ((two * d - one) * x_a + x_apA) / (two * d);
+        case 4:
+        case 7: {  // FLUX / MAG_FLUX: M scheme (Eqs. 23-27) with the moving correction (Eq. 24)
+            R phiX, dmove;
+            const R eu = ex * ux + ey * uy + ez * uz;
+            if (L.kind == 4) {
+                phiX = P.C0 + cE * mE[4] + cA * mA[4];
+                dmove = two * w * phiX * eu / c2;
+            } else {
+                const int k = L.caxis;
+                R Bx = P.Bext[0] + cE * mE[5] + cA * mA[5];
+                R By = P.Bext[1] + cE * mE[6] + cA * mA[6];
+                R Bz = P.Bext[2] + cE * mE[7] + cA * mA[7];
+                phiX = k == 0 ? Bx : (k == 1 ? By : Bz);
+                R uk = k == 0 ? ux : (k == 1 ? uy : uz);
+                dmove = two * w * (eu * phiX - (ex * Bx + ey * By + ez * Bz) * uk) / c2;
+            }
+            R dflux = (L.a1 * phiX - L.a3) * L.weight;
+            R xM = (half - d) * x_apE + (half + d) * x_apA + dflux + dmove;
+            return ((d - half) * x_a + xM) / (d + half);
+        }
+        default:
+            return x_apA;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the node update
+// ---------------------------------------------------------------------------
+// MODE 0: full step (gather, links, moments, collide, stash, scatter)
+// MODE 1: observe (gather, links, moments) -> caller handles the output
+template <class C, int ODD, int MODE>
+struct NodeRes {
+    typename C::R x[C::QT];  // populations at the current time (deviations)
+    Mom<typename C::R> m;
+};
+
+template <class C, int ODD, int MODE>
+__device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C::R>& P,
+                                            typename C::T* __restrict__ S,
+                                            const uint8_t* __restrict__ flags,
+                                            const uint32_t* __restrict__ lstart,
+                                            const DevLink<typename C::R>* __restrict__ links,
+                                            typename C::R* __restrict__ stash,
+                                            typename C::R* __restrict__ M, int parity,
+                                            int links_ready, uint32_t n,
+                                            NodeRes<C, ODD, MODE>& res) {
+    using R = typename C::R;
+    using FL = typename C::FL;
+    using HL = typename C::HL;
+    using GL = typename C::GL;
+    constexpr int QF = C::QF, QH = C::QH, QG = C::QG, NCP = C::NCOMP, QT = C::QT;
+    const uint8_t fl = flags[n];
+    if (!(fl & NF_FLUID)) return false;
+    const size_t PL = G.plane;
+
+    // coordinates and wrapped neighbour offsets (fluid nodes never touch a
+    // non-periodic edge of the padded grid, so wrapping only ever applies on
+    // periodic axes)
+    const int x = (int)(n % (uint32_t)G.NX);
+    const uint32_t t1 = n / (uint32_t)G.NX;
+    const int y = (int)(t1 % (uint32_t)G.NY);
+    const int z = (int)(t1 / (uint32_t)G.NY);
+    const int sx = G.NX * G.NY;
+    const int oxm = x == 0 ? G.NX - 1 : -1;
+    const int oxp = x == G.NX - 1 ? -(G.NX - 1) : 1;
+    const int oym = y == 0 ? (G.NY - 1) * G.NX : -G.NX;
+    const int oyp = y == G.NY - 1 ? -(G.NY - 1) * G.NX : G.NX;
+    const int ozm = z == 0 ? (G.NZ - 1) * sx : -sx;
+    const int ozp = z == G.NZ - 1 ? -(G.NZ - 1) * sx : sx;
+    auto off = [&](int ex, int ey, int ez) -> int {
+        return (ex > 0 ? oxp : (ex < 0 ? oxm : 0)) + (ey > 0 ? oyp : (ey < 0 ? oym : 0)) +
+               (ez > 0 ? ozp : (ez < 0 ? ozm : 0));
+    };
+
+    R* x_ = res.x;
+    // ---- gather (streaming) ----
+#pragma unroll
+    for (int i = 0; i < QF; ++i) {
+        size_t idx = ODD ? (size_t)FL::opp(i) * PL + (size_t)((int)n + off(-FL::ex(i), -FL::ey(i), -FL::ez(i)))
+                         : (size_t)i * PL + n;
+        x_[i] = ld<typename C::S>(S, idx) * P.isc[0];
+    }
+#pragma unroll
+    for (int i = 0; i < QH; ++i) {
+        size_t idx = ODD ? (size_t)(C::H0 + HL::opp(i)) * PL + (size_t)((int)n + off(-HL::ex(i), -HL::ey(i), -HL::ez(i)))
+                         : (size_t)(C::H0 + i) * PL + n;
+        x_[C::H0 + i] = ld<typename C::S>(S, idx) * P.isc[1];
+    }
+#pragma unroll
+    for (int c = 0; c < NCP; ++c)
+#pragma unroll
+        for (int i = 0; i < QG; ++i) {
+            const int b = C::G0 + c * QG;
+            size_t idx = ODD ? (size_t)(b + GL::opp(i)) * PL + (size_t)((int)n + off(-GL::ex(i), -GL::ey(i), -GL::ez(i)))
+                             : (size_t)(b + i) * PL + n;
+            x_[b + i] = ld<typename C::S>(S, idx) * P.isc[2];
+        }
+
+    // ---- boundary links ----
+    uint32_t k0 = 0, k1 = 0;
+    if (fl & NF_LINKS) {
+        k0 = lstart[n];
+        k1 = lstart[n + 1];
+    }
+    if (links_ready && k1 > k0) {
+        const R* Mp = M + (size_t)(parity ^ 1) * 8 * PL;  // moments of the previous time
+        R mA[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) mA[q] = Mp[(size_t)q * PL + n];
+        for (uint32_t k = k0; k < k1; ++k) {
+            const DevLink<R> L = links[k];
+            const R s0 = stash[2 * (size_t)k], s1 = stash[2 * (size_t)k + 1];
+            R xs = s0;
+            if (!(L.flags & 2)) {
+#pragma unroll
+                for (int q = 0; q < QT; ++q) xs = (q == (int)L.pap) ? x_[q] : xs;
+            }
+            R mE[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) mE[q] = Mp[(size_t)q * PL + L.E];
+            const int e2 = L.ex * L.ex + L.ey * L.ey + L.ez * L.ez;
+            R w, c2;
+            if (L.field == 0) {
+                w = (R)(QF == 9 ? (e2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0) : (e2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0));
+                c2 = (R)(1.0 / 3.0);
+            } else {
+                w = (R)0.125;
+                c2 = (R)0.25;
+            }
+            const R v = link_value<R>(L, P, s1, s0, xs, mA, mE, w, c2);
+#pragma unroll
+            for (int q = 0; q < QT; ++q) x_[q] = (q == (int)L.pa) ? v : x_[q];
+        }
+    }
+
+    // ---- moments ----
+    Mom<R>& m = res.m;
+    R jx = 0, jy = 0, jz = 0, drho = 0;
+#pragma unroll
+    for (int i = 0; i < QF; ++i) {
+        drho += x_[i];
+        jx += (R)FL::ex(i) * x_[i];
+        jy += (R)FL::ey(i) * x_[i];
+        jz += (R)FL::ez(i) * x_[i];
+    }
+    const R rho = P.rho0 + drho;
+    const R irho = (R)1 / rho;
+    R dC = 0;
+#pragma unroll
+    for (int i = 0; i < QH; ++i) dC += x_[C::H0 + i];
+    R dB[3] = {0, 0, 0}, B[3] = {P.Bext[0], P.Bext[1], P.Bext[2]};
+    R lam[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // lam[c][i] = sum_a e_ai g_a,c
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) {
+        R s = 0, l0 = 0, l1 = 0, l2 = 0;
+#pragma unroll
+        for (int i = 0; i < QG; ++i) {
+            const R g = x_[C::G0 + c * QG + i];
+            s += g;
+            l0 += (R)GL::ex(i) * g;
+            l1 += (R)GL::ey(i) * g;
+            l2 += (R)GL::ez(i) * g;
+        }
+        // evolved component slot c is Cartesian axis c
+        dB[c] = s;
+        B[c] = P.Bext[c] + s;
+        lam[c][0] = l0;
+        lam[c][1] = l1;
+        lam[c][2] = l2;
+    }
+    R F[3] = {rho * P.acc[0], rho * P.acc[1], rho * P.acc[2]};
+    if (NCP > 0) {
+        // grad B from the non-equilibrium first moment of g, evaluated with the
+        // velocity that carries half the body force only (explicit current)
+        const R u0[3] = {(jx + (R)0.5 * F[0]) * irho, (jy + (R)0.5 * F[1]) * irho, (jz + (R)0.5 * F[2]) * irho};
+        R gB[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // gB[i][k] = d_i B_k
+#pragma unroll
+        for (int c = 0; c < NCP; ++c) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const R leq = u0[i] * B[c] - B[i] * u0[c];
+                gB[i][c] = -(lam[c][i] - leq) * P.grad_c;
+            }
+        }
+        const R J0 = (gB[1][2] - gB[2][1]) * P.inv_mu;
+        const R J1 = (gB[2][0] - gB[0][2]) * P.inv_mu;
+        const R J2 = (gB[0][1] - gB[1][0]) * P.inv_mu;
+        F[0] += J1 * B[2] - J2 * B[1];
+        F[1] += J2 * B[0] - J0 * B[2];
+        F[2] += J0 * B[1] - J1 * B[0];
+    }
+    const R ux = (jx + (R)0.5 * F[0]) * irho, uy = (jy + (R)0.5 * F[1]) * irho, uz = (jz + (R)0.5 * F[2]) * irho;
+    m.drho = drho;
+    m.u[0] = ux;
+    m.u[1] = uy;
+    m.u[2] = uz;
+    m.dC = dC;
+    m.dB[0] = dB[0];
+    m.dB[1] = dB[1];
+    m.dB[2] = dB[2];
+    if (MODE != 0) return true;
+
+    // moments of link nodes for the next step's extrapolations (Eq. 13)
+    if (fl & NF_MOM) {
+        R* Mc = M + (size_t)parity * 8 * PL;
+        Mc[0 * PL + n] = drho;
+        Mc[1 * PL + n] = ux;
+        Mc[2 * PL + n] = uy;
+        Mc[3 * PL + n] = uz;
+        Mc[4 * PL + n] = dC;
+        Mc[5 * PL + n] = dB[0];
+        Mc[6 * PL + n] = dB[1];
+        Mc[7 * PL + n] = dB[2];
+    }
+
+    // ---- collision (deviation form) ----
+    const R usq = ux * ux + uy * uy + uz * uz;
+    constexpr R cs2 = (R)(1.0 / 3.0);
+    constexpr R ics2 = (R)3.0;
+#pragma unroll
+    for (int i = 0; i < QF; ++i) {
+        const R ex = (R)FL::ex(i), ey = (R)FL::ey(i), ez = (R)FL::ez(i);
+        const R w = (R)FL::w(i);
+        const R eu = ex * ux + ey * uy + ez * uz;
+        const R feq = w * (drho + rho * (eu * ics2 + (R)0.5 * eu * eu * ics2 * ics2 - (R)0.5 * usq * ics2));
+        const R eF = ex * F[0] + ey * F[1] + ez * F[2];
+        const R uF = ux * F[0] + uy * F[1] + uz * F[2];
+        const R src = P.guo * w * ((eF - uF) * ics2 + eu * eF * ics2 * ics2);
+        x_[i] = x_[i] + P.omf * (feq - x_[i]) + src;
+    }
+    (void)cs2;
+#pragma unroll
+    for (int i = 0; i < QH; ++i) {
+        const R eu = (R)HL::ex(i) * ux + (R)HL::ey(i) * uy + (R)HL::ez(i) * uz;
+        const R heq = (R)HL::w(i) * (dC + (P.C0 + dC) * eu * (R)4.0);
+        x_[C::H0 + i] += P.omc * (heq - x_[C::H0 + i]);
+    }
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) {
+        const R Bk = B[c];
+        const R uk = c == 0 ? ux : (c == 1 ? uy : uz);
+#pragma unroll
+        for (int i = 0; i < QG; ++i) {
+            const R ex = (R)GL::ex(i), ey = (R)GL::ey(i), ez = (R)GL::ez(i);
+            const R s = (ex * ux + ey * uy + ez * uz) * Bk - (ex * B[0] + ey * B[1] + ez * B[2]) * uk;
+            const R geq = (R)GL::w(i) * (dB[c] + s * (R)4.0);
+            const int p = C::G0 + c * QG + i;
+            x_[p] += P.omm * (geq - x_[p]);
+        }
+    }
+
+    // ---- stash the two post-collision values each link of A needs next step ----
+    for (uint32_t k = k0; k < k1; ++k) {
+        const uint8_t pa = links[k].pa, pap = links[k].pap;
+        R a0 = 0, a1 = 0;
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+            a0 = (q == (int)pap) ? x_[q] : a0;
+            a1 = (q == (int)pa) ? x_[q] : a1;
+        }
+        stash[2 * (size_t)k] = a0;
+        stash[2 * (size_t)k + 1] = a1;
+    }
+
+    // ---- scatter (streaming) ----
+#pragma unroll
+    for (int i = 0; i < QF; ++i) {
+        size_t idx = ODD ? (size_t)i * PL + (size_t)((int)n + off(FL::ex(i), FL::ey(i), FL::ez(i)))
+                         : (size_t)FL::opp(i) * PL + n;
+        st<typename C::S>(S, idx, x_[i] * P.sc[0]);
+    }
+#pragma unroll
+    for (int i = 0; i < QH; ++i) {
+        size_t idx = ODD ? (size_t)(C::H0 + i) * PL + (size_t)((int)n + off(HL::ex(i), HL::ey(i), HL::ez(i)))
+                         : (size_t)(C::H0 + HL::opp(i)) * PL + n;
+        st<typename C::S>(S, idx, x_[C::H0 + i] * P.sc[1]);
+    }
+#pragma unroll
+    for (int c = 0; c < NCP; ++c)
+#pragma unroll
+        for (int i = 0; i < QG; ++i) {
+            const int b = C::G0 + c * QG;
+            size_t idx = ODD ? (size_t)(b + i) * PL + (size_t)((int)n + off(GL::ex(i), GL::ey(i), GL::ez(i)))
+                             : (size_t)(b + GL::opp(i)) * PL + n;
+            st<typename C::S>(S, idx, x_[b + i] * P.sc[2]);
+        }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+template <class C, int ODD>
+__global__ __launch_bounds__(256) void k_step(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
+                                              const uint8_t* __restrict__ flags,
+                                              const uint32_t* __restrict__ lstart,
+                                              const DevLink<typename C::R>* __restrict__ links,
+                                              typename C::R* __restrict__ stash,
+                                              typename C::R* __restrict__ M, int links_ready, uint32_t nnodes) {
+    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t n = b * blockDim.x + threadIdx.x;
+    if (n >= nnodes) return;
+    NodeRes<C, ODD, 0> r;
+    node_update<C, ODD, 0>(G, P, S, flags, lstart, links, stash, M, ODD, links_ready, n, r);
+}
+
+template <class R>
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// observe: moments / populations / FP64 reductions at the current time
+template <class C, int ODD>
+__global__ __launch_bounds__(256) void k_observe(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
+                                                 const uint8_t* __restrict__ flags,
+                                                 const uint32_t* __restrict__ lstart,
+                                                 const DevLink<typename C::R>* __restrict__ links,
+                                                 typename C::R* __restrict__ stash,
+                                                 typename C::R* __restrict__ M, int links_ready,
+                                                 uint32_t nnodes, int mode, int field, void* out,
+                                                 int out_f64, double* acc, typename C::R* snap,
+                                                 int snap_valid) {
+    using R = typename C::R;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    NodeRes<C, ODD, 1> r;
+    bool fluid = false;
+    if (n < nnodes) fluid = node_update<C, ODD, 1>(G, P, S, flags, lstart, links, stash, M, ODD, links_ready, n, r);
+    // domain index of this node (if inside the domain)
+    int dom = -1;
+    if (n < nnodes) {
+        const int x = (int)(n % (uint32_t)G.NX);
+        const uint32_t t1 = n / (uint32_t)G.NX;
+        const int y = (int)(t1 % (uint32_t)G.NY);
+        const int z = (int)(t1 / (uint32_t)G.NY);
+        const int dx = x - G.hx, dy = y - G.hy, dz = z - G.hz;
+        if (dx >= 0 && dx < G.n0 && dy >= 0 && dy < G.n1 && dz >= 0 && dz < G.n2)
+            dom = dx + G.n0 * (dy + G.n1 * dz);
+    }
+    const size_t N = (size_t)G.n0 * G.n1 * G.n2;
+    if (mode == OBS_MOMENTS) {
+        if (dom < 0) return;
+        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (fluid) {
+            v[0] = (double)P.rho0 + (double)r.m.drho;
+            v[1] = r.m.u[0];
+            v[2] = r.m.u[1];
+            v[3] = r.m.u[2];
+            v[4] = (double)P.C0 + (double)r.m.dC;
+            for (int k = 0; k < 3; ++k) v[5 + k] = (double)P.Bext[k] + (double)r.m.dB[k];
+        }
+        for (int q = 0; q < 8; ++q) {
+            if (out_f64) ((double*)out)[(size_t)q * N + dom] = v[q];
+            else ((float*)out)[(size_t)q * N + dom] = (float)v[q];
+        }
+        return;
+    }
+    if (mode == OBS_POPS) {
+        if (dom < 0) return;
+        double* o = (double*)out;
+        if (field == 0) {
+            for (int i = 0; i < C::QF; ++i)
+                o[(size_t)i * N + dom] = fluid ? (double)r.x[i] + C::FL::w(i) * (double)P.rho0 : 0.0;
+        } else if (field == 1) {
+            for (int i = 0; i < C::QH; ++i)
+                o[(size_t)i * N + dom] = fluid ? (double)r.x[C::H0 + i] + C::HL::w(i) * (double)P.C0 : 0.0;
+        } else {
+            for (int c = 0; c < C::NCOMP; ++c)
+                for (int i = 0; i < C::QG; ++i)
+                    o[(size_t)(c * C::QG + i) * N + dom] =
+                        fluid ? (double)r.x[C::G0 + c * C::QG + i] + C::GL::w(i) * (double)P.Bext[c] : 0.0;
+        }
+        return;
+    }
+    // OBS_REDUCE: sums of rho, C, B; squared change of u, C - C0, B - B_ext
+    // since the snapshot and their squared norms; non-finite count
+    double v[NACC];
+    for (int q = 0; q < NACC; ++q) v[q] = 0.0;
+    if (fluid) {
+        const size_t PL = G.plane;
+        double phi[7] = {r.m.u[0], r.m.u[1], r.m.u[2], r.m.dC, r.m.dB[0], r.m.dB[1], r.m.dB[2]};
+        v[0] = (double)P.rho0 + (double)r.m.drho;
+        v[1] = (double)P.C0 + (double)r.m.dC;
+        for (int k = 0; k < 3; ++k) v[2 + k] = (double)P.Bext[k] + (double)r.m.dB[k];
+        for (int q = 0; q < 7; ++q) {
+            const double s = snap_valid ? (double)snap[(size_t)q * PL + n] : 0.0;
+            const double dd = phi[q] - s;
+            const int fld = q < 3 ? 0 : (q == 3 ? 1 : 2);
+            v[5 + fld] += dd * dd;     // 5..7: |phi - snap|^2 per field
+            v[8 + fld] += phi[q] * phi[q];  // 8..10: |phi|^2 per field
+            snap[(size_t)q * PL + n] = (R)phi[q];
+        }
+        bool bad = !(v[0] == v[0]) || !(v[1] == v[1]) || !(phi[0] == phi[0]) || !(phi[4] == phi[4]);
+        for (int q = 0; q < 5; ++q) bad = bad || (v[q] - v[q] != 0.0);
+        v[11] = bad ? 1.0 : 0.0;
+    }
+    __shared__ double red[NACC][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q = 0; q < 12; ++q) {
+        double s = wave_sum<R>(v[q]);
+        if (lane == 0) red[q][wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        double s = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[threadIdx.x][k];
+        atomicAdd(&acc[threadIdx.x], s);
+    }
+}
+
+// equilibrium initialisation: canonical layout slot i at node n holds x_i
+template <class C>
+__global__ __launch_bounds__(256) void k_init(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
+                                              const uint8_t* __restrict__ flags, uint32_t nnodes,
+                                              const double* __restrict__ rho_in,
+                                              const double* __restrict__ u_in,
+                                              const double* __restrict__ C_in,
+                                              const double* __restrict__ B_in) {
+    using R = typename C::R;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nnodes || !(flags[n] & NF_FLUID)) return;
+    const int x = (int)(n % (uint32_t)G.NX);
+    const uint32_t t1 = n / (uint32_t)G.NX;
+    const int y = (int)(t1 % (uint32_t)G.NY);
+    const int z = (int)(t1 / (uint32_t)G.NY);
+    const size_t N = (size_t)G.n0 * G.n1 * G.n2;
+    const size_t dom = (size_t)(x - G.hx) + (size_t)G.n0 * ((size_t)(y - G.hy) + (size_t)G.n1 * (size_t)(z - G.hz));
+    const size_t PL = G.plane;
+    const R rho = rho_in ? (R)rho_in[dom] : P.rho0;
+    const R drho = rho_in ? (R)(rho_in[dom] - (double)P.rho0) : (R)0;
+    R u[3] = {0, 0, 0};
+    if (u_in)
+        for (int k = 0; k < 3; ++k) u[k] = (R)u_in[(size_t)k * N + dom];
+    const R dC = C_in ? (R)(C_in[dom] - (double)P.C0) : (R)0;
+    const R Cc = P.C0 + dC;
+    R B[3] = {P.Bext[0], P.Bext[1], P.Bext[2]}, dB[3] = {0, 0, 0};
+    if (B_in)
+        for (int k = 0; k < 3; ++k) {
+            dB[k] = (R)(B_in[(size_t)k * N + dom] - (double)P.Bext[k]);
+            B[k] = P.Bext[k] + dB[k];
+        }
+    const R usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    using FL = typename C::FL;
+    using HL = typename C::HL;
+    using GL = typename C::GL;
+#pragma unroll
+    for (int i = 0; i < C::QF; ++i) {
+        const R eu = (R)FL::ex(i) * u[0] + (R)FL::ey(i) * u[1] + (R)FL::ez(i) * u[2];
+        const R v = (R)FL::w(i) * (drho + rho * ((R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * usq));
+        st<typename C::S>(S, (size_t)i * PL + n, v * P.sc[0]);
+    }
+#pragma unroll
+    for (int i = 0; i < C::QH; ++i) {
+        const R eu = (R)HL::ex(i) * u[0] + (R)HL::ey(i) * u[1] + (R)HL::ez(i) * u[2];
+        const R v = (R)HL::w(i) * (dC + Cc * eu * (R)4);
+        st<typename C::S>(S, (size_t)(C::H0 + i) * PL + n, v * P.sc[1]);
+    }
+#pragma unroll
+    for (int c = 0; c < C::NCOMP; ++c) {
+        const R uk = u[c];
+#pragma unroll
+        for (int i = 0; i < C::QG; ++i) {
+            const R ex = (R)GL::ex(i), ey = (R)GL::ey(i), ez = (R)GL::ez(i);
+            const R s = (ex * u[0] + ey * u[1] + ez * u[2]) * B[c] - (ex * B[0] + ey * B[1] + ez * B[2]) * uk;
+            const R v = (R)GL::w(i) * (dB[c] + s * (R)4);
+            st<typename C::S>(S, (size_t)(C::G0 + c * C::QG + i) * PL + n, v * P.sc[2]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+inline Geo make_geo(const KArgs& a) {
+    Geo g;
+    g.NX = a.NX;
+    g.NY = a.NY;
+    g.NZ = a.NZ;
+    g.hx = a.hx;
+    g.hy = a.hy;
+    g.hz = a.hz;
+    g.n0 = a.n0;
+    g.n1 = a.n1;
+    g.n2 = a.n2;
+    g.plane = (uint32_t)a.plane;
+    return g;
+}
+
+template <class C>
+struct Launch {
+    using R = typename C::R;
+    static double cg2() { return C::QG ? 0.25 : 1.0; }
+    static hipError_t step(const KArgs& a) {
+        const uint32_t nn = (uint32_t)((size_t)a.NX * a.NY * a.NZ);
+        const int bs = a.block > 0 ? a.block : 256;
+        dim3 grid((nn + bs - 1) / bs);
+        const Phys<R> P = make_phys<R>(a, cg2());
+        const Geo G = make_geo(a);
+        if (a.parity)
+            hipLaunchKernelGGL((k_step<C, 1>), grid, dim3(bs), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
+                               a.lstart, (const DevLink<R>*)a.links, (R*)a.stash, (R*)a.M, a.links_ready, nn);
+        else
+            hipLaunchKernelGGL((k_step<C, 0>), grid, dim3(bs), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
+                               a.lstart, (const DevLink<R>*)a.links, (R*)a.stash, (R*)a.M, a.links_ready, nn);
+        return hipGetLastError();
+    }
+    static hipError_t observe(const KArgs& a) {
+        const uint32_t nn = (uint32_t)((size_t)a.NX * a.NY * a.NZ);
+        dim3 grid((nn + 255) / 256);
+        const Phys<R> P = make_phys<R>(a, cg2());
+        const Geo G = make_geo(a);
+        if (a.parity)
+            hipLaunchKernelGGL((k_observe<C, 1>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
+                               a.lstart, (const DevLink<R>*)a.links, (R*)a.stash, (R*)a.M, a.links_ready, nn,
+                               a.mode, a.field, a.out, a.out_f64, a.acc, (R*)a.snap, a.snap_valid);
+        else
+            hipLaunchKernelGGL((k_observe<C, 0>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
+                               a.lstart, (const DevLink<R>*)a.links, (R*)a.stash, (R*)a.M, a.links_ready, nn,
+                               a.mode, a.field, a.out, a.out_f64, a.acc, (R*)a.snap, a.snap_valid);
+        return hipGetLastError();
+    }
+    static hipError_t init(const KArgs& a) {
+        const uint32_t nn = (uint32_t)((size_t)a.NX * a.NY * a.NZ);
+        dim3 grid((nn + 255) / 256);
+        const Phys<R> P = make_phys<R>(a, cg2());
+        const Geo G = make_geo(a);
+        hipLaunchKernelGGL((k_init<C>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S, a.flags, nn,
+                           a.init_rho, a.init_u, a.init_C, a.init_B);
+        return hipGetLastError();
+    }
+    static KernelSet set() {
+        KernelSet k;
+        k.step = &step;
+        k.observe = &observe;
+        k.init = &init;
+        k.QT = C::QT;
+        return k;
+    }
+};
+
+// the lattice combinations the library instantiates
+template <class SF>
+KernelSet select_kernels(int fl, int sl, int ml, int nc) {
+#define LBM_CASE(F, H, M, N)                              \
+    if (fl == F && sl == H && ml == M && (M == 0 || nc == N)) \
+        return Launch<Cfg<F, H, M, N, SF>>::set();
+    LBM_CASE(1, 0, 0, 0)
+    LBM_CASE(1, 3, 0, 0)
+    LBM_CASE(1, 0, 3, 1)
+    LBM_CASE(1, 0, 3, 2)
+    LBM_CASE(1, 3, 3, 1)
+    LBM_CASE(1, 3, 3, 2)
+    LBM_CASE(2, 0, 0, 0)
+    LBM_CASE(2, 4, 0, 0)
+    LBM_CASE(2, 0, 4, 1)
+    LBM_CASE(2, 0, 4, 3)
+    LBM_CASE(2, 4, 4, 1)
+    LBM_CASE(2, 4, 4, 3)
+#undef LBM_CASE
+    return KernelSet{};
+}
+
+}  // namespace lbmi

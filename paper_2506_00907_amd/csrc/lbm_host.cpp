@@ -1,0 +1,998 @@
+// Host side of liblbm: parameter validation, the geometry / boundary-link
+// builder, the device buffer layout and the C ABI declared in include/lbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+
+using lbmi::DevLink;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// lattice tables (host view of the device lattices)
+// ---------------------------------------------------------------------------
+struct HostLat {
+    int Q = 0;
+    int e[19][3] = {};
+    double w[19] = {};
+    double c2 = 1.0;
+    int opp[19] = {};
+};
+
+template <class L>
+HostLat host_lat() {
+    HostLat h;
+    h.Q = L::Q;
+    h.c2 = L::c2;
+    for (int a = 0; a < L::Q; ++a) {
+        h.e[a][0] = L::ex(a);
+        h.e[a][1] = L::ey(a);
+        h.e[a][2] = L::ez(a);
+        h.w[a] = L::w(a);
+        h.opp[a] = L::opp(a);
+    }
+    return h;
+}
+
+HostLat lattice_of(int code) {
+    switch (code) {
+        case LBM_D2Q9: return host_lat<lbmi::LD2Q9>();
+        case LBM_D3Q19: return host_lat<lbmi::LD3Q19>();
+        case LBM_D2Q5: return host_lat<lbmi::LD2Q5>();
+        case LBM_D3Q7: return host_lat<lbmi::LD3Q7>();
+        default: return HostLat{};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// parameter validation
+// ---------------------------------------------------------------------------
+bool valid_params(const lbm_params* p, std::string* why) {
+    auto fail = [&](const char* m) {
+        if (why) *why = m;
+        return false;
+    };
+    if (!p) return fail("params is NULL");
+    if (p->dim != 2 && p->dim != 3) return fail("dim must be 2 or 3");
+    for (int k = 0; k < 3; ++k)
+        if (p->n[k] < 1) return fail("node counts must be >= 1");
+    if (p->dim == 2) {
+        if (p->n[2] != 1 || !p->periodic[2]) return fail("2D domains need n[2] = 1 and periodic[2] = 1");
+        if (p->fluid != LBM_D2Q9) return fail("2D flow lattice must be D2Q9");
+        if (p->scalar != LBM_NONE && p->scalar != LBM_D2Q5) return fail("2D scalar lattice must be D2Q5");
+        if (p->magnetic != LBM_NONE && p->magnetic != LBM_D2Q5) return fail("2D magnetic lattice must be D2Q5");
+        if (p->magnetic && (p->mag_ncomp < 1 || p->mag_ncomp > 2)) return fail("2D magnetic components: 1 or 2");
+    } else {
+        if (p->fluid != LBM_D3Q19) return fail("3D flow lattice must be D3Q19");
+        if (p->scalar != LBM_NONE && p->scalar != LBM_D3Q7) return fail("3D scalar lattice must be D3Q7");
+        if (p->magnetic != LBM_NONE && p->magnetic != LBM_D3Q7) return fail("3D magnetic lattice must be D3Q7");
+        if (p->magnetic && p->mag_ncomp != 1 && p->mag_ncomp != 3) return fail("3D magnetic components: 1 or 3");
+    }
+    if (!p->magnetic && p->mag_ncomp != 0) return fail("mag_ncomp must be 0 without a magnetic lattice");
+    for (int c = 0; c < p->mag_ncomp; ++c)
+        if (p->mag_comp[c] != c) return fail("evolved magnetic component c must be Cartesian axis c");
+    if (!(p->tau_f > 0.5) || (p->scalar && !(p->tau_c > 0.5)) || (p->magnetic && !(p->tau_m > 0.5)))
+        return fail("relaxation times must exceed 1/2");
+    if (!(p->rho0 > 0.0)) return fail("rho0 must be positive");
+    if (p->magnetic && !(p->mu > 0.0)) return fail("mu must be positive");
+    if (p->storage < LBM_F64 || p->storage > LBM_BF16) return fail("unknown storage");
+    for (int k = 0; k < 3; ++k)
+        if (!(p->store_scale[k] > 0.0) || !std::isfinite(p->store_scale[k])) return fail("store_scale must be positive");
+    const double nn = (double)(p->n[0] + 2) * (p->n[1] + 2) * (p->n[2] + 2);
+    if (nn > 2.0e9) return fail("lattice too large for 32-bit node indices");
+    return true;
+}
+
+struct Pad {
+    int NX, NY, NZ, hx, hy, hz;
+    size_t nodes, plane;
+};
+
+Pad padding(const lbm_params* p) {
+    Pad d;
+    d.hx = p->periodic[0] ? 0 : 1;
+    d.hy = p->periodic[1] ? 0 : 1;
+    d.hz = p->periodic[2] ? 0 : 1;
+    d.NX = p->n[0] + 2 * d.hx;
+    d.NY = p->n[1] + 2 * d.hy;
+    d.NZ = p->n[2] + 2 * d.hz;
+    d.nodes = (size_t)d.NX * d.NY * d.NZ;
+    d.plane = round_up(d.nodes, 64);
+    return d;
+}
+
+size_t value_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
+size_t compute_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
+size_t link_bytes(int storage) { return storage == LBM_F64 ? sizeof(DevLink<double>) : sizeof(DevLink<float>); }
+
+int total_planes(const lbm_params* p) {
+    int q = lattice_of(p->fluid).Q;
+    if (p->scalar) q += lattice_of(p->scalar).Q;
+    if (p->magnetic) q += p->mag_ncomp * lattice_of(p->magnetic).Q;
+    return q;
+}
+
+lbmi::KernelSet kernels_for(const lbm_params* p) {
+    const int nc = p->magnetic ? p->mag_ncomp : 0;
+    switch (p->storage) {
+        case LBM_F64: return lbmi::kernels_f64(p->fluid, p->scalar, p->magnetic, nc);
+        case LBM_F32: return lbmi::kernels_f32(p->fluid, p->scalar, p->magnetic, nc);
+        case LBM_F16: return lbmi::kernels_f16(p->fluid, p->scalar, p->magnetic, nc);
+        default: return lbmi::kernels_bf16(p->fluid, p->scalar, p->magnetic, nc);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// geometry and boundary-link builder
+// ---------------------------------------------------------------------------
+struct Cand {
+    int bnd = -1;
+    double d = 0.0;
+    bool open = true;
+};
+
+class LinkBuilder {
+   public:
+    LinkBuilder(const lbm_params& p, const lbm_boundary* b, int nb) : p_(p), b_(b, b + nb) {
+        N_ = (size_t)p.n[0] * p.n[1] * p.n[2];
+    }
+
+    // fluid iff strictly inside every cylinder
+    void classify() {
+        mask_.assign(N_, 1);
+        for (int z = 0; z < p_.n[2]; ++z)
+            for (int y = 0; y < p_.n[1]; ++y)
+                for (int x = 0; x < p_.n[0]; ++x) {
+                    const int c[3] = {x, y, z};
+                    for (const auto& bd : b_)
+                        if (bd.type == 1 && !inside(bd, c)) mask_[index(c)] = 0;
+                }
+    }
+
+    std::string build(std::vector<lbm_link>* out) {
+        classify();
+        const int fields[3] = {p_.fluid, p_.scalar, p_.magnetic};
+        for (int field = 0; field < 3; ++field) {
+            if (!fields[field]) continue;
+            const HostLat L = lattice_of(fields[field]);
+            const int ncomp = field == 2 ? p_.mag_ncomp : 1;
+            std::vector<std::vector<double>> segs(b_.size());
+            for (int z = 0; z < p_.n[2]; ++z)
+                for (int y = 0; y < p_.n[1]; ++y)
+                    for (int x = 0; x < p_.n[0]; ++x) {
+                        const int A[3] = {x, y, z};
+                        const size_t ia = index(A);
+                        if (!mask_[ia]) continue;
+                        for (int a = 1; a < L.Q; ++a) {
+                            int src[3] = {x - L.e[a][0], y - L.e[a][1], z - L.e[a][2]};
+                            const int raw[3] = {src[0], src[1], src[2]};
+                            if (wrap(src) && mask_[index(src)]) continue;
+                            Cand best;
+                            for (int i = 0; i < (int)b_.size(); ++i) {
+                                const lbm_boundary& bd = b_[i];
+                                if (bc_of(bd, field, 0).kind == 0) continue;
+                                double d = -1.0;
+                                if (bd.type == 0) {
+                                    const int ax = bd.axis;
+                                    const bool crossed = bd.side == 0 ? raw[ax] < 0 : raw[ax] >= p_.n[ax];
+                                    if (crossed && !p_.periodic[ax]) d = bd.q;
+                                } else if (!inside(bd, raw)) {
+                                    d = cylinder_fraction(bd, A, L.e[a]);
+                                }
+                                if (!(d > 0.0)) continue;
+                                const bool open = bd.is_open != 0;
+                                bool take = best.bnd < 0;
+                                if (!take && best.open && !open) take = true;
+                                if (!take && best.open == open && d < best.d) take = true;
+                                if (take) best = Cand{i, d, open};
+                            }
+                            if (best.bnd < 0) {
+                                char msg[160];
+                                snprintf(msg, sizeof msg, "no boundary condition for node (%d,%d,%d) field %d dir %d",
+                                         x, y, z, field, a);
+                                return msg;
+                            }
+                            const lbm_boundary& bd = b_[best.bnd];
+                            int E[3] = {x + L.e[a][0], y + L.e[a][1], z + L.e[a][2]};
+                            const bool e_ok = wrap(E) && mask_[index(E)];
+                            for (int c = 0; c < ncomp; ++c) {
+                                const lbm_bc& bc = bc_of(bd, field, c);
+                                lbm_link lk;
+                                std::memset(&lk, 0, sizeof lk);
+                                lk.node = (uint32_t)ia;
+                                lk.enode = e_ok ? (uint32_t)index(E) : (uint32_t)ia;
+                                lk.field = (uint8_t)field;
+                                lk.dir = (uint8_t)a;
+                                lk.kind = (uint8_t)bc.kind;
+                                lk.comp = (uint8_t)(field == 2 ? c : 0);
+                                lk.flags = (uint8_t)((bc.u_given ? 1 : 0) | (e_ok ? 0 : 2));
+                                lk.d = best.d;
+                                lk.value = bc.value;
+                                lk.a1 = bc.a1;
+                                if (bc.a1_profile && bc.profile_len > 0) {
+                                    int pos = A[bc.profile_axis];
+                                    pos = std::min(pos, bc.profile_len - 1);
+                                    lk.a1 = bc.a1_profile[pos];
+                                }
+                                lk.a3 = bc.a3;
+                                lk.weight = 1.0;
+                                for (int k = 0; k < 3; ++k) lk.u_w[k] = bd.u_w[k];
+                                const bool flux = bc.kind == LBM_LK_FLUX || bc.kind == LBM_LK_MAG_FLUX;
+                                if (bd.type == 1 && flux) {
+                                    if (segs[best.bnd].empty()) segs[best.bnd] = segments(bd, L);
+                                    lk.weight = split(bd, L, segs[best.bnd], raw, a);
+                                }
+                                out->push_back(lk);
+                            }
+                        }
+                    }
+        }
+        std::stable_sort(out->begin(), out->end(), [](const lbm_link& u, const lbm_link& v) {
+            if (u.node != v.node) return u.node < v.node;
+            if (u.field != v.field) return u.field < v.field;
+            if (u.comp != v.comp) return u.comp < v.comp;
+            return u.dir < v.dir;
+        });
+        return std::string();
+    }
+
+    const std::vector<uint8_t>& mask() const { return mask_; }
+
+   private:
+    size_t index(const int* c) const { return (size_t)c[0] + (size_t)p_.n[0] * ((size_t)c[1] + (size_t)p_.n[1] * c[2]); }
+
+    bool wrap(int* c) const {
+        for (int k = 0; k < 3; ++k) {
+            if (c[k] >= 0 && c[k] < p_.n[k]) continue;
+            if (!p_.periodic[k]) return false;
+            c[k] = ((c[k] % p_.n[k]) + p_.n[k]) % p_.n[k];
+        }
+        return true;
+    }
+
+    static void plane_axes(int axis, int* u, int* v) {
+        static const int tab[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+        *u = tab[axis][0];
+        *v = tab[axis][1];
+    }
+
+    static bool inside(const lbm_boundary& c, const int* q) {
+        int u, v;
+        plane_axes(c.axis, &u, &v);
+        const double du = q[u] - c.center[u], dv = q[v] - c.center[v];
+        return du * du + dv * dv < c.radius * c.radius;
+    }
+
+    // fraction s in (0, 1] of the link A -> A - e where the ray meets the
+    // circle (stable form of the quadratic's positive root)
+    static double cylinder_fraction(const lbm_boundary& c, const int* A, const int* e) {
+        int u, v;
+        plane_axes(c.axis, &u, &v);
+        const double pu = A[u] - c.center[u], pv = A[v] - c.center[v];
+        const double du = -e[u], dv = -e[v];
+        const double qa = du * du + dv * dv;
+        if (qa == 0.0) return -1.0;
+        const double qb = pu * du + pv * dv;
+        const double qc = pu * pu + pv * pv - c.radius * c.radius;  // < 0 inside
+        const double disc = qb * qb - qa * qc;
+        if (disc < 0.0) return -1.0;
+        const double sq = std::sqrt(disc);
+        const double t = qb >= 0.0 ? -(qb + sq) : -(qb - sq);
+        const double r1 = t / qa, r2 = qc / t;
+        return r1 > 0.0 ? r1 : r2;
+    }
+
+    static const lbm_bc& bc_of(const lbm_boundary& b, int field, int comp) {
+        return field == 0 ? b.f : (field == 1 ? b.h : b.g[comp]);
+    }
+
+    // surface element S_i of every outer-layer solid node of a cylinder in
+    // one cross-section (Section 6.2): nodes sorted by azimuth (then radius),
+    // S_i = (theta_{i+1} - theta_{i-1}) R / 2 with cyclic neighbours
+    std::vector<double> segments(const lbm_boundary& c, const HostLat& L) const {
+        int u, v;
+        plane_axes(c.axis, &u, &v);
+        const int nu = p_.n[u], nv = p_.n[v];
+        struct Node {
+            int iu, iv;
+            double th, r;
+        };
+        std::vector<Node> outer;
+        for (int jv = 0; jv < nv; ++jv)
+            for (int ju = 0; ju < nu; ++ju) {
+                int q[3] = {0, 0, 0};
+                q[u] = ju;
+                q[v] = jv;
+                if (inside(c, q)) continue;
+                bool touches = false;
+                for (int a = 1; a < L.Q && !touches; ++a) {
+                    if (L.e[a][c.axis] != 0) continue;
+                    int s[3] = {q[0] + L.e[a][0], q[1] + L.e[a][1], q[2] + L.e[a][2]};
+                    s[c.axis] = 0;
+                    if (s[u] < 0 || s[u] >= nu || s[v] < 0 || s[v] >= nv) continue;
+                    touches = inside(c, s);
+                }
+                if (!touches) continue;
+                const double du = ju - c.center[u], dv = jv - c.center[v];
+                outer.push_back(Node{ju, jv, std::atan2(dv, du), std::hypot(du, dv)});
+            }
+        std::sort(outer.begin(), outer.end(), [](const Node& a, const Node& b) {
+            return a.th != b.th ? a.th < b.th : a.r < b.r;
+        });
+        std::vector<double> S((size_t)nu * nv, 0.0);
+        const size_t m = outer.size();
+        const double two_pi = 2.0 * M_PI;
+        for (size_t i = 0; i < m; ++i) {
+            const double prev = i == 0 ? outer[m - 1].th - two_pi : outer[i - 1].th;
+            const double next = i + 1 == m ? outer[0].th + two_pi : outer[i + 1].th;
+            S[(size_t)outer[i].iu + (size_t)nu * outer[i].iv] = 0.5 * (next - prev) * c.radius;
+        }
+        return S;
+    }
+
+    // Eq. 48: the share of S_B carried by the link entering A along e_alpha
+    // from the solid node B
+    double split(const lbm_boundary& c, const HostLat& L, const std::vector<double>& S, const int* B,
+                 int alpha) const {
+        int u, v;
+        plane_axes(c.axis, &u, &v);
+        const int nu = p_.n[u], nv = p_.n[v];
+        double SB = 0.0;
+        if (B[u] >= 0 && B[u] < nu && B[v] >= 0 && B[v] < nv) SB = S[(size_t)B[u] + (size_t)nu * B[v]];
+        double nx = c.center[u] - B[u], ny = c.center[v] - B[v];
+        const double len = std::hypot(nx, ny);
+        nx /= len;
+        ny /= len;
+        double total = 0.0, top = -1e300;
+        int arg = -1;
+        for (int g = 1; g < L.Q; ++g) {
+            if (L.e[g][c.axis] != 0) continue;
+            int s[3] = {B[0] + L.e[g][0], B[1] + L.e[g][1], B[2] + L.e[g][2]};
+            s[c.axis] = 0;
+            if (s[u] < 0 || s[u] >= nu || s[v] < 0 || s[v] >= nv || !inside(c, s)) continue;
+            const double en = L.e[g][u] * nx + L.e[g][v] * ny;
+            if (en > 0.0) total += en;
+            if (en > top) {
+                top = en;
+                arg = g;
+            }
+        }
+        const double ea = L.e[alpha][u] * nx + L.e[alpha][v] * ny;
+        if (total > 0.0) return ea > 0.0 ? SB * ea / total : 0.0;
+        return alpha == arg ? SB : 0.0;
+    }
+
+    const lbm_params& p_;
+    std::vector<lbm_boundary> b_;
+    size_t N_;
+    std::vector<uint8_t> mask_;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct lbm_ctx {
+    lbm_params p;
+    Pad pad;
+    lbmi::KernelSet ks;
+    void* buf[LBM_NBUF];
+    size_t size[LBM_NBUF];
+    size_t cap_links = 0, n_links = 0;
+    hipStream_t stream = nullptr;
+    int64_t t = 0, t_snap = 0;
+    bool have_geometry = false, have_links = false, initialized = false, snap_valid = false;
+    std::vector<uint8_t> mask;   // domain
+    std::string err;
+    // a captured run of kGraphSteps steps (even start parity, links ready),
+    // replayed by lbm_step on the caller's stream
+    hipGraphExec_t graph = nullptr;
+    hipStream_t capture_stream = nullptr;
+    bool graph_failed = false;
+    int graph_steps = 64;
+};
+
+namespace {
+
+void drop_graph(lbm_ctx* c) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+}
+
+lbm_status set_err(lbm_ctx* c, lbm_status s, const std::string& m) {
+    if (c) c->err = m;
+    return s;
+}
+
+lbm_status hip_check(lbm_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return LBM_OK;
+    return set_err(c, LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void layout(const lbm_params* p, size_t n_links, size_t sz[LBM_NBUF]) {
+    const Pad d = padding(p);
+    const size_t vb = value_bytes(p->storage), cb = compute_bytes(p->storage);
+    sz[0] = round_up((size_t)total_planes(p) * d.plane * vb, kAlign);
+    sz[1] = round_up(d.plane, kAlign);
+    sz[2] = round_up((d.plane + 1) * sizeof(uint32_t), kAlign);
+    sz[3] = round_up(std::max<size_t>(n_links, 1) * link_bytes(p->storage), kAlign);
+    sz[4] = round_up(std::max<size_t>(n_links, 1) * 2 * cb, kAlign);
+    sz[5] = round_up(2 * 8 * d.plane * cb, kAlign);
+    sz[6] = round_up(7 * d.plane * cb, kAlign) + round_up(lbmi::NACC * sizeof(double), kAlign);
+    sz[7] = 0;
+}
+
+lbmi::KArgs base_args(const lbm_ctx* c) {
+    lbmi::KArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.NX = c->pad.NX;
+    a.NY = c->pad.NY;
+    a.NZ = c->pad.NZ;
+    a.hx = c->pad.hx;
+    a.hy = c->pad.hy;
+    a.hz = c->pad.hz;
+    a.n0 = c->p.n[0];
+    a.n1 = c->p.n[1];
+    a.n2 = c->p.n[2];
+    a.plane = c->pad.plane;
+    a.S = c->buf[0];
+    a.flags = (const uint8_t*)c->buf[1];
+    a.lstart = (const uint32_t*)c->buf[2];
+    a.links = c->buf[3];
+    a.stash = c->buf[4];
+    a.M = c->buf[5];
+    a.tau_f = c->p.tau_f;
+    a.tau_c = c->p.scalar ? c->p.tau_c : 1.0;
+    a.tau_m = c->p.magnetic ? c->p.tau_m : 1.0;
+    a.rho0 = c->p.rho0;
+    a.C0 = c->p.C0;
+    a.mu = c->p.magnetic ? c->p.mu : 1.0;
+    for (int k = 0; k < 3; ++k) {
+        a.Bext[k] = c->p.B_ext[k];
+        a.accel[k] = c->p.accel[k];
+        const bool scaled = c->p.storage == LBM_F16 || c->p.storage == LBM_BF16;
+        a.scale[k] = scaled ? c->p.store_scale[k] : 1.0;
+        a.comp[k] = k;
+    }
+    a.parity = (int)(c->t & 1);
+    a.links_ready = c->t > 0 ? 1 : 0;
+    a.block = 256;
+    a.stream = c->stream;
+    return a;
+}
+
+size_t domain_nodes(const lbm_params& p) { return (size_t)p.n[0] * p.n[1] * p.n[2]; }
+
+template <class R>
+void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::vector<uint32_t>& padA,
+                   const std::vector<uint32_t>& padE, std::vector<unsigned char>* bytes) {
+    const HostLat Lf = lattice_of(c->p.fluid), Lh = lattice_of(c->p.scalar), Lg = lattice_of(c->p.magnetic);
+    const int QF = Lf.Q, QH = c->p.scalar ? Lh.Q : 0, QG = Lg.Q;
+    bytes->assign(std::max<size_t>(L.size(), 1) * sizeof(DevLink<R>), 0);
+    DevLink<R>* out = (DevLink<R>*)bytes->data();
+    for (size_t i = 0; i < L.size(); ++i) {
+        const lbm_link& s = L[i];
+        const HostLat& lat = s.field == 0 ? Lf : (s.field == 1 ? Lh : Lg);
+        const int base = s.field == 0 ? 0 : (s.field == 1 ? QF : QF + QH + s.comp * QG);
+        DevLink<R> d;
+        std::memset(&d, 0, sizeof d);
+        d.A = padA[i];
+        d.E = padE[i];
+        d.kind = s.kind;
+        d.flags = s.flags & 3;
+        d.pa = (uint8_t)(base + s.dir);
+        d.pap = (uint8_t)(base + lat.opp[s.dir]);
+        d.field = s.field;
+        d.caxis = s.field == 2 ? s.comp : 0;
+        d.ex = (int8_t)lat.e[s.dir][0];
+        d.ey = (int8_t)lat.e[s.dir][1];
+        d.ez = (int8_t)lat.e[s.dir][2];
+        d.d = (R)s.d;
+        // given values enter as deviations from the rest state, formed in
+        // double precision so that small differences survive FP32
+        double rest = 0.0;
+        if (s.kind == LBM_LK_PRES) rest = c->p.rho0;
+        else if (s.kind == LBM_LK_CONC) rest = c->p.C0;
+        else if (s.kind == LBM_LK_MAG_DIR) rest = c->p.B_ext[s.comp];
+        d.value = (R)(s.value - rest);
+        d.a1 = (R)s.a1;
+        d.a3 = (R)s.a3;
+        d.weight = (R)s.weight;
+        d.uw0 = (R)s.u_w[0];
+        d.uw1 = (R)s.u_w[1];
+        d.uw2 = (R)s.u_w[2];
+        out[i] = d;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* lbm_version(void) { return "liblbm 0.1 (gfx950, AA-pattern fused coupled sweep)"; }
+
+lbm_status lbm_lattice_table(int32_t lattice, int32_t* Q, int32_t* e, double* w, double* c2, int32_t* opp) {
+    if (lattice < LBM_D2Q9 || lattice > LBM_D3Q7 || !Q || !e || !w || !c2 || !opp) return LBM_EINVAL;
+    const HostLat L = lattice_of(lattice);
+    *Q = L.Q;
+    *c2 = L.c2;
+    for (int a = 0; a < L.Q; ++a) {
+        for (int k = 0; k < 3; ++k) e[3 * a + k] = L.e[a][k];
+        w[a] = L.w[a];
+        opp[a] = L.opp[a];
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_build_links(const lbm_params* p, const lbm_boundary* bnds, int32_t nb, uint8_t* mask_out,
+                           lbm_link* links_out, size_t cap, size_t* n_out) {
+    std::string why;
+    if (!valid_params(p, &why) || nb < 0 || (nb > 0 && !bnds) || !n_out) return LBM_EINVAL;
+    for (int i = 0; i < nb; ++i) {
+        const lbm_boundary& b = bnds[i];
+        if (b.type != 0 && b.type != 1) return LBM_EINVAL;
+        if (b.axis < 0 || b.axis > 2) return LBM_EINVAL;
+        if (b.type == 0 && !(b.q > 0.0 && b.q <= 1.0)) return LBM_EINVAL;
+        if (b.type == 1 && !(b.radius > 0.0)) return LBM_EINVAL;
+    }
+    LinkBuilder lb(*p, bnds, nb);
+    std::vector<lbm_link> links;
+    const std::string e = lb.build(&links);
+    if (!e.empty()) return LBM_EINVAL;
+    *n_out = links.size();
+    if (mask_out) std::memcpy(mask_out, lb.mask().data(), lb.mask().size());
+    if (links_out) {
+        if (cap < links.size()) return LBM_ESIZE;
+        std::memcpy(links_out, links.data(), links.size() * sizeof(lbm_link));
+    }
+    return LBM_OK;
+}
+
+size_t lbm_required_bytes(const lbm_params* p, size_t n_links, size_t sizes_out[LBM_NBUF]) {
+    if (!valid_params(p, nullptr)) return 0;
+    size_t sz[LBM_NBUF];
+    layout(p, n_links, sz);
+    size_t tot = 0;
+    for (int i = 0; i < LBM_NBUF; ++i) {
+        if (sizes_out) sizes_out[i] = sz[i];
+        tot += sz[i];
+    }
+    return tot;
+}
+
+lbm_status lbm_create(const lbm_params* p, size_t n_links, void* const dev_bufs[LBM_NBUF], void* hip_stream,
+                      lbm_ctx** out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    std::string why;
+    if (!valid_params(p, &why) || !dev_bufs) return LBM_EINVAL;
+    lbmi::KernelSet ks = kernels_for(p);
+    if (!ks.step) return LBM_EINVAL;
+    size_t sz[LBM_NBUF];
+    layout(p, n_links, sz);
+    for (int i = 0; i < LBM_NBUF; ++i) {
+        if (sz[i] > 0 && !dev_bufs[i]) return LBM_EINVAL;
+        if (sz[i] > 0 && ((uintptr_t)dev_bufs[i] % kAlign) != 0) return LBM_EINVAL;
+    }
+    lbm_ctx* c = new lbm_ctx();
+    c->p = *p;
+    c->pad = padding(p);
+    c->ks = ks;
+    for (int i = 0; i < LBM_NBUF; ++i) {
+        c->buf[i] = dev_bufs[i];
+        c->size[i] = sz[i];
+    }
+    c->cap_links = n_links;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* host_mask) {
+    if (!c) return LBM_EINVAL;
+    if (!host_mask) return set_err(c, LBM_EINVAL, "mask is NULL");
+    const size_t N = domain_nodes(c->p);
+    c->mask.assign(host_mask, host_mask + N);
+    for (auto& m : c->mask) m = m ? 1 : 0;
+    c->have_geometry = true;
+    c->have_links = false;
+    c->initialized = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
+    if (!c) return LBM_EINVAL;
+    if (!c->have_geometry) return set_err(c, LBM_ESTATE, "lbm_set_geometry must come first");
+    if (n > c->cap_links) return set_err(c, LBM_ESIZE, "more links than the context was created for");
+    if (n > 0 && !L) return set_err(c, LBM_EINVAL, "links is NULL");
+    const lbm_params& p = c->p;
+    const Pad& d = c->pad;
+    const size_t N = domain_nodes(p);
+    const int codes[3] = {p.fluid, p.scalar, p.magnetic};
+    HostLat lats[3] = {lattice_of(p.fluid), lattice_of(p.scalar), lattice_of(p.magnetic)};
+    auto coords = [&](uint32_t i, int* q) {
+        q[0] = (int)(i % (uint32_t)p.n[0]);
+        q[1] = (int)((i / (uint32_t)p.n[0]) % (uint32_t)p.n[1]);
+        q[2] = (int)(i / ((uint32_t)p.n[0] * (uint32_t)p.n[1]));
+    };
+    auto wrap = [&](int* q) {
+        for (int k = 0; k < 3; ++k) {
+            if (q[k] >= 0 && q[k] < p.n[k]) continue;
+            if (!p.periodic[k]) return false;
+            q[k] = ((q[k] % p.n[k]) + p.n[k]) % p.n[k];
+        }
+        return true;
+    };
+    auto dom = [&](const int* q) { return (size_t)q[0] + (size_t)p.n[0] * ((size_t)q[1] + (size_t)p.n[1] * q[2]); };
+    auto padidx = [&](const int* q) {
+        return (uint32_t)((q[0] + d.hx) + (size_t)d.NX * ((q[1] + d.hy) + (size_t)d.NY * (q[2] + d.hz)));
+    };
+
+    // validate each link; mark the (node, slot) pairs it covers
+    const int QF = lats[0].Q, QH = p.scalar ? lats[1].Q : 0, QG = p.magnetic ? lats[2].Q : 0;
+    const int QT = QF + QH + p.mag_ncomp * QG;
+    std::vector<uint8_t> covered(N * (size_t)QT, 0);
+    std::vector<lbm_link> links(L, L + n);
+    for (size_t i = 0; i < n; ++i) {
+        const lbm_link& k = links[i];
+        char msg[200];
+        auto bad = [&](const char* why) {
+            snprintf(msg, sizeof msg, "link %zu (node %u field %u dir %u): %s", i, k.node, k.field, k.dir, why);
+            return set_err(c, LBM_EINVAL, msg);
+        };
+        if (k.node >= N || !c->mask[k.node]) return bad("A is not a fluid node");
+        if (k.field > 2 || !codes[k.field]) return bad("field has no lattice");
+        const HostLat& lat = lats[k.field];
+        if (k.dir < 1 || k.dir >= lat.Q) return bad("direction out of range");
+        if (k.field == 2 ? k.comp >= p.mag_ncomp : k.comp != 0) return bad("component out of range");
+        const bool okkind = k.field == 0 ? (k.kind == LBM_LK_VEL || k.kind == LBM_LK_PRES)
+                            : k.field == 1 ? (k.kind == LBM_LK_CONC || k.kind == LBM_LK_FLUX || k.kind == LBM_LK_BB0)
+                                           : (k.kind == LBM_LK_MAG_DIR || k.kind == LBM_LK_MAG_FLUX || k.kind == LBM_LK_BB0);
+        if (!okkind) return bad("kind not allowed for this field");
+        if (!(k.d > 0.0 && k.d <= 1.0)) return bad("d outside (0, 1]");
+        if (!std::isfinite(k.value) || !std::isfinite(k.a1) || !std::isfinite(k.a3) || !std::isfinite(k.weight))
+            return bad("non-finite wall data");
+        int q[3];
+        coords(k.node, q);
+        int s[3] = {q[0] - lat.e[k.dir][0], q[1] - lat.e[k.dir][1], q[2] - lat.e[k.dir][2]};
+        if (wrap(s) && c->mask[dom(s)]) return bad("the source node is fluid (population is known)");
+        if (!(k.flags & 2)) {
+            int e[3] = {q[0] + lat.e[k.dir][0], q[1] + lat.e[k.dir][1], q[2] + lat.e[k.dir][2]};
+            if (!wrap(e) || !c->mask[dom(e)] || dom(e) != k.enode) return bad("enode is not the fluid node A + e_alpha");
+        }
+        const int base = k.field == 0 ? 0 : (k.field == 1 ? QF : QF + QH + k.comp * QG);
+        uint8_t& cov = covered[(size_t)k.node * QT + base + k.dir];
+        if (cov) return bad("duplicate link");
+        cov = 1;
+    }
+    // completeness: every unknown population has a link
+    for (size_t i = 0; i < N; ++i) {
+        if (!c->mask[i]) continue;
+        int q[3];
+        coords((uint32_t)i, q);
+        for (int f = 0; f < 3; ++f) {
+            if (!codes[f]) continue;
+            const HostLat& lat = lats[f];
+            const int nc = f == 2 ? p.mag_ncomp : 1;
+            for (int a = 1; a < lat.Q; ++a) {
+                int s[3] = {q[0] - lat.e[a][0], q[1] - lat.e[a][1], q[2] - lat.e[a][2]};
+                if (wrap(s) && c->mask[dom(s)]) continue;
+                for (int cc = 0; cc < nc; ++cc) {
+                    const int base = f == 0 ? 0 : (f == 1 ? QF : QF + QH + cc * QG);
+                    if (!covered[i * QT + base + a]) {
+                        char msg[160];
+                        snprintf(msg, sizeof msg, "node %zu field %d dir %d comp %d has no boundary link", i, f, a, cc);
+                        return set_err(c, LBM_EINVAL, msg);
+                    }
+                }
+            }
+        }
+    }
+
+    // order by padded node, build the per-node offsets and flags
+    std::vector<uint32_t> padA(n), padE(n);
+    for (size_t i = 0; i < n; ++i) {
+        int q[3];
+        coords(links[i].node, q);
+        padA[i] = padidx(q);
+        const uint32_t en = (links[i].flags & 2) ? links[i].node : links[i].enode;
+        coords(en, q);
+        padE[i] = padidx(q);
+    }
+    std::vector<size_t> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        if (padA[a] != padA[b]) return padA[a] < padA[b];
+        const lbm_link &u = links[a], &v = links[b];
+        if (u.field != v.field) return u.field < v.field;
+        if (u.comp != v.comp) return u.comp < v.comp;
+        return u.dir < v.dir;
+    });
+    std::vector<lbm_link> sl(n);
+    std::vector<uint32_t> sA(n), sE(n);
+    for (size_t i = 0; i < n; ++i) {
+        sl[i] = links[order[i]];
+        sA[i] = padA[order[i]];
+        sE[i] = padE[order[i]];
+    }
+    std::vector<uint8_t> flags(d.plane, 0);
+    for (size_t i = 0; i < N; ++i)
+        if (c->mask[i]) {
+            int q[3];
+            coords((uint32_t)i, q);
+            flags[padidx(q)] = lbmi::NF_FLUID;
+        }
+    std::vector<uint32_t> lstart(d.plane + 1, 0);
+    for (size_t i = 0; i < n; ++i) {
+        lstart[sA[i] + 1]++;
+        flags[sA[i]] |= lbmi::NF_LINKS | lbmi::NF_MOM;
+        flags[sE[i]] |= lbmi::NF_MOM;
+    }
+    for (size_t i = 0; i < d.plane; ++i) lstart[i + 1] += lstart[i];
+
+    std::vector<unsigned char> dl;
+    if (p.storage == LBM_F64) fill_devlinks<double>(c, sl, sA, sE, &dl);
+    else fill_devlinks<float>(c, sl, sA, sE, &dl);
+
+    lbm_status st;
+    if ((st = hip_check(c, hipMemcpyAsync(c->buf[1], flags.data(), flags.size(), hipMemcpyHostToDevice, c->stream), "flags upload")))
+        return st;
+    if ((st = hip_check(c, hipMemcpyAsync(c->buf[2], lstart.data(), lstart.size() * 4, hipMemcpyHostToDevice, c->stream), "offsets upload")))
+        return st;
+    if ((st = hip_check(c, hipMemcpyAsync(c->buf[3], dl.data(), dl.size(), hipMemcpyHostToDevice, c->stream), "links upload")))
+        return st;
+    if ((st = hip_check(c, hipMemsetAsync(c->buf[4], 0, c->size[4], c->stream), "stash clear"))) return st;
+    if ((st = hip_check(c, hipMemsetAsync(c->buf[5], 0, c->size[5], c->stream), "moment clear"))) return st;
+    if ((st = hip_check(c, hipStreamSynchronize(c->stream), "link upload sync"))) return st;
+    c->n_links = n;
+    drop_graph(c);
+    c->have_links = true;
+    c->initialized = false;
+    c->t = 0;
+    c->snap_valid = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_ctx* c, const double* rho, const double* u, const double* C, const double* B) {
+    if (!c) return LBM_EINVAL;
+    if (!c->have_links) return set_err(c, LBM_ESTATE, "lbm_set_links must come first");
+    lbm_status st;
+    if ((st = hip_check(c, hipMemsetAsync(c->buf[0], 0, c->size[0], c->stream), "population clear"))) return st;
+    lbmi::KArgs a = base_args(c);
+    a.init_rho = rho;
+    a.init_u = u;
+    a.init_C = C;
+    a.init_B = B;
+    if ((st = hip_check(c, c->ks.init(a), "init launch"))) return st;
+    c->t = 0;
+    c->initialized = true;
+    c->snap_valid = false;
+    return LBM_OK;
+}
+
+namespace {
+
+// Captures graph_steps steps starting at an even time with links ready.
+// The capture runs on a private stream (the caller's stream may be the legacy
+// default stream, which cannot be captured); the launch arguments do not
+// depend on the time beyond its parity.
+lbm_status make_graph(lbm_ctx* c) {
+    if (!c->capture_stream) {
+        if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+            c->capture_stream = nullptr;
+            return LBM_EDEVICE;
+        }
+    }
+    lbmi::KArgs a = base_args(c);
+    a.stream = c->capture_stream;
+    a.links_ready = 1;
+    if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_EDEVICE;
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < c->graph_steps && le == hipSuccess; ++i) {
+        a.parity = i & 1;
+        le = c->ks.step(a);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(c->capture_stream, &g);
+    if (le != hipSuccess || ee != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return LBM_EDEVICE;
+    }
+    hipError_t ie = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        c->graph = nullptr;
+        return LBM_EDEVICE;
+    }
+    return LBM_OK;
+}
+
+lbm_status step_launches(lbm_ctx* c, int64_t n) {
+    lbmi::KArgs a = base_args(c);
+    for (int64_t i = 0; i < n; ++i) {
+        a.parity = (int)(c->t & 1);
+        a.links_ready = c->t > 0 ? 1 : 0;
+        lbm_status st = hip_check(c, c->ks.step(a), "step launch");
+        if (st) return st;
+        c->t++;
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+    if (!c) return LBM_EINVAL;
+    if (n < 0) return set_err(c, LBM_EINVAL, "negative step count");
+    if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
+    // single launches until the time is even and positive
+    while (n > 0 && (c->t == 0 || (c->t & 1))) {
+        lbm_status st = step_launches(c, 1);
+        if (st) return st;
+        --n;
+    }
+    const int64_t G = c->graph_steps;
+    if (n >= G && !c->graph_failed) {
+        if (!c->graph && make_graph(c) != LBM_OK) {
+            c->graph_failed = true;  // fall back to plain launches of the same kernels
+            (void)hipGetLastError();
+        }
+        while (c->graph && n >= G) {
+            lbm_status st = hip_check(c, hipGraphLaunch(c->graph, c->stream), "graph launch");
+            if (st) return st;
+            c->t += G;
+            n -= G;
+        }
+    }
+    return step_launches(c, n);
+}
+
+lbm_status lbm_read_moments(lbm_ctx* c, void* dev_out, int32_t out_type) {
+    if (!c) return LBM_EINVAL;
+    if (!dev_out || (out_type != LBM_F64 && out_type != LBM_F32)) return set_err(c, LBM_EINVAL, "bad output");
+    if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
+    lbmi::KArgs a = base_args(c);
+    a.mode = lbmi::OBS_MOMENTS;
+    a.out = dev_out;
+    a.out_f64 = out_type == LBM_F64;
+    return hip_check(c, c->ks.observe(a), "moments launch");
+}
+
+lbm_status lbm_read_populations(lbm_ctx* c, int32_t field, double* dev_out) {
+    if (!c) return LBM_EINVAL;
+    const int codes[3] = {c->p.fluid, c->p.scalar, c->p.magnetic};
+    if (!dev_out || field < 0 || field > 2 || !codes[field]) return set_err(c, LBM_EINVAL, "bad field or output");
+    if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
+    lbmi::KArgs a = base_args(c);
+    a.mode = lbmi::OBS_POPS;
+    a.field = field;
+    a.out = dev_out;
+    return hip_check(c, c->ks.observe(a), "populations launch");
+}
+
+lbm_status lbm_reduce(lbm_ctx* c, double out[8]) {
+    if (!c || !out) return LBM_EINVAL;
+    if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
+    const size_t cb = compute_bytes(c->p.storage);
+    char* aux = (char*)c->buf[6];
+    double* acc = (double*)(aux + round_up(7 * c->pad.plane * cb, kAlign));
+    lbm_status st;
+    if ((st = hip_check(c, hipMemsetAsync(acc, 0, lbmi::NACC * sizeof(double), c->stream), "accumulator clear")))
+        return st;
+    lbmi::KArgs a = base_args(c);
+    a.mode = lbmi::OBS_REDUCE;
+    a.acc = acc;
+    a.snap = aux;
+    a.snap_valid = c->snap_valid ? 1 : 0;
+    if ((st = hip_check(c, c->ks.observe(a), "reduce launch"))) return st;
+    double h[lbmi::NACC];
+    if ((st = hip_check(c, hipMemcpyAsync(h, acc, sizeof h, hipMemcpyDeviceToHost, c->stream), "reduce copy")))
+        return st;
+    if ((st = hip_check(c, hipStreamSynchronize(c->stream), "reduce sync"))) return st;
+    const double dt = (double)(c->t - c->t_snap);
+    double res = -1.0;
+    if (c->snap_valid && dt > 0) {
+        res = 0.0;
+        for (int f = 0; f < 3; ++f) {
+            const double nrm = std::sqrt(h[8 + f]);
+            if (h[8 + f] == 0.0 && h[5 + f] == 0.0) continue;
+            res = std::max(res, std::sqrt(h[5 + f]) / (dt * std::max(nrm, 1e-30)));
+        }
+    }
+    out[0] = res;
+    out[1] = h[0];
+    out[2] = h[1];
+    out[3] = h[2];
+    out[4] = h[3];
+    out[5] = h[4];
+    out[6] = c->snap_valid ? dt : 0.0;
+    out[7] = h[11];
+    c->snap_valid = true;
+    c->t_snap = c->t;
+    if (h[11] > 0) return set_err(c, LBM_EUNSTABLE, "non-finite moments");
+    return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_ctx* c) {
+    if (!c) return 0;
+    return 64 + c->size[0] + c->size[4] + c->size[5];
+}
+
+lbm_status lbm_save(lbm_ctx* c, void* host) {
+    if (!c || !host) return LBM_EINVAL;
+    if (!c->initialized) return set_err(c, LBM_ESTATE, "nothing to save");
+    char* h = (char*)host;
+    std::memset(h, 0, 64);
+    std::memcpy(h, &c->t, sizeof c->t);
+    const uint64_t magic = 0x4C424D53544154ull;  // "LBMSTAT"
+    std::memcpy(h + 8, &magic, 8);
+    size_t o = 64;
+    lbm_status st;
+    const int ids[3] = {0, 4, 5};
+    for (int i : ids) {
+        if ((st = hip_check(c, hipMemcpyAsync(h + o, c->buf[i], c->size[i], hipMemcpyDeviceToHost, c->stream), "save copy")))
+            return st;
+        o += c->size[i];
+    }
+    return hip_check(c, hipStreamSynchronize(c->stream), "save sync");
+}
+
+lbm_status lbm_load(lbm_ctx* c, const void* host) {
+    if (!c || !host) return LBM_EINVAL;
+    if (!c->have_links) return set_err(c, LBM_ESTATE, "lbm_set_links must come first");
+    const char* h = (const char*)host;
+    uint64_t magic;
+    std::memcpy(&magic, h + 8, 8);
+    if (magic != 0x4C424D53544154ull) return set_err(c, LBM_EINVAL, "not a saved state");
+    int64_t t;
+    std::memcpy(&t, h, sizeof t);
+    size_t o = 64;
+    lbm_status st;
+    const int ids[3] = {0, 4, 5};
+    for (int i : ids) {
+        if ((st = hip_check(c, hipMemcpyAsync(c->buf[i], h + o, c->size[i], hipMemcpyHostToDevice, c->stream), "load copy")))
+            return st;
+        o += c->size[i];
+    }
+    if ((st = hip_check(c, hipStreamSynchronize(c->stream), "load sync"))) return st;
+    c->t = t;
+    c->initialized = true;
+    c->snap_valid = false;
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+lbm_status lbm_set_stream(lbm_ctx* c, void* s) {
+    if (!c) return LBM_EINVAL;
+    c->stream = (hipStream_t)s;
+    drop_graph(c);
+    return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void lbm_destroy(lbm_ctx* c) {
+    if (!c) return;
+    drop_graph(c);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal interface between the host side of liblbm (lbm_host.cpp) and the
+// kernel instantiations (lbm_kernels_*.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbmi {
+
+// per-node flags (one byte per padded node)
+enum : uint8_t { NF_FLUID = 1, NF_LINKS = 2, NF_MOM = 4 };
+
+// kernel modes of the observe kernel
+enum : int { OBS_MOMENTS = 0, OBS_POPS = 1, OBS_REDUCE = 2 };
+
+// number of FP64 accumulators used by the reduction
+constexpr int NACC = 16;
+
+// Boundary link as the kernels read it: precomputed plane indices and the
+// lattice vector of alpha, wall data in the compute type R.
+template <class R>
+struct alignas(16) DevLink {
+    uint32_t A, E;        // padded node indices; E == A when E is not fluid
+    uint8_t kind;         // lbm_link_kind
+    uint8_t flags;        // bit 0: u_w given; bit 1: E not fluid
+    uint8_t pa, pap;      // population planes of alpha and of its opposite alpha'
+    uint8_t field;        // 0 f, 1 h, 2 g
+    uint8_t caxis;        // Cartesian axis of the magnetic component (g links)
+    int8_t ex, ey, ez;    // e_alpha
+    uint8_t pad[3];
+    R d;
+    R value;  // given value minus its rest value (rho0, C0 or B_ext,k)
+    R a1, a3, weight, uw0, uw1, uw2;
+};
+
+// Launch description: sizes, pointers and physical parameters in double; the
+// instantiation converts to the compute type.
+struct KArgs {
+    int NX, NY, NZ;        // padded extents
+    int hx, hy, hz;        // halo widths (0 periodic, 1 otherwise)
+    int n0, n1, n2;        // domain extents
+    size_t plane;          // padded node count rounded up (population plane stride)
+    void* S;               // populations [QT][plane]
+    const uint8_t* flags;  // [plane]
+    const uint32_t* lstart;  // [plane + 1]
+    const void* links;     // DevLink<R>[n_links]
+    void* stash;           // R[2 * n_links]
+    void* M;               // R[2][8][plane]
+    double tau_f, tau_c, tau_m, rho0, C0, mu;
+    double Bext[3], accel[3], scale[3];
+    int comp[3];           // Cartesian axis of each evolved magnetic component
+    int parity;            // parity of the current time (t % 2)
+    int links_ready;       // 0 at t = 0: populations are the initial state
+    // observe / init
+    int mode;              // OBS_*
+    int field;             // OBS_POPS: 0 f, 1 h, 2 g
+    void* out;             // OBS_MOMENTS: [8][N] (out_f64 ? double : float); OBS_POPS: double
+    int out_f64;
+    double* acc;           // OBS_REDUCE: FP64 accumulators [NACC]
+    void* snap;            // OBS_REDUCE: R[7][plane] snapshot of u, C - C0, B - B_ext
+    int snap_valid;
+    const double *init_rho, *init_u, *init_C, *init_B;
+    int block;             // threads per block
+    hipStream_t stream;
+};
+
+using Launcher = hipError_t (*)(const KArgs&);
+
+struct KernelSet {
+    Launcher step = nullptr;     // one fused step at the given parity
+    Launcher observe = nullptr;  // moments / populations / reductions at the current time
+    Launcher init = nullptr;     // equilibrium initialisation
+    int QT = 0;                  // population planes
+};
+
+// storage codes as in lbm.h
+KernelSet kernels_f64(int fl, int sl, int ml, int nc);
+KernelSet kernels_f32(int fl, int sl, int ml, int nc);
+KernelSet kernels_f16(int fl, int sl, int ml, int nc);
+KernelSet kernels_bf16(int fl, int sl, int ml, int nc);
+
+}  // namespace lbmi

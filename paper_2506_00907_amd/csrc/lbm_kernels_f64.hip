@@ -1,0 +1,6 @@
+// Kernel instantiations for F64 population storage.
+#include "lbm_device.hpp"
+
+namespace lbmi {
+KernelSet kernels_f64(int fl, int sl, int ml, int nc) { return select_kernels<F64S>(fl, sl, ml, nc); }
+}  // namespace lbmi

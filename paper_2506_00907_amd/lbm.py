@@ -1,0 +1,229 @@
+"""Python face of liblbm: the C-ABI calls with PyTorch device buffers.
+
+Argument marshalling only.  PyTorch allocates the device buffers the library
+asks for and supplies the HIP stream; all arithmetic runs in liblbm's kernels.
+Names follow include/lbm.h: ``build_links``, ``Lattice.step``,
+``Lattice.read_moments``, ``Lattice.reduce`` ...
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Tuple
+
+import numpy as np
+
+from . import _lib as L
+
+LATTICES = {"D2Q9": 1, "D3Q19": 2, "D2Q5": 3, "D3Q7": 4}
+KINDS = {"VEL": 1, "PRES": 2, "CONC": 3, "FLUX": 4, "BB0": 5, "MAG_DIR": 6, "MAG_FLUX": 7}
+STORAGES = {"f64": L.LBM_F64, "f32": L.LBM_F32, "f16": L.LBM_F16, "bf16": L.LBM_BF16}
+
+LINK_DTYPE = np.dtype([("node", "<u4"), ("enode", "<u4"), ("field", "u1"), ("dir", "u1"), ("kind", "u1"),
+                       ("comp", "u1"), ("flags", "u1"), ("pad", "u1", 3), ("d", "<f8"), ("value", "<f8"),
+                       ("a1", "<f8"), ("a3", "<f8"), ("weight", "<f8"), ("u_w", "<f8", 3)])
+assert LINK_DTYPE.itemsize == C.sizeof(L.lbm_link)
+
+
+def params_from_scene(sc) -> L.lbm_params:
+    p = L.lbm_params()
+    p.dim = sc.dim
+    for k in range(3):
+        p.n[k] = sc.n[k]
+        p.periodic[k] = int(sc.periodic[k])
+        p.B_ext[k] = sc.B_ext[k]
+        p.accel[k] = sc.accel[k]
+        p.store_scale[k] = sc.store_scale[k]
+    p.fluid = LATTICES[sc.fluid_lattice]
+    p.scalar = LATTICES[sc.scalar_lattice] if sc.scalar_lattice else 0
+    p.magnetic = LATTICES[sc.mag_lattice] if sc.mag_lattice else 0
+    p.mag_ncomp = len(sc.mag_comps) if sc.mag_lattice else 0
+    for i, c in enumerate(sc.mag_comps):
+        p.mag_comp[i] = c
+    p.storage = STORAGES[sc.storage]
+    p.tau_f, p.tau_c, p.tau_m = sc.tau_f, sc.tau_c, sc.tau_m
+    p.rho0, p.C0, p.mu = sc.rho0, sc.C0, sc.mu
+    return p
+
+
+def boundaries_from_scene(sc):
+    keep = []
+    arr = (L.lbm_boundary * max(1, len(sc.boundaries)))()
+
+    def put(dst, bc):
+        if bc is None:
+            dst.kind = 0
+            return
+        dst.kind = KINDS[bc.kind]
+        dst.u_given = int(bc.u_given)
+        dst.value, dst.a1, dst.a3 = bc.value, bc.a1, bc.a3
+        dst.profile_axis = bc.profile_axis
+        if bc.a1_profile is not None:
+            prof = np.ascontiguousarray(bc.a1_profile, dtype=np.float64)
+            keep.append(prof)
+            dst.a1_profile = prof.ctypes.data_as(C.POINTER(C.c_double))
+            dst.profile_len = len(prof)
+
+    for i, b in enumerate(sc.boundaries):
+        d = arr[i]
+        d.type = 0 if b.type == "plane" else 1
+        d.axis, d.side, d.is_open, d.q, d.radius = b.axis, b.side, int(b.is_open), b.q, b.radius
+        for k in range(3):
+            d.center[k] = b.center[k]
+            d.u_w[k] = b.u_w[k]
+        put(d.f, b.f)
+        put(d.h, b.h)
+        for k in range(3):
+            put(d.g[k], b.g[k] if k < len(b.g) else None)
+    return arr, len(sc.boundaries), keep
+
+
+def build_links(sc) -> Tuple[np.ndarray, np.ndarray]:
+    """lbm_build_links: (fluid mask [nz, ny, nx] uint8, link table)."""
+    p = params_from_scene(sc)
+    arr, nb, keep = boundaries_from_scene(sc)
+    n = C.c_size_t()
+    mask = np.zeros(sc.nodes, np.uint8)
+    L.check(L.lib().lbm_build_links(C.byref(p), arr, nb, mask.ctypes.data_as(C.c_void_p), None, 0,
+                                    C.byref(n)), what="lbm_build_links (count)")
+    links = np.zeros(max(n.value, 1), LINK_DTYPE)
+    L.check(L.lib().lbm_build_links(C.byref(p), arr, nb, mask.ctypes.data_as(C.c_void_p),
+                                    links.ctypes.data_as(C.c_void_p), n.value, C.byref(n)),
+            what="lbm_build_links")
+    del keep
+    return mask.reshape(sc.n[2], sc.n[1], sc.n[0]), links[:n.value]
+
+
+def lattice_table(code: int):
+    Q = C.c_int32()
+    e = np.zeros((19, 3), np.int32)
+    w = np.zeros(19)
+    opp = np.zeros(19, np.int32)
+    c2 = C.c_double()
+    L.check(L.lib().lbm_lattice_table(code, C.byref(Q), e.ctypes.data_as(C.c_void_p),
+                                      w.ctypes.data_as(C.c_void_p), C.byref(c2),
+                                      opp.ctypes.data_as(C.c_void_p)), what="lbm_lattice_table")
+    q = Q.value
+    return e[:q].copy(), w[:q].copy(), c2.value, opp[:q].copy()
+
+
+def required_bytes(p: L.lbm_params, n_links: int):
+    sizes = (C.c_size_t * L.LBM_NBUF)()
+    tot = L.lib().lbm_required_bytes(C.byref(p), n_links, sizes)
+    if tot == 0:
+        raise L.LbmError(-1, "invalid parameters")
+    return list(sizes)
+
+
+class Lattice:
+    """One context of the fused coupled sweep on a torch device and stream."""
+
+    def __init__(self, sc, device: str = "cuda", stream=None, links: Optional[np.ndarray] = None,
+                 mask: Optional[np.ndarray] = None, init: bool = True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a HIP device")
+        self.torch = torch
+        self.scene = sc
+        self.params = params_from_scene(sc)
+        if links is None or mask is None:
+            mask, links = build_links(sc)
+        self.mask = np.ascontiguousarray(mask, np.uint8).reshape(-1)
+        self.links = np.ascontiguousarray(links)
+        self.n_links = len(self.links)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.sizes = required_bytes(self.params, self.n_links)
+        self.bufs = [torch.empty(max(s, 1), dtype=torch.uint8, device=self.device) for s in self.sizes]
+        ptrs = (C.c_void_p * L.LBM_NBUF)(*[b.data_ptr() if s > 0 else None
+                                          for b, s in zip(self.bufs, self.sizes)])
+        ctx = C.c_void_p()
+        L.check(L.lib().lbm_create(C.byref(self.params), self.n_links, ptrs,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(ctx)), what="lbm_create")
+        self.ctx = ctx
+        self._call("lbm_set_geometry", self.mask.ctypes.data_as(C.c_void_p))
+        self._call("lbm_set_links", self.links.ctypes.data_as(C.c_void_p), self.n_links)
+        self.N = sc.nodes
+        self.shape = (sc.n[2], sc.n[1], sc.n[0])
+        if init:
+            self.init(sc.init_rho, sc.init_u, sc.init_Cf, sc.init_B, C_uniform=sc.init_C)
+
+    def _call(self, name, *args):
+        L.check(getattr(L.lib(), name)(self.ctx, *args), self.ctx)
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                L.lib().lbm_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # -- ABI calls ----------------------------------------------------------
+    def init(self, rho=None, u=None, C_=None, B=None, C_uniform: Optional[float] = None):
+        """lbm_init from fields (arrays of the domain shape; u, B with a last
+        axis of 3) or the uniform rest state; C_uniform fills C when given."""
+        torch = self.torch
+        N = self.N
+
+        def dev(a, comps):
+            if a is None:
+                return None
+            t = torch.as_tensor(np.asarray(a, np.float64))
+            if comps == 1:
+                t = t.reshape(N)
+            else:
+                t = t.reshape(N, 3).t().contiguous()
+            return t.to(self.device)
+
+        tr, tu, tC, tB = dev(rho, 1), dev(u, 3), dev(C_, 1), dev(B, 3)
+        if tC is None and C_uniform is not None and C_uniform != self.params.C0:
+            tC = torch.full((N,), float(C_uniform), dtype=torch.float64, device=self.device)
+        self._keep_init = (tr, tu, tC, tB)
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        self._call("lbm_init", ptr(tr), ptr(tu), ptr(tC), ptr(tB))
+
+    def step(self, n: int = 1):
+        self._call("lbm_step", int(n))
+
+    @property
+    def time(self) -> int:
+        return L.lib().lbm_time(self.ctx)
+
+    def read_moments(self, dtype: str = "f64", out=None):
+        """[8, nz, ny, nx] tensor of rho, u, C, B at the current time."""
+        torch = self.torch
+        td = torch.float64 if dtype == "f64" else torch.float32
+        if out is None:
+            out = torch.empty((8,) + self.shape, dtype=td, device=self.device)
+        self._call("lbm_read_moments", C.c_void_p(out.data_ptr()), L.LBM_F64 if dtype == "f64" else L.LBM_F32)
+        return out
+
+    def read_populations(self, field: int):
+        """[slots, nz, ny, nx] FP64 tensor of one field's populations."""
+        torch = self.torch
+        sc = self.scene
+        lat = {0: sc.fluid_lattice, 1: sc.scalar_lattice, 2: sc.mag_lattice}[field]
+        q = len(lattice_table(LATTICES[lat])[1])
+        nc = len(sc.mag_comps) if field == 2 else 1
+        out = torch.empty((nc * q,) + self.shape, dtype=torch.float64, device=self.device)
+        self._call("lbm_read_populations", field, C.c_void_p(out.data_ptr()))
+        return out
+
+    def reduce(self) -> np.ndarray:
+        out = (C.c_double * 8)()
+        code = L.lib().lbm_reduce(self.ctx, out)
+        vals = np.array(out[:])
+        if code == -4:
+            raise L.LbmError(code, "non-finite values")
+        L.check(code, self.ctx)
+        return vals
+
+    def save(self) -> bytes:
+        nb = L.lib().lbm_state_bytes(self.ctx)
+        buf = (C.c_char * nb)()
+        self._call("lbm_save", buf)
+        return bytes(buf)
+
+    def load(self, blob: bytes):
+        buf = (C.c_char * len(blob)).from_buffer_copy(blob)
+        self._call("lbm_load", buf)

@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded scenes.  Bars: FP64 storage 1e-12 relative L2 per moment field
+(populations to 1e-13 absolute); FP32 storage 1e-5 relative L2 on u, C, B;
+FP16/BF16 storage has no parity bound and is checked against loose error
+bounds only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from oracle import analytic as an
+from scenes import BC, Boundary, Scene
+
+from .gpu_util import field_errors, gpu_moments, gpu_populations, run_pair
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _case(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+def _periodic_box(storage="f64"):
+    rng = scenes.SplitMix64(scenes.BASE_SEED + 11)
+    nx, ny = 24, 17
+    u = 0.01 * rng.normal_array(nx * ny * 3).reshape(1, ny, nx, 3)
+    u[..., 2] = 0.0
+    rho = 1.0 + 1e-3 * rng.normal_array(nx * ny).reshape(1, ny, nx)
+    return Scene(name="periodic", dim=2, n=(nx, ny, 1), periodic=(True, True, True), fluid_lattice="D2Q9",
+                 tau_f=0.7, storage=storage, init_rho=rho, init_u=u, accel=(1e-5, -2e-6, 0.0))
+
+
+def _thin(ny, storage="f64"):
+    return scenes.poiseuille(nx=5, ny=ny, q=0.4, u_top=0.01, g=1e-5, storage=storage)
+
+
+FP64_CASES = {
+    "poiseuille_d05": lambda: scenes.poiseuille(nx=16, ny=12, storage="f64"),
+    "couette_d03": lambda: scenes.poiseuille(nx=7, ny=13, q=0.3, u_top=0.01, g=1e-6, storage="f64"),
+    "periodic_box": _periodic_box,
+    "thin_ny1": lambda: _thin(1),
+    "thin_ny2": lambda: _thin(2),
+    "reactive": lambda: scenes.reactive_channel(nx=41, ny=19, q=0.3, k_range=(1e-3, 1e-1), storage="f64"),
+    "reactive_q08": lambda: scenes.reactive_channel(nx=33, ny=11, q=0.8, storage="f64"),
+    "hartmann_c01": lambda: scenes.hartmann_couette(nx=13, ny=21, c_top=0.1, storage="f64"),
+    "hartmann_cinf": lambda: scenes.hartmann_couette(nx=7, ny=19, c_top=math.inf, qb=1.0, qt=0.25, storage="f64"),
+    "hartmann_c0": lambda: scenes.hartmann_couette(nx=9, ny=15, c_top=0.0, qb=0.5, qt=0.5, storage="f64"),
+    "pipe_shercliff": lambda: scenes.mhd_pipe(nx=3, side=23, R=9.37, wall="shercliff", storage="f64"),
+    "pipe_insulating3": lambda: scenes.mhd_pipe(nx=2, side=19, R=7.3, wall="insulating", ncomp=3, storage="f64"),
+    "pipe_conducting": lambda: scenes.mhd_pipe(nx=1, side=21, R=8.1, wall="conducting", storage="f64"),
+    "diffreact_full": lambda: scenes.diffusion_reaction(layout="full", Da=48.0, W_nodes=12),
+    "duct_item": lambda: scenes.batch_items(4, side_lo=48, side_hi=64, storage="f64")[0].scene,
+    "pipe_item": lambda: scenes.batch_items(4, side_lo=48, side_hi=64, storage="f64")[1].scene,
+}
+
+
+def _developed(key, storage=None):
+    sc = FP64_CASES[key]()
+    if storage:
+        sc = sc.with_(storage=storage)
+    # the diffusion-reaction case keeps its fluid at rest, as in the paper
+    return scenes.developed(sc, u_amp=0.0 if key.startswith("diffreact") else 0.02)
+
+
+@pytest.mark.parametrize("key", sorted(FP64_CASES))
+def test_fp64_parity(key):
+    _case(key)
+    sc = _developed(key)
+    lat, o = run_pair(sc, 300, chunks=3)
+    mo = o.moments()
+    mg = gpu_moments(lat)
+    mask = o.mask()
+    errs = field_errors(mg, mo, mask, sc.B_ext)
+    print(key, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    for f, e in errs.items():
+        assert e < 1e-12, (f, e)
+    for field in (0, 1, 2):
+        if {0: sc.fluid_lattice, 1: sc.scalar_lattice, 2: sc.mag_lattice}[field] is None:
+            continue
+        fl = mask.astype(bool)
+        pg = gpu_populations(lat, field)[..., fl]
+        po = o.populations(field)[..., fl]
+        assert np.abs(pg - po).max() < 1e-13, (field, np.abs(pg - po).max())
+
+
+@pytest.mark.parametrize("key", ["reactive", "hartmann_c01", "hartmann_cinf", "pipe_shercliff", "pipe_insulating3",
+                                 "diffreact_full", "pipe_item", "periodic_box"])
+def test_fp32_parity(key):
+    """FP32 storage, 128 steps from a developed seeded state."""
+    _case("fp32 " + key)
+    sc = _developed(key, "f32")
+    lat, o = run_pair(sc, 128, chunks=2)
+    errs = field_errors(gpu_moments(lat), o.moments(), o.mask(), sc.B_ext)
+    print(key, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    for f in ("rho", "u", "C", "b"):
+        assert errs[f] < 1e-5, (f, errs[f])
+
+
+STEADY = {
+    "hartmann_transpiring": (lambda: scenes.hartmann_couette(nx=4, ny=24, c_top=0.1, v0=2e-4, storage="f32"), 30000),
+    "pipe_shercliff": (lambda: scenes.mhd_pipe(nx=1, side=17, R=6.3, g=1e-5, wall="shercliff", storage="f32"), 8000),
+    "reactive": (lambda: scenes.reactive_channel(nx=40, ny=12, q=0.3, k=0.05, storage="f32"), 80000),
+}
+
+
+@pytest.mark.parametrize("key", sorted(STEADY))
+def test_fp32_parity_at_steady_state(key):
+    """FP32 storage against the FP64 oracle once both have reached the steady
+    state (residual below 1e-8 on the GPU)."""
+    _case("fp32 steady " + key)
+    mk, steps = STEADY[key]
+    sc = mk()
+    lat, o = run_pair(sc, steps, chunks=1)
+    lat.reduce()
+    lat.step(100)
+    o.step(100)
+    assert lat.reduce()[0] < 1e-8
+    errs = field_errors(gpu_moments(lat), o.moments(), o.mask(), sc.B_ext)
+    print(key, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    for f in ("rho", "u", "C", "b"):
+        assert errs[f] < 1e-5, (f, errs[f])
+
+
+@pytest.mark.parametrize("storage,bound", [("f16", 2e-2), ("bf16", 1e-1)])
+@pytest.mark.parametrize("key", ["hartmann_c01", "pipe_shercliff", "reactive"])
+def test_half_storage_error(key, storage, bound):
+    """16-bit deviation storage: no parity bound; the error against the FP64
+    oracle is reported and must stay small."""
+    _case(f"{storage} {key}")
+    sc = _developed(key, storage)
+    lat, o = run_pair(sc, 300, chunks=3)
+    errs = field_errors(gpu_moments(lat), o.moments(), o.mask(), sc.B_ext)
+    print(storage, key, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    for f in ("u", "C", "b"):
+        assert errs[f] < bound, (f, errs[f])
+
+
+# ---------------------------------------------------------------------------
+# full workload sizes, in the launch configuration the benchmark times
+# ---------------------------------------------------------------------------
+def test_full_poiseuille_fp64_matches_oracle_and_closed_form():
+    """The 64 x 32 channel from rest to steady state (20 000 steps)."""
+    _case("full poiseuille 64x32 fp64 20000 steps")
+    sc = scenes.config(1)
+    lat, o = run_pair(sc, 20000, chunks=4)
+    mo, mg = o.moments(), gpu_moments(lat)
+    errs = field_errors(mg, mo, o.mask())
+    assert errs["u"] < 1e-12 and errs["rho"] < 1e-12, errs
+    ex = an.poiseuille_discrete(32, 0.8, 1e-6)
+    assert np.abs(mg[0, :, :, 1] - ex[:, None]).max() / ex.max() < 1e-7
+
+
+@pytest.mark.parametrize("cfg,steps", [(2, 200), (3, 100), (4, 40)])
+def test_full_size_fp32_parity(cfg, steps):
+    _case(f"full size config {cfg} fp32, {steps} steps")
+    sc = scenes.developed(scenes.config(cfg, storage="f32"))
+    lat, o = run_pair(sc, steps)
+    errs = field_errors(gpu_moments(lat), o.moments(), o.mask(), sc.B_ext)
+    print(cfg, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    for f, e in errs.items():
+        assert e < 1e-5, (f, e)
+
+
+# ---------------------------------------------------------------------------
+# state handling, reductions, failure detection
+# ---------------------------------------------------------------------------
+def test_save_load_roundtrip():
+    _case("save/load")
+    from paper_2506_00907_amd import lbm
+    sc = scenes.hartmann_couette(nx=8, ny=13, storage="f32")
+    lat = lbm.Lattice(sc)
+    lat.step(37)
+    blob = lat.save()
+    lat.step(20)
+    a = lat.read_populations(0).cpu().numpy()
+    lat.load(blob)
+    assert lat.time == 37
+    lat.step(20)
+    b = lat.read_populations(0).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_reduce_mass_and_residual():
+    _case("reduce")
+    sc = scenes.poiseuille(nx=8, ny=12, storage="f64")
+    lat, o = run_pair(sc, 50)
+    r0 = lat.reduce()
+    m = o.moments()
+    assert abs(r0[1] - m[..., 0].sum()) < 1e-10
+    assert r0[0] == -1.0
+    res = []
+    for _ in range(4):
+        lat.step(500)
+        res.append(lat.reduce()[0])
+    assert all(b < a for a, b in zip(res, res[1:])), res
+
+
+def test_nonfinite_state_is_reported():
+    _case("nan detection")
+    from paper_2506_00907_amd import _lib as L
+    from paper_2506_00907_amd import lbm
+    sc = scenes.poiseuille(nx=8, ny=6, storage="f32")
+    rho = np.ones((1, 6, 8))
+    rho[0, 3, 4] = np.nan
+    lat = lbm.Lattice(sc.with_(init_rho=rho))
+    lat.step(3)
+    with pytest.raises(L.LbmError):
+        lat.reduce()

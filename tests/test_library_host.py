@@ -1,0 +1,234 @@
+"""Host-side checks of liblbm (no GPU): the C ABI is complete, the library's
+own geometry / link builder agrees with the oracle's independent builder, and
+invalid inputs are rejected before any device work."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from paper_2506_00907_amd import _lib as L
+from paper_2506_00907_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    names = header_functions()
+    assert len(names) >= 18
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in L.SIGNATURES, n
+    assert set(L.SIGNATURES) == set(names)
+    assert b"gfx950" in lib.lbm_version()
+
+
+def _lat_map(name):
+    """library direction index -> oracle direction index, matched by e."""
+    code = lbm.LATTICES[name]
+    el, wl, c2l, oppl = lbm.lattice_table(code)
+    eo, wo, c2o, oppo = oracle.lattice_table(name)
+    m = np.zeros(len(wl), int)
+    for a in range(len(wl)):
+        hits = [b for b in range(len(wo)) if np.array_equal(eo[b], el[a])]
+        assert len(hits) == 1
+        m[a] = hits[0]
+    return m
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D2Q5", "D3Q7"])
+def test_lattice_tables_agree(name):
+    code = lbm.LATTICES[name]
+    el, wl, c2l, oppl = lbm.lattice_table(code)
+    eo, wo, c2o, oppo = oracle.lattice_table(name)
+    m = _lat_map(name)
+    assert c2l == c2o
+    assert np.allclose(wl, wo[m], rtol=0, atol=1e-17)
+    for a in range(len(wl)):
+        assert np.array_equal(el[oppl[a]], -el[a])
+
+
+SCENES = {
+    "poiseuille": lambda: scenes.poiseuille(nx=8, ny=6),
+    "reactive": lambda: scenes.reactive_channel(nx=14, ny=9, q=0.3, k_range=(1e-3, 1e-1)),
+    "reactive_q08": lambda: scenes.reactive_channel(nx=9, ny=6, q=0.8),
+    "hartmann": lambda: scenes.hartmann_couette(nx=5, ny=11, c_top=0.1),
+    "hartmann_cinf": lambda: scenes.hartmann_couette(nx=3, ny=7, c_top=math.inf, qb=1.0, qt=0.2),
+    "pipe_shercliff": lambda: scenes.mhd_pipe(nx=2, side=27, R=11.37, wall="shercliff"),
+    "pipe_ins3": lambda: scenes.mhd_pipe(nx=1, side=17, R=6.3, wall="insulating", ncomp=3),
+    "diffreact_full": lambda: scenes.diffusion_reaction(layout="full", W_nodes=8),
+    "duct_item": lambda: scenes.batch_items(3, side_lo=20, side_hi=30)[0].scene,
+    "pipe_item": lambda: scenes.batch_items(3, side_lo=20, side_hi=30)[1].scene,
+}
+
+
+def compare_link_tables(sc):
+    mask, ll = lbm.build_links(sc)
+    o = oracle.OracleSim(sc)
+    ol = o.links()
+    assert np.array_equal(mask, o.mask())
+    assert len(ll) == len(ol)
+    names = {0: sc.fluid_lattice, 1: sc.scalar_lattice, 2: sc.mag_lattice}
+    maps = {f: _lat_map(n) for f, n in names.items() if n}
+    okey = {}
+    for r in ol:
+        okey[(int(r["A"]), int(r["field"]), int(r["comp"]), int(r["dir"]))] = r
+    for r in ll:
+        f = int(r["field"])
+        k = (int(r["node"]), f, int(r["comp"]), int(maps[f][r["dir"]]))
+        o_ = okey[k]
+        assert int(r["kind"]) == int(o_["kind"])
+        assert abs(r["d"] - o_["d"]) < 1e-12
+        e_invalid = bool(r["flags"] & 2)
+        assert e_invalid == (o_["E"] < 0)
+        if not e_invalid:
+            assert int(r["enode"]) == int(o_["E"])
+        assert bool(r["flags"] & 1) == bool(o_["u_given"])
+        for fld in ("value", "a1", "a3"):
+            assert r[fld] == o_[fld]
+        assert abs(r["weight"] - o_["weight"]) < 1e-12 * max(1.0, abs(o_["weight"]))
+        assert np.array_equal(r["u_w"], o_["u_w"])
+    return ll
+
+
+@pytest.mark.parametrize("key", sorted(SCENES))
+def test_link_builder_matches_oracle(key):
+    ll = compare_link_tables(SCENES[key]())
+    assert len(ll) > 0
+
+
+def test_link_builder_ordering_and_counts():
+    sc = scenes.hartmann_couette(nx=6, ny=9)
+    mask, ll = lbm.build_links(sc)
+    keys = [(int(r["node"]), int(r["field"]), int(r["comp"]), int(r["dir"])) for r in ll]
+    assert keys == sorted(keys)
+    # flat walls: 3 f links and (1 per component) g links per wall node
+    assert len(ll) == 6 * 2 * (3 + 2 * 1)
+
+
+# ---------------------------------------------------------------------------
+# validation (no device work happens before it)
+# ---------------------------------------------------------------------------
+class _FakeCtx:
+    """A context over fake, aligned device addresses: lbm_create and the
+    validation paths of lbm_set_geometry / lbm_set_links never touch them."""
+
+    def __init__(self, sc, n_links):
+        self.p = lbm.params_from_scene(sc)
+        sizes = lbm.required_bytes(self.p, n_links)
+        ptrs = (C.c_void_p * L.LBM_NBUF)(*[(0x100000 * (i + 1)) if s else None for i, s in enumerate(sizes)])
+        self.ctx = C.c_void_p()
+        assert L.lib().lbm_create(C.byref(self.p), n_links, ptrs, None, C.byref(self.ctx)) == 0
+
+    def set_links(self, links):
+        a = np.ascontiguousarray(links)
+        return L.lib().lbm_set_links(self.ctx, a.ctypes.data_as(C.c_void_p), len(a))
+
+    def err(self):
+        return L.lib().lbm_last_error(self.ctx).decode()
+
+    def __del__(self):
+        L.lib().lbm_destroy(self.ctx)
+
+
+@pytest.fixture
+def small():
+    sc = scenes.reactive_channel(nx=10, ny=6, q=0.3)
+    mask, links = lbm.build_links(sc)
+    fc = _FakeCtx(sc, len(links) + 4)
+    assert L.lib().lbm_set_geometry(fc.ctx, mask.ctypes.data_as(C.c_void_p)) == 0
+    return sc, mask, links, fc
+
+
+def test_rejects_missing_link(small):
+    sc, mask, links, fc = small
+    assert fc.set_links(links[1:]) == -1
+    assert "no boundary link" in fc.err()
+
+
+def test_rejects_duplicate_link(small):
+    sc, mask, links, fc = small
+    assert fc.set_links(np.concatenate([links, links[:1]])) == -1
+    assert "duplicate" in fc.err()
+
+
+@pytest.mark.parametrize("field,value", [("d", 0.0), ("d", 1.5), ("d", float("nan")), ("kind", 3),
+                                         ("dir", 0), ("node", 10 ** 6), ("a1", float("inf"))])
+def test_rejects_bad_link_fields(small, field, value):
+    sc, mask, links, fc = small
+    bad = links.copy()
+    bad[0][field] = value
+    assert fc.set_links(bad) == -1
+
+
+def test_rejects_wrong_second_node(small):
+    sc, mask, links, fc = small
+    bad = links.copy()
+    i = int(np.nonzero((bad["flags"] & 2) == 0)[0][0])
+    bad[i]["enode"] = bad[i]["node"]
+    assert fc.set_links(bad) == -1
+    assert "enode" in fc.err()
+
+
+def test_rejects_known_population(small):
+    sc, mask, links, fc = small
+    bad = links.copy()
+    i = int(np.nonzero(bad["field"] == 0)[0][0])
+    bad[i]["dir"] = 0 if bad[i]["dir"] != 1 else 3
+    assert fc.set_links(bad) == -1
+
+
+def test_too_many_links_and_order(small):
+    sc, mask, links, fc = small
+    assert fc.set_links(np.concatenate([links] * 2)) == -2
+    fc2 = _FakeCtx(sc, len(links))
+    assert fc2.set_links(links) == -5        # geometry first
+    assert L.lib().lbm_step(fc2.ctx, 1) == -5  # init first
+
+
+@pytest.mark.parametrize("mut", [
+    dict(dim=4), dict(tau_f=0.5), dict(fluid=2), dict(storage=9), dict(mag_ncomp=2),
+    dict(n=(0, 4, 1)), dict(store_scale=(0.0, 1.0, 1.0)),
+])
+def test_rejects_bad_params(mut):
+    sc = scenes.poiseuille(nx=4, ny=4)
+    p = lbm.params_from_scene(sc)
+    for k, v in mut.items():
+        if isinstance(v, tuple):
+            for i, x in enumerate(v):
+                getattr(p, k)[i] = x
+        else:
+            setattr(p, k, v)
+    sizes = (C.c_size_t * L.LBM_NBUF)()
+    assert L.lib().lbm_required_bytes(C.byref(p), 10, sizes) == 0
+    ctx = C.c_void_p()
+    ptrs = (C.c_void_p * L.LBM_NBUF)(*[0x100000] * L.LBM_NBUF)
+    assert L.lib().lbm_create(C.byref(p), 10, ptrs, None, C.byref(ctx)) == -1
+
+
+def test_buffer_layout():
+    sc = scenes.hartmann_couette(nx=64, ny=30, storage="f16")
+    p = lbm.params_from_scene(sc)
+    sizes = lbm.required_bytes(p, 100)
+    plane = ((64 * 32 + 63) // 64) * 64
+    assert sizes[0] == ((19 * plane * 2 + 255) // 256) * 256      # populations, 2 bytes
+    assert sizes[5] == ((2 * 8 * plane * 4 + 255) // 256) * 256   # moment planes in FP32
+    assert all(s % 256 == 0 for s in sizes)
+
+
+def test_builder_rejects_uncovered_boundary():
+    sc = scenes.poiseuille(nx=4, ny=4)
+    sc.boundaries[1].f = None
+    with pytest.raises(L.LbmError):
+        lbm.build_links(sc)
