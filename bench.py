@@ -48,11 +48,13 @@ def make_scene(name: str, storage: str):
 
 
 def algorithmic_bytes(lat) -> dict:
-    """Bytes one step must move at least once, by the kernel's design:
-    populations read + written once per fluid node, one flag byte per padded
-    node, each link record, its two stashed values read and written, two link
-    offsets per link node, and one store + one load of the eight moments of
-    every node some link extrapolates from."""
+    """Bytes each kernel of a step must move at least once, by its design.
+
+    sweep (the fused stream-collide kernel): every population of every fluid
+    node read once and written once, one flag byte per padded node, and the
+    eight moments stored for each node a link extrapolates from.
+    links: per link its record, three population reads and one write, and
+    the eight moments of A and of E."""
     sc = lat.scene
     s = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[sc.storage]
     cb = 8 if sc.storage == "f64" else 4
@@ -65,13 +67,12 @@ def algorithmic_bytes(lat) -> dict:
     for k in range(3):
         padded *= sc.n[k] + (0 if sc.periodic[k] else 2)
     links = lat.links
-    link_nodes = np.unique(links["node"]).size
     e_valid = (links["flags"] & 2) == 0
     mom_nodes = np.unique(np.concatenate([links["node"], links["enode"][e_valid]])).size
-    per_node = 2 * QT * s
-    total = n_fluid * per_node + padded + len(links) * (rec + 4 * cb) + link_nodes * 8 + mom_nodes * 16 * cb
-    return dict(total=int(total), per_fluid_node_populations=per_node, fluid_nodes=n_fluid, links=int(len(links)),
-                link_nodes=int(link_nodes), moment_nodes=int(mom_nodes), planes=QT)
+    sweep = n_fluid * 2 * QT * s + padded + mom_nodes * 8 * cb
+    link = len(links) * (rec + 4 * s + 16 * cb)
+    return dict(sweep=int(sweep), links=int(link), per_fluid_node_populations=2 * QT * s,
+                fluid_nodes=n_fluid, n_links=int(len(links)), moment_nodes=int(mom_nodes), planes=QT)
 
 
 def time_gpu(lat, steps: int, warmup: int):
@@ -89,19 +90,10 @@ def time_gpu(lat, steps: int, warmup: int):
 
 
 def time_launches(lat, n: int = 200):
-    """Mean duration of single step launches: HIP events recorded right
-    before and after each launch on the stream the kernel runs on."""
-    import torch
-    stream = lat.stream
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
-    torch.cuda.synchronize()
-    for a, b in ev:
-        a.record(stream)
-        lat.step(1)
-        b.record(stream)
-    torch.cuda.synchronize()
-    d = np.array([a.elapsed_time(b) for a, b in ev])
-    return float(np.mean(d)), float(np.median(d))
+    """Mean durations (ms) of the boundary-link kernel and of the fused sweep
+    kernel: HIP events recorded around each launch on the stream the kernels
+    run on (lbm_step_timed)."""
+    return lat.step_timed(n)
 
 
 def cpu_baseline(sc, budget_s: float = 12.0):
@@ -145,8 +137,8 @@ def main():
     ab = algorithmic_bytes(lat)
     ms = time_gpu(lat, args.steps, args.warmup)
     mlups = ab["fluid_nodes"] * args.steps / (ms / 1e3) / 1e6
-    mean_ms, med_ms = time_launches(lat)
-    achieved = ab["total"] / (mean_ms / 1e3)
+    link_ms, sweep_ms = time_launches(lat)
+    achieved = ab["sweep"] / (sweep_ms / 1e3)
     res = lat.reduce()
     if not np.isfinite(res[1:6]).all():
         raise SystemExit("non-finite state")
@@ -164,11 +156,13 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32"}[args.storage],
         "data": "synthetic (seeded scene, SplitMix64)",
         "config": {"workload": desc, "storage": args.storage, "fluid_nodes": ab["fluid_nodes"],
-                   "links": ab["links"], "launch": "hipGraph of 64 fused steps, 256 threads/block"},
+                   "links": ab["n_links"],
+                   "launch": "hipGraph of 64 steps (link kernel + fused sweep each), 256 threads/block"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": None,
-                     "bytes_per_launch": ab["total"], "mean_launch_ms": mean_ms, "median_launch_ms": med_ms,
-                     "kernel": "k_step (fused stream-collide + links), both parities"},
+                     "kernel": "k_step (fused stream-collide sweep), both parities",
+                     "bytes_per_launch": ab["sweep"], "mean_launch_ms": sweep_ms,
+                     "link_kernel": {"bytes_per_launch": ab["links"], "mean_launch_ms": link_ms}},
     }
     if args.extra:
         extra = {}
@@ -178,10 +172,10 @@ def main():
             l2 = lbm.Lattice(s2)
             a2 = algorithmic_bytes(l2)
             m2 = time_gpu(l2, 1000, 100)
-            mean2, _ = time_launches(l2, 50)
+            lk2, sw2 = time_launches(l2, 50)
             extra[f"{w}_{st}"] = dict(mlups=round(a2["fluid_nodes"] * 1000 / (m2 / 1e3) / 1e6, 1),
-                                      roofline_frac=a2["total"] / (mean2 / 1e3) / HBM_PEAK,
-                                      bytes_per_launch=a2["total"], mean_launch_ms=mean2)
+                                      sweep_frac=a2["sweep"] / (sw2 / 1e3) / HBM_PEAK,
+                                      sweep_bytes=a2["sweep"], sweep_ms=sw2, link_ms=lk2)
             del l2
             torch.cuda.empty_cache()
         out["extra"] = extra

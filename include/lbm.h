@@ -164,9 +164,10 @@ lbm_status lbm_build_links(const lbm_params* p, const lbm_boundary* bnds, int32_
 
 /* Sizes (bytes) of the LBM_NBUF device buffers a context needs for n_links
  * links; returns their sum, 0 on invalid parameters.  Buffer roles:
- *  0 populations (AA layout, in place), 1 node flags, 2 link offsets per node,
- *  3 link records, 4 per-link post-collision stash, 5 moment planes (two
- *  parities), 6 residual snapshot and FP64 accumulators, 7 reserved (may be 0). */
+ *  0 populations (AA layout, in place; boundary-link values are written into
+ *    the slots the next sweep gathers them from), 1 node flags, 2 link
+ *  records, 3 moment planes of the link nodes (two parities), 4 residual
+ *  snapshot and FP64 accumulators; 5-7 are unused (size 0, may be NULL). */
 size_t lbm_required_bytes(const lbm_params* p, size_t n_links, size_t sizes_out[LBM_NBUF]);
 
 /* Creates a context over caller-allocated device buffers dev_bufs[i] of at
@@ -193,6 +194,13 @@ lbm_status lbm_init(lbm_ctx* ctx, const double* dev_rho, const double* dev_u, co
 /* Advances n >= 0 steps (asynchronous). */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
+/* As lbm_step, with HIP events recorded on the context's stream around the
+ * two launches of every step (the boundary-link kernel, then the fused
+ * sweep); synchronises the stream and returns their mean durations in ms in
+ * ms_out[0] (links; 0 when a step has no link launch) and ms_out[1]
+ * (sweep).  Steps run as single launches (no graph replay). */
+lbm_status lbm_step_timed(lbm_ctx* ctx, int64_t n, float ms_out[2]);
+
 /* Moments at the current time into dev_out, SoA [8][N] of rho, u_x, u_y, u_z,
  * C, B_x, B_y, B_z (0 at solid nodes); out_type LBM_F64 or LBM_F32. */
 lbm_status lbm_read_moments(lbm_ctx* ctx, void* dev_out, int32_t out_type);
@@ -212,7 +220,7 @@ lbm_status lbm_read_populations(lbm_ctx* ctx, int32_t field, double* dev_out);
 lbm_status lbm_reduce(lbm_ctx* ctx, double out[8]);
 
 /* Checkpoint: lbm_state_bytes() bytes of host memory hold the populations,
- * stash, moment planes and time.  lbm_save synchronises the stream. */
+ * moment planes and time.  lbm_save synchronises the stream. */
 size_t lbm_state_bytes(const lbm_ctx* ctx);
 lbm_status lbm_save(lbm_ctx* ctx, void* host);
 lbm_status lbm_load(lbm_ctx* ctx, const void* host);

@@ -65,6 +65,7 @@ SIGNATURES = {
     "lbm_set_links": (C.c_int, [_VP, _VP, C.c_size_t]),
     "lbm_init": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "lbm_step": (C.c_int, [_VP, C.c_int64]),
+    "lbm_step_timed": (C.c_int, [_VP, C.c_int64, C.POINTER(C.c_float)]),
     "lbm_read_moments": (C.c_int, [_VP, _VP, C.c_int32]),
     "lbm_read_populations": (C.c_int, [_VP, C.c_int32, _VP]),
     "lbm_reduce": (C.c_int, [_VP, C.POINTER(C.c_double)]),

@@ -17,12 +17,14 @@
 //
 // Boundary links.  The unknown population f_alpha(A, t+1) needs, from time t,
 // the post-collision values f*_alpha'(A), f*_alpha(A), f*_alpha'(E) and the
-// moments at A and E (Eq. 13).  f*_alpha'(E) is exactly what A receives along
-// alpha' by ordinary streaming, so it is already in a register.  The two
-// values of A itself are written by A after its collision into a per-link
-// stash and read back by A on the next step (A owns them, no race).  Moments
-// of the link nodes are written to one of two moment planes by parity, so the
-// plane read during a step is never written during it.
+// moments at A and E (Eq. 13).  After a sweep all three values sit in the
+// population array at slots fixed by the parity (f*_alpha'(E) is what A
+// receives along alpha' by streaming), and the slot the next sweep gathers
+// f_alpha(A) from holds nothing else (a halo or solid slot, or A's own slot
+// that no node streams into).  A short kernel, one thread per link, therefore
+// reads its inputs from the array and writes the link value straight into
+// that slot; the fused sweep needs no link code at all.  Moments of the
+// link nodes go to one of two moment planes by parity.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -123,23 +125,23 @@ struct F32S { using T = float; using R = float; };
 struct F16S { using T = uint16_t; using R = float; };
 struct BF16S { using T = uint16_t; using R = float; };
 
-template <class SF> __device__ __forceinline__ typename SF::R ld(const typename SF::T* p, size_t i);
-template <> __device__ __forceinline__ double ld<F64S>(const double* p, size_t i) { return p[i]; }
-template <> __device__ __forceinline__ float ld<F32S>(const float* p, size_t i) { return p[i]; }
-template <> __device__ __forceinline__ float ld<F16S>(const uint16_t* p, size_t i) {
+template <class SF> __device__ __forceinline__ typename SF::R ld(const typename SF::T* p, uint32_t i);
+template <> __device__ __forceinline__ double ld<F64S>(const double* p, uint32_t i) { return p[i]; }
+template <> __device__ __forceinline__ float ld<F32S>(const float* p, uint32_t i) { return p[i]; }
+template <> __device__ __forceinline__ float ld<F16S>(const uint16_t* p, uint32_t i) {
     return (float)__builtin_bit_cast(_Float16, p[i]);
 }
-template <> __device__ __forceinline__ float ld<BF16S>(const uint16_t* p, size_t i) {
+template <> __device__ __forceinline__ float ld<BF16S>(const uint16_t* p, uint32_t i) {
     return __builtin_bit_cast(float, (uint32_t)p[i] << 16);
 }
 
-template <class SF> __device__ __forceinline__ void st(typename SF::T* p, size_t i, typename SF::R v);
-template <> __device__ __forceinline__ void st<F64S>(double* p, size_t i, double v) { p[i] = v; }
-template <> __device__ __forceinline__ void st<F32S>(float* p, size_t i, float v) { p[i] = v; }
-template <> __device__ __forceinline__ void st<F16S>(uint16_t* p, size_t i, float v) {
+template <class SF> __device__ __forceinline__ void st(typename SF::T* p, uint32_t i, typename SF::R v);
+template <> __device__ __forceinline__ void st<F64S>(double* p, uint32_t i, double v) { p[i] = v; }
+template <> __device__ __forceinline__ void st<F32S>(float* p, uint32_t i, float v) { p[i] = v; }
+template <> __device__ __forceinline__ void st<F16S>(uint16_t* p, uint32_t i, float v) {
     p[i] = __builtin_bit_cast(uint16_t, (_Float16)v);  // round to nearest even
 }
-template <> __device__ __forceinline__ void st<BF16S>(uint16_t* p, size_t i, float v) {
+template <> __device__ __forceinline__ void st<BF16S>(uint16_t* p, uint32_t i, float v) {
     // round to nearest even on the upper 16 bits (finite inputs)
     uint32_t b = __builtin_bit_cast(uint32_t, v);
     b += 0x7FFFu + ((b >> 16) & 1u);
@@ -164,6 +166,7 @@ struct Cfg {
     static constexpr int QT = QF + QH + NCOMP * QG;
     static constexpr int H0 = QF;          // first h plane
     static constexpr int G0 = QF + QH;     // first g plane
+    static constexpr bool SCALED = sizeof(T) == 2;  // 16-bit storage carries a power-of-two scale
 };
 
 // physical parameters in the compute type
@@ -173,7 +176,6 @@ struct Phys {
     R rho0, C0, inv_mu, grad_c;    // grad_c = 1/(tau_m c_g^2)
     R Bext[3], acc[3];
     R sc[3], isc[3];               // storage scale and inverse (f, h, g)
-    int comp[3];
 };
 
 template <class R>
@@ -192,9 +194,25 @@ __host__ Phys<R> make_phys(const KArgs& a, double cg2) {
         p.acc[k] = (R)a.accel[k];
         p.sc[k] = (R)a.scale[k];
         p.isc[k] = (R)(1.0 / a.scale[k]);
-        p.comp[k] = a.comp[k];
     }
     return p;
+}
+
+// division of a 32-bit index by a fixed divisor with a multiply-high
+// (round-up reciprocal, valid for every 32-bit dividend)
+struct FastDiv {
+    uint32_t m, s1, s2;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+    if (d <= 1) return FastDiv{0u, 0u, 0u};
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    const uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+    return FastDiv{(uint32_t)m, 1u, l - 1};
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+    const uint32_t t = __umulhi(n, f.m);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
 }
 
 // Grid geometry of one launch.
@@ -202,6 +220,7 @@ struct Geo {
     int NX, NY, NZ;
     int hx, hy, hz, n0, n1, n2;
     uint32_t plane;
+    FastDiv dx, dy;
 };
 
 // logical workgroup index: consecutive blocks are dispatched round-robin over
@@ -222,8 +241,8 @@ struct Mom {
 // ---------------------------------------------------------------------------
 // boundary link value (deviation form; Sections 3-4)
 // ---------------------------------------------------------------------------
-// x_a:   post-collision deviation of A along alpha (stash)
-// x_apA: post-collision deviation of A along alpha' (stash)
+// x_a:   post-collision deviation of A along alpha
+// x_apA: post-collision deviation of A along alpha'
 // x_apE: post-collision deviation of E along alpha' (streamed value)
 // mA, mE: moments at A and E at the previous time (deviations + u)
 template <class R>
@@ -289,43 +308,103 @@ __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R
     }
 }
 
+// One thread per link: the unknown population entering A along alpha at time
+// t (parity ODD), from the state after step t-1, written into the slot the
+// sweep of step t gathers it from.
+//   t odd  (t-1 even: x*_i(x) sits at slot opp(i) of x):
+//     x*_alpha(A) = [alpha', A], x*_alpha'(A) = [alpha, A],
+//     streamed x*_alpha'(E) = [alpha, E]; target [alpha', B]
+//   t even (t-1 odd: x*_i(x) sits at slot i of x + e_i):
+//     x*_alpha(A) = [alpha, E], x*_alpha'(A) = [alpha', B],
+//     streamed x*_alpha'(E) = [alpha', A]; target [alpha, A]
+// with E = A + e_alpha and B = A - e_alpha.  No other link of the launch
+// reads a target slot, so the kernel is race-free.
+template <class C, int ODD>
+__global__ __launch_bounds__(256) void k_links(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
+                                               const DevLink<typename C::R>* __restrict__ links,
+                                               const typename C::R* __restrict__ M, uint32_t nlinks) {
+    using R = typename C::R;
+    using SF = typename C::S;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nlinks) return;
+    const DevLink<R> L = links[k];
+    const size_t PL = G.plane;
+    typename C::T* Sa = S + (size_t)L.pa * PL;
+    typename C::T* Sp = S + (size_t)L.pap * PL;
+    R x_a, x_apA, xs;
+    if (ODD) {
+        x_a = ld<SF>(Sp, L.A);
+        x_apA = ld<SF>(Sa, L.A);
+        xs = (L.flags & 2) ? x_apA : ld<SF>(Sa, L.E);
+    } else {
+        x_a = ld<SF>(Sa, L.E);
+        x_apA = ld<SF>(Sp, L.B);
+        xs = (L.flags & 2) ? x_apA : ld<SF>(Sp, L.A);
+    }
+    R isc = (R)1, sc = (R)1;
+    if (C::SCALED) {
+        isc = L.field == 0 ? P.isc[0] : (L.field == 1 ? P.isc[1] : P.isc[2]);
+        sc = L.field == 0 ? P.sc[0] : (L.field == 1 ? P.sc[1] : P.sc[2]);
+        x_a *= isc;
+        x_apA *= isc;
+        xs *= isc;
+    }
+    const R* Mp = M + (size_t)(ODD ^ 1) * 8 * PL;  // moments of the previous time
+    R mA[8], mE[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        mA[q] = Mp[(size_t)q * PL + L.A];
+        mE[q] = Mp[(size_t)q * PL + L.mE];
+    }
+    const int e2 = L.ex * L.ex + L.ey * L.ey + L.ez * L.ez;
+    R w, c2;
+    if (L.field == 0) {
+        w = (R)(C::QF == 9 ? (e2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0) : (e2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0));
+        c2 = (R)(1.0 / 3.0);
+    } else {
+        w = (R)0.125;
+        c2 = (R)0.25;
+    }
+    const R v = link_value<R>(L, P, x_a, x_apA, xs, mA, mE, w, c2);
+    if (ODD) st<SF>(Sp, L.B, C::SCALED ? v * sc : v);
+    else st<SF>(Sa, L.A, C::SCALED ? v * sc : v);
+}
+
 // ---------------------------------------------------------------------------
-// the node update
+// the fused node update
 // ---------------------------------------------------------------------------
-// MODE 0: full step (gather, links, moments, collide, stash, scatter)
-// MODE 1: observe (gather, links, moments) -> caller handles the output
-template <class C, int ODD, int MODE>
+template <class C>
 struct NodeRes {
-    typename C::R x[C::QT];  // populations at the current time (deviations)
+    typename C::R x[C::QT];  // populations (deviations), post-collision after MODE 0
     Mom<typename C::R> m;
 };
 
+// MODE 0: full step (gather, moments, collide, scatter)
+// MODE 1: observe (gather, moments)
 template <class C, int ODD, int MODE>
 __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C::R>& P,
                                             typename C::T* __restrict__ S,
                                             const uint8_t* __restrict__ flags,
-                                            const uint32_t* __restrict__ lstart,
-                                            const DevLink<typename C::R>* __restrict__ links,
-                                            typename C::R* __restrict__ stash,
-                                            typename C::R* __restrict__ M, int parity,
-                                            int links_ready, uint32_t n,
-                                            NodeRes<C, ODD, MODE>& res) {
+                                            typename C::R* __restrict__ M, uint32_t n,
+                                            NodeRes<C>& res) {
     using R = typename C::R;
+    using SF = typename C::S;
     using FL = typename C::FL;
     using HL = typename C::HL;
     using GL = typename C::GL;
     constexpr int QF = C::QF, QH = C::QH, QG = C::QG, NCP = C::NCOMP, QT = C::QT;
     const uint8_t fl = flags[n];
     if (!(fl & NF_FLUID)) return false;
-    const size_t PL = G.plane;
+    const uint32_t PL = G.plane;
 
     // coordinates and wrapped neighbour offsets (fluid nodes never touch a
     // non-periodic edge of the padded grid, so wrapping only ever applies on
     // periodic axes)
-    const int x = (int)(n % (uint32_t)G.NX);
-    const uint32_t t1 = n / (uint32_t)G.NX;
-    const int y = (int)(t1 % (uint32_t)G.NY);
-    const int z = (int)(t1 / (uint32_t)G.NY);
+    const uint32_t t1 = fdiv(n, G.dx);
+    const int x = (int)(n - t1 * (uint32_t)G.NX);
+    const uint32_t zz = fdiv(t1, G.dy);
+    const int y = (int)(t1 - zz * (uint32_t)G.NY);
+    const int z = (int)zz;
     const int sx = G.NX * G.NY;
     const int oxm = x == 0 ? G.NX - 1 : -1;
     const int oxp = x == G.NX - 1 ? -(G.NX - 1) : 1;
@@ -333,71 +412,35 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
     const int oyp = y == G.NY - 1 ? -(G.NY - 1) * G.NX : G.NX;
     const int ozm = z == 0 ? (G.NZ - 1) * sx : -sx;
     const int ozp = z == G.NZ - 1 ? -(G.NZ - 1) * sx : sx;
-    auto off = [&](int ex, int ey, int ez) -> int {
-        return (ex > 0 ? oxp : (ex < 0 ? oxm : 0)) + (ey > 0 ? oyp : (ey < 0 ? oym : 0)) +
-               (ez > 0 ? ozp : (ez < 0 ? ozm : 0));
+    auto nb = [&](int ex, int ey, int ez) -> uint32_t {
+        return (uint32_t)((int)n + (ex > 0 ? oxp : (ex < 0 ? oxm : 0)) + (ey > 0 ? oyp : (ey < 0 ? oym : 0)) +
+                          (ez > 0 ? ozp : (ez < 0 ? ozm : 0)));
     };
+    // plane p as a wave-uniform base pointer; per-lane 32-bit element index
+    auto plane = [&](int p) -> typename C::T* { return S + (size_t)p * PL; };
 
     R* x_ = res.x;
     // ---- gather (streaming) ----
 #pragma unroll
     for (int i = 0; i < QF; ++i) {
-        size_t idx = ODD ? (size_t)FL::opp(i) * PL + (size_t)((int)n + off(-FL::ex(i), -FL::ey(i), -FL::ez(i)))
-                         : (size_t)i * PL + n;
-        x_[i] = ld<typename C::S>(S, idx) * P.isc[0];
+        R v = ODD ? ld<SF>(plane(FL::opp(i)), nb(-FL::ex(i), -FL::ey(i), -FL::ez(i))) : ld<SF>(plane(i), n);
+        x_[i] = C::SCALED ? v * P.isc[0] : v;
     }
 #pragma unroll
     for (int i = 0; i < QH; ++i) {
-        size_t idx = ODD ? (size_t)(C::H0 + HL::opp(i)) * PL + (size_t)((int)n + off(-HL::ex(i), -HL::ey(i), -HL::ez(i)))
-                         : (size_t)(C::H0 + i) * PL + n;
-        x_[C::H0 + i] = ld<typename C::S>(S, idx) * P.isc[1];
+        R v = ODD ? ld<SF>(plane(C::H0 + HL::opp(i)), nb(-HL::ex(i), -HL::ey(i), -HL::ez(i)))
+                  : ld<SF>(plane(C::H0 + i), n);
+        x_[C::H0 + i] = C::SCALED ? v * P.isc[1] : v;
     }
 #pragma unroll
     for (int c = 0; c < NCP; ++c)
 #pragma unroll
         for (int i = 0; i < QG; ++i) {
             const int b = C::G0 + c * QG;
-            size_t idx = ODD ? (size_t)(b + GL::opp(i)) * PL + (size_t)((int)n + off(-GL::ex(i), -GL::ey(i), -GL::ez(i)))
-                             : (size_t)(b + i) * PL + n;
-            x_[b + i] = ld<typename C::S>(S, idx) * P.isc[2];
+            R v = ODD ? ld<SF>(plane(b + GL::opp(i)), nb(-GL::ex(i), -GL::ey(i), -GL::ez(i)))
+                      : ld<SF>(plane(b + i), n);
+            x_[b + i] = C::SCALED ? v * P.isc[2] : v;
         }
-
-    // ---- boundary links ----
-    uint32_t k0 = 0, k1 = 0;
-    if (fl & NF_LINKS) {
-        k0 = lstart[n];
-        k1 = lstart[n + 1];
-    }
-    if (links_ready && k1 > k0) {
-        const R* Mp = M + (size_t)(parity ^ 1) * 8 * PL;  // moments of the previous time
-        R mA[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) mA[q] = Mp[(size_t)q * PL + n];
-        for (uint32_t k = k0; k < k1; ++k) {
-            const DevLink<R> L = links[k];
-            const R s0 = stash[2 * (size_t)k], s1 = stash[2 * (size_t)k + 1];
-            R xs = s0;
-            if (!(L.flags & 2)) {
-#pragma unroll
-                for (int q = 0; q < QT; ++q) xs = (q == (int)L.pap) ? x_[q] : xs;
-            }
-            R mE[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) mE[q] = Mp[(size_t)q * PL + L.E];
-            const int e2 = L.ex * L.ex + L.ey * L.ey + L.ez * L.ez;
-            R w, c2;
-            if (L.field == 0) {
-                w = (R)(QF == 9 ? (e2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0) : (e2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0));
-                c2 = (R)(1.0 / 3.0);
-            } else {
-                w = (R)0.125;
-                c2 = (R)0.25;
-            }
-            const R v = link_value<R>(L, P, s1, s0, xs, mA, mE, w, c2);
-#pragma unroll
-            for (int q = 0; q < QT; ++q) x_[q] = (q == (int)L.pa) ? v : x_[q];
-        }
-    }
 
     // ---- moments ----
     Mom<R>& m = res.m;
@@ -405,9 +448,9 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
 #pragma unroll
     for (int i = 0; i < QF; ++i) {
         drho += x_[i];
-        jx += (R)FL::ex(i) * x_[i];
-        jy += (R)FL::ey(i) * x_[i];
-        jz += (R)FL::ez(i) * x_[i];
+        if (FL::ex(i)) jx += (R)FL::ex(i) * x_[i];
+        if (FL::ey(i)) jy += (R)FL::ey(i) * x_[i];
+        if (FL::ez(i)) jz += (R)FL::ez(i) * x_[i];
     }
     const R rho = P.rho0 + drho;
     const R irho = (R)1 / rho;
@@ -423,9 +466,9 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
         for (int i = 0; i < QG; ++i) {
             const R g = x_[C::G0 + c * QG + i];
             s += g;
-            l0 += (R)GL::ex(i) * g;
-            l1 += (R)GL::ey(i) * g;
-            l2 += (R)GL::ez(i) * g;
+            if (GL::ex(i)) l0 += (R)GL::ex(i) * g;
+            if (GL::ey(i)) l1 += (R)GL::ey(i) * g;
+            if (GL::ez(i)) l2 += (R)GL::ez(i) * g;
         }
         // evolved component slot c is Cartesian axis c
         dB[c] = s;
@@ -468,87 +511,101 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
 
     // moments of link nodes for the next step's extrapolations (Eq. 13)
     if (fl & NF_MOM) {
-        R* Mc = M + (size_t)parity * 8 * PL;
-        Mc[0 * PL + n] = drho;
-        Mc[1 * PL + n] = ux;
-        Mc[2 * PL + n] = uy;
-        Mc[3 * PL + n] = uz;
-        Mc[4 * PL + n] = dC;
-        Mc[5 * PL + n] = dB[0];
-        Mc[6 * PL + n] = dB[1];
-        Mc[7 * PL + n] = dB[2];
+        R* Mc = M + (size_t)ODD * 8 * PL;
+        Mc[0 * (size_t)PL + n] = drho;
+        Mc[1 * (size_t)PL + n] = ux;
+        Mc[2 * (size_t)PL + n] = uy;
+        Mc[3 * (size_t)PL + n] = uz;
+        Mc[4 * (size_t)PL + n] = dC;
+        Mc[5 * (size_t)PL + n] = dB[0];
+        Mc[6 * (size_t)PL + n] = dB[1];
+        Mc[7 * (size_t)PL + n] = dB[2];
     }
 
-    // ---- collision (deviation form) ----
+    // ---- collision (deviation form), opposite directions in pairs: the
+    // equilibrium and the Guo source split into a part even in e (shared by
+    // the pair) and a part odd in e (opposite signs) ----
     const R usq = ux * ux + uy * uy + uz * uz;
-    constexpr R cs2 = (R)(1.0 / 3.0);
-    constexpr R ics2 = (R)3.0;
-#pragma unroll
-    for (int i = 0; i < QF; ++i) {
-        const R ex = (R)FL::ex(i), ey = (R)FL::ey(i), ez = (R)FL::ez(i);
-        const R w = (R)FL::w(i);
-        const R eu = ex * ux + ey * uy + ez * uz;
-        const R feq = w * (drho + rho * (eu * ics2 + (R)0.5 * eu * eu * ics2 * ics2 - (R)0.5 * usq * ics2));
-        const R eF = ex * F[0] + ey * F[1] + ez * F[2];
-        const R uF = ux * F[0] + uy * F[1] + uz * F[2];
-        const R src = P.guo * w * ((eF - uF) * ics2 + eu * eF * ics2 * ics2);
-        x_[i] = x_[i] + P.omf * (feq - x_[i]) + src;
+    const R uF = ux * F[0] + uy * F[1] + uz * F[2];
+    const R omf = P.omf, guo = P.guo;
+    {
+        const R w0 = (R)FL::w(0);
+        const R feq = w0 * (drho - (R)1.5 * rho * usq);
+        x_[0] += omf * (feq - x_[0]) - (R)3 * guo * w0 * uF;
     }
-    (void)cs2;
 #pragma unroll
-    for (int i = 0; i < QH; ++i) {
-        const R eu = (R)HL::ex(i) * ux + (R)HL::ey(i) * uy + (R)HL::ez(i) * uz;
-        const R heq = (R)HL::w(i) * (dC + (P.C0 + dC) * eu * (R)4.0);
-        x_[C::H0 + i] += P.omc * (heq - x_[C::H0 + i]);
+    for (int a = 1; a < QF; ++a) {
+        if (FL::opp(a) < a) continue;
+        const int b = FL::opp(a);
+        const R ex = (R)FL::ex(a), ey = (R)FL::ey(a), ez = (R)FL::ez(a);
+        const R w = (R)FL::w(a);
+        const R eu = ex * ux + ey * uy + ez * uz;
+        const R eF = ex * F[0] + ey * F[1] + ez * F[2];
+        const R ev = w * (drho + rho * ((R)4.5 * eu * eu - (R)1.5 * usq)) ;
+        const R od = (R)3 * w * rho * eu;
+        const R evs = guo * w * ((R)9 * eu * eF - (R)3 * uF);
+        const R ods = (R)3 * guo * w * eF;
+        const R xa = x_[a], xb = x_[b];
+        x_[a] = xa + omf * (ev + od - xa) + (evs + ods);
+        x_[b] = xb + omf * (ev - od - xb) + (evs - ods);
+    }
+    if (QH > 0) {
+        const R Cc = P.C0 + dC, omc = P.omc;
+        x_[C::H0] += omc * ((R)HL::w(0) * dC - x_[C::H0]);
+#pragma unroll
+        for (int a = 1; a < QH; ++a) {
+            if (HL::opp(a) < a) continue;
+            const int b = HL::opp(a);
+            const R w = (R)HL::w(a);
+            const R eu = (R)HL::ex(a) * ux + (R)HL::ey(a) * uy + (R)HL::ez(a) * uz;
+            const R ev = w * dC, od = (R)4 * w * Cc * eu;
+            const R xa = x_[C::H0 + a], xb = x_[C::H0 + b];
+            x_[C::H0 + a] = xa + omc * (ev + od - xa);
+            x_[C::H0 + b] = xb + omc * (ev - od - xb);
+        }
     }
 #pragma unroll
     for (int c = 0; c < NCP; ++c) {
         const R Bk = B[c];
         const R uk = c == 0 ? ux : (c == 1 ? uy : uz);
+        const R omm = P.omm;
+        const int p0 = C::G0 + c * QG;
+        x_[p0] += omm * ((R)GL::w(0) * dB[c] - x_[p0]);
 #pragma unroll
-        for (int i = 0; i < QG; ++i) {
-            const R ex = (R)GL::ex(i), ey = (R)GL::ey(i), ez = (R)GL::ez(i);
+        for (int a = 1; a < QG; ++a) {
+            if (GL::opp(a) < a) continue;
+            const int b = GL::opp(a);
+            const R ex = (R)GL::ex(a), ey = (R)GL::ey(a), ez = (R)GL::ez(a);
+            const R w = (R)GL::w(a);
             const R s = (ex * ux + ey * uy + ez * uz) * Bk - (ex * B[0] + ey * B[1] + ez * B[2]) * uk;
-            const R geq = (R)GL::w(i) * (dB[c] + s * (R)4.0);
-            const int p = C::G0 + c * QG + i;
-            x_[p] += P.omm * (geq - x_[p]);
+            const R ev = w * dB[c], od = (R)4 * w * s;
+            const R xa = x_[p0 + a], xb = x_[p0 + b];
+            x_[p0 + a] = xa + omm * (ev + od - xa);
+            x_[p0 + b] = xb + omm * (ev - od - xb);
         }
-    }
-
-    // ---- stash the two post-collision values each link of A needs next step ----
-    for (uint32_t k = k0; k < k1; ++k) {
-        const uint8_t pa = links[k].pa, pap = links[k].pap;
-        R a0 = 0, a1 = 0;
-#pragma unroll
-        for (int q = 0; q < QT; ++q) {
-            a0 = (q == (int)pap) ? x_[q] : a0;
-            a1 = (q == (int)pa) ? x_[q] : a1;
-        }
-        stash[2 * (size_t)k] = a0;
-        stash[2 * (size_t)k + 1] = a1;
     }
 
     // ---- scatter (streaming) ----
 #pragma unroll
     for (int i = 0; i < QF; ++i) {
-        size_t idx = ODD ? (size_t)i * PL + (size_t)((int)n + off(FL::ex(i), FL::ey(i), FL::ez(i)))
-                         : (size_t)FL::opp(i) * PL + n;
-        st<typename C::S>(S, idx, x_[i] * P.sc[0]);
+        const R v = C::SCALED ? x_[i] * P.sc[0] : x_[i];
+        if (ODD) st<SF>(plane(i), nb(FL::ex(i), FL::ey(i), FL::ez(i)), v);
+        else st<SF>(plane(FL::opp(i)), n, v);
     }
 #pragma unroll
     for (int i = 0; i < QH; ++i) {
-        size_t idx = ODD ? (size_t)(C::H0 + i) * PL + (size_t)((int)n + off(HL::ex(i), HL::ey(i), HL::ez(i)))
-                         : (size_t)(C::H0 + HL::opp(i)) * PL + n;
-        st<typename C::S>(S, idx, x_[C::H0 + i] * P.sc[1]);
+        const R v = C::SCALED ? x_[C::H0 + i] * P.sc[1] : x_[C::H0 + i];
+        if (ODD) st<SF>(plane(C::H0 + i), nb(HL::ex(i), HL::ey(i), HL::ez(i)), v);
+        else st<SF>(plane(C::H0 + HL::opp(i)), n, v);
     }
 #pragma unroll
     for (int c = 0; c < NCP; ++c)
 #pragma unroll
         for (int i = 0; i < QG; ++i) {
             const int b = C::G0 + c * QG;
-            size_t idx = ODD ? (size_t)(b + i) * PL + (size_t)((int)n + off(GL::ex(i), GL::ey(i), GL::ez(i)))
-                             : (size_t)(b + GL::opp(i)) * PL + n;
-            st<typename C::S>(S, idx, x_[b + i] * P.sc[2]);
+            const R v = C::SCALED ? x_[b + i] * P.sc[2] : x_[b + i];
+            if (ODD) st<SF>(plane(b + i), nb(GL::ex(i), GL::ey(i), GL::ez(i)), v);
+            else st<SF>(plane(b + GL::opp(i)), n, v);
         }
     return true;
 }
@@ -559,18 +616,14 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
 template <class C, int ODD>
 __global__ __launch_bounds__(256) void k_step(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
                                               const uint8_t* __restrict__ flags,
-                                              const uint32_t* __restrict__ lstart,
-                                              const DevLink<typename C::R>* __restrict__ links,
-                                              typename C::R* __restrict__ stash,
-                                              typename C::R* __restrict__ M, int links_ready, uint32_t nnodes) {
+                                              typename C::R* __restrict__ M, uint32_t nnodes) {
     const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t n = b * blockDim.x + threadIdx.x;
     if (n >= nnodes) return;
-    NodeRes<C, ODD, 0> r;
-    node_update<C, ODD, 0>(G, P, S, flags, lstart, links, stash, M, ODD, links_ready, n, r);
+    NodeRes<C> r;
+    node_update<C, ODD, 0>(G, P, S, flags, M, n, r);
 }
 
-template <class R>
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     return v;
@@ -580,18 +633,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <class C, int ODD>
 __global__ __launch_bounds__(256) void k_observe(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
                                                  const uint8_t* __restrict__ flags,
-                                                 const uint32_t* __restrict__ lstart,
-                                                 const DevLink<typename C::R>* __restrict__ links,
-                                                 typename C::R* __restrict__ stash,
-                                                 typename C::R* __restrict__ M, int links_ready,
+                                                 typename C::R* __restrict__ M,
                                                  uint32_t nnodes, int mode, int field, void* out,
                                                  int out_f64, double* acc, typename C::R* snap,
                                                  int snap_valid) {
     using R = typename C::R;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
-    NodeRes<C, ODD, 1> r;
+    NodeRes<C> r;
     bool fluid = false;
-    if (n < nnodes) fluid = node_update<C, ODD, 1>(G, P, S, flags, lstart, links, stash, M, ODD, links_ready, n, r);
+    if (n < nnodes) fluid = node_update<C, ODD, 1>(G, P, S, flags, M, n, r);
     // domain index of this node (if inside the domain)
     int dom = -1;
     if (n < nnodes) {
@@ -652,18 +702,19 @@ __global__ __launch_bounds__(256) void k_observe(Geo G, Phys<typename C::R> P, t
             const double s = snap_valid ? (double)snap[(size_t)q * PL + n] : 0.0;
             const double dd = phi[q] - s;
             const int fld = q < 3 ? 0 : (q == 3 ? 1 : 2);
-            v[5 + fld] += dd * dd;     // 5..7: |phi - snap|^2 per field
+            v[5 + fld] += dd * dd;          // 5..7: |phi - snap|^2 per field
             v[8 + fld] += phi[q] * phi[q];  // 8..10: |phi|^2 per field
             snap[(size_t)q * PL + n] = (R)phi[q];
         }
-        bool bad = !(v[0] == v[0]) || !(v[1] == v[1]) || !(phi[0] == phi[0]) || !(phi[4] == phi[4]);
-        for (int q = 0; q < 5; ++q) bad = bad || (v[q] - v[q] != 0.0);
+        bool bad = false;
+        for (int q = 0; q < 5; ++q) bad = bad || !(v[q] - v[q] == 0.0);
+        for (int q = 0; q < 7; ++q) bad = bad || !(phi[q] - phi[q] == 0.0);
         v[11] = bad ? 1.0 : 0.0;
     }
     __shared__ double red[NACC][4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int q = 0; q < 12; ++q) {
-        double s = wave_sum<R>(v[q]);
+        double s = wave_sum(v[q]);
         if (lane == 0) red[q][wv] = s;
     }
     __syncthreads();
@@ -713,13 +764,13 @@ __global__ __launch_bounds__(256) void k_init(Geo G, Phys<typename C::R> P, type
     for (int i = 0; i < C::QF; ++i) {
         const R eu = (R)FL::ex(i) * u[0] + (R)FL::ey(i) * u[1] + (R)FL::ez(i) * u[2];
         const R v = (R)FL::w(i) * (drho + rho * ((R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * usq));
-        st<typename C::S>(S, (size_t)i * PL + n, v * P.sc[0]);
+        st<typename C::S>(S + (size_t)i * PL, (uint32_t)n, C::SCALED ? v * P.sc[0] : v);
     }
 #pragma unroll
     for (int i = 0; i < C::QH; ++i) {
         const R eu = (R)HL::ex(i) * u[0] + (R)HL::ey(i) * u[1] + (R)HL::ez(i) * u[2];
         const R v = (R)HL::w(i) * (dC + Cc * eu * (R)4);
-        st<typename C::S>(S, (size_t)(C::H0 + i) * PL + n, v * P.sc[1]);
+        st<typename C::S>(S + (size_t)(C::H0 + i) * PL, (uint32_t)n, C::SCALED ? v * P.sc[1] : v);
     }
 #pragma unroll
     for (int c = 0; c < C::NCOMP; ++c) {
@@ -729,7 +780,7 @@ __global__ __launch_bounds__(256) void k_init(Geo G, Phys<typename C::R> P, type
             const R ex = (R)GL::ex(i), ey = (R)GL::ey(i), ez = (R)GL::ez(i);
             const R s = (ex * u[0] + ey * u[1] + ez * u[2]) * B[c] - (ex * B[0] + ey * B[1] + ez * B[2]) * uk;
             const R v = (R)GL::w(i) * (dB[c] + s * (R)4);
-            st<typename C::S>(S, (size_t)(C::G0 + c * C::QG + i) * PL + n, v * P.sc[2]);
+            st<typename C::S>(S + (size_t)(C::G0 + c * C::QG + i) * PL, (uint32_t)n, C::SCALED ? v * P.sc[2] : v);
         }
     }
 }
@@ -749,6 +800,8 @@ inline Geo make_geo(const KArgs& a) {
     g.n1 = a.n1;
     g.n2 = a.n2;
     g.plane = (uint32_t)a.plane;
+    g.dx = make_fastdiv((uint32_t)a.NX);
+    g.dy = make_fastdiv((uint32_t)a.NY);
     return g;
 }
 
@@ -756,7 +809,26 @@ template <class C>
 struct Launch {
     using R = typename C::R;
     static double cg2() { return C::QG ? 0.25 : 1.0; }
+    static hipError_t links(const KArgs& a, const Geo& G, const Phys<R>& P) {
+        if (!a.links_ready || a.n_links == 0) return hipSuccess;
+        dim3 grid((unsigned)((a.n_links + 255) / 256));
+        if (a.parity)
+            hipLaunchKernelGGL((k_links<C, 1>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S,
+                               (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links);
+        else
+            hipLaunchKernelGGL((k_links<C, 0>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S,
+                               (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links);
+        return hipGetLastError();
+    }
+    static hipError_t links_only(const KArgs& a) {
+        return links(a, make_geo(a), make_phys<R>(a, cg2()));
+    }
     static hipError_t step(const KArgs& a) {
+        hipError_t e = links_only(a);
+        if (e != hipSuccess) return e;
+        return sweep(a);
+    }
+    static hipError_t sweep(const KArgs& a) {
         const uint32_t nn = (uint32_t)((size_t)a.NX * a.NY * a.NZ);
         const int bs = a.block > 0 ? a.block : 256;
         dim3 grid((nn + bs - 1) / bs);
@@ -764,10 +836,10 @@ struct Launch {
         const Geo G = make_geo(a);
         if (a.parity)
             hipLaunchKernelGGL((k_step<C, 1>), grid, dim3(bs), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
-                               a.lstart, (const DevLink<R>*)a.links, (R*)a.stash, (R*)a.M, a.links_ready, nn);
+                               (R*)a.M, nn);
         else
             hipLaunchKernelGGL((k_step<C, 0>), grid, dim3(bs), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
-                               a.lstart, (const DevLink<R>*)a.links, (R*)a.stash, (R*)a.M, a.links_ready, nn);
+                               (R*)a.M, nn);
         return hipGetLastError();
     }
     static hipError_t observe(const KArgs& a) {
@@ -775,14 +847,14 @@ struct Launch {
         dim3 grid((nn + 255) / 256);
         const Phys<R> P = make_phys<R>(a, cg2());
         const Geo G = make_geo(a);
+        hipError_t e = links(a, G, P);
+        if (e != hipSuccess) return e;
         if (a.parity)
             hipLaunchKernelGGL((k_observe<C, 1>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
-                               a.lstart, (const DevLink<R>*)a.links, (R*)a.stash, (R*)a.M, a.links_ready, nn,
-                               a.mode, a.field, a.out, a.out_f64, a.acc, (R*)a.snap, a.snap_valid);
+                               (R*)a.M, nn, a.mode, a.field, a.out, a.out_f64, a.acc, (R*)a.snap, a.snap_valid);
         else
             hipLaunchKernelGGL((k_observe<C, 0>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
-                               a.lstart, (const DevLink<R>*)a.links, (R*)a.stash, (R*)a.M, a.links_ready, nn,
-                               a.mode, a.field, a.out, a.out_f64, a.acc, (R*)a.snap, a.snap_valid);
+                               (R*)a.M, nn, a.mode, a.field, a.out, a.out_f64, a.acc, (R*)a.snap, a.snap_valid);
         return hipGetLastError();
     }
     static hipError_t init(const KArgs& a) {
@@ -796,6 +868,8 @@ struct Launch {
     }
     static KernelSet set() {
         KernelSet k;
+        k.links = &links_only;
+        k.sweep = &sweep;
         k.step = &step;
         k.observe = &observe;
         k.init = &init;
@@ -807,7 +881,7 @@ struct Launch {
 // the lattice combinations the library instantiates
 template <class SF>
 KernelSet select_kernels(int fl, int sl, int ml, int nc) {
-#define LBM_CASE(F, H, M, N)                              \
+#define LBM_CASE(F, H, M, N)                                  \
     if (fl == F && sl == H && ml == M && (M == 0 || nc == N)) \
         return Launch<Cfg<F, H, M, N, SF>>::set();
     LBM_CASE(1, 0, 0, 0)

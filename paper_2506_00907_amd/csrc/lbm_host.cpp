@@ -425,14 +425,12 @@ lbm_status hip_check(lbm_ctx* c, hipError_t e, const char* what) {
 void layout(const lbm_params* p, size_t n_links, size_t sz[LBM_NBUF]) {
     const Pad d = padding(p);
     const size_t vb = value_bytes(p->storage), cb = compute_bytes(p->storage);
-    sz[0] = round_up((size_t)total_planes(p) * d.plane * vb, kAlign);
-    sz[1] = round_up(d.plane, kAlign);
-    sz[2] = round_up((d.plane + 1) * sizeof(uint32_t), kAlign);
-    sz[3] = round_up(std::max<size_t>(n_links, 1) * link_bytes(p->storage), kAlign);
-    sz[4] = round_up(std::max<size_t>(n_links, 1) * 2 * cb, kAlign);
-    sz[5] = round_up(2 * 8 * d.plane * cb, kAlign);
-    sz[6] = round_up(7 * d.plane * cb, kAlign) + round_up(lbmi::NACC * sizeof(double), kAlign);
-    sz[7] = 0;
+    sz[0] = round_up((size_t)total_planes(p) * d.plane * vb, kAlign);          // populations
+    sz[1] = round_up(d.plane, kAlign);                                          // node flags
+    sz[2] = round_up(std::max<size_t>(n_links, 1) * link_bytes(p->storage), kAlign);  // link records
+    sz[3] = round_up(2 * 8 * d.plane * cb, kAlign);                            // moment planes
+    sz[4] = round_up(7 * d.plane * cb, kAlign) + round_up(lbmi::NACC * sizeof(double), kAlign);  // reductions
+    sz[5] = sz[6] = sz[7] = 0;
 }
 
 lbmi::KArgs base_args(const lbm_ctx* c) {
@@ -450,10 +448,9 @@ lbmi::KArgs base_args(const lbm_ctx* c) {
     a.plane = c->pad.plane;
     a.S = c->buf[0];
     a.flags = (const uint8_t*)c->buf[1];
-    a.lstart = (const uint32_t*)c->buf[2];
-    a.links = c->buf[3];
-    a.stash = c->buf[4];
-    a.M = c->buf[5];
+    a.links = c->buf[2];
+    a.M = c->buf[3];
+    a.n_links = c->n_links;
     a.tau_f = c->p.tau_f;
     a.tau_c = c->p.scalar ? c->p.tau_c : 1.0;
     a.tau_m = c->p.magnetic ? c->p.tau_m : 1.0;
@@ -478,7 +475,8 @@ size_t domain_nodes(const lbm_params& p) { return (size_t)p.n[0] * p.n[1] * p.n[
 
 template <class R>
 void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::vector<uint32_t>& padA,
-                   const std::vector<uint32_t>& padE, std::vector<unsigned char>* bytes) {
+                   const std::vector<uint32_t>& padE, const std::vector<uint32_t>& padB,
+                   std::vector<unsigned char>* bytes) {
     const HostLat Lf = lattice_of(c->p.fluid), Lh = lattice_of(c->p.scalar), Lg = lattice_of(c->p.magnetic);
     const int QF = Lf.Q, QH = c->p.scalar ? Lh.Q : 0, QG = Lg.Q;
     bytes->assign(std::max<size_t>(L.size(), 1) * sizeof(DevLink<R>), 0);
@@ -491,6 +489,8 @@ void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::
         std::memset(&d, 0, sizeof d);
         d.A = padA[i];
         d.E = padE[i];
+        d.B = padB[i];
+        d.mE = (s.flags & 2) ? padA[i] : padE[i];
         d.kind = s.kind;
         d.flags = s.flags & 3;
         d.pa = (uint8_t)(base + s.dir);
@@ -705,15 +705,27 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
         }
     }
 
-    // order by padded node, build the per-node offsets and flags
-    std::vector<uint32_t> padA(n), padE(n);
+    // order by padded node; padded indices of A, of E = A + e_alpha and of
+    // B = A - e_alpha (the latter two with periodic wrap, fluid or not)
+    auto padwrap = [&](const int* q) {
+        int w[3];
+        for (int k = 0; k < 3; ++k) {
+            w[k] = q[k];
+            if (p.periodic[k]) w[k] = ((w[k] % p.n[k]) + p.n[k]) % p.n[k];
+        }
+        return (uint32_t)((w[0] + d.hx) + (size_t)d.NX * ((w[1] + d.hy) + (size_t)d.NY * (w[2] + d.hz)));
+    };
+    std::vector<uint32_t> padA(n), padE(n), padB(n);
     for (size_t i = 0; i < n; ++i) {
+        const HostLat& lat = lats[links[i].field];
         int q[3];
         coords(links[i].node, q);
         padA[i] = padidx(q);
-        const uint32_t en = (links[i].flags & 2) ? links[i].node : links[i].enode;
-        coords(en, q);
-        padE[i] = padidx(q);
+        const int* e = lat.e[links[i].dir];
+        const int qe[3] = {q[0] + e[0], q[1] + e[1], q[2] + e[2]};
+        const int qb[3] = {q[0] - e[0], q[1] - e[1], q[2] - e[2]};
+        padE[i] = padwrap(qe);
+        padB[i] = padwrap(qb);
     }
     std::vector<size_t> order(n);
     for (size_t i = 0; i < n; ++i) order[i] = i;
@@ -725,11 +737,12 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
         return u.dir < v.dir;
     });
     std::vector<lbm_link> sl(n);
-    std::vector<uint32_t> sA(n), sE(n);
+    std::vector<uint32_t> sA(n), sE(n), sB(n);
     for (size_t i = 0; i < n; ++i) {
         sl[i] = links[order[i]];
         sA[i] = padA[order[i]];
         sE[i] = padE[order[i]];
+        sB[i] = padB[order[i]];
     }
     std::vector<uint8_t> flags(d.plane, 0);
     for (size_t i = 0; i < N; ++i)
@@ -738,27 +751,21 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
             coords((uint32_t)i, q);
             flags[padidx(q)] = lbmi::NF_FLUID;
         }
-    std::vector<uint32_t> lstart(d.plane + 1, 0);
     for (size_t i = 0; i < n; ++i) {
-        lstart[sA[i] + 1]++;
         flags[sA[i]] |= lbmi::NF_LINKS | lbmi::NF_MOM;
-        flags[sE[i]] |= lbmi::NF_MOM;
+        if (!(sl[i].flags & 2)) flags[sE[i]] |= lbmi::NF_MOM;
     }
-    for (size_t i = 0; i < d.plane; ++i) lstart[i + 1] += lstart[i];
 
     std::vector<unsigned char> dl;
-    if (p.storage == LBM_F64) fill_devlinks<double>(c, sl, sA, sE, &dl);
-    else fill_devlinks<float>(c, sl, sA, sE, &dl);
+    if (p.storage == LBM_F64) fill_devlinks<double>(c, sl, sA, sE, sB, &dl);
+    else fill_devlinks<float>(c, sl, sA, sE, sB, &dl);
 
     lbm_status st;
     if ((st = hip_check(c, hipMemcpyAsync(c->buf[1], flags.data(), flags.size(), hipMemcpyHostToDevice, c->stream), "flags upload")))
         return st;
-    if ((st = hip_check(c, hipMemcpyAsync(c->buf[2], lstart.data(), lstart.size() * 4, hipMemcpyHostToDevice, c->stream), "offsets upload")))
+    if ((st = hip_check(c, hipMemcpyAsync(c->buf[2], dl.data(), dl.size(), hipMemcpyHostToDevice, c->stream), "links upload")))
         return st;
-    if ((st = hip_check(c, hipMemcpyAsync(c->buf[3], dl.data(), dl.size(), hipMemcpyHostToDevice, c->stream), "links upload")))
-        return st;
-    if ((st = hip_check(c, hipMemsetAsync(c->buf[4], 0, c->size[4], c->stream), "stash clear"))) return st;
-    if ((st = hip_check(c, hipMemsetAsync(c->buf[5], 0, c->size[5], c->stream), "moment clear"))) return st;
+    if ((st = hip_check(c, hipMemsetAsync(c->buf[3], 0, c->size[3], c->stream), "moment clear"))) return st;
     if ((st = hip_check(c, hipStreamSynchronize(c->stream), "link upload sync"))) return st;
     c->n_links = n;
     drop_graph(c);
@@ -863,6 +870,52 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     return step_launches(c, n);
 }
 
+lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, float ms_out[2]) {
+    if (!c || !ms_out) return LBM_EINVAL;
+    if (n < 1) return set_err(c, LBM_EINVAL, "step count must be positive");
+    if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
+    std::vector<hipEvent_t> ev((size_t)n * 3, nullptr);
+    lbm_status st = LBM_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            st = set_err(c, LBM_EDEVICE, "event create");
+            break;
+        }
+    lbmi::KArgs a = base_args(c);
+    int64_t with_links = 0;
+    for (int64_t i = 0; i < n && st == LBM_OK; ++i) {
+        a.parity = (int)(c->t & 1);
+        a.links_ready = c->t > 0 ? 1 : 0;
+        if (a.links_ready && a.n_links) ++with_links;
+        hipEvent_t* e = &ev[(size_t)i * 3];
+        if ((st = hip_check(c, hipEventRecord(e[0], c->stream), "event record"))) break;
+        if ((st = hip_check(c, c->ks.links(a), "link launch"))) break;
+        if ((st = hip_check(c, hipEventRecord(e[1], c->stream), "event record"))) break;
+        if ((st = hip_check(c, c->ks.sweep(a), "sweep launch"))) break;
+        if ((st = hip_check(c, hipEventRecord(e[2], c->stream), "event record"))) break;
+        c->t++;
+    }
+    if (st == LBM_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "timed step sync");
+    double sl = 0.0, ss = 0.0;
+    if (st == LBM_OK)
+        for (int64_t i = 0; i < n; ++i) {
+            float t0 = 0.f, t1 = 0.f;
+            hipEvent_t* e = &ev[(size_t)i * 3];
+            if (hipEventElapsedTime(&t0, e[0], e[1]) != hipSuccess || hipEventElapsedTime(&t1, e[1], e[2]) != hipSuccess) {
+                st = set_err(c, LBM_EDEVICE, "event elapsed time");
+                break;
+            }
+            sl += t0;
+            ss += t1;
+        }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st != LBM_OK) return st;
+    ms_out[0] = with_links ? (float)(sl / (double)with_links) : 0.f;
+    ms_out[1] = (float)(ss / (double)n);
+    return LBM_OK;
+}
+
 lbm_status lbm_read_moments(lbm_ctx* c, void* dev_out, int32_t out_type) {
     if (!c) return LBM_EINVAL;
     if (!dev_out || (out_type != LBM_F64 && out_type != LBM_F32)) return set_err(c, LBM_EINVAL, "bad output");
@@ -890,7 +943,7 @@ lbm_status lbm_reduce(lbm_ctx* c, double out[8]) {
     if (!c || !out) return LBM_EINVAL;
     if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
     const size_t cb = compute_bytes(c->p.storage);
-    char* aux = (char*)c->buf[6];
+    char* aux = (char*)c->buf[4];
     double* acc = (double*)(aux + round_up(7 * c->pad.plane * cb, kAlign));
     lbm_status st;
     if ((st = hip_check(c, hipMemsetAsync(acc, 0, lbmi::NACC * sizeof(double), c->stream), "accumulator clear")))
@@ -931,7 +984,7 @@ lbm_status lbm_reduce(lbm_ctx* c, double out[8]) {
 
 size_t lbm_state_bytes(const lbm_ctx* c) {
     if (!c) return 0;
-    return 64 + c->size[0] + c->size[4] + c->size[5];
+    return 64 + c->size[0] + c->size[3];
 }
 
 lbm_status lbm_save(lbm_ctx* c, void* host) {
@@ -944,7 +997,7 @@ lbm_status lbm_save(lbm_ctx* c, void* host) {
     std::memcpy(h + 8, &magic, 8);
     size_t o = 64;
     lbm_status st;
-    const int ids[3] = {0, 4, 5};
+    const int ids[2] = {0, 3};
     for (int i : ids) {
         if ((st = hip_check(c, hipMemcpyAsync(h + o, c->buf[i], c->size[i], hipMemcpyDeviceToHost, c->stream), "save copy")))
             return st;
@@ -964,7 +1017,7 @@ lbm_status lbm_load(lbm_ctx* c, const void* host) {
     std::memcpy(&t, h, sizeof t);
     size_t o = 64;
     lbm_status st;
-    const int ids[3] = {0, 4, 5};
+    const int ids[2] = {0, 3};
     for (int i : ids) {
         if ((st = hip_check(c, hipMemcpyAsync(c->buf[i], h + o, c->size[i], hipMemcpyHostToDevice, c->stream), "load copy")))
             return st;

@@ -18,11 +18,13 @@ enum : int { OBS_MOMENTS = 0, OBS_POPS = 1, OBS_REDUCE = 2 };
 // number of FP64 accumulators used by the reduction
 constexpr int NACC = 16;
 
-// Boundary link as the kernels read it: precomputed plane indices and the
-// lattice vector of alpha, wall data in the compute type R.
+// Boundary link as the kernels read it: padded node indices, population
+// planes, the lattice vector of alpha, wall data in the compute type R.
 template <class R>
 struct alignas(16) DevLink {
-    uint32_t A, E;        // padded node indices; E == A when E is not fluid
+    uint32_t A;           // first fluid node
+    uint32_t E, B;        // A + e_alpha and A - e_alpha (periodic wrap), fluid or not
+    uint32_t mE;          // node whose moments stand for E: E if fluid, else A
     uint8_t kind;         // lbm_link_kind
     uint8_t flags;        // bit 0: u_w given; bit 1: E not fluid
     uint8_t pa, pap;      // population planes of alpha and of its opposite alpha'
@@ -44,10 +46,9 @@ struct KArgs {
     size_t plane;          // padded node count rounded up (population plane stride)
     void* S;               // populations [QT][plane]
     const uint8_t* flags;  // [plane]
-    const uint32_t* lstart;  // [plane + 1]
     const void* links;     // DevLink<R>[n_links]
-    void* stash;           // R[2 * n_links]
     void* M;               // R[2][8][plane]
+    size_t n_links;
     double tau_f, tau_c, tau_m, rho0, C0, mu;
     double Bext[3], accel[3], scale[3];
     int comp[3];           // Cartesian axis of each evolved magnetic component
@@ -64,12 +65,15 @@ struct KArgs {
     const double *init_rho, *init_u, *init_C, *init_B;
     int block;             // threads per block
     hipStream_t stream;
+    hipEvent_t ev[3];      // optional: recorded before links, between, after sweep
 };
 
 using Launcher = hipError_t (*)(const KArgs&);
 
 struct KernelSet {
-    Launcher step = nullptr;     // one fused step at the given parity
+    Launcher links = nullptr;    // the boundary-link kernel of a step (no-op at t = 0)
+    Launcher sweep = nullptr;    // the fused sweep of a step
+    Launcher step = nullptr;     // links then sweep
     Launcher observe = nullptr;  // moments / populations / reductions at the current time
     Launcher init = nullptr;     // equilibrium initialisation
     int QT = 0;                  // population planes

@@ -185,6 +185,12 @@ class Lattice:
     def step(self, n: int = 1):
         self._call("lbm_step", int(n))
 
+    def step_timed(self, n: int):
+        """lbm_step_timed: mean (link kernel, sweep kernel) durations in ms."""
+        out = (C.c_float * 2)()
+        self._call("lbm_step_timed", int(n), out)
+        return float(out[0]), float(out[1])
+
     @property
     def time(self) -> int:
         return L.lib().lbm_time(self.ctx)

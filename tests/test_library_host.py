@@ -223,7 +223,8 @@ def test_buffer_layout():
     sizes = lbm.required_bytes(p, 100)
     plane = ((64 * 32 + 63) // 64) * 64
     assert sizes[0] == ((19 * plane * 2 + 255) // 256) * 256      # populations, 2 bytes
-    assert sizes[5] == ((2 * 8 * plane * 4 + 255) // 256) * 256   # moment planes in FP32
+    assert sizes[3] == ((2 * 8 * plane * 4 + 255) // 256) * 256   # moment planes in FP32
+    assert sizes[5] == sizes[6] == sizes[7] == 0
     assert all(s % 256 == 0 for s in sizes)
 
 
