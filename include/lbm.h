@@ -230,6 +230,97 @@ lbm_status lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
 const char* lbm_last_error(const lbm_ctx* ctx);
 void lbm_destroy(lbm_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent lattices ("items"), each with its own size,
+ * geometry, boundary links and parameters, advanced together by shared
+ * launches.  Every item runs the same step as a single context (the same
+ * node update and link update), so an item evolves exactly as it would
+ * alone.  All items of a batch use one lattice combination (dim, fluid,
+ * scalar, magnetic, mag_ncomp) and one storage format.
+ *
+ * Execution modes (lbm_batch_config.mode):
+ *  LBM_BATCH_TILED    one step = one boundary-link launch over link tiles of
+ *                     all active items, then one sweep launch over node tiles
+ *                     (block nodes each) of all active items;
+ *  LBM_BATCH_RESIDENT one workgroup of `block` threads per active item runs
+ *                     steps_per_launch steps inside one launch, separating the
+ *                     link and sweep phases with workgroup barriers (items
+ *                     never exchange data, so no grid-wide synchronisation).
+ * Runs of graph_steps steps are captured once in a HIP graph and replayed.
+ * Steady-state detection (lbm_batch_run) evaluates every item's residual on
+ * the device every `interval` steps, in FP64, with the definition of
+ * lbm_reduce out[0]; an item whose residual falls below tol, or whose moments
+ * turn non-finite, is frozen by a per-item flag that every later launch reads,
+ * and the host drops frozen items from the work tables.
+ * --------------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+typedef enum { LBM_BATCH_TILED = 1, LBM_BATCH_RESIDENT = 2 } lbm_batch_mode;
+
+/* per-item state reported by lbm_batch_run */
+typedef enum { LBM_ITEM_ACTIVE = 0, LBM_ITEM_STEADY = 1, LBM_ITEM_NONFINITE = 2 } lbm_item_status;
+
+typedef struct {
+    int32_t mode;              /* lbm_batch_mode */
+    int32_t block;             /* TILED: nodes per tile = threads per block, 64, 128 or 256;
+                                  RESIDENT: threads per item, a multiple of 64 up to the
+                                  kernel's limit (1024, or 512 above 30 population planes) */
+    int32_t steps_per_launch;  /* RESIDENT: even, >= 2; TILED: 1 */
+    int32_t graph_steps;       /* steps per captured graph: even, a multiple of steps_per_launch */
+} lbm_batch_config;
+
+/* Device buffer sizes of a batch of n_items items with parameters items[i]
+ * and link capacities n_links[i] (host arrays).  Returns the sum, 0 when an
+ * item's parameters are invalid or the items do not share a lattice
+ * combination and storage.  Buffer roles: 0-4 the items' buffers 0-4 of
+ * lbm_required_bytes back to back; 5 item descriptors; 6 work tables; 7
+ * per-item convergence state. */
+size_t lbm_batch_required_bytes(int32_t n_items, const lbm_params* items, const size_t* n_links,
+                                size_t sizes_out[LBM_NBUF]);
+
+/* Creates a batch over caller-allocated device buffers (256-byte aligned,
+ * sizes from lbm_batch_required_bytes) on hip_stream.  The default
+ * configuration is TILED, block 256, graph_steps 64. */
+lbm_status lbm_batch_create(int32_t n_items, const lbm_params* items, const size_t* n_links,
+                            void* const dev_bufs[LBM_NBUF], void* hip_stream, lbm_batch** out);
+
+/* The context of item i (owned by the batch: lbm_destroy ignores it and
+ * lbm_set_stream refuses it).  Set it up with lbm_set_geometry,
+ * lbm_set_links and lbm_init; read it with lbm_read_moments,
+ * lbm_read_populations, lbm_reduce, lbm_save; it may also be stepped alone
+ * with lbm_step.  NULL when i is out of range. */
+lbm_ctx* lbm_batch_item(lbm_batch* b, int32_t i);
+
+lbm_status lbm_batch_configure(lbm_batch* b, const lbm_batch_config* cfg);
+lbm_status lbm_batch_get_config(const lbm_batch* b, lbm_batch_config* cfg);
+
+/* Advances every item by n >= 0 steps (asynchronous).  Every item must be
+ * initialised and all items must have times of equal parity. */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
+
+/* Runs every item until its residual (every `interval` steps, interval even
+ * >= 2) is below tol, its moments are non-finite, or max_steps steps have
+ * run; synchronises.  Host outputs, n_items entries each, may be NULL:
+ * steps_out steps run by the item in this call, resid_out its last residual
+ * (-1 if none was evaluated), status_out its lbm_item_status.  Each item's
+ * time advances by its own step count.  At most two single steps run first
+ * when an item is at time 0 or the times are odd. */
+lbm_status lbm_batch_run(lbm_batch* b, double tol, int32_t interval, int64_t max_steps, int64_t* steps_out,
+                         double* resid_out, int32_t* status_out);
+
+/* Autotuner: times every candidate configuration (TILED with block 64, 128,
+ * 256; RESIDENT with block 256, 512, 1024 within the kernel's limit and
+ * steps_per_launch 2, 8, 32) on trial_steps real steps of the batch (the
+ * items advance), with HIP events on the batch's stream, and configures the
+ * fastest.  Host outputs: best (may be NULL); cands and ms_per_step (cap
+ * entries each, may be NULL) every candidate and its time per step; *n_out
+ * the number of candidates. */
+lbm_status lbm_batch_tune(lbm_batch* b, int64_t trial_steps, lbm_batch_config* best, lbm_batch_config* cands,
+                          double* ms_per_step, int32_t cap, int32_t* n_out);
+
+const char* lbm_batch_last_error(const lbm_batch* b);
+void lbm_batch_destroy(lbm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

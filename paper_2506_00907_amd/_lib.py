@@ -52,6 +52,14 @@ class lbm_boundary(C.Structure):
                 ("u_w", C.c_double * 3), ("f", lbm_bc), ("h", lbm_bc), ("g", lbm_bc * 3)]
 
 
+class lbm_batch_config(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("block", C.c_int32), ("steps_per_launch", C.c_int32),
+                ("graph_steps", C.c_int32)]
+
+
+LBM_BATCH_TILED, LBM_BATCH_RESIDENT = 1, 2
+ITEM_STATUS = {0: "active", 1: "steady", 2: "nonfinite"}
+
 # every entry point declared in include/lbm.h: name -> (restype, argtypes)
 _VP = C.c_void_p
 SIGNATURES = {
@@ -76,6 +84,20 @@ SIGNATURES = {
     "lbm_set_stream": (C.c_int, [_VP, _VP]),
     "lbm_last_error": (C.c_char_p, [_VP]),
     "lbm_destroy": (None, [_VP]),
+    "lbm_batch_required_bytes": (C.c_size_t, [C.c_int32, C.POINTER(lbm_params), C.POINTER(C.c_size_t),
+                                              C.POINTER(C.c_size_t)]),
+    "lbm_batch_create": (C.c_int, [C.c_int32, C.POINTER(lbm_params), C.POINTER(C.c_size_t), C.POINTER(_VP), _VP,
+                                   C.POINTER(_VP)]),
+    "lbm_batch_item": (_VP, [_VP, C.c_int32]),
+    "lbm_batch_configure": (C.c_int, [_VP, C.POINTER(lbm_batch_config)]),
+    "lbm_batch_get_config": (C.c_int, [_VP, C.POINTER(lbm_batch_config)]),
+    "lbm_batch_step": (C.c_int, [_VP, C.c_int64]),
+    "lbm_batch_run": (C.c_int, [_VP, C.c_double, C.c_int32, C.c_int64, C.POINTER(C.c_int64),
+                                C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "lbm_batch_tune": (C.c_int, [_VP, C.c_int64, C.POINTER(lbm_batch_config), C.POINTER(lbm_batch_config),
+                                 C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
+    "lbm_batch_last_error": (C.c_char_p, [_VP]),
+    "lbm_batch_destroy": (None, [_VP]),
 }
 
 _lib = None

@@ -1,0 +1,66 @@
+// Host-side state of one lattice context and the helpers shared by the
+// single-lattice entry points (lbm_host.cpp) and the batch (lbm_batch.cpp).
+// Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.hpp"
+
+namespace lbmh {
+
+constexpr size_t kAlign = 256;
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// padded grid: one halo node on each non-periodic axis
+struct Pad {
+    int NX, NY, NZ, hx, hy, hz;
+    size_t nodes, plane;  // padded node count and the population plane stride
+};
+
+bool valid_params(const lbm_params* p, std::string* why);
+Pad padding(const lbm_params* p);
+size_t value_bytes(int storage);
+size_t compute_bytes(int storage);
+int total_planes(const lbm_params* p);
+lbmi::KernelSet kernels_for(const lbm_params* p);
+// device buffer sizes of one context (roles as in lbm.h)
+void layout(const lbm_params* p, size_t n_links, size_t sz[LBM_NBUF]);
+
+}  // namespace lbmh
+
+struct lbm_ctx {
+    lbm_params p;
+    lbmh::Pad pad;
+    lbmi::KernelSet ks;
+    void* buf[LBM_NBUF];
+    size_t size[LBM_NBUF];
+    size_t cap_links = 0, n_links = 0;
+    hipStream_t stream = nullptr;
+    int64_t t = 0, t_snap = 0;
+    bool have_geometry = false, have_links = false, initialized = false, snap_valid = false;
+    std::vector<uint8_t> mask;   // domain
+    std::string err;
+    // a captured run of graph_steps steps (even start parity, links ready),
+    // replayed by lbm_step on the caller's stream
+    hipGraphExec_t graph = nullptr;
+    hipStream_t capture_stream = nullptr;
+    bool graph_failed = false;
+    int graph_steps = 64;
+    // item of a batch: the batch owns the context and its buffers
+    bool batch_owned = false;
+};
+
+namespace lbmh {
+
+void drop_graph(lbm_ctx* c);
+lbm_status set_err(lbm_ctx* c, lbm_status s, const std::string& m);
+lbm_status hip_check(lbm_ctx* c, hipError_t e, const char* what);
+lbmi::KArgs base_args(const lbm_ctx* c);
+
+}  // namespace lbmh

@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 
 #include "lbm_internal.hpp"
 
@@ -320,14 +321,10 @@ __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R
 // with E = A + e_alpha and B = A - e_alpha.  No other link of the launch
 // reads a target slot, so the kernel is race-free.
 template <class C, int ODD>
-__global__ __launch_bounds__(256) void k_links(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
-                                               const DevLink<typename C::R>* __restrict__ links,
-                                               const typename C::R* __restrict__ M, uint32_t nlinks) {
+__device__ __forceinline__ void link_update(const Geo& G, const Phys<typename C::R>& P, typename C::T* __restrict__ S,
+                                            const DevLink<typename C::R>& L, const typename C::R* __restrict__ M) {
     using R = typename C::R;
     using SF = typename C::S;
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nlinks) return;
-    const DevLink<R> L = links[k];
     const size_t PL = G.plane;
     typename C::T* Sa = S + (size_t)L.pa * PL;
     typename C::T* Sp = S + (size_t)L.pap * PL;
@@ -368,6 +365,15 @@ __global__ __launch_bounds__(256) void k_links(Geo G, Phys<typename C::R> P, typ
     const R v = link_value<R>(L, P, x_a, x_apA, xs, mA, mE, w, c2);
     if (ODD) st<SF>(Sp, L.B, C::SCALED ? v * sc : v);
     else st<SF>(Sa, L.A, C::SCALED ? v * sc : v);
+}
+
+template <class C, int ODD>
+__global__ __launch_bounds__(256) void k_links(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
+                                               const DevLink<typename C::R>* __restrict__ links,
+                                               const typename C::R* __restrict__ M, uint32_t nlinks) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nlinks) return;
+    link_update<C, ODD>(G, P, S, links[k], M);
 }
 
 // ---------------------------------------------------------------------------
@@ -629,6 +635,52 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Per-node terms of the FP64 reductions: sums of rho, C, B (0..4); squared
+// change of u, C - C0, B - B_ext since the snapshot (5..7) and their squared
+// norms (8..10); a non-finite flag (11).  The snapshot is replaced by the
+// current values.
+template <class C>
+__device__ __forceinline__ void reduce_node(const Phys<typename C::R>& P, const NodeRes<C>& r, bool fluid,
+                                            typename C::R* snap, int snap_valid, uint32_t PL, uint32_t n,
+                                            double v[NACC]) {
+    using R = typename C::R;
+    for (int q = 0; q < NACC; ++q) v[q] = 0.0;
+    if (!fluid) return;
+    double phi[7] = {r.m.u[0], r.m.u[1], r.m.u[2], r.m.dC, r.m.dB[0], r.m.dB[1], r.m.dB[2]};
+    v[0] = (double)P.rho0 + (double)r.m.drho;
+    v[1] = (double)P.C0 + (double)r.m.dC;
+    for (int k = 0; k < 3; ++k) v[2 + k] = (double)P.Bext[k] + (double)r.m.dB[k];
+    for (int q = 0; q < 7; ++q) {
+        const double s = snap_valid ? (double)snap[(size_t)q * PL + n] : 0.0;
+        const double dd = phi[q] - s;
+        const int fld = q < 3 ? 0 : (q == 3 ? 1 : 2);
+        v[5 + fld] += dd * dd;
+        v[8 + fld] += phi[q] * phi[q];
+        snap[(size_t)q * PL + n] = (R)phi[q];
+    }
+    bool bad = false;
+    for (int q = 0; q < 5; ++q) bad = bad || !(v[q] - v[q] == 0.0);
+    for (int q = 0; q < 7; ++q) bad = bad || !(phi[q] - phi[q] == 0.0);
+    v[11] = bad ? 1.0 : 0.0;
+}
+
+// block sum of the first 12 accumulators: wave shuffles, then LDS, then one
+// FP64 atomic per value and block
+__device__ __forceinline__ void block_accumulate(const double v[NACC], double* acc) {
+    __shared__ double red[12][16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q = 0; q < 12; ++q) {
+        double s = wave_sum(v[q]);
+        if (lane == 0) red[q][wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        double s = 0.0;
+        for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) s += red[threadIdx.x][k];
+        atomicAdd(&acc[threadIdx.x], s);
+    }
+}
+
 // observe: moments / populations / FP64 reductions at the current time
 template <class C, int ODD>
 __global__ __launch_bounds__(256) void k_observe(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
@@ -688,41 +740,10 @@ __global__ __launch_bounds__(256) void k_observe(Geo G, Phys<typename C::R> P, t
         }
         return;
     }
-    // OBS_REDUCE: sums of rho, C, B; squared change of u, C - C0, B - B_ext
-    // since the snapshot and their squared norms; non-finite count
+    // OBS_REDUCE
     double v[NACC];
-    for (int q = 0; q < NACC; ++q) v[q] = 0.0;
-    if (fluid) {
-        const size_t PL = G.plane;
-        double phi[7] = {r.m.u[0], r.m.u[1], r.m.u[2], r.m.dC, r.m.dB[0], r.m.dB[1], r.m.dB[2]};
-        v[0] = (double)P.rho0 + (double)r.m.drho;
-        v[1] = (double)P.C0 + (double)r.m.dC;
-        for (int k = 0; k < 3; ++k) v[2 + k] = (double)P.Bext[k] + (double)r.m.dB[k];
-        for (int q = 0; q < 7; ++q) {
-            const double s = snap_valid ? (double)snap[(size_t)q * PL + n] : 0.0;
-            const double dd = phi[q] - s;
-            const int fld = q < 3 ? 0 : (q == 3 ? 1 : 2);
-            v[5 + fld] += dd * dd;          // 5..7: |phi - snap|^2 per field
-            v[8 + fld] += phi[q] * phi[q];  // 8..10: |phi|^2 per field
-            snap[(size_t)q * PL + n] = (R)phi[q];
-        }
-        bool bad = false;
-        for (int q = 0; q < 5; ++q) bad = bad || !(v[q] - v[q] == 0.0);
-        for (int q = 0; q < 7; ++q) bad = bad || !(phi[q] - phi[q] == 0.0);
-        v[11] = bad ? 1.0 : 0.0;
-    }
-    __shared__ double red[NACC][4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int q = 0; q < 12; ++q) {
-        double s = wave_sum(v[q]);
-        if (lane == 0) red[q][wv] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < 12) {
-        double s = 0.0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[threadIdx.x][k];
-        atomicAdd(&acc[threadIdx.x], s);
-    }
+    reduce_node<C>(P, r, fluid, snap, snap_valid, G.plane, n, v);
+    block_accumulate(v, acc);
 }
 
 // equilibrium initialisation: canonical layout slot i at node n holds x_i
@@ -783,6 +804,158 @@ __global__ __launch_bounds__(256) void k_init(Geo G, Phys<typename C::R> P, type
             st<typename C::S>(S + (size_t)(C::G0 + c * C::QG + i) * PL, (uint32_t)n, C::SCALED ? v * P.sc[2] : v);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// batched items: many independent lattices of one lattice combination and
+// storage format, each with its own geometry, links and parameters
+// ---------------------------------------------------------------------------
+template <class C>
+struct BItem {
+    Geo G;
+    Phys<typename C::R> P;
+    typename C::T* S;
+    const uint8_t* flags;
+    const DevLink<typename C::R>* links;
+    typename C::R* M;
+    typename C::R* snap;  // [7][plane] residual snapshot
+    double* acc;          // [NACC] FP64 accumulators
+    uint32_t nnodes, nlinks;
+};
+
+// fused sweep over node tiles; the tile table lists (item, first node)
+template <class C, int ODD>
+__global__ __launch_bounds__(256) void kb_sweep(const BItem<C>* __restrict__ items,
+                                                const uint32_t* __restrict__ tiles,
+                                                const uint32_t* __restrict__ status, uint32_t ntiles) {
+    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    if (b >= ntiles) return;
+    const uint32_t it = tiles[2 * b];
+    if (status[it] != BS_ACTIVE) return;
+    const BItem<C>& I = items[it];
+    const uint32_t n = tiles[2 * b + 1] + threadIdx.x;
+    if (n >= I.nnodes) return;
+    NodeRes<C> r;
+    node_update<C, ODD, 0>(I.G, I.P, I.S, I.flags, I.M, n, r);
+}
+
+template <class C, int ODD>
+__global__ __launch_bounds__(256) void kb_links(const BItem<C>* __restrict__ items,
+                                                const uint32_t* __restrict__ ltiles,
+                                                const uint32_t* __restrict__ status, uint32_t nltiles) {
+    const uint32_t b = blockIdx.x;
+    if (b >= nltiles) return;
+    const uint32_t it = ltiles[2 * b];
+    if (status[it] != BS_ACTIVE) return;
+    const BItem<C>& I = items[it];
+    const uint32_t k = ltiles[2 * b + 1] + threadIdx.x;
+    if (k >= I.nlinks) return;
+    link_update<C, ODD>(I.G, I.P, I.S, I.links[k], I.M);
+}
+
+// One workgroup advances one item by nsteps steps (nsteps even, starting at
+// an even time with links ready): per step the links, a workgroup barrier, the
+// sweep over all nodes of the item, a barrier.  The barriers order the
+// global-memory writes of one phase before the reads of the next within the
+// workgroup; items never touch each other's memory.
+template <class C>
+__global__ __launch_bounds__(C::QT > 30 ? 512 : 1024) void kb_resident(const BItem<C>* __restrict__ items,
+                                                                      const uint32_t* __restrict__ active,
+                                                                      const uint32_t* __restrict__ status,
+                                                                      int nsteps) {
+    const uint32_t it = active[blockIdx.x];
+    if (status[it] != BS_ACTIVE) return;
+    const BItem<C>& I = items[it];
+    const Geo G = I.G;
+    const Phys<typename C::R> P = I.P;
+    typename C::T* S = I.S;
+    typename C::R* M = I.M;
+    const uint8_t* flags = I.flags;
+    const DevLink<typename C::R>* links = I.links;
+    const uint32_t nn = I.nnodes, nl = I.nlinks, bd = blockDim.x;
+    for (int s = 0; s < nsteps; s += 2) {
+        for (uint32_t k = threadIdx.x; k < nl; k += bd) link_update<C, 0>(G, P, S, links[k], M);
+        __syncthreads();
+        for (uint32_t n = threadIdx.x; n < nn; n += bd) {
+            NodeRes<C> r;
+            node_update<C, 0, 0>(G, P, S, flags, M, n, r);
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < nl; k += bd) link_update<C, 1>(G, P, S, links[k], M);
+        __syncthreads();
+        for (uint32_t n = threadIdx.x; n < nn; n += bd) {
+            NodeRes<C> r;
+            node_update<C, 1, 0>(G, P, S, flags, M, n, r);
+        }
+        __syncthreads();
+    }
+}
+
+// per-item FP64 sums over node tiles (after the links of the current time)
+template <class C, int ODD>
+__global__ __launch_bounds__(256) void kb_reduce(const BItem<C>* __restrict__ items,
+                                                 const uint32_t* __restrict__ tiles,
+                                                 const uint32_t* __restrict__ status,
+                                                 const uint32_t* __restrict__ snap_ok, uint32_t ntiles) {
+    const uint32_t b = blockIdx.x;
+    if (b >= ntiles) return;
+    const uint32_t it = tiles[2 * b];
+    if (status[it] != BS_ACTIVE) return;
+    const BItem<C>& I = items[it];
+    const uint32_t n = tiles[2 * b + 1] + threadIdx.x;
+    NodeRes<C> r;
+    bool fluid = false;
+    if (n < I.nnodes) fluid = node_update<C, ODD, 1>(I.G, I.P, I.S, I.flags, I.M, n, r);
+    double v[NACC];
+    reduce_node<C>(I.P, r, fluid, I.snap, (int)snap_ok[it], I.G.plane, n, v);
+    block_accumulate(v, I.acc);
+}
+
+// One thread per active item: the steady-state residual from the sums of
+// kb_reduce (the largest over u, C - C0, B - B_ext of |change| / (interval
+// |value|)), the item's flags, then the accumulators cleared for the next
+// evaluation.
+template <class C>
+__global__ __launch_bounds__(256) void kb_judge(const BItem<C>* __restrict__ items,
+                                                const uint32_t* __restrict__ active, uint32_t nact,
+                                                uint32_t* status, uint32_t* steps, double* resid,
+                                                uint32_t* snap_ok, int interval, double tol) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nact) return;
+    const uint32_t it = active[i];
+    if (status[it] != BS_ACTIVE) return;
+    double* a = items[it].acc;
+    steps[it] += (uint32_t)interval;
+    double res = -1.0;
+    if (snap_ok[it]) {
+        res = 0.0;
+        for (int f = 0; f < 3; ++f) {
+            if (a[8 + f] == 0.0 && a[5 + f] == 0.0) continue;
+            res = fmax(res, sqrt(a[5 + f]) / ((double)interval * fmax(sqrt(a[8 + f]), 1e-30)));
+        }
+    }
+    resid[it] = res;
+    if (a[11] > 0.0) status[it] = BS_NONFINITE;
+    else if (res >= 0.0 && res < tol) status[it] = BS_STEADY;
+    snap_ok[it] = 1u;
+    for (int q = 0; q < NACC; ++q) a[q] = 0.0;
+}
+
+// accumulators, counters and flags of the listed items back to their start
+template <class C>
+__global__ __launch_bounds__(256) void kb_clear(const BItem<C>* __restrict__ items,
+                                                const uint32_t* __restrict__ active, uint32_t nact,
+                                                uint32_t* status, uint32_t* steps, double* resid,
+                                                uint32_t* snap_ok) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nact) return;
+    const uint32_t it = active[i];
+    double* a = items[it].acc;
+    for (int q = 0; q < NACC; ++q) a[q] = 0.0;
+    status[it] = BS_ACTIVE;
+    steps[it] = 0u;
+    resid[it] = -1.0;
+    snap_ok[it] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -866,8 +1039,87 @@ struct Launch {
                            a.init_rho, a.init_u, a.init_C, a.init_B);
         return hipGetLastError();
     }
+    // ---- batched items ----
+    static size_t describe(const KArgs& a, void* out) {
+        BItem<C> d;
+        memset(&d, 0, sizeof d);
+        d.G = make_geo(a);
+        d.P = make_phys<R>(a, cg2());
+        d.S = (typename C::T*)a.S;
+        d.flags = a.flags;
+        d.links = (const DevLink<R>*)a.links;
+        d.M = (R*)a.M;
+        d.snap = (R*)a.snap;
+        d.acc = a.acc;
+        d.nnodes = (uint32_t)((size_t)a.NX * a.NY * a.NZ);
+        d.nlinks = a.links_ready ? (uint32_t)a.n_links : 0u;
+        if (out) memcpy(out, &d, sizeof d);
+        return sizeof d;
+    }
+    static hipError_t b_sweep(const BArgs& b) {
+        if (b.n_tiles == 0) return hipSuccess;
+        const BItem<C>* it = (const BItem<C>*)b.items;
+        if (b.parity)
+            hipLaunchKernelGGL((kb_sweep<C, 1>), dim3(b.n_tiles), dim3(b.tile), 0, b.stream, it, b.tiles, b.status,
+                               b.n_tiles);
+        else
+            hipLaunchKernelGGL((kb_sweep<C, 0>), dim3(b.n_tiles), dim3(b.tile), 0, b.stream, it, b.tiles, b.status,
+                               b.n_tiles);
+        return hipGetLastError();
+    }
+    static hipError_t b_links(const BArgs& b) {
+        if (b.n_ltiles == 0) return hipSuccess;
+        const BItem<C>* it = (const BItem<C>*)b.items;
+        if (b.parity)
+            hipLaunchKernelGGL((kb_links<C, 1>), dim3(b.n_ltiles), dim3(256), 0, b.stream, it, b.ltiles, b.status,
+                               b.n_ltiles);
+        else
+            hipLaunchKernelGGL((kb_links<C, 0>), dim3(b.n_ltiles), dim3(256), 0, b.stream, it, b.ltiles, b.status,
+                               b.n_ltiles);
+        return hipGetLastError();
+    }
+    static hipError_t b_resident(const BArgs& b) {
+        if (b.n_active == 0) return hipSuccess;
+        hipLaunchKernelGGL((kb_resident<C>), dim3(b.n_active), dim3(b.block), 0, b.stream,
+                           (const BItem<C>*)b.items, b.active, b.status, b.nsteps);
+        return hipGetLastError();
+    }
+    static hipError_t b_reduce(const BArgs& b) {
+        hipError_t e = b_links(b);
+        if (e != hipSuccess || b.n_tiles == 0) return e;
+        const BItem<C>* it = (const BItem<C>*)b.items;
+        if (b.parity)
+            hipLaunchKernelGGL((kb_reduce<C, 1>), dim3(b.n_tiles), dim3(b.tile), 0, b.stream, it, b.tiles, b.status,
+                               b.snap_ok, b.n_tiles);
+        else
+            hipLaunchKernelGGL((kb_reduce<C, 0>), dim3(b.n_tiles), dim3(b.tile), 0, b.stream, it, b.tiles, b.status,
+                               b.snap_ok, b.n_tiles);
+        return hipGetLastError();
+    }
+    static hipError_t b_judge(const BArgs& b) {
+        if (b.n_active == 0) return hipSuccess;
+        hipLaunchKernelGGL((kb_judge<C>), dim3((b.n_active + 255) / 256), dim3(256), 0, b.stream,
+                           (const BItem<C>*)b.items, b.active, b.n_active, b.status, b.steps, b.resid, b.snap_ok,
+                           b.interval, b.tol);
+        return hipGetLastError();
+    }
+    static hipError_t b_clear(const BArgs& b) {
+        if (b.n_active == 0) return hipSuccess;
+        hipLaunchKernelGGL((kb_clear<C>), dim3((b.n_active + 255) / 256), dim3(256), 0, b.stream,
+                           (const BItem<C>*)b.items, b.active, b.n_active, b.status, b.steps, b.resid, b.snap_ok);
+        return hipGetLastError();
+    }
+
     static KernelSet set() {
         KernelSet k;
+        k.describe = &describe;
+        k.item_bytes = sizeof(BItem<C>);
+        k.b_sweep = &b_sweep;
+        k.b_links = &b_links;
+        k.b_resident = &b_resident;
+        k.b_reduce = &b_reduce;
+        k.b_judge = &b_judge;
+        k.b_clear = &b_clear;
         k.links = &links_only;
         k.sweep = &sweep;
         k.step = &step;

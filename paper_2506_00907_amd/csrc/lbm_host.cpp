@@ -10,15 +10,13 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "lbm_ctx.hpp"
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 
 using lbmi::DevLink;
 
-namespace {
-
-constexpr size_t kAlign = 256;
-size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+namespace lbmh {
 
 // ---------------------------------------------------------------------------
 // lattice tables (host view of the device lattices)
@@ -94,11 +92,6 @@ bool valid_params(const lbm_params* p, std::string* why) {
     if (nn > 2.0e9) return fail("lattice too large for 32-bit node indices");
     return true;
 }
-
-struct Pad {
-    int NX, NY, NZ, hx, hy, hz;
-    size_t nodes, plane;
-};
 
 Pad padding(const lbm_params* p) {
     Pad d;
@@ -380,32 +373,11 @@ class LinkBuilder {
     std::vector<uint8_t> mask_;
 };
 
-}  // namespace
+}  // namespace lbmh
 
-// ---------------------------------------------------------------------------
-// context
-// ---------------------------------------------------------------------------
-struct lbm_ctx {
-    lbm_params p;
-    Pad pad;
-    lbmi::KernelSet ks;
-    void* buf[LBM_NBUF];
-    size_t size[LBM_NBUF];
-    size_t cap_links = 0, n_links = 0;
-    hipStream_t stream = nullptr;
-    int64_t t = 0, t_snap = 0;
-    bool have_geometry = false, have_links = false, initialized = false, snap_valid = false;
-    std::vector<uint8_t> mask;   // domain
-    std::string err;
-    // a captured run of kGraphSteps steps (even start parity, links ready),
-    // replayed by lbm_step on the caller's stream
-    hipGraphExec_t graph = nullptr;
-    hipStream_t capture_stream = nullptr;
-    bool graph_failed = false;
-    int graph_steps = 64;
-};
+using namespace lbmh;
 
-namespace {
+namespace lbmh {
 
 void drop_graph(lbm_ctx* c) {
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
@@ -518,7 +490,7 @@ void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::
     }
 }
 
-}  // namespace
+}  // namespace lbmh
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -1034,6 +1006,7 @@ int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
 
 lbm_status lbm_set_stream(lbm_ctx* c, void* s) {
     if (!c) return LBM_EINVAL;
+    if (c->batch_owned) return set_err(c, LBM_EINVAL, "an item of a batch runs on the batch's stream");
     c->stream = (hipStream_t)s;
     drop_graph(c);
     return LBM_OK;
@@ -1042,7 +1015,7 @@ lbm_status lbm_set_stream(lbm_ctx* c, void* s) {
 const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 void lbm_destroy(lbm_ctx* c) {
-    if (!c) return;
+    if (!c || c->batch_owned) return;
     drop_graph(c);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     delete c;

@@ -70,6 +70,35 @@ struct KArgs {
 
 using Launcher = hipError_t (*)(const KArgs&);
 
+// status of one item of a batch
+enum : uint32_t { BS_ACTIVE = 0, BS_STEADY = 1, BS_NONFINITE = 2 };
+
+// Launch description of the batched kernels: the item descriptors, the
+// per-launch work tables and the per-item convergence state, all on the
+// device.
+struct BArgs {
+    const void* items;          // item descriptors, KernelSet::item_bytes each
+    const uint32_t* tiles;      // node tiles: (item, first padded node) pairs
+    uint32_t n_tiles, tile;     // tile = nodes per tile = threads per block
+    const uint32_t* ltiles;     // link tiles: (item, first link) pairs, 256 links each
+    uint32_t n_ltiles;
+    const uint32_t* active;     // indices of the items a resident launch runs
+    uint32_t n_active;
+    uint32_t* status;           // BS_* per item
+    uint32_t* steps;            // steps run per item since the counters were cleared
+    double* resid;              // last steady-state residual per item (-1: none yet)
+    uint32_t* snap_ok;          // per item: the residual snapshot holds a previous state
+    int parity;                 // parity of the current time
+    int nsteps;                 // resident launch: steps per launch (even)
+    int block;                  // resident launch: threads per item
+    int interval;               // steps between two residual evaluations
+    double tol;                 // steady when the residual falls below it
+    hipStream_t stream;
+};
+
+using BLauncher = hipError_t (*)(const BArgs&);
+using Describer = size_t (*)(const KArgs&, void* out);
+
 struct KernelSet {
     Launcher links = nullptr;    // the boundary-link kernel of a step (no-op at t = 0)
     Launcher sweep = nullptr;    // the fused sweep of a step
@@ -77,6 +106,15 @@ struct KernelSet {
     Launcher observe = nullptr;  // moments / populations / reductions at the current time
     Launcher init = nullptr;     // equilibrium initialisation
     int QT = 0;                  // population planes
+    // batched items
+    Describer describe = nullptr;  // writes one item descriptor from its launch description
+    size_t item_bytes = 0;         // size of one item descriptor
+    BLauncher b_sweep = nullptr;   // fused sweep over node tiles of many items
+    BLauncher b_links = nullptr;   // boundary links over link tiles of many items
+    BLauncher b_resident = nullptr;  // one workgroup per item, nsteps steps per launch
+    BLauncher b_reduce = nullptr;  // links, then per-item FP64 sums over node tiles
+    BLauncher b_judge = nullptr;   // per-item residual, steady / non-finite flags
+    BLauncher b_clear = nullptr;   // zero the per-item accumulators and counters
 };
 
 // storage codes as in lbm.h

@@ -114,15 +114,26 @@ def required_bytes(p: L.lbm_params, n_links: int):
     return list(sizes)
 
 
+def _torch_device(torch, device):
+    if not torch.cuda.is_available():
+        raise RuntimeError("liblbm needs a HIP device")
+    return torch.device(device)
+
+
+def _pool(torch, device, sizes):
+    bufs = [torch.empty(max(s, 1), dtype=torch.uint8, device=device) for s in sizes]
+    ptrs = (C.c_void_p * L.LBM_NBUF)(*[b.data_ptr() if s > 0 else None for b, s in zip(bufs, sizes)])
+    return bufs, ptrs
+
+
 class Lattice:
     """One context of the fused coupled sweep on a torch device and stream."""
 
     def __init__(self, sc, device: str = "cuda", stream=None, links: Optional[np.ndarray] = None,
-                 mask: Optional[np.ndarray] = None, init: bool = True):
+                 mask: Optional[np.ndarray] = None, init: bool = True, _ctx=None, _owner=None):
         import torch
-        if not torch.cuda.is_available():
-            raise RuntimeError("liblbm needs a HIP device")
         self.torch = torch
+        self.device = _torch_device(torch, device)
         self.scene = sc
         self.params = params_from_scene(sc)
         if links is None or mask is None:
@@ -130,16 +141,17 @@ class Lattice:
         self.mask = np.ascontiguousarray(mask, np.uint8).reshape(-1)
         self.links = np.ascontiguousarray(links)
         self.n_links = len(self.links)
-        self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.sizes = required_bytes(self.params, self.n_links)
-        self.bufs = [torch.empty(max(s, 1), dtype=torch.uint8, device=self.device) for s in self.sizes]
-        ptrs = (C.c_void_p * L.LBM_NBUF)(*[b.data_ptr() if s > 0 else None
-                                          for b, s in zip(self.bufs, self.sizes)])
-        ctx = C.c_void_p()
-        L.check(L.lib().lbm_create(C.byref(self.params), self.n_links, ptrs,
-                                   C.c_void_p(self.stream.cuda_stream), C.byref(ctx)), what="lbm_create")
-        self.ctx = ctx
+        self._owner = _owner
+        if _ctx is None:
+            self.sizes = required_bytes(self.params, self.n_links)
+            self.bufs, ptrs = _pool(torch, self.device, self.sizes)
+            ctx = C.c_void_p()
+            L.check(L.lib().lbm_create(C.byref(self.params), self.n_links, ptrs,
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(ctx)), what="lbm_create")
+            self.ctx = ctx
+        else:
+            self.ctx = _ctx  # an item of a Batch (owned by it)
         self._call("lbm_set_geometry", self.mask.ctypes.data_as(C.c_void_p))
         self._call("lbm_set_links", self.links.ctypes.data_as(C.c_void_p), self.n_links)
         self.N = sc.nodes
@@ -152,9 +164,9 @@ class Lattice:
 
     def __del__(self):
         try:
-            if getattr(self, "ctx", None):
+            if getattr(self, "ctx", None) and self._owner is None:
                 L.lib().lbm_destroy(self.ctx)
-                self.ctx = None
+            self.ctx = None
         except Exception:
             pass
 
@@ -233,3 +245,89 @@ class Lattice:
     def load(self, blob: bytes):
         buf = (C.c_char * len(blob)).from_buffer_copy(blob)
         self._call("lbm_load", buf)
+
+
+class Batch:
+    """lbm_batch_*: many independent scenes (one lattice combination and
+    storage) advanced by shared launches.  ``items[i]`` is a Lattice view of
+    item i (geometry, links, init and readback go through the single-context
+    calls)."""
+
+    def __init__(self, scs, device: str = "cuda", stream=None, init: bool = True, tables=None):
+        import torch
+        self.torch = torch
+        self.device = _torch_device(torch, device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.scenes = list(scs)
+        n = len(self.scenes)
+        if tables is None:
+            tables = [build_links(sc) for sc in self.scenes]
+        self.params = (L.lbm_params * n)(*[params_from_scene(sc) for sc in self.scenes])
+        self.cap = (C.c_size_t * n)(*[len(t[1]) for t in tables])
+        sizes = (C.c_size_t * L.LBM_NBUF)()
+        if L.lib().lbm_batch_required_bytes(n, self.params, self.cap, sizes) == 0:
+            raise L.LbmError(-1, "invalid batch (parameters, or items differ in lattices or storage)")
+        self.sizes = list(sizes)
+        self.bufs, ptrs = _pool(torch, self.device, self.sizes)
+        b = C.c_void_p()
+        L.check(L.lib().lbm_batch_create(n, self.params, self.cap, ptrs, C.c_void_p(self.stream.cuda_stream),
+                                         C.byref(b)), what="lbm_batch_create")
+        self.b = b
+        self.items = []
+        for i, (sc, (mask, links)) in enumerate(zip(self.scenes, tables)):
+            ctx = C.c_void_p(L.lib().lbm_batch_item(self.b, i))
+            self.items.append(Lattice(sc, device=device, stream=self.stream, links=links, mask=mask,
+                                      init=init, _ctx=ctx, _owner=self))
+
+    def _call(self, name, *args):
+        code = getattr(L.lib(), name)(self.b, *args)
+        if code != 0:
+            raise L.LbmError(code, L.lib().lbm_batch_last_error(self.b).decode())
+
+    def __len__(self):
+        return len(self.items)
+
+    def __del__(self):
+        try:
+            if getattr(self, "b", None):
+                for it in self.items:
+                    it.ctx = None
+                L.lib().lbm_batch_destroy(self.b)
+                self.b = None
+        except Exception:
+            pass
+
+    @property
+    def config(self) -> dict:
+        c = L.lbm_batch_config()
+        self._call("lbm_batch_get_config", C.byref(c))
+        return dict(mode={1: "tiled", 2: "resident"}[c.mode], block=c.block,
+                    steps_per_launch=c.steps_per_launch, graph_steps=c.graph_steps)
+
+    def configure(self, mode: str = "tiled", block: int = 256, steps_per_launch: int = 1, graph_steps: int = 64):
+        c = L.lbm_batch_config({"tiled": 1, "resident": 2}[mode], block, steps_per_launch, graph_steps)
+        self._call("lbm_batch_configure", C.byref(c))
+
+    def step(self, n: int = 1):
+        self._call("lbm_batch_step", int(n))
+
+    def run(self, tol: float = 1e-8, interval: int = 100, max_steps: int = 10 ** 7):
+        """lbm_batch_run: per item (steps, residual, status name)."""
+        n = len(self.items)
+        steps = (C.c_int64 * n)()
+        res = (C.c_double * n)()
+        st = (C.c_int32 * n)()
+        self._call("lbm_batch_run", float(tol), int(interval), int(max_steps), steps, res, st)
+        return np.array(steps[:]), np.array(res[:]), [L.ITEM_STATUS[s] for s in st[:]]
+
+    def tune(self, trial_steps: int = 128):
+        """lbm_batch_tune: (best config dict, [(config dict, ms per step)])."""
+        cap = 32
+        cands = (L.lbm_batch_config * cap)()
+        ms = (C.c_double * cap)()
+        nout = C.c_int32()
+        best = L.lbm_batch_config()
+        self._call("lbm_batch_tune", int(trial_steps), C.byref(best), cands, ms, cap, C.byref(nout))
+        conv = lambda c: dict(mode={1: "tiled", 2: "resident"}[c.mode], block=c.block,
+                              steps_per_launch=c.steps_per_launch, graph_steps=c.graph_steps)
+        return conv(best), [(conv(cands[k]), ms[k]) for k in range(nout.value)]

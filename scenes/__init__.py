@@ -356,17 +356,19 @@ class BatchItem:
     nz: int
     q: Tuple[float, ...]  # duct: (y-lo, y-hi, z-lo, z-hi); pipe: (q,)
     Ha: float
-    c_w: float
+    c_w: float                # drawn wall conductance ratio
+    c_eff: Tuple[float, ...]  # ratio each wall carries (c_w raised to the stable limit of a1), order of q
     scene: Scene
 
 
-# The flux increment is explicit: the wall term a1 * B_X added to one bounced
-# population per link diverges once |a1| (times the link's share of the
-# surface) passes about 1.5 in lattice units.  Walls with eta/(c_w H) above
-# these limits are, to within c_w H / H, insulating already; their
-# coefficient is capped so that every item stays inside the stable range.
-A1_MAX_FLAT = 1.0
-A1_MAX_CURVED = 0.7
+# The wall flux is explicit: every step adds a1 * weight * B_X to one bounced
+# population per link.  It diverges once a node's links together pass the
+# explicit limit: at duct corners with d near 0.1 that happens between
+# |a1| = 0.4 and 0.5, on pipe walls between 0.5 and 0.7 (FP64 runs of 3000
+# steps over widths 16-64 and d in [0.1, 0.9]).  Walls whose eta / (c_w H)
+# exceeds A1_MAX carry |a1| = A1_MAX instead, i.e. the conductance ratio
+# c_eff = eta / (A1_MAX H) > c_w; the item records both.
+A1_MAX = 0.3
 
 
 def batch_items(n_items: int = 256, seed: int = BASE_SEED + 5, side_lo: int = 64,
@@ -393,11 +395,13 @@ def batch_items(n_items: int = 256, seed: int = BASE_SEED + 5, side_lo: int = 64
             B0 = hartmann_B0(Ha, Hy, 1.0, nu, eta, 1.0)
             # Poiseuille-duct centre speed ~ g h^2/(2 nu) * 0.59 (h = short half side)
             g = u_target * 2.0 * nu / (0.59 * Hmin * Hmin * (1.0 + 0.0 * Hy))
-            bnds = []
+            bnds, c_eff = [], []
             for ax, (side, qq) in [(1, (0, qs[0])), (1, (1, qs[1])), (2, (0, qs[2])), (2, (1, qs[3]))]:
                 H = Hy if ax == 1 else Hz
+                a1 = min(eta / (c_w * H), A1_MAX)
+                c_eff.append(eta / (a1 * H))
                 bnds.append(Boundary("plane", axis=ax, side=side, q=qq, f=BC(VEL),
-                                     g=[BC(MAG_FLUX, a1=-min(eta / (c_w * H), A1_MAX_FLAT), a3=0.0)]))
+                                     g=[BC(MAG_FLUX, a1=-a1, a3=0.0)]))
             ny, nz = a, b
         else:
             s = rng.randint(side_lo, side_hi)
@@ -406,15 +410,17 @@ def batch_items(n_items: int = 256, seed: int = BASE_SEED + 5, side_lo: int = 64
             B0 = hartmann_B0(Ha, R, 1.0, nu, eta, 1.0)
             g = u_target * 4.0 * nu / (R * R)
             c = (s - 1) / 2.0
+            a1 = min(eta / (c_w * R), A1_MAX)
+            c_eff = [eta / (a1 * R)]
             bnds = [Boundary("cylinder", axis=0, center=(0.0, c, c), radius=R, f=BC(VEL),
-                             g=[BC(MAG_FLUX, a1=-min(eta / (c_w * R), A1_MAX_CURVED), a3=0.0)])]
+                             g=[BC(MAG_FLUX, a1=-a1, a3=0.0)])]
             ny = nz = s
             qs = (qq,)
         sc = Scene(name=f"item{i}_{shape}", dim=3, n=(1, ny, nz), periodic=(True, False, False),
                    fluid_lattice=D3Q19, mag_lattice=D3Q7, mag_comps=(0,), tau_f=tau_f,
                    tau_m=tau_m, B_ext=(0.0, B0, 0.0), accel=(g, 0.0, 0.0), boundaries=bnds,
                    storage=storage, store_scale=(1024.0, 1.0, 1024.0))
-        items.append(BatchItem(shape, ny, nz, qs, Ha, c_w, sc))
+        items.append(BatchItem(shape, ny, nz, qs, Ha, c_w, tuple(c_eff), sc))
     return items
 
 

@@ -1,0 +1,156 @@
+"""Batched items (lbm_batch_*): every item of a batch evolves exactly as the
+same scene run alone, in every execution mode (batch invariance); the
+device-side steady-state detection stops each item where the single-context
+residual says it is steady; the autotuner's trial steps are real steps."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from .gpu_util import field_errors, gpu_moments
+from paper_2506_00907_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+MODES = [("tiled", 256, 1, 64), ("tiled", 64, 1, 64), ("resident", 256, 2, 64), ("resident", 1024, 8, 64),
+         ("resident", 512, 32, 64)]
+
+
+def duct_pipe_items(storage, n=5, lo=20, hi=44, seed=None, developed=True, Ha_hi=8.0):
+    """Small duct / pipe items; Ha is capped so that B0 stays well below the
+    lattice speeds at these widths (the full-size items are 64-256 wide)."""
+    kw = {} if seed is None else {"seed": seed}
+    its = scenes.batch_items(n, side_lo=lo, side_hi=hi, storage=storage, Ha_hi=Ha_hi, **kw)
+    scs = [it.scene for it in its]
+    if developed:
+        scs = [scenes.developed(sc, seed=1000 + i, u_amp=0.005) for i, sc in enumerate(scs)]
+    return scs
+
+
+def reactive_items(storage):
+    shapes = [(40, 20, 0.3), (57, 26, 0.7), (33, 31, 0.5)]
+    return [scenes.developed(scenes.reactive_channel(nx=nx, ny=ny, q=q, k_range=(1e-3, 1e-1), storage=storage),
+                             seed=2000 + i, u_amp=0.005)
+            for i, (nx, ny, q) in enumerate(shapes)]
+
+
+def assert_items_equal_alone(B, scs, steps):
+    for i, sc in enumerate(scs):
+        alone = lbm.Lattice(sc)
+        alone.step(steps)
+        assert B.items[i].time == alone.time == steps
+        a, b = gpu_moments(B.items[i]), gpu_moments(alone)
+        assert np.isfinite(a).all()
+        assert np.array_equal(a, b), (i, np.abs(a - b).max())
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("mode", MODES, ids=lambda m: f"{m[0]}{m[1]}x{m[2]}")
+def test_batch_item_equals_item_alone(storage, mode):
+    scs = duct_pipe_items(storage)
+    B = lbm.Batch(scs)
+    B.configure(*mode)
+    B.step(130)  # two single steps from time 0, two captured runs of 64 steps
+    assert_items_equal_alone(B, scs, 130)
+
+
+@pytest.mark.parametrize("mode", [MODES[0], MODES[3]], ids=["tiled", "resident"])
+def test_batch_of_2d_channels_equals_alone(mode):
+    scs = reactive_items("f32")
+    B = lbm.Batch(scs)
+    B.configure(*mode)
+    B.step(71)  # odd count: a single step after the captured run
+    assert_items_equal_alone(B, scs, 71)
+
+
+def test_batch_fp64_item_matches_oracle():
+    scs = duct_pipe_items("f64", n=3, lo=16, hi=24)
+    B = lbm.Batch(scs)
+    B.configure("resident", 256, 8, 64)
+    B.step(66)
+    for i, sc in enumerate(scs):
+        o = oracle.OracleSim(sc, "ld")
+        o.step(66)
+        err = field_errors(gpu_moments(B.items[i]), o.moments(), o.mask(), sc.B_ext)
+        assert max(err.values()) < 1e-12, (i, err)
+
+
+def test_batch_run_stops_each_item_where_its_residual_is_below_tol():
+    scs = duct_pipe_items("f32", n=4, lo=14, hi=22, seed=77, developed=False, Ha_hi=5.0)
+    B = lbm.Batch(scs)
+    B.configure("resident", 256, 8, 64)
+    tol, I = 1e-6, 100
+    steps, res, status = B.run(tol=tol, interval=I, max_steps=40000)
+    assert status == ["steady"] * len(scs), (status, steps, res)
+    assert (res < tol).all() and (res > 0).all()
+    assert len(set(steps.tolist())) > 1  # items converge at their own pace
+    for i, sc in enumerate(scs):
+        # the same residual with the single-context reduction, evaluated at
+        # the same times: snapshot after the two start steps and one interval
+        alone = lbm.Lattice(sc)
+        alone.step(2 + I)
+        alone.reduce()
+        t_steady = None
+        while alone.time < 40000:
+            alone.step(I)
+            r = alone.reduce()[0]
+            if r < tol:
+                t_steady = alone.time
+                break
+        assert t_steady == steps[i], (i, t_steady, steps[i])
+        assert B.items[i].time == steps[i]
+        assert np.array_equal(gpu_moments(B.items[i]), gpu_moments(alone))
+
+
+def test_batch_run_respects_max_steps():
+    scs = duct_pipe_items("f32", n=3, lo=30, hi=40, developed=False)
+    B = lbm.Batch(scs)
+    steps, res, status = B.run(tol=1e-12, interval=50, max_steps=302)
+    assert status == ["active"] * 3
+    assert (steps == 302).all()  # 2 start steps + 6 intervals of 50
+    assert (res > 0).all()
+
+
+def test_batch_run_flags_a_nonfinite_item_and_keeps_the_others():
+    scs = duct_pipe_items("f32", n=3, lo=20, hi=24, developed=False)
+    scs[1] = scs[1].with_(accel=(0.5, 0.0, 0.0), tau_f=0.5001)
+    B = lbm.Batch(scs)
+    steps, res, status = B.run(tol=1e-12, interval=20, max_steps=2002)
+    assert status[1] == "nonfinite"
+    assert status[0] == status[2] == "active"
+    assert steps[1] < 2002 and steps[0] == steps[2] == 2002
+    for i in (0, 2):
+        assert np.isfinite(gpu_moments(B.items[i])).all()
+
+
+def test_tuner_candidates_and_real_steps():
+    scs = duct_pipe_items("f16", n=6, lo=24, hi=48)
+    B = lbm.Batch(scs)
+    best, cands = B.tune(trial_steps=64)
+    assert len(cands) == 12
+    assert all(ms > 0 for _, ms in cands)
+    assert best in [c for c, _ in cands]
+    assert min(cands, key=lambda c: c[1])[0] == best
+    assert B.config == best
+    t = B.items[0].time
+    assert t == 2 + 12 * 128
+    assert_items_equal_alone(B, scs, t)
+
+
+def test_full_size_fp16_items_against_fp32_batch():
+    its = scenes.batch_items(8)
+    s16 = [scenes.developed(it.scene, seed=3000 + i, u_amp=0.005) for i, it in enumerate(its)]
+    s32 = [sc.with_(storage="f32") for sc in s16]
+    B16, B32 = lbm.Batch(s16), lbm.Batch(s32)
+    B16.configure("resident", 1024, 32, 64)
+    B16.step(258)
+    B32.step(258)
+    for i in range(len(its)):
+        m16, m32 = gpu_moments(B16.items[i]), gpu_moments(B32.items[i])
+        err = field_errors(m16, m32, B16.items[i].mask.reshape(m16.shape[:3]), s16[i].B_ext)
+        assert np.isfinite(m16).all()
+        assert err["rho"] < 1e-3 and err["u"] < 3e-2 and err["b"] < 3e-2, (i, err)
+    # one item of the FP16 batch against the same item alone
+    alone = lbm.Lattice(s16[0])
+    alone.step(258)
+    assert np.array_equal(gpu_moments(B16.items[0]), gpu_moments(alone))

@@ -233,3 +233,95 @@ def test_builder_rejects_uncovered_boundary():
     sc.boundaries[1].f = None
     with pytest.raises(L.LbmError):
         lbm.build_links(sc)
+
+
+# ---------------------------------------------------------------------------
+# batches (host-side checks only)
+# ---------------------------------------------------------------------------
+def _batch_params(scs):
+    n = len(scs)
+    return (L.lbm_params * n)(*[lbm.params_from_scene(s) for s in scs])
+
+
+def test_batch_layout_is_items_back_to_back():
+    items = [it.scene for it in scenes.batch_items(4, side_lo=20, side_hi=40)]
+    tables = [lbm.build_links(sc) for sc in items]
+    params = _batch_params(items)
+    caps = (C.c_size_t * 4)(*[len(t[1]) for t in tables])
+    sizes = (C.c_size_t * L.LBM_NBUF)()
+    tot = L.lib().lbm_batch_required_bytes(4, params, caps, sizes)
+    assert tot == sum(sizes)
+    for k in range(5):
+        per = [lbm.required_bytes(params[i], caps[i])[k] for i in range(4)]
+        assert sizes[k] == sum(((s + 255) // 256) * 256 for s in per)
+    assert all(sizes[k] > 0 for k in range(5, 8))
+    assert all(s % 256 == 0 for s in sizes)
+
+
+def test_batch_rejects_mixed_items():
+    a = scenes.batch_items(2, side_lo=20, side_hi=30)[0].scene
+    b = a.with_(storage="f32")
+    c = scenes.hartmann_couette(nx=4, ny=9)
+    sizes = (C.c_size_t * L.LBM_NBUF)()
+    for pair in ([a, b], [a, c]):
+        caps = (C.c_size_t * 2)(10, 10)
+        assert L.lib().lbm_batch_required_bytes(2, _batch_params(pair), caps, sizes) == 0
+    assert L.lib().lbm_batch_required_bytes(0, _batch_params([a]), (C.c_size_t * 1)(10), sizes) == 0
+    bad = a.with_(tau_f=0.4)
+    assert L.lib().lbm_batch_required_bytes(1, _batch_params([bad]), (C.c_size_t * 1)(10), sizes) == 0
+
+
+class _FakeBatch:
+    """A batch over fake aligned device addresses: creation, item contexts,
+    configuration and the state checks never touch device memory."""
+
+    def __init__(self, scs):
+        n = len(scs)
+        self.tables = [lbm.build_links(sc) for sc in scs]
+        self.params = _batch_params(scs)
+        self.caps = (C.c_size_t * n)(*[len(t[1]) for t in self.tables])
+        sizes = (C.c_size_t * L.LBM_NBUF)()
+        assert L.lib().lbm_batch_required_bytes(n, self.params, self.caps, sizes) > 0
+        base, ptrs = 1 << 40, []
+        for s in sizes:
+            ptrs.append(base if s else None)
+            base += ((s + (1 << 20)) >> 20) << 20
+        self.b = C.c_void_p()
+        assert L.lib().lbm_batch_create(n, self.params, self.caps, (C.c_void_p * L.LBM_NBUF)(*ptrs), None,
+                                        C.byref(self.b)) == 0
+
+    def err(self):
+        return L.lib().lbm_batch_last_error(self.b).decode()
+
+    def __del__(self):
+        L.lib().lbm_batch_destroy(self.b)
+
+
+def test_batch_items_and_configuration():
+    scs = [it.scene for it in scenes.batch_items(3, side_lo=20, side_hi=30)]
+    fb = _FakeBatch(scs)
+    lib = L.lib()
+    items = [lib.lbm_batch_item(fb.b, i) for i in range(3)]
+    assert all(items) and len(set(items)) == 3
+    assert lib.lbm_batch_item(fb.b, 3) is None and lib.lbm_batch_item(fb.b, -1) is None
+    # an item belongs to the batch: destroy is a no-op, its stream is fixed
+    lib.lbm_destroy(items[0])
+    assert lib.lbm_set_stream(items[0], None) == -1
+    # the geometry of an item goes through the single-context call
+    mask = fb.tables[0][0]
+    assert lib.lbm_set_geometry(items[0], mask.ctypes.data_as(C.c_void_p)) == 0
+    cfg = L.lbm_batch_config()
+    assert lib.lbm_batch_get_config(fb.b, C.byref(cfg)) == 0
+    assert (cfg.mode, cfg.block, cfg.steps_per_launch, cfg.graph_steps) == (1, 256, 1, 64)
+    good = [(1, 64, 1, 64), (1, 128, 1, 2), (2, 1024, 2, 64), (2, 256, 32, 64), (2, 64, 8, 8)]
+    bad = [(1, 96, 1, 64), (1, 256, 2, 64), (2, 1088, 2, 64), (2, 256, 3, 64), (2, 256, 8, 12),
+           (2, 100, 2, 64), (3, 256, 1, 64), (1, 256, 1, 63)]
+    for g in good:
+        assert lib.lbm_batch_configure(fb.b, C.byref(L.lbm_batch_config(*g))) == 0, g
+    for bcfg in bad:
+        assert lib.lbm_batch_configure(fb.b, C.byref(L.lbm_batch_config(*bcfg))) == -1, bcfg
+    # stepping needs every item initialised
+    assert lib.lbm_batch_step(fb.b, 4) == -5
+    assert "not initialised" in fb.err()
+    assert lib.lbm_batch_run(fb.b, 1e-8, 3, 100, None, None, None) == -1   # odd interval
+    assert lib.lbm_batch_tune(fb.b, 1, None, None, None, 0, None) == -1
