@@ -29,6 +29,34 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # bytes/s, MI355X
 
+# HBM bytes per launch of the fused sweep (mean of the two parities) from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE passes of the commands listed in
+# profiles/, scaled by the same counters of a 1 GiB device copy (FETCH_SIZE
+# reports half of the bytes read, WRITE_SIZE all bytes written): 2 x FETCH +
+# WRITE.  Valid only for the kernel source they were taken with.
+KERNEL_SOURCES = ("paper_2506_00907_amd/csrc/lbm_device.hpp", "paper_2506_00907_amd/csrc/lbm_internal.hpp")
+MEASURED_TRAFFIC = {
+    # (workload, storage): (kernel source digest, bytes per launch)
+    ("reactive", "f32"): ("e1694ec413e8df2e", 15110144.0),
+    ("hartmann_wide", "f32"): ("e1694ec413e8df2e", 2576588800.0),
+}
+
+
+def kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, storage: str):
+    rec = MEASURED_TRAFFIC.get((workload, storage))
+    if rec is None or rec[0] != kernel_digest():
+        return None
+    return rec[1]
+
 
 def make_scene(name: str, storage: str):
     import scenes
@@ -96,6 +124,37 @@ def time_launches(lat, n: int = 200):
     return lat.step_timed(n)
 
 
+def bench_batch(n_items: int, steps: int, storage: str = "f16", tune: bool = True):
+    """The duct/pipe cross-section batch (D3Q19 + D3Q7, 64-256 wide, FP16
+    storage): autotuned configuration, then `steps` steps of every item timed
+    with HIP events on the batch's stream."""
+    import torch
+    import scenes
+    from paper_2506_00907_amd import lbm
+    its = scenes.batch_items(n_items, storage=storage)
+    B = lbm.Batch([it.scene for it in its])
+    tuned = None
+    if tune:
+        best, cands = B.tune(trial_steps=64)
+        tuned = {"best": best, "candidates": [dict(c, ms_per_step=round(ms, 5)) for c, ms in cands]}
+    ab = [algorithmic_bytes(it) for it in B.items]
+    n_fluid = sum(a["fluid_nodes"] for a in ab)
+    step_bytes = sum(a["sweep"] + a["links"] for a in ab)
+    B.step(64)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(B.stream)
+    B.step(steps)
+    t1.record(B.stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    return dict(items=n_items, storage=storage, fluid_nodes=n_fluid, links=sum(a["n_links"] for a in ab),
+                steps=steps, ms_per_step=ms / steps, mlups=n_fluid * steps / (ms / 1e3) / 1e6,
+                bytes_per_step=step_bytes, hbm_frac=step_bytes / (ms / steps / 1e3) / HBM_PEAK,
+                config=B.config, tuning=tuned)
+
+
 def cpu_baseline(sc, budget_s: float = 12.0):
     import oracle
     o = oracle.OracleSim(sc)
@@ -122,6 +181,10 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", action="store_true", help="add throughput of the other workloads")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only time a plain 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--batch", type=int, default=0, metavar="N",
+                    help="add the batch of N duct/pipe cross-sections (autotuned)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the sweep shards by "
@@ -132,6 +195,24 @@ def main():
     from paper_2506_00907_amd import lbm
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # 1 GiB read + 1 GiB written per copy: the byte counters of this copy
+        # calibrate those of the sweep
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / 10
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "ms": ms,
+                          "GB/s": 2 * (1 << 30) / (ms / 1e3) / 1e9}))
+        return
     sc, desc = make_scene(args.workload, args.storage)
     lat = lbm.Lattice(sc)
     ab = algorithmic_bytes(lat)
@@ -159,7 +240,7 @@ def main():
                    "links": ab["n_links"],
                    "launch": "hipGraph of 64 steps (link kernel + fused sweep each), 256 threads/block"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": None,
+                     "frac": achieved / HBM_PEAK, "traffic": measured_traffic(args.workload, args.storage),
                      "kernel": "k_step (fused stream-collide sweep), both parities",
                      "bytes_per_launch": ab["sweep"], "mean_launch_ms": sweep_ms,
                      "link_kernel": {"bytes_per_launch": ab["links"], "mean_launch_ms": link_ms}},
@@ -179,6 +260,8 @@ def main():
             del l2
             torch.cuda.empty_cache()
         out["extra"] = extra
+    if args.batch:
+        out["batch"] = bench_batch(args.batch, 1000)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(out))
