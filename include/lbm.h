@@ -321,6 +321,69 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t trial_steps, lbm_batch_config* b
 const char* lbm_batch_last_error(const lbm_batch* b);
 void lbm_batch_destroy(lbm_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Warm-start network: a three-level convolutional encoder-decoder mapping
+ * per-node geometry and parameter maps of a cross-section (fluid mask, wall
+ * distance, Hartmann number, wall conductance) to its steady fields (scaled
+ * axial velocity and induced field), used to initialise a lattice through
+ * lbm_init.  The lattice update always runs to convergence from that state,
+ * so the network only changes where the iteration starts.
+ *
+ * Layers (w = width, S = size, all 3x3 convolutions with ReLU, zero padding):
+ *   e1: in_ch -> w -> w        at S          (skip 1)
+ *   2x2 average pooling
+ *   e2: w -> 2w -> 2w          at S/2        (skip 2)
+ *   2x2 average pooling
+ *   e3: 2w -> 4w -> 4w         at S/4
+ *   nearest x2 upsampling, concatenated with skip 2 (6w channels)
+ *   d2: 6w -> 2w -> 2w         at S/2
+ *   nearest x2 upsampling, concatenated with skip 1 (3w channels)
+ *   d1: 3w -> w -> w           at S
+ *   head: 1x1 convolution w -> out_ch, linear.
+ * Parameters, FP32, in this layer order: W[c_out][c_in][ky][kx] then b[c_out]
+ * per layer (w = 32, in_ch = 4, out_ch = 2: 471,874 parameters).
+ * Convolutions, their input gradients and weight gradients run on the matrix
+ * cores: BF16 activations and weights with FP32 accumulation (precision
+ * LBM_BF16), or FP32 throughout (LBM_F32, for gradient checks).  Adam keeps
+ * FP32 master weights and moments.
+ * Images are NHWC FP32: x [n][S][S][in_ch], y and target [n][S][S][out_ch],
+ * weight [n][S][S].  The loss is sum_p weight_p sum_c (y - target)^2 / out_ch.
+ * --------------------------------------------------------------------------- */
+typedef struct lbm_nn lbm_nn;
+
+typedef struct {
+    int32_t batch;      /* largest number of images per call */
+    int32_t size;       /* image side S, a multiple of 8 */
+    int32_t in_ch;      /* input channels, 1..16 */
+    int32_t out_ch;     /* output channels, 1..32 */
+    int32_t width;      /* channels of the first level, a multiple of 32 */
+    int32_t precision;  /* LBM_BF16 or LBM_F32 */
+} lbm_nn_desc;
+
+/* Sizes of the 4 device buffers: 0 parameters, gradients and Adam moments
+ * (FP32), 1 compute weights, 2 activations, their gradients and scratch, 3 the
+ * loss accumulator.  Returns the sum, 0 on an invalid description. */
+size_t lbm_nn_required_bytes(const lbm_nn_desc* d, size_t sizes_out[4]);
+lbm_status lbm_nn_create(const lbm_nn_desc* d, void* const dev_bufs[4], void* hip_stream, lbm_nn** out);
+int64_t lbm_nn_num_params(const lbm_nn* n);
+/* Copies the parameters from dev_params (device, num_params FP32) and resets
+ * the Adam state. */
+lbm_status lbm_nn_set_params(lbm_nn* n, const float* dev_params);
+lbm_status lbm_nn_get_params(lbm_nn* n, float* dev_out);
+/* Forward pass of n <= batch images; dev_y may be NULL (the output stays
+ * inside for lbm_nn_backward).  Asynchronous. */
+lbm_status lbm_nn_forward(lbm_nn* n, int32_t n_images, const float* dev_x, float* dev_y);
+/* Loss and parameter gradients of the last forward pass against dev_target
+ * and dev_weight; host_loss (may be NULL) receives the loss after a
+ * synchronisation. */
+lbm_status lbm_nn_backward(lbm_nn* n, const float* dev_target, const float* dev_weight, double* host_loss);
+lbm_status lbm_nn_get_grads(lbm_nn* n, float* dev_out);
+/* One Adam update of the FP32 master weights with the current gradients
+ * (bias-corrected moments), then the compute weights are refreshed. */
+lbm_status lbm_nn_adam_step(lbm_nn* n, float lr, float beta1, float beta2, float eps);
+const char* lbm_nn_last_error(const lbm_nn* n);
+void lbm_nn_destroy(lbm_nn* n);
+
 #ifdef __cplusplus
 }
 #endif

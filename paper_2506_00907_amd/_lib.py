@@ -57,6 +57,11 @@ class lbm_batch_config(C.Structure):
                 ("graph_steps", C.c_int32)]
 
 
+class lbm_nn_desc(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("size", C.c_int32), ("in_ch", C.c_int32), ("out_ch", C.c_int32),
+                ("width", C.c_int32), ("precision", C.c_int32)]
+
+
 LBM_BATCH_TILED, LBM_BATCH_RESIDENT = 1, 2
 ITEM_STATUS = {0: "active", 1: "steady", 2: "nonfinite"}
 
@@ -98,6 +103,17 @@ SIGNATURES = {
                                  C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
     "lbm_batch_last_error": (C.c_char_p, [_VP]),
     "lbm_batch_destroy": (None, [_VP]),
+    "lbm_nn_required_bytes": (C.c_size_t, [C.POINTER(lbm_nn_desc), C.POINTER(C.c_size_t)]),
+    "lbm_nn_create": (C.c_int, [C.POINTER(lbm_nn_desc), C.POINTER(_VP), _VP, C.POINTER(_VP)]),
+    "lbm_nn_num_params": (C.c_int64, [_VP]),
+    "lbm_nn_set_params": (C.c_int, [_VP, _VP]),
+    "lbm_nn_get_params": (C.c_int, [_VP, _VP]),
+    "lbm_nn_forward": (C.c_int, [_VP, C.c_int32, _VP, _VP]),
+    "lbm_nn_backward": (C.c_int, [_VP, _VP, _VP, C.POINTER(C.c_double)]),
+    "lbm_nn_get_grads": (C.c_int, [_VP, _VP]),
+    "lbm_nn_adam_step": (C.c_int, [_VP, C.c_float, C.c_float, C.c_float, C.c_float]),
+    "lbm_nn_last_error": (C.c_char_p, [_VP]),
+    "lbm_nn_destroy": (None, [_VP]),
 }
 
 _lib = None

@@ -331,3 +331,92 @@ class Batch:
         conv = lambda c: dict(mode={1: "tiled", 2: "resident"}[c.mode], block=c.block,
                               steps_per_launch=c.steps_per_launch, graph_steps=c.graph_steps)
         return conv(best), [(conv(cands[k]), ms[k]) for k in range(nout.value)]
+
+
+class Network:
+    """lbm_nn_*: the warm-start encoder-decoder on torch device buffers.
+    Images are NHWC float32 device tensors."""
+
+    def __init__(self, batch: int, size: int, in_ch: int = 4, out_ch: int = 2, width: int = 32,
+                 precision: str = "bf16", device: str = "cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.device = _torch_device(torch, device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.desc = L.lbm_nn_desc(batch, size, in_ch, out_ch, width,
+                                  {"bf16": L.LBM_BF16, "f32": L.LBM_F32}[precision])
+        sizes = (C.c_size_t * 4)()
+        if L.lib().lbm_nn_required_bytes(C.byref(self.desc), sizes) == 0:
+            raise L.LbmError(-1, "invalid network description")
+        self.sizes = list(sizes)
+        self.bufs = [torch.empty(s, dtype=torch.uint8, device=self.device) for s in self.sizes]
+        ptrs = (C.c_void_p * 4)(*[b.data_ptr() for b in self.bufs])
+        n = C.c_void_p()
+        L.check(L.lib().lbm_nn_create(C.byref(self.desc), ptrs, C.c_void_p(self.stream.cuda_stream), C.byref(n)),
+                what="lbm_nn_create")
+        self.n = n
+        self.size, self.in_ch, self.out_ch, self.batch = size, in_ch, out_ch, batch
+
+    def _call(self, name, *args):
+        code = getattr(L.lib(), name)(self.n, *args)
+        if code != 0:
+            raise L.LbmError(code, L.lib().lbm_nn_last_error(self.n).decode())
+
+    def __del__(self):
+        try:
+            if getattr(self, "n", None):
+                L.lib().lbm_nn_destroy(self.n)
+                self.n = None
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(L.lib().lbm_nn_num_params(self.n))
+
+    def _dev(self, a, shape=None):
+        t = self.torch.as_tensor(a, dtype=self.torch.float32, device=self.device).contiguous()
+        if shape is not None:
+            assert tuple(t.shape) == tuple(shape), (tuple(t.shape), shape)
+        return t
+
+    def set_params(self, theta):
+        t = self._dev(theta).reshape(-1)
+        assert t.numel() == self.num_params
+        self._call("lbm_nn_set_params", C.c_void_p(t.data_ptr()))
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+    def params(self):
+        out = self.torch.empty(self.num_params, dtype=self.torch.float32, device=self.device)
+        self._call("lbm_nn_get_params", C.c_void_p(out.data_ptr()))
+        return out
+
+    def grads(self):
+        out = self.torch.empty(self.num_params, dtype=self.torch.float32, device=self.device)
+        self._call("lbm_nn_get_grads", C.c_void_p(out.data_ptr()))
+        return out
+
+    def forward(self, x, out=None):
+        """x [n, S, S, in_ch] -> y [n, S, S, out_ch]."""
+        x = self._dev(x)
+        n = x.shape[0]
+        assert tuple(x.shape[1:]) == (self.size, self.size, self.in_ch)
+        if out is None:
+            out = self.torch.empty((n, self.size, self.size, self.out_ch), dtype=self.torch.float32,
+                                   device=self.device)
+        self._x = x  # kept alive while the launches run
+        self._call("lbm_nn_forward", int(n), C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()))
+        return out
+
+    def backward(self, target, weight, want_loss: bool = True):
+        n = self._x.shape[0]
+        t = self._dev(target, (n, self.size, self.size, self.out_ch))
+        w = self._dev(weight, (n, self.size, self.size))
+        self._tw = (t, w)
+        loss = C.c_double()
+        self._call("lbm_nn_backward", C.c_void_p(t.data_ptr()), C.c_void_p(w.data_ptr()),
+                   C.byref(loss) if want_loss else None)
+        return loss.value if want_loss else None
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self._call("lbm_nn_adam_step", float(lr), float(beta1), float(beta2), float(eps))

@@ -53,17 +53,31 @@ class SplitMix64:
         """Integer uniform on [lo, hi] inclusive."""
         return lo + int(self.uniform() * (hi - lo + 1)) if hi > lo else lo
 
+    def _block(self, n: int) -> np.ndarray:
+        """the next n raw outputs at once (the state advances by n increments)."""
+        k = np.arange(1, n + 1, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            z = np.uint64(self.state) + k * np.uint64(0x9E3779B97F4A7C15)
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            z = z ^ (z >> np.uint64(31))
+        self.state = (self.state + n * 0x9E3779B97F4A7C15) & _M64
+        return z
+
+    def uniform_array(self, n: int) -> np.ndarray:
+        """n uniforms on [0, 1), the same values as n calls of uniform()."""
+        return (self._block(n) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
     def normal_array(self, n: int) -> np.ndarray:
-        """Box-Muller normals (used only to draw perturbed initial states)."""
-        out = np.empty(n)
-        for i in range(0, n, 2):
-            u1 = max(self.uniform(), 1e-300)
-            u2 = self.uniform()
-            r = math.sqrt(-2.0 * math.log(u1))
-            out[i] = r * math.cos(2 * math.pi * u2)
-            if i + 1 < n:
-                out[i + 1] = r * math.sin(2 * math.pi * u2)
-        return out
+        """Box-Muller normals from consecutive pairs of uniforms (used to draw
+        perturbed initial states and network parameters)."""
+        m = (n + 1) // 2
+        u = self.uniform_array(2 * m)
+        r = np.sqrt(-2.0 * np.log(np.maximum(u[0::2], 1e-300)))
+        out = np.empty(2 * m)
+        out[0::2] = r * np.cos(2 * math.pi * u[1::2])
+        out[1::2] = r * np.sin(2 * math.pi * u[1::2])
+        return out[:n]
 
 
 # ---------------------------------------------------------------------------

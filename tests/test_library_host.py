@@ -325,3 +325,25 @@ def test_batch_items_and_configuration():
     assert "not initialised" in fb.err()
     assert lib.lbm_batch_run(fb.b, 1e-8, 3, 100, None, None, None) == -1   # odd interval
     assert lib.lbm_batch_tune(fb.b, 1, None, None, None, 0, None) == -1
+
+
+# ---------------------------------------------------------------------------
+# warm-start network (host-side checks only)
+# ---------------------------------------------------------------------------
+def test_network_layout_and_parameter_count():
+    from oracle import surrogate
+    d = L.lbm_nn_desc(16, 256, 4, 2, 32, L.LBM_BF16)
+    sizes = (C.c_size_t * 4)()
+    assert L.lib().lbm_nn_required_bytes(C.byref(d), sizes) == sum(sizes) > 0
+    assert sizes[0] == 4 * ((surrogate.num_params(4, 2, 32) * 4 + 255) // 256) * 256
+    ptrs = (C.c_void_p * 4)(*[(1 << 40) + (k << 36) for k in range(4)])
+    n = C.c_void_p()
+    assert L.lib().lbm_nn_create(C.byref(d), ptrs, None, C.byref(n)) == 0
+    assert L.lib().lbm_nn_num_params(n) == surrogate.num_params(4, 2, 32) == 471874
+    assert L.lib().lbm_nn_forward(n, 1, C.c_void_p(1 << 40), None) == -5   # parameters first
+    assert L.lib().lbm_nn_forward(n, 17, C.c_void_p(1 << 40), None) == -1  # more than the batch
+    assert L.lib().lbm_nn_backward(n, C.c_void_p(1 << 40), C.c_void_p(1 << 40), None) == -5
+    L.lib().lbm_nn_destroy(n)
+    for bad in [(0, 256, 4, 2, 32, 4), (1, 250, 4, 2, 32, 4), (1, 256, 17, 2, 32, 4), (1, 256, 4, 33, 32, 4),
+                (1, 256, 4, 2, 48, 4), (1, 256, 4, 2, 32, 3)]:
+        assert L.lib().lbm_nn_required_bytes(C.byref(L.lbm_nn_desc(*bad)), sizes) == 0, bad
