@@ -258,13 +258,12 @@ typedef struct lbm_batch lbm_batch;
 typedef enum { LBM_BATCH_TILED = 1, LBM_BATCH_RESIDENT = 2 } lbm_batch_mode;
 
 /* per-item state reported by lbm_batch_run */
-typedef enum { LBM_ITEM_ACTIVE = 0, LBM_ITEM_STEADY = 1, LBM_ITEM_NONFINITE = 2 } lbm_item_status;
+typedef enum { LBM_ITEM_ACTIVE = 0, LBM_ITEM_STEADY = 1, LBM_ITEM_NONFINITE = 2, LBM_ITEM_DISABLED = 3 } lbm_item_status;
 
 typedef struct {
     int32_t mode;              /* lbm_batch_mode */
     int32_t block;             /* TILED: nodes per tile = threads per block, 64, 128 or 256;
-                                  RESIDENT: threads per item, a multiple of 64 up to the
-                                  kernel's limit (1024, or 512 above 30 population planes) */
+                                  RESIDENT: threads per item, a multiple of 64 up to 512 */
     int32_t steps_per_launch;  /* RESIDENT: even, >= 2; TILED: 1 */
     int32_t graph_steps;       /* steps per captured graph: even, a multiple of steps_per_launch */
 } lbm_batch_config;
@@ -291,11 +290,17 @@ lbm_status lbm_batch_create(int32_t n_items, const lbm_params* items, const size
  * with lbm_step.  NULL when i is out of range. */
 lbm_ctx* lbm_batch_item(lbm_batch* b, int32_t i);
 
+/* Selects the items that take part in lbm_batch_step, lbm_batch_run and
+ * lbm_batch_tune (host array of n_items bytes, nonzero = take part; all items
+ * do after creation).  The others keep their state and time, and lbm_batch_run
+ * reports them as LBM_ITEM_DISABLED. */
+lbm_status lbm_batch_set_active(lbm_batch* b, const uint8_t* host_flags);
+
 lbm_status lbm_batch_configure(lbm_batch* b, const lbm_batch_config* cfg);
 lbm_status lbm_batch_get_config(const lbm_batch* b, lbm_batch_config* cfg);
 
-/* Advances every item by n >= 0 steps (asynchronous).  Every item must be
- * initialised and all items must have times of equal parity. */
+/* Advances every enabled item by n >= 0 steps (asynchronous).  Every enabled
+ * item must be initialised and their times must have equal parity. */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
 
 /* Runs every item until its residual (every `interval` steps, interval even
@@ -309,10 +314,9 @@ lbm_status lbm_batch_run(lbm_batch* b, double tol, int32_t interval, int64_t max
                          double* resid_out, int32_t* status_out);
 
 /* Autotuner: times every candidate configuration (TILED with block 64, 128,
- * 256; RESIDENT with block 256, 512, 1024 within the kernel's limit and
- * steps_per_launch 2, 8, 32) on trial_steps real steps of the batch (the
- * items advance), with HIP events on the batch's stream, and configures the
- * fastest.  Host outputs: best (may be NULL); cands and ms_per_step (cap
+ * 256; RESIDENT with block 128, 256, 512 and steps_per_launch 2, 8, 32) on
+ * trial_steps real steps of the batch (the items advance), with HIP events on
+ * the batch's stream, and configures the fastest.  Host outputs: best (may be NULL); cands and ms_per_step (cap
  * entries each, may be NULL) every candidate and its time per step; *n_out
  * the number of candidates. */
 lbm_status lbm_batch_tune(lbm_batch* b, int64_t trial_steps, lbm_batch_config* best, lbm_batch_config* cands,

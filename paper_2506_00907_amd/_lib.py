@@ -63,7 +63,7 @@ class lbm_nn_desc(C.Structure):
 
 
 LBM_BATCH_TILED, LBM_BATCH_RESIDENT = 1, 2
-ITEM_STATUS = {0: "active", 1: "steady", 2: "nonfinite"}
+ITEM_STATUS = {0: "active", 1: "steady", 2: "nonfinite", 3: "disabled"}
 
 # every entry point declared in include/lbm.h: name -> (restype, argtypes)
 _VP = C.c_void_p
@@ -94,6 +94,7 @@ SIGNATURES = {
     "lbm_batch_create": (C.c_int, [C.c_int32, C.POINTER(lbm_params), C.POINTER(C.c_size_t), C.POINTER(_VP), _VP,
                                    C.POINTER(_VP)]),
     "lbm_batch_item": (_VP, [_VP, C.c_int32]),
+    "lbm_batch_set_active": (C.c_int, [_VP, _VP]),
     "lbm_batch_configure": (C.c_int, [_VP, C.POINTER(lbm_batch_config)]),
     "lbm_batch_get_config": (C.c_int, [_VP, C.POINTER(lbm_batch_config)]),
     "lbm_batch_step": (C.c_int, [_VP, C.c_int64]),

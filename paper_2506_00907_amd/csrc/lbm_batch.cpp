@@ -40,6 +40,7 @@ struct lbm_batch {
     // host copies: descriptors, work tables, statuses
     std::vector<char> desc_h;
     std::vector<uint32_t> tiles_h, ltiles_h, active_h, status_h;
+    std::vector<uint8_t> enabled;  // items that take part in batched calls
     uint32_t n_tiles = 0, n_ltiles = 0, n_active = 0, tile = 0;
     // the device holds descriptors / work tables for the items' current state
     // (valid within one entry point: the items may change between calls)
@@ -72,7 +73,7 @@ bool same_combo(const lbm_params& a, const lbm_params& b) {
            a.mag_ncomp == b.mag_ncomp && a.storage == b.storage;
 }
 
-int resident_limit(const lbmi::KernelSet& ks) { return ks.QT > 30 ? 512 : 1024; }
+int resident_limit(const lbmi::KernelSet&) { return 512; }
 
 // Per-item buffer sizes and offsets inside the batch buffers 0-4, and the
 // sizes of buffers 5-7.
@@ -141,15 +142,34 @@ void drop_bgraph(lbm_batch* b) {
     b->graph_kind = 0;
 }
 
-// all items set up, times of one parity
+// every enabled item set up, their times of one parity
 lbm_status check_ready(lbm_batch* b) {
+    int first = -1;
     for (int i = 0; i < b->n; ++i) {
+        if (!b->enabled[i]) continue;
         const lbm_ctx* c = b->items[i];
         if (!c->initialized) return bset_err(b, LBM_ESTATE, "item " + std::to_string(i) + " is not initialised");
-        if ((c->t & 1) != (b->items[0]->t & 1))
-            return bset_err(b, LBM_ESTATE, "item times differ in parity");
+        if (first < 0) first = i;
+        if ((c->t & 1) != (b->items[first]->t & 1)) return bset_err(b, LBM_ESTATE, "item times differ in parity");
     }
     return LBM_OK;
+}
+
+bool any_enabled(const lbm_batch* b) {
+    for (uint8_t e : b->enabled)
+        if (e) return true;
+    return false;
+}
+
+int first_enabled(const lbm_batch* b) {
+    for (int i = 0; i < b->n; ++i)
+        if (b->enabled[i]) return i;
+    return 0;
+}
+
+void advance(lbm_batch* b, int64_t k) {
+    for (int i = 0; i < b->n; ++i)
+        if (b->enabled[i]) b->items[i]->t += k;
 }
 
 // the residual snapshot and accumulators of an item (its buffer 4)
@@ -169,12 +189,21 @@ lbm_status upload_descriptors(lbm_batch* b) {
         lbmi::KArgs a = base_args(c);
         aux_of(c, &a.snap, &a.acc);
         a.links_ready = c->t > 0 ? 1 : 0;
+        a.tbase = time_base(c);
+        a.tstep = (uint32_t)c->t;
         b->ks.describe(a, b->desc_h.data() + (size_t)i * ib);
     }
     b->desc_valid = false;
     lbm_status st = bhip(b, hipMemcpyAsync(b->desc, b->desc_h.data(), b->desc_h.size(), hipMemcpyHostToDevice,
                                            b->stream), "descriptor upload");
     if (st) return st;
+    // every item's time base starts at its time
+    lbmi::BArgs ta;
+    std::memset(&ta, 0, sizeof ta);
+    ta.items = b->desc;
+    ta.n_active = (uint32_t)b->n;
+    ta.stream = b->stream;
+    if ((st = bhip(b, b->ks.b_set_time(ta), "time base"))) return st;
     drop_bgraph(b);
     if ((st = bhip(b, hipStreamSynchronize(b->stream), "descriptor upload sync"))) return st;
     b->desc_valid = true;
@@ -263,13 +292,22 @@ lbm_status reset_state(lbm_batch* b) {
     b->status_h.assign(b->n, lbmi::BS_ACTIVE);
     std::vector<uint32_t> all(b->n);
     for (int i = 0; i < b->n; ++i) all[i] = (uint32_t)i;
-    if ((st = bhip(b, hipMemcpyAsync(b->active, all.data(), all.size() * 4, hipMemcpyHostToDevice, b->stream),
-                   "active list upload")))
+    // enabled items start active with cleared counters; the others are frozen
+    uint32_t ne = 0;
+    for (int i = 0; i < b->n; ++i) {
+        if (b->enabled[i]) all[ne++] = (uint32_t)i;
+        else b->status_h[i] = lbmi::BS_DISABLED;
+    }
+    if ((st = bhip(b, hipMemcpyAsync(b->status, b->status_h.data(), (size_t)b->n * 4, hipMemcpyHostToDevice, b->stream),
+                   "status upload")))
+        return st;
+    if (ne && (st = bhip(b, hipMemcpyAsync(b->active, all.data(), (size_t)ne * 4, hipMemcpyHostToDevice, b->stream),
+                         "active list upload")))
         return st;
     if ((st = need_tables(b, false))) return st;
     lbmi::BArgs a = bargs(b, b->stream);
     a.active = b->active;
-    a.n_active = (uint32_t)b->n;
+    a.n_active = ne;
     if ((st = bhip(b, b->ks.b_clear(a), "clear launch"))) return st;
     st = bhip(b, hipStreamSynchronize(b->stream), "clear sync");
     b->tables_valid = false;  // the active list was overwritten
@@ -286,12 +324,14 @@ lbm_status enqueue_steps(lbm_batch* b, int64_t n, int parity, hipStream_t s) {
         const int64_t spl = b->cfg.steps_per_launch;
         while (n - i >= 2) {
             a.nsteps = (int)std::min<int64_t>(spl, (n - i) & ~int64_t(1));
+            a.tstep = (uint32_t)i;
             if (hipError_t e = b->ks.b_resident(a)) return bhip(b, e, "resident launch");
             i += a.nsteps;
         }
     }
     for (; i < n; ++i) {
         a.parity = (int)((parity + i) & 1);
+        a.tstep = (uint32_t)i;
         if (hipError_t e = b->ks.b_links(a)) return bhip(b, e, "link launch");
         if (hipError_t e = b->ks.b_sweep(a)) return bhip(b, e, "sweep launch");
     }
@@ -302,6 +342,7 @@ lbm_status enqueue_check(lbm_batch* b, int interval, double tol, hipStream_t s) 
     if (lbm_status st = need_tables(b, true)) return st;
     lbmi::BArgs a = bargs(b, s);
     a.parity = 0;
+    a.tstep = (uint32_t)interval;  // the check runs at the end of the interval
     a.interval = interval;
     a.tol = tol;
     if (hipError_t e = b->ks.b_reduce(a)) return bhip(b, e, "reduce launch");
@@ -319,8 +360,15 @@ lbm_status capture(lbm_batch* b, int kind, int interval, double tol) {
     }
     if (hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bset_err(b, LBM_EDEVICE, "begin capture");
-    lbm_status st = enqueue_steps(b, kind == 1 ? b->cfg.graph_steps : interval, 0, b->capture_stream);
+    const int steps = kind == 1 ? b->cfg.graph_steps : interval;
+    lbm_status st = enqueue_steps(b, steps, 0, b->capture_stream);
     if (!st && kind == 2) st = enqueue_check(b, interval, tol, b->capture_stream);
+    if (!st) {
+        // the time bases of the listed items follow the run
+        lbmi::BArgs a = bargs(b, b->capture_stream);
+        a.tstep = (uint32_t)steps;
+        if (hipError_t e = b->ks.b_tick(a)) st = bhip(b, e, "time base");
+    }
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(b->capture_stream, &g);
     if (st || ee != hipSuccess || !g) {
@@ -346,7 +394,7 @@ lbm_status pre_steps(lbm_batch* b, int64_t budget, int64_t* done) {
     *done = 0;
     auto needs = [&]() {
         for (int i = 0; i < b->n; ++i)
-            if (b->items[i]->t == 0 || (b->items[i]->t & 1)) return true;
+            if (b->enabled[i] && (b->items[i]->t == 0 || (b->items[i]->t & 1))) return true;
         return false;
     };
     while (*done < budget && needs()) {
@@ -355,10 +403,10 @@ lbm_status pre_steps(lbm_batch* b, int64_t budget, int64_t* done) {
         if ((st = build_tables(b, table_tile(b)))) return st;
         if ((st = need_tables(b, true))) return st;
         lbmi::BArgs a = bargs(b, b->stream);
-        a.parity = (int)(b->items[0]->t & 1);
+        a.parity = (int)(b->items[first_enabled(b)]->t & 1);
         if ((st = bhip(b, b->ks.b_links(a), "link launch"))) return st;
         if ((st = bhip(b, b->ks.b_sweep(a), "sweep launch"))) return st;
-        for (auto* c : b->items) c->t++;
+        advance(b, 1);
         ++*done;
     }
     if (*done) {
@@ -441,6 +489,7 @@ lbm_status lbm_batch_create(int32_t n_items, const lbm_params* items, const size
     b->max_tiles = L.max_tiles;
     b->max_ltiles = L.max_ltiles;
     b->status_h.assign(n_items, lbmi::BS_ACTIVE);
+    b->enabled.assign(n_items, 1);
     for (int i = 0; i < n_items; ++i) {
         lbm_ctx* c = new lbm_ctx();
         c->p = items[i];
@@ -468,6 +517,15 @@ lbm_ctx* lbm_batch_item(lbm_batch* b, int32_t i) {
     return b->items[i];
 }
 
+lbm_status lbm_batch_set_active(lbm_batch* b, const uint8_t* host_flags) {
+    if (!b) return LBM_EINVAL;
+    if (!host_flags) return bset_err(b, LBM_EINVAL, "flags is NULL");
+    for (int i = 0; i < b->n; ++i) b->enabled[i] = host_flags[i] ? 1 : 0;
+    b->desc_valid = b->tables_valid = false;
+    drop_bgraph(b);
+    return LBM_OK;
+}
+
 lbm_status lbm_batch_configure(lbm_batch* b, const lbm_batch_config* cfg) {
     if (!b || !cfg) return LBM_EINVAL;
     std::string why;
@@ -489,7 +547,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
     if (n < 0) return bset_err(b, LBM_EINVAL, "negative step count");
     lbm_status st;
     if ((st = check_ready(b))) return st;
-    if (n == 0) return LBM_OK;
+    if (n == 0 || !any_enabled(b)) return LBM_OK;
     if ((st = reset_state(b))) return st;
     int64_t pre = 0;
     if ((st = pre_steps(b, n, &pre))) return st;
@@ -505,12 +563,12 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
         if ((st = capture(b, 1, 0, 0.0))) return st;
         for (; n >= G; n -= G) {
             if ((st = bhip(b, hipGraphLaunch(b->graph, b->stream), "graph launch"))) return st;
-            for (auto* c : b->items) c->t += G;
+            advance(b, G);
         }
     }
     if (n > 0) {
         if ((st = enqueue_steps(b, n, 0, b->stream))) return st;
-        for (auto* c : b->items) c->t += n;
+        advance(b, n);
     }
     after_batch_steps(b);
     return LBM_OK;
@@ -562,8 +620,9 @@ lbm_status lbm_batch_run(lbm_batch* b, double tol, int32_t interval, int64_t max
         if ((st = bhip(b, hipStreamSynchronize(b->stream), "run sync"))) return st;
     }
     for (int i = 0; i < b->n; ++i) {
+        if (!b->enabled[i]) steps_h[i] = 0;
         b->items[i]->t += steps_h[i];
-        if (steps_out) steps_out[i] = pre + (int64_t)steps_h[i];
+        if (steps_out) steps_out[i] = b->enabled[i] ? pre + (int64_t)steps_h[i] : 0;
         if (resid_out) resid_out[i] = resid_h[i];
         if (status_out) status_out[i] = (int32_t)b->status_h[i];
     }
@@ -579,12 +638,13 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t trial_steps, lbm_batch_config* b
     if (cap < 0 || (cap > 0 && (!cands || !ms_per_step))) return bset_err(b, LBM_EINVAL, "bad candidate outputs");
     lbm_status st;
     if ((st = check_ready(b))) return st;
+    if (!any_enabled(b)) return bset_err(b, LBM_ESTATE, "no item is enabled");
     if ((st = reset_state(b))) return st;
     int64_t pre = 0;
     if ((st = pre_steps(b, 2, &pre))) return st;
     std::vector<lbm_batch_config> list;
     for (int blk : {64, 128, 256}) list.push_back({LBM_BATCH_TILED, blk, 1, 64});
-    for (int blk : {256, 512, 1024})
+    for (int blk : {128, 256, 512})
         if (blk <= resident_limit(b->ks))
             for (int spl : {2, 8, 32}) list.push_back({LBM_BATCH_RESIDENT, blk, spl, 64});
     const lbm_batch_config keep = b->cfg;
@@ -608,7 +668,7 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t trial_steps, lbm_batch_config* b
         float el = 0.f;
         if ((st = bhip(b, hipEventElapsedTime(&el, e0, e1), "elapsed time"))) break;
         ms[k] = (double)el / (double)(reps * 64);
-        for (auto* c : b->items) c->t += 64 * (reps + 1);
+        advance(b, 64 * (reps + 1));
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -62,5 +62,7 @@ void drop_graph(lbm_ctx* c);
 lbm_status set_err(lbm_ctx* c, lbm_status s, const std::string& m);
 lbm_status hip_check(lbm_ctx* c, hipError_t e, const char* what);
 lbmi::KArgs base_args(const lbm_ctx* c);
+// device word holding the time at the start of a captured run (end of buffer 3)
+uint32_t* time_base(const lbm_ctx* c);
 
 }  // namespace lbmh

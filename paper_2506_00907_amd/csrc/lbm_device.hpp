@@ -149,6 +149,39 @@ template <> __device__ __forceinline__ void st<BF16S>(uint16_t* p, uint32_t i, f
     p[i] = (uint16_t)(b >> 16);
 }
 
+// Stores with stochastic rounding for the 16-bit formats: a dither drawn
+// from (destination slot, destination node, time) is added below the last
+// kept mantissa bit before truncation, so increments smaller than half a unit
+// in the last place survive on average instead of being rounded away.  The
+// dither is a counter-based hash (the 32-bit finaliser of MurmurHash3), so a
+// slot written at a given time gets the same rounding on every path.
+__device__ __forceinline__ uint32_t dither(uint32_t node, uint32_t slot, uint32_t t) {
+    uint32_t h = node * 0x9E3779B1u + slot * 0x85EBCA77u + t * 0xC2B2AE3Du;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+template <class SF>
+__device__ __forceinline__ void st_sr(typename SF::T* p, uint32_t i, typename SF::R v, uint32_t r) {
+    st<SF>(p, i, v);
+}
+template <> __device__ __forceinline__ void st_sr<F16S>(uint16_t* p, uint32_t i, float v, uint32_t r) {
+    uint32_t b = __builtin_bit_cast(uint32_t, v);
+    const uint32_t e = (b >> 23) & 0xFFu;
+    // normal FP16 range below the largest binade: dither the 13 dropped bits
+    if (e >= 113u && e < 142u) b = (b + (r & 0x1FFFu)) & ~0x1FFFu;
+    p[i] = __builtin_bit_cast(uint16_t, (_Float16)__builtin_bit_cast(float, b));
+}
+template <> __device__ __forceinline__ void st_sr<BF16S>(uint16_t* p, uint32_t i, float v, uint32_t r) {
+    uint32_t b = __builtin_bit_cast(uint32_t, v);
+    if (((b >> 23) & 0xFFu) < 0xFEu) b += r & 0xFFFFu;  // finite and not next to overflow
+    p[i] = (uint16_t)(b >> 16);
+}
+
 // ---------------------------------------------------------------------------
 // configuration bundle
 // ---------------------------------------------------------------------------
@@ -322,7 +355,8 @@ __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R
 // reads a target slot, so the kernel is race-free.
 template <class C, int ODD>
 __device__ __forceinline__ void link_update(const Geo& G, const Phys<typename C::R>& P, typename C::T* __restrict__ S,
-                                            const DevLink<typename C::R>& L, const typename C::R* __restrict__ M) {
+                                            const DevLink<typename C::R>& L, const typename C::R* __restrict__ M,
+                                            uint32_t seed) {
     using R = typename C::R;
     using SF = typename C::S;
     const size_t PL = G.plane;
@@ -363,17 +397,23 @@ __device__ __forceinline__ void link_update(const Geo& G, const Phys<typename C:
         c2 = (R)0.25;
     }
     const R v = link_value<R>(L, P, x_a, x_apA, xs, mA, mE, w, c2);
-    if (ODD) st<SF>(Sp, L.B, C::SCALED ? v * sc : v);
-    else st<SF>(Sa, L.A, C::SCALED ? v * sc : v);
+    if (ODD) st_sr<SF>(Sp, L.B, C::SCALED ? v * sc : v, C::SCALED ? dither(L.B, L.pap, seed) : 0u);
+    else st_sr<SF>(Sa, L.A, C::SCALED ? v * sc : v, C::SCALED ? dither(L.A, L.pa, seed) : 0u);
+}
+
+// time of the step being taken: base word (if any) plus offset
+__device__ __forceinline__ uint32_t step_time(const uint32_t* tbase, uint32_t tstep) {
+    return (tbase ? *tbase : 0u) + tstep;
 }
 
 template <class C, int ODD>
 __global__ __launch_bounds__(256) void k_links(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
                                                const DevLink<typename C::R>* __restrict__ links,
-                                               const typename C::R* __restrict__ M, uint32_t nlinks) {
+                                               const typename C::R* __restrict__ M, uint32_t nlinks,
+                                               const uint32_t* __restrict__ tbase, uint32_t tstep) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nlinks) return;
-    link_update<C, ODD>(G, P, S, links[k], M);
+    link_update<C, ODD>(G, P, S, links[k], M, C::SCALED ? step_time(tbase, tstep) : 0u);
 }
 
 // ---------------------------------------------------------------------------
@@ -392,7 +432,7 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
                                             typename C::T* __restrict__ S,
                                             const uint8_t* __restrict__ flags,
                                             typename C::R* __restrict__ M, uint32_t n,
-                                            NodeRes<C>& res) {
+                                            NodeRes<C>& res, uint32_t seed = 0u) {
     using R = typename C::R;
     using SF = typename C::S;
     using FL = typename C::FL;
@@ -591,18 +631,22 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
         }
     }
 
-    // ---- scatter (streaming) ----
+    // ---- scatter (streaming); 16-bit formats round stochastically with a
+    // dither of (slot, destination node, time) ----
+    auto put = [&](int slot, uint32_t dest, R v) {
+        st_sr<SF>(plane(slot), dest, v, C::SCALED ? dither(dest, (uint32_t)slot, seed) : 0u);
+    };
 #pragma unroll
     for (int i = 0; i < QF; ++i) {
         const R v = C::SCALED ? x_[i] * P.sc[0] : x_[i];
-        if (ODD) st<SF>(plane(i), nb(FL::ex(i), FL::ey(i), FL::ez(i)), v);
-        else st<SF>(plane(FL::opp(i)), n, v);
+        if (ODD) put(i, nb(FL::ex(i), FL::ey(i), FL::ez(i)), v);
+        else put(FL::opp(i), n, v);
     }
 #pragma unroll
     for (int i = 0; i < QH; ++i) {
         const R v = C::SCALED ? x_[C::H0 + i] * P.sc[1] : x_[C::H0 + i];
-        if (ODD) st<SF>(plane(C::H0 + i), nb(HL::ex(i), HL::ey(i), HL::ez(i)), v);
-        else st<SF>(plane(C::H0 + HL::opp(i)), n, v);
+        if (ODD) put(C::H0 + i, nb(HL::ex(i), HL::ey(i), HL::ez(i)), v);
+        else put(C::H0 + HL::opp(i), n, v);
     }
 #pragma unroll
     for (int c = 0; c < NCP; ++c)
@@ -610,8 +654,8 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
         for (int i = 0; i < QG; ++i) {
             const int b = C::G0 + c * QG;
             const R v = C::SCALED ? x_[b + i] * P.sc[2] : x_[b + i];
-            if (ODD) st<SF>(plane(b + i), nb(GL::ex(i), GL::ey(i), GL::ez(i)), v);
-            else st<SF>(plane(b + GL::opp(i)), n, v);
+            if (ODD) put(b + i, nb(GL::ex(i), GL::ey(i), GL::ez(i)), v);
+            else put(b + GL::opp(i), n, v);
         }
     return true;
 }
@@ -622,12 +666,23 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
 template <class C, int ODD>
 __global__ __launch_bounds__(256) void k_step(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
                                               const uint8_t* __restrict__ flags,
-                                              typename C::R* __restrict__ M, uint32_t nnodes) {
+                                              typename C::R* __restrict__ M, uint32_t nnodes,
+                                              const uint32_t* __restrict__ tbase, uint32_t tstep) {
     const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t n = b * blockDim.x + threadIdx.x;
     if (n >= nnodes) return;
     NodeRes<C> r;
-    node_update<C, ODD, 0>(G, P, S, flags, M, n, r);
+    node_update<C, ODD, 0>(G, P, S, flags, M, n, r, C::SCALED ? step_time(tbase, tstep) : 0u);
+}
+
+// time base of a captured run: *tbase = t (set) or *tbase += t (tick); one
+// lane, through a vector-memory atomic
+template <class C>
+__global__ void k_time(uint32_t* tbase, uint32_t t, int add) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (add) atomicAdd(tbase, t);
+        else atomicExch(tbase, t);
+    }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -820,6 +875,8 @@ struct BItem {
     typename C::R* M;
     typename C::R* snap;  // [7][plane] residual snapshot
     double* acc;          // [NACC] FP64 accumulators
+    uint32_t* tbase;      // time base word of the item
+    uint32_t t0;          // the item's time when the descriptor was written
     uint32_t nnodes, nlinks;
 };
 
@@ -827,7 +884,8 @@ struct BItem {
 template <class C, int ODD>
 __global__ __launch_bounds__(256) void kb_sweep(const BItem<C>* __restrict__ items,
                                                 const uint32_t* __restrict__ tiles,
-                                                const uint32_t* __restrict__ status, uint32_t ntiles) {
+                                                const uint32_t* __restrict__ status, uint32_t ntiles,
+                                                uint32_t tstep) {
     const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
     if (b >= ntiles) return;
     const uint32_t it = tiles[2 * b];
@@ -836,13 +894,14 @@ __global__ __launch_bounds__(256) void kb_sweep(const BItem<C>* __restrict__ ite
     const uint32_t n = tiles[2 * b + 1] + threadIdx.x;
     if (n >= I.nnodes) return;
     NodeRes<C> r;
-    node_update<C, ODD, 0>(I.G, I.P, I.S, I.flags, I.M, n, r);
+    node_update<C, ODD, 0>(I.G, I.P, I.S, I.flags, I.M, n, r, C::SCALED ? step_time(I.tbase, tstep) : 0u);
 }
 
 template <class C, int ODD>
 __global__ __launch_bounds__(256) void kb_links(const BItem<C>* __restrict__ items,
                                                 const uint32_t* __restrict__ ltiles,
-                                                const uint32_t* __restrict__ status, uint32_t nltiles) {
+                                                const uint32_t* __restrict__ status, uint32_t nltiles,
+                                                uint32_t tstep) {
     const uint32_t b = blockIdx.x;
     if (b >= nltiles) return;
     const uint32_t it = ltiles[2 * b];
@@ -850,7 +909,18 @@ __global__ __launch_bounds__(256) void kb_links(const BItem<C>* __restrict__ ite
     const BItem<C>& I = items[it];
     const uint32_t k = ltiles[2 * b + 1] + threadIdx.x;
     if (k >= I.nlinks) return;
-    link_update<C, ODD>(I.G, I.P, I.S, I.links[k], I.M);
+    link_update<C, ODD>(I.G, I.P, I.S, I.links[k], I.M, C::SCALED ? step_time(I.tbase, tstep) : 0u);
+}
+
+// item time bases: set from the descriptors (all items), or advanced for the
+// listed items
+template <class C>
+__global__ __launch_bounds__(256) void kb_time(const BItem<C>* __restrict__ items, const uint32_t* __restrict__ active,
+                                               uint32_t n, uint32_t add) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (active) atomicAdd(items[active[i]].tbase, add);
+    else atomicExch(items[i].tbase, items[i].t0);
 }
 
 // One workgroup advances one item by nsteps steps (nsteps even, starting at
@@ -859,10 +929,10 @@ __global__ __launch_bounds__(256) void kb_links(const BItem<C>* __restrict__ ite
 // global-memory writes of one phase before the reads of the next within the
 // workgroup; items never touch each other's memory.
 template <class C>
-__global__ __launch_bounds__(C::QT > 30 ? 512 : 1024) void kb_resident(const BItem<C>* __restrict__ items,
+__global__ __launch_bounds__(512) void kb_resident(const BItem<C>* __restrict__ items,
                                                                       const uint32_t* __restrict__ active,
                                                                       const uint32_t* __restrict__ status,
-                                                                      int nsteps) {
+                                                                      int nsteps, uint32_t tstep) {
     const uint32_t it = active[blockIdx.x];
     if (status[it] != BS_ACTIVE) return;
     const BItem<C>& I = items[it];
@@ -873,19 +943,21 @@ __global__ __launch_bounds__(C::QT > 30 ? 512 : 1024) void kb_resident(const BIt
     const uint8_t* flags = I.flags;
     const DevLink<typename C::R>* links = I.links;
     const uint32_t nn = I.nnodes, nl = I.nlinks, bd = blockDim.x;
+    const uint32_t t0 = C::SCALED ? step_time(I.tbase, tstep) : 0u;
     for (int s = 0; s < nsteps; s += 2) {
-        for (uint32_t k = threadIdx.x; k < nl; k += bd) link_update<C, 0>(G, P, S, links[k], M);
+        const uint32_t te = t0 + (uint32_t)s, to = te + 1u;
+        for (uint32_t k = threadIdx.x; k < nl; k += bd) link_update<C, 0>(G, P, S, links[k], M, te);
         __syncthreads();
         for (uint32_t n = threadIdx.x; n < nn; n += bd) {
             NodeRes<C> r;
-            node_update<C, 0, 0>(G, P, S, flags, M, n, r);
+            node_update<C, 0, 0>(G, P, S, flags, M, n, r, te);
         }
         __syncthreads();
-        for (uint32_t k = threadIdx.x; k < nl; k += bd) link_update<C, 1>(G, P, S, links[k], M);
+        for (uint32_t k = threadIdx.x; k < nl; k += bd) link_update<C, 1>(G, P, S, links[k], M, to);
         __syncthreads();
         for (uint32_t n = threadIdx.x; n < nn; n += bd) {
             NodeRes<C> r;
-            node_update<C, 1, 0>(G, P, S, flags, M, n, r);
+            node_update<C, 1, 0>(G, P, S, flags, M, n, r, to);
         }
         __syncthreads();
     }
@@ -987,10 +1059,10 @@ struct Launch {
         dim3 grid((unsigned)((a.n_links + 255) / 256));
         if (a.parity)
             hipLaunchKernelGGL((k_links<C, 1>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S,
-                               (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links);
+                               (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links, a.tbase, a.tstep);
         else
             hipLaunchKernelGGL((k_links<C, 0>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S,
-                               (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links);
+                               (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links, a.tbase, a.tstep);
         return hipGetLastError();
     }
     static hipError_t links_only(const KArgs& a) {
@@ -1009,10 +1081,18 @@ struct Launch {
         const Geo G = make_geo(a);
         if (a.parity)
             hipLaunchKernelGGL((k_step<C, 1>), grid, dim3(bs), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
-                               (R*)a.M, nn);
+                               (R*)a.M, nn, a.tbase, a.tstep);
         else
             hipLaunchKernelGGL((k_step<C, 0>), grid, dim3(bs), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
-                               (R*)a.M, nn);
+                               (R*)a.M, nn, a.tbase, a.tstep);
+        return hipGetLastError();
+    }
+    static hipError_t set_time(const KArgs& a) {
+        hipLaunchKernelGGL((k_time<C>), dim3(1), dim3(64), 0, a.stream, a.tbase, a.tstep, 0);
+        return hipGetLastError();
+    }
+    static hipError_t tick(const KArgs& a) {
+        hipLaunchKernelGGL((k_time<C>), dim3(1), dim3(64), 0, a.stream, a.tbase, a.tstep, 1);
         return hipGetLastError();
     }
     static hipError_t observe(const KArgs& a) {
@@ -1051,6 +1131,8 @@ struct Launch {
         d.M = (R*)a.M;
         d.snap = (R*)a.snap;
         d.acc = a.acc;
+        d.tbase = a.tbase;
+        d.t0 = a.tstep;
         d.nnodes = (uint32_t)((size_t)a.NX * a.NY * a.NZ);
         d.nlinks = a.links_ready ? (uint32_t)a.n_links : 0u;
         if (out) memcpy(out, &d, sizeof d);
@@ -1061,10 +1143,10 @@ struct Launch {
         const BItem<C>* it = (const BItem<C>*)b.items;
         if (b.parity)
             hipLaunchKernelGGL((kb_sweep<C, 1>), dim3(b.n_tiles), dim3(b.tile), 0, b.stream, it, b.tiles, b.status,
-                               b.n_tiles);
+                               b.n_tiles, b.tstep);
         else
             hipLaunchKernelGGL((kb_sweep<C, 0>), dim3(b.n_tiles), dim3(b.tile), 0, b.stream, it, b.tiles, b.status,
-                               b.n_tiles);
+                               b.n_tiles, b.tstep);
         return hipGetLastError();
     }
     static hipError_t b_links(const BArgs& b) {
@@ -1072,16 +1154,16 @@ struct Launch {
         const BItem<C>* it = (const BItem<C>*)b.items;
         if (b.parity)
             hipLaunchKernelGGL((kb_links<C, 1>), dim3(b.n_ltiles), dim3(256), 0, b.stream, it, b.ltiles, b.status,
-                               b.n_ltiles);
+                               b.n_ltiles, b.tstep);
         else
             hipLaunchKernelGGL((kb_links<C, 0>), dim3(b.n_ltiles), dim3(256), 0, b.stream, it, b.ltiles, b.status,
-                               b.n_ltiles);
+                               b.n_ltiles, b.tstep);
         return hipGetLastError();
     }
     static hipError_t b_resident(const BArgs& b) {
         if (b.n_active == 0) return hipSuccess;
         hipLaunchKernelGGL((kb_resident<C>), dim3(b.n_active), dim3(b.block), 0, b.stream,
-                           (const BItem<C>*)b.items, b.active, b.status, b.nsteps);
+                           (const BItem<C>*)b.items, b.active, b.status, b.nsteps, b.tstep);
         return hipGetLastError();
     }
     static hipError_t b_reduce(const BArgs& b) {
@@ -1110,8 +1192,25 @@ struct Launch {
         return hipGetLastError();
     }
 
+    static hipError_t b_set_time(const BArgs& b) {
+        if (b.n_active == 0) return hipSuccess;
+        hipLaunchKernelGGL((kb_time<C>), dim3((b.n_active + 255) / 256), dim3(256), 0, b.stream,
+                           (const BItem<C>*)b.items, (const uint32_t*)nullptr, b.n_active, 0u);
+        return hipGetLastError();
+    }
+    static hipError_t b_tick(const BArgs& b) {
+        if (b.n_active == 0) return hipSuccess;
+        hipLaunchKernelGGL((kb_time<C>), dim3((b.n_active + 255) / 256), dim3(256), 0, b.stream,
+                           (const BItem<C>*)b.items, b.active, b.n_active, b.tstep);
+        return hipGetLastError();
+    }
+
     static KernelSet set() {
         KernelSet k;
+        k.set_time = &set_time;
+        k.tick = &tick;
+        k.b_set_time = &b_set_time;
+        k.b_tick = &b_tick;
         k.describe = &describe;
         k.item_bytes = sizeof(BItem<C>);
         k.b_sweep = &b_sweep;

@@ -400,7 +400,7 @@ void layout(const lbm_params* p, size_t n_links, size_t sz[LBM_NBUF]) {
     sz[0] = round_up((size_t)total_planes(p) * d.plane * vb, kAlign);          // populations
     sz[1] = round_up(d.plane, kAlign);                                          // node flags
     sz[2] = round_up(std::max<size_t>(n_links, 1) * link_bytes(p->storage), kAlign);  // link records
-    sz[3] = round_up(2 * 8 * d.plane * cb, kAlign);                            // moment planes
+    sz[3] = round_up(2 * 8 * d.plane * cb, kAlign) + kAlign;                   // moment planes, time base
     sz[4] = round_up(7 * d.plane * cb, kAlign) + round_up(lbmi::NACC * sizeof(double), kAlign);  // reductions
     sz[5] = sz[6] = sz[7] = 0;
 }
@@ -438,9 +438,15 @@ lbmi::KArgs base_args(const lbm_ctx* c) {
     }
     a.parity = (int)(c->t & 1);
     a.links_ready = c->t > 0 ? 1 : 0;
+    a.tbase = nullptr;
+    a.tstep = (uint32_t)c->t;
     a.block = 256;
     a.stream = c->stream;
     return a;
+}
+
+uint32_t* time_base(const lbm_ctx* c) {
+    return (uint32_t*)((char*)c->buf[3] + round_up(2 * 8 * c->pad.plane * compute_bytes(c->p.storage), kAlign));
 }
 
 size_t domain_nodes(const lbm_params& p) { return (size_t)p.n[0] * p.n[1] * p.n[2]; }
@@ -781,11 +787,18 @@ lbm_status make_graph(lbm_ctx* c) {
     lbmi::KArgs a = base_args(c);
     a.stream = c->capture_stream;
     a.links_ready = 1;
+    a.tbase = time_base(c);
     if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_EDEVICE;
     hipError_t le = hipSuccess;
     for (int i = 0; i < c->graph_steps && le == hipSuccess; ++i) {
         a.parity = i & 1;
+        a.tstep = (uint32_t)i;
         le = c->ks.step(a);
+    }
+    if (le == hipSuccess) {
+        // the time base follows the run
+        a.tstep = (uint32_t)c->graph_steps;
+        le = c->ks.tick(a);
     }
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(c->capture_stream, &g);
@@ -807,6 +820,7 @@ lbm_status step_launches(lbm_ctx* c, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
         a.parity = (int)(c->t & 1);
         a.links_ready = c->t > 0 ? 1 : 0;
+        a.tstep = (uint32_t)c->t;
         lbm_status st = hip_check(c, c->ks.step(a), "step launch");
         if (st) return st;
         c->t++;
@@ -831,6 +845,13 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         if (!c->graph && make_graph(c) != LBM_OK) {
             c->graph_failed = true;  // fall back to plain launches of the same kernels
             (void)hipGetLastError();
+        }
+        if (c->graph && n >= G) {
+            // runs start from the context's time
+            lbmi::KArgs a = base_args(c);
+            a.tbase = time_base(c);
+            lbm_status st = hip_check(c, c->ks.set_time(a), "time base");
+            if (st) return st;
         }
         while (c->graph && n >= G) {
             lbm_status st = hip_check(c, hipGraphLaunch(c->graph, c->stream), "graph launch");
@@ -858,6 +879,7 @@ lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, float ms_out[2]) {
     for (int64_t i = 0; i < n && st == LBM_OK; ++i) {
         a.parity = (int)(c->t & 1);
         a.links_ready = c->t > 0 ? 1 : 0;
+        a.tstep = (uint32_t)c->t;
         if (a.links_ready && a.n_links) ++with_links;
         hipEvent_t* e = &ev[(size_t)i * 3];
         if ((st = hip_check(c, hipEventRecord(e[0], c->stream), "event record"))) break;

@@ -52,6 +52,8 @@ struct KArgs {
     double tau_f, tau_c, tau_m, rho0, C0, mu;
     double Bext[3], accel[3], scale[3];
     int comp[3];           // Cartesian axis of each evolved magnetic component
+    uint32_t* tbase;       // device word: the time at the start of a captured run (null: use tstep alone)
+    uint32_t tstep;        // time of this step, counted from *tbase (or absolute without tbase)
     int parity;            // parity of the current time (t % 2)
     int links_ready;       // 0 at t = 0: populations are the initial state
     // observe / init
@@ -71,7 +73,7 @@ struct KArgs {
 using Launcher = hipError_t (*)(const KArgs&);
 
 // status of one item of a batch
-enum : uint32_t { BS_ACTIVE = 0, BS_STEADY = 1, BS_NONFINITE = 2 };
+enum : uint32_t { BS_ACTIVE = 0, BS_STEADY = 1, BS_NONFINITE = 2, BS_DISABLED = 3 };
 
 // Launch description of the batched kernels: the item descriptors, the
 // per-launch work tables and the per-item convergence state, all on the
@@ -89,6 +91,7 @@ struct BArgs {
     double* resid;              // last steady-state residual per item (-1: none yet)
     uint32_t* snap_ok;          // per item: the residual snapshot holds a previous state
     int parity;                 // parity of the current time
+    uint32_t tstep;             // time of the (first) step counted from each item's time base
     int nsteps;                 // resident launch: steps per launch (even)
     int block;                  // resident launch: threads per item
     int interval;               // steps between two residual evaluations
@@ -105,6 +108,8 @@ struct KernelSet {
     Launcher step = nullptr;     // links then sweep
     Launcher observe = nullptr;  // moments / populations / reductions at the current time
     Launcher init = nullptr;     // equilibrium initialisation
+    Launcher set_time = nullptr; // *tbase = tstep
+    Launcher tick = nullptr;     // *tbase += tstep
     int QT = 0;                  // population planes
     // batched items
     Describer describe = nullptr;  // writes one item descriptor from its launch description
@@ -115,6 +120,8 @@ struct KernelSet {
     BLauncher b_reduce = nullptr;  // links, then per-item FP64 sums over node tiles
     BLauncher b_judge = nullptr;   // per-item residual, steady / non-finite flags
     BLauncher b_clear = nullptr;   // zero the per-item accumulators and counters
+    BLauncher b_set_time = nullptr;  // every item's time base = its time when described
+    BLauncher b_tick = nullptr;    // time bases of the listed items += tstep
 };
 
 // storage codes as in lbm.h

@@ -308,6 +308,12 @@ class Batch:
         c = L.lbm_batch_config({"tiled": 1, "resident": 2}[mode], block, steps_per_launch, graph_steps)
         self._call("lbm_batch_configure", C.byref(c))
 
+    def set_active(self, flags):
+        """lbm_batch_set_active: which items take part in step / run / tune."""
+        f = np.ascontiguousarray(np.asarray(flags, dtype=bool).astype(np.uint8))
+        assert f.size == len(self.items)
+        self._call("lbm_batch_set_active", f.ctypes.data_as(C.c_void_p))
+
     def step(self, n: int = 1):
         self._call("lbm_batch_step", int(n))
 

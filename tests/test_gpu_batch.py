@@ -12,7 +12,7 @@ from paper_2506_00907_amd import lbm
 
 pytestmark = pytest.mark.gpu
 
-MODES = [("tiled", 256, 1, 64), ("tiled", 64, 1, 64), ("resident", 256, 2, 64), ("resident", 1024, 8, 64),
+MODES = [("tiled", 256, 1, 64), ("tiled", 64, 1, 64), ("resident", 256, 2, 64), ("resident", 128, 8, 64),
          ("resident", 512, 32, 64)]
 
 
@@ -142,7 +142,7 @@ def test_full_size_fp16_items_against_fp32_batch():
     s16 = [scenes.developed(it.scene, seed=3000 + i, u_amp=0.005) for i, it in enumerate(its)]
     s32 = [sc.with_(storage="f32") for sc in s16]
     B16, B32 = lbm.Batch(s16), lbm.Batch(s32)
-    B16.configure("resident", 1024, 32, 64)
+    B16.configure("resident", 512, 32, 64)
     B16.step(258)
     B32.step(258)
     for i in range(len(its)):
@@ -154,3 +154,24 @@ def test_full_size_fp16_items_against_fp32_batch():
     alone = lbm.Lattice(s16[0])
     alone.step(258)
     assert np.array_equal(gpu_moments(B16.items[0]), gpu_moments(alone))
+
+
+def test_disabled_items_keep_their_state():
+    scs = duct_pipe_items("f32", n=4, lo=20, hi=30)
+    B = lbm.Batch(scs)
+    B.step(40)
+    before = [gpu_moments(it) for it in B.items]
+    B.set_active([True, False, True, False])
+    B.configure("resident", 256, 8, 64)
+    B.step(66)
+    assert [it.time for it in B.items] == [106, 40, 106, 40]
+    for i in (1, 3):
+        assert np.array_equal(gpu_moments(B.items[i]), before[i])
+    for i in (0, 2):
+        alone = lbm.Lattice(scs[i])
+        alone.step(106)
+        assert np.array_equal(gpu_moments(B.items[i]), gpu_moments(alone))
+    steps, res, status = B.run(tol=1e-12, interval=20, max_steps=100)
+    assert status == ["active", "disabled", "active", "disabled"]
+    assert steps.tolist() == [100, 0, 100, 0]
+    assert [it.time for it in B.items] == [206, 40, 206, 40]

@@ -223,7 +223,7 @@ def test_buffer_layout():
     sizes = lbm.required_bytes(p, 100)
     plane = ((64 * 32 + 63) // 64) * 64
     assert sizes[0] == ((19 * plane * 2 + 255) // 256) * 256      # populations, 2 bytes
-    assert sizes[3] == ((2 * 8 * plane * 4 + 255) // 256) * 256   # moment planes in FP32
+    assert sizes[3] == ((2 * 8 * plane * 4 + 255) // 256) * 256 + 256   # moment planes (FP32), time base
     assert sizes[5] == sizes[6] == sizes[7] == 0
     assert all(s % 256 == 0 for s in sizes)
 
@@ -313,8 +313,8 @@ def test_batch_items_and_configuration():
     cfg = L.lbm_batch_config()
     assert lib.lbm_batch_get_config(fb.b, C.byref(cfg)) == 0
     assert (cfg.mode, cfg.block, cfg.steps_per_launch, cfg.graph_steps) == (1, 256, 1, 64)
-    good = [(1, 64, 1, 64), (1, 128, 1, 2), (2, 1024, 2, 64), (2, 256, 32, 64), (2, 64, 8, 8)]
-    bad = [(1, 96, 1, 64), (1, 256, 2, 64), (2, 1088, 2, 64), (2, 256, 3, 64), (2, 256, 8, 12),
+    good = [(1, 64, 1, 64), (1, 128, 1, 2), (2, 512, 2, 64), (2, 256, 32, 64), (2, 64, 8, 8)]
+    bad = [(1, 96, 1, 64), (1, 256, 2, 64), (2, 1024, 2, 64), (2, 256, 3, 64), (2, 256, 8, 12),
            (2, 100, 2, 64), (3, 256, 1, 64), (1, 256, 1, 63)]
     for g in good:
         assert lib.lbm_batch_configure(fb.b, C.byref(L.lbm_batch_config(*g))) == 0, g
