@@ -75,6 +75,32 @@ def make_scene(name: str, storage: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def links_moment_reads(links, sc) -> np.ndarray:
+    """Moments per node (at A, and again at E) each link's formula reads:
+    u at X when extrapolated (3), rho_X for a velocity link moving along
+    e_alpha (1), C_X (1) or B_X (1, or 3 with a moving wall)."""
+    from paper_2506_00907_amd import lbm
+    kind, flags, comp = links["kind"], links["flags"], links["comp"]
+    u_given = (flags & 1) != 0
+    uw = links["u_w"]
+    lat = {0: sc.fluid_lattice, 1: sc.scalar_lattice, 2: sc.mag_lattice}
+    eu = np.zeros(len(links))
+    for f in (0, 1, 2):
+        if not lat[f]:
+            continue
+        e = lbm.lattice_table(lbm.LATTICES[lat[f]])[0]
+        sel = links["field"] == f
+        eu[sel] = (e[links["dir"][sel]] * uw[sel]).sum(axis=1)
+    uw_zero = u_given & (np.abs(uw).sum(axis=1) == 0)
+    u3 = np.where(u_given, 0, 3)
+    n = np.zeros(len(links), int)
+    n = np.where(kind == 1, np.where(u_given & (eu == 0), 0, 1) + u3, n)
+    n = np.where(kind == 2, 3, n)
+    n = np.where(kind == 4, 1 + u3, n)
+    n = np.where(kind == 7, np.where(uw_zero, 1, 3 + u3), n)
+    return n
+
+
 def algorithmic_bytes(lat) -> dict:
     """Bytes each kernel of a step must move at least once, by its design.
 
@@ -82,7 +108,7 @@ def algorithmic_bytes(lat) -> dict:
     node read once and written once, one flag byte per padded node, and the
     eight moments stored for each node a link extrapolates from.
     links: per link its record, three population reads and one write, and
-    the eight moments of A and of E."""
+    the moments of A and of E its formula uses."""
     sc = lat.scene
     s = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[sc.storage]
     cb = 8 if sc.storage == "f64" else 4
@@ -98,7 +124,7 @@ def algorithmic_bytes(lat) -> dict:
     e_valid = (links["flags"] & 2) == 0
     mom_nodes = np.unique(np.concatenate([links["node"], links["enode"][e_valid]])).size
     sweep = n_fluid * 2 * QT * s + padded + mom_nodes * 8 * cb
-    link = len(links) * (rec + 4 * s + 16 * cb)
+    link = len(links) * (rec + 4 * s) + 2 * cb * int(links_moment_reads(links, sc).sum())
     return dict(sweep=int(sweep), links=int(link), per_fluid_node_populations=2 * QT * s,
                 fluid_nodes=n_fluid, n_links=int(len(links)), moment_nodes=int(mom_nodes), planes=QT)
 

@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "liblbm.so")
+# the in-tree build; LBM_LIBRARY names another build of the same sources
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(_PKG, "liblbm.so")
 
 LBM_NBUF = 8
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ESIZE", -3: "LBM_EDEVICE", -4: "LBM_EUNSTABLE",

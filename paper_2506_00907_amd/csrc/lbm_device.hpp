@@ -34,6 +34,20 @@
 
 #include "lbm_internal.hpp"
 
+// launch shape and store flavour of the sweep (build-time knobs for
+// measurements; the defaults are the tuned choice)
+#ifndef LBM_SWEEP_BLOCK
+#define LBM_SWEEP_BLOCK 256
+#endif
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 0
+#endif
+#ifdef LBM_MIN_WAVES
+#define LBM_SWEEP_OCC __attribute__((amdgpu_waves_per_eu(LBM_MIN_WAVES)))
+#else
+#define LBM_SWEEP_OCC
+#endif
+
 namespace lbmi {
 
 // ---------------------------------------------------------------------------
@@ -138,7 +152,13 @@ template <> __device__ __forceinline__ float ld<BF16S>(const uint16_t* p, uint32
 
 template <class SF> __device__ __forceinline__ void st(typename SF::T* p, uint32_t i, typename SF::R v);
 template <> __device__ __forceinline__ void st<F64S>(double* p, uint32_t i, double v) { p[i] = v; }
-template <> __device__ __forceinline__ void st<F32S>(float* p, uint32_t i, float v) { p[i] = v; }
+template <> __device__ __forceinline__ void st<F32S>(float* p, uint32_t i, float v) {
+#if LBM_NT_STORE
+    __builtin_nontemporal_store(v, p + i);
+#else
+    p[i] = v;
+#endif
+}
 template <> __device__ __forceinline__ void st<F16S>(uint16_t* p, uint32_t i, float v) {
     p[i] = __builtin_bit_cast(uint16_t, (_Float16)v);  // round to nearest even
 }
@@ -381,11 +401,17 @@ __device__ __forceinline__ void link_update(const Geo& G, const Phys<typename C:
         xs *= isc;
     }
     const R* Mp = M + (size_t)(ODD ^ 1) * 8 * PL;  // moments of the previous time
+    // only the moments this link's formula uses are read (the rest stay 0)
     R mA[8], mE[8];
+    const uint32_t need = L.need;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        mA[q] = Mp[(size_t)q * PL + L.A];
-        mE[q] = Mp[(size_t)q * PL + L.mE];
+        mA[q] = (R)0;
+        mE[q] = (R)0;
+        if (need & (1u << q)) {
+            mA[q] = Mp[(size_t)q * PL + L.A];
+            mE[q] = Mp[(size_t)q * PL + L.mE];
+        }
     }
     const int e2 = L.ex * L.ex + L.ey * L.ey + L.ez * L.ez;
     R w, c2;
@@ -664,7 +690,7 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
 // kernels
 // ---------------------------------------------------------------------------
 template <class C, int ODD>
-__global__ __launch_bounds__(256) void k_step(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
+__global__ __launch_bounds__(LBM_SWEEP_BLOCK) LBM_SWEEP_OCC void k_step(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
                                               const uint8_t* __restrict__ flags,
                                               typename C::R* __restrict__ M, uint32_t nnodes,
                                               const uint32_t* __restrict__ tbase, uint32_t tstep) {
@@ -1075,7 +1101,7 @@ struct Launch {
     }
     static hipError_t sweep(const KArgs& a) {
         const uint32_t nn = (uint32_t)((size_t)a.NX * a.NY * a.NZ);
-        const int bs = a.block > 0 ? a.block : 256;
+        const int bs = LBM_SWEEP_BLOCK;
         dim3 grid((nn + bs - 1) / bs);
         const Phys<R> P = make_phys<R>(a, cg2());
         const Geo G = make_geo(a);

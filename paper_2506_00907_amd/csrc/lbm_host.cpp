@@ -451,6 +451,27 @@ uint32_t* time_base(const lbm_ctx* c) {
 
 size_t domain_nodes(const lbm_params& p) { return (size_t)p.n[0] * p.n[1] * p.n[2]; }
 
+// Moments (bit q: rho, u_x, u_y, u_z, C, B_x, B_y, B_z) a link's formula reads
+// at A and E, following link_value: the velocity at X when it is extrapolated
+// (Eq. 13), rho_X for the moving-wall increment of a velocity link, C_X or B_X
+// of a flux link and the other components of B_X where the moving correction
+// (Eq. 24) uses them.
+uint8_t moments_needed(const lbm_link& k, const int* e) {
+    const bool u_given = k.flags & 1;
+    const bool eu_zero = u_given && e[0] * k.u_w[0] + e[1] * k.u_w[1] + e[2] * k.u_w[2] == 0.0;
+    const bool uw_zero = u_given && k.u_w[0] == 0.0 && k.u_w[1] == 0.0 && k.u_w[2] == 0.0;
+    const uint8_t U = 0x0E;  // u_x, u_y, u_z
+    switch (k.kind) {
+        case LBM_LK_VEL: return (uint8_t)((eu_zero ? 0 : 0x01) | (u_given ? 0 : U));
+        case LBM_LK_PRES: return U;
+        case LBM_LK_FLUX: return (uint8_t)(0x10 | (u_given ? 0 : U));
+        case LBM_LK_MAG_FLUX:
+            if (uw_zero) return (uint8_t)(0x20 << k.comp);
+            return (uint8_t)(0xE0 | (u_given ? 0 : U));
+        default: return 0;  // CONC, BB0, MAG_DIR: no moments
+    }
+}
+
 template <class R>
 void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::vector<uint32_t>& padA,
                    const std::vector<uint32_t>& padE, const std::vector<uint32_t>& padB,
@@ -492,6 +513,7 @@ void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::
         d.uw0 = (R)s.u_w[0];
         d.uw1 = (R)s.u_w[1];
         d.uw2 = (R)s.u_w[2];
+        d.need = moments_needed(s, lat.e[s.dir]);
         out[i] = d;
     }
 }

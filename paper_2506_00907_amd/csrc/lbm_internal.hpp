@@ -31,7 +31,8 @@ struct alignas(16) DevLink {
     uint8_t field;        // 0 f, 1 h, 2 g
     uint8_t caxis;        // Cartesian axis of the magnetic component (g links)
     int8_t ex, ey, ez;    // e_alpha
-    uint8_t pad[3];
+    uint8_t need;         // bit q: the link's formula uses moment q (rho, u_x, u_y, u_z, C, B_x, B_y, B_z)
+    uint8_t pad[2];
     R d;
     R value;  // given value minus its rest value (rho0, C0 or B_ext,k)
     R a1, a3, weight, uw0, uw1, uw2;

@@ -8,14 +8,17 @@ items) with the FP16 batch, builds the network inputs and targets from the
 converged fields and trains the warm-start network; writes net.npy and
 train.json.
 
-eval: on the evaluation items, three ways to the same steady state:
+eval: on the evaluation items, four ways to a steady state (residual of
+lbm_reduce over a window of `interval` steps below tol):
   plain  FP32 storage, one item at a time (single-context kernels, graph
-         replays), rest initial state, residual checked every `interval` steps;
-  cold   FP16 storage, all items in the batch (autotuned), rest initial state,
-         then an FP32 batch from the FP16 fields (polish);
+         replays), rest initial state;
+  batch  FP32 storage, all items in one batch (autotuned), rest initial state;
+  cold   FP16 storage in the batch to the FP16 tolerance (above the noise floor
+         of stochastically rounded storage), then an FP32 batch from its
+         fields (polish) to tol;
   warm   as cold, from the network's prediction (inference included);
-and an FP64 batch run to a tighter tolerance as the reference of every
-field error.  Writes eval.json.
+and the batch's final state continued in FP64 to a tighter tolerance as the
+reference of every field error.  Writes eval.json.
 """
 from __future__ import annotations
 
@@ -61,7 +64,8 @@ def cmd_train(a):
     import torch
     items = scenes.batch_items(a.items, seed=TRAIN_SEED)
     log(f"[train] solving {len(items)} training items (FP16 batch, tol {a.tol:g})")
-    sol = ws.solve(items, "f16", tol=a.tol, interval=a.interval, max_steps=a.max_steps, chunk=a.chunk, log=log)
+    sol = ws.solve(items, "f16", tol=a.tol, interval=a.interval, max_steps=a.max_steps, chunk=a.chunk, log=log,
+                   max_seconds=a.max_seconds)
     log(f"[train] solved in {sol['seconds']:.1f} s; statuses {dict(zip(*np.unique(sol['status'], return_counts=True)))}")
     mom = ws.moments_of(sol["batch"])
     X, T, W = dataset(items, sol["batch"], mom, a.size)
@@ -113,33 +117,42 @@ def plain(items, tol, interval, max_steps):
     return dict(steps=np.array(steps), seconds=secs, moments=moms)
 
 
+def inits_from(moms):
+    """(u, B) initial fields from moment arrays [nz, ny, nx, 8]."""
+    return [(m[..., 1:4], m[..., 5:8]) for m in moms]
+
+
+def summary(sol, moms, ref_m, items, masks):
+    e = field_error(items, moms, ref_m, masks)
+    return dict(seconds=sol["seconds"], steps=sol["steps"].tolist(), status=sol["status"],
+                n_not_steady=int(sum(s != "steady" for s in sol["status"])),
+                n_stalled=int(sum(s == "stalled" for s in sol["status"])),
+                error_median=float(np.median(e)), error_max=float(np.max(e)), tuned=sol.get("tuned"))
+
+
 def cmd_eval(a):
     import torch
     from paper_2506_00907_amd import lbm
     items = scenes.batch_items(a.items, seed=EVAL_SEED)
-    res = dict(items=a.items, seed=EVAL_SEED, tol=a.tol, interval=a.interval)
-    # reference: FP64 batch to a tighter tolerance
-    log(f"[eval] FP64 reference, tol {a.ref_tol:g}")
-    ref = ws.solve(items, "f64", tol=a.ref_tol, interval=a.interval, max_steps=a.max_steps, chunk=a.chunk, log=log)
-    ref_m = ws.moments_of(ref["batch"])
-    masks = [lat.mask for lat in ref["batch"].items]
-    res["reference"] = dict(seconds=ref["seconds"], steps=ref["steps"].tolist(), status=ref["status"])
-    del ref
+    res = dict(items=a.items, seed=EVAL_SEED, tol=a.tol, tol_fp16=a.tol16, interval=a.interval,
+               ref_tol=a.ref_tol)
+    kw = dict(interval=a.interval, max_steps=a.max_steps, chunk=a.chunk, log=log)
+
+    log(f"[eval] batch: FP32, rest start, tol {a.tol:g}")
+    bsol = ws.solve(items, "f32", tol=a.tol, **kw)
+    b_m = ws.moments_of(bsol["batch"])
+    masks = [lat.mask for lat in bsol["batch"].items]
+    del bsol["batch"]
     torch.cuda.empty_cache()
 
-    def polish(sol, label):
-        """FP32 batch from the fields of an FP16 run."""
-        m16 = ws.moments_of(sol["batch"])
-        inits = []
-        for i, it in enumerate(items):
-            m = m16[i]
-            inits.append((m[..., 1:4], m[..., 5:8]))
-        p = ws.solve(items, "f32", tol=a.tol, interval=a.interval, max_steps=a.max_steps, chunk=a.chunk,
-                     inits=inits, log=log)
-        mp = ws.moments_of(p["batch"])
-        return p, m16, mp
+    log(f"[eval] reference: FP64 from the batch's final state, tol {a.ref_tol:g}")
+    rsol = ws.solve(items, "f64", tol=a.ref_tol, inits=inits_from(b_m), **kw)
+    ref_m = ws.moments_of(rsol["batch"])
+    res["reference"] = dict(seconds=rsol["seconds"], steps=rsol["steps"].tolist(), status=rsol["status"])
+    del rsol
+    torch.cuda.empty_cache()
+    res["batch"] = summary(bsol, b_m, ref_m, items, masks)
 
-    out = {}
     for label in ("cold", "warm"):
         inits, t_inf = None, 0.0
         if label == "warm":
@@ -153,42 +166,50 @@ def cmd_eval(a):
                 X[i] = torch.from_numpy(ws.features(it, masks[i], a.size))
             pred = ws.predict(net, X).cpu().numpy()
             inits = [ws.init_fields(it, masks[i], pred[i]) for i, it in enumerate(items)]
+            torch.cuda.synchronize()
             t_inf = time.perf_counter() - t0
-            # prediction error against the reference (before any lattice step)
             pe = []
             for i, it in enumerate(items):
                 t_ref, w = ws.targets(it, masks[i], ref_m[i], a.size)
                 sel = w > 0
                 pe.append(float(np.linalg.norm((pred[i] - t_ref)[sel]) / max(np.linalg.norm(t_ref[sel]), 1e-30)))
-            out["prediction_error"] = dict(median=float(np.median(pe)), max=float(np.max(pe)))
-        log(f"[eval] {label}: FP16 batch")
-        s16 = ws.solve(items, "f16", tol=a.tol, interval=a.interval, max_steps=a.max_steps, chunk=a.chunk,
-                       inits=inits, log=log)
-        log(f"[eval] {label}: FP32 polish")
-        p, m16, mp = polish(s16, label)
-        e16 = field_error(items, m16, ref_m, masks)
-        ep = field_error(items, mp, ref_m, masks)
-        out[label] = dict(inference_seconds=t_inf, fp16_seconds=s16["seconds"], fp16_steps=s16["steps"].tolist(),
-                          fp16_status=s16["status"], fp16_error_median=float(np.median(e16)),
-                          fp16_error_max=float(np.max(e16)), polish_seconds=p["seconds"],
-                          polish_steps=p["steps"].tolist(), polish_status=p["status"],
-                          error_median=float(np.median(ep)), error_max=float(np.max(ep)),
-                          total_seconds=t_inf + s16["seconds"] + p["seconds"], tuned=s16["tuned"])
-        del s16, p
+            res["prediction_error"] = dict(median=float(np.median(pe)), max=float(np.max(pe)))
+            log(f"[eval] warm: inference {t_inf:.2f} s, prediction error median {np.median(pe):.3f}")
+        log(f"[eval] {label}: FP16 batch, tol {a.tol16:g}")
+        s16 = ws.solve(items, "f16", tol=a.tol16, inits=inits, stall=0.5, **kw)
+        m16 = ws.moments_of(s16["batch"])
+        del s16["batch"]
         torch.cuda.empty_cache()
-        log(f"[eval] {label}: {out[label]['total_seconds']:.1f} s, error median {out[label]['error_median']:.2e}")
+        log(f"[eval] {label}: FP32 polish, tol {a.tol:g}")
+        p = ws.solve(items, "f32", tol=a.tol, inits=inits_from(m16), **kw)
+        mp = ws.moments_of(p["batch"])
+        del p["batch"]
+        torch.cuda.empty_cache()
+        r = summary(p, mp, ref_m, items, masks)
+        r16 = summary(s16, m16, ref_m, items, masks)
+        res[label] = dict(inference_seconds=t_inf, fp16=r16, polish=r,
+                          total_seconds=t_inf + s16["seconds"] + p["seconds"],
+                          error_median=r["error_median"], error_max=r["error_max"])
+        log(f"[eval] {label}: {res[label]['total_seconds']:.1f} s, error median {r['error_median']:.2e}")
     if a.plain:
         log("[eval] plain FP32, one item at a time")
         pl = plain(items, a.tol, a.interval, a.max_steps)
         e = field_error(items, pl["moments"], ref_m, masks)
-        out["plain"] = dict(seconds=pl["seconds"], steps=pl["steps"].tolist(), error_median=float(np.median(e)),
+        res["plain"] = dict(seconds=pl["seconds"], steps=pl["steps"].tolist(), error_median=float(np.median(e)),
                             error_max=float(np.max(e)))
-        for label in ("cold", "warm"):
-            out[label]["speedup_vs_plain"] = pl["seconds"] / out[label]["total_seconds"]
-    res.update(out)
+        for label in ("batch", "cold", "warm"):
+            tot = res[label]["seconds"] if label == "batch" else res[label]["total_seconds"]
+            res[label]["speedup_vs_plain"] = pl["seconds"] / tot
     os.makedirs(a.out, exist_ok=True)
     json.dump(res, open(os.path.join(a.out, "eval.json"), "w"), indent=1)
-    log(json.dumps({k: v for k, v in res.items() if k not in ("reference",)}, default=str)[:3000])
+    brief = {k: v for k, v in res.items() if k != "reference"}
+    for k in ("batch", "cold", "warm", "plain"):
+        if k in brief:
+            brief[k] = {kk: vv for kk, vv in brief[k].items() if kk not in ("steps", "status")}
+            for sub in ("fp16", "polish"):
+                if sub in brief[k]:
+                    brief[k][sub] = {kk: vv for kk, vv in brief[k][sub].items() if kk not in ("steps", "status")}
+    log(json.dumps(brief, default=str))
 
 
 def main(argv=None):
@@ -199,17 +220,19 @@ def main(argv=None):
         p.add_argument("--items", type=int, default=4096 if name == "train" else 256)
         p.add_argument("--size", type=int, default=256)
         p.add_argument("--tol", type=float, default=1e-6 if name == "train" else 1e-8)
-        p.add_argument("--interval", type=int, default=100)
+        p.add_argument("--interval", type=int, default=1000)
         p.add_argument("--max-steps", type=int, default=2_000_000)
-        p.add_argument("--chunk", type=int, default=20_000)
+        p.add_argument("--chunk", type=int, default=50_000)
         p.add_argument("--out", default="gpurun_out/steady")
         if name == "train":
+            p.add_argument("--max-seconds", type=float, default=float("inf"))
             p.add_argument("--epochs", type=int, default=20)
             p.add_argument("--batch", type=int, default=16)
             p.add_argument("--lr", type=float, default=1e-3)
         else:
             p.add_argument("--weights", required=True)
             p.add_argument("--ref-tol", type=float, default=1e-10)
+            p.add_argument("--tol16", type=float, default=1e-6)
             p.add_argument("--plain", action="store_true")
     a = ap.parse_args(argv)
     import torch

@@ -106,11 +106,15 @@ def init_fields(item, mask: np.ndarray, pred: np.ndarray):
 # ---------------------------------------------------------------------------
 # solving many items with the batch
 # ---------------------------------------------------------------------------
-def solve(items, storage: str = "f16", tol: float = 1e-8, interval: int = 100, max_steps: int = 2_000_000,
-          chunk: int = 20_000, inits: Optional[list] = None, tune: bool = True, log=print):
+def solve(items, storage: str = "f16", tol: float = 1e-8, interval: int = 1000, max_steps: int = 2_000_000,
+          chunk: int = 20_000, inits: Optional[list] = None, tune: bool = True, log=print,
+          max_seconds: float = float("inf"), stall: Optional[float] = None):
     """Runs every item to its steady state with lbm_batch_run in chunks of
     `chunk` steps (items that finish are disabled between chunks).
-    inits[i] = (u, B) initial fields or None for rest.  Returns a dict with
+    inits[i] = (u, B) initial fields or None for rest; the solve also stops
+    after max_seconds (checked between chunks).  With stall = s, an item whose
+    residual fell by less than the factor s over a chunk (the noise floor of
+    its storage format) stops with status "stalled".  Returns a dict with
     per-item steps, residuals and statuses, the batch (for readback) and the
     wall time of the solve (synchronised, excluding set-up)."""
     import torch
@@ -134,7 +138,7 @@ def solve(items, storage: str = "f16", tol: float = 1e-8, interval: int = 100, m
     status = ["active"] * n
     start_t = np.array([it.time for it in B.items])
     done = 0
-    while done < max_steps:
+    while done < max_steps and time.perf_counter() - t0 < max_seconds:
         active = [s == "active" for s in status]
         if not any(active):
             break
@@ -143,8 +147,11 @@ def solve(items, storage: str = "f16", tol: float = 1e-8, interval: int = 100, m
         st, rs, ss = B.run(tol=tol, interval=interval, max_steps=k)
         for i in range(n):
             if active[i]:
+                prev = res[i]
                 res[i] = rs[i]
                 status[i] = ss[i]
+                if stall is not None and ss[i] == "active" and prev > 0 and rs[i] > stall * prev:
+                    status[i] = "stalled"
         done += k
         n_act = sum(s == "active" for s in status)
         log(f"  [{storage}] {done} steps: {n - n_act}/{n} items finished, "
