@@ -34,20 +34,6 @@
 
 #include "lbm_internal.hpp"
 
-// launch shape and store flavour of the sweep (build-time knobs for
-// measurements; the defaults are the tuned choice)
-#ifndef LBM_SWEEP_BLOCK
-#define LBM_SWEEP_BLOCK 256
-#endif
-#ifndef LBM_NT_STORE
-#define LBM_NT_STORE 0
-#endif
-#ifdef LBM_MIN_WAVES
-#define LBM_SWEEP_OCC __attribute__((amdgpu_waves_per_eu(LBM_MIN_WAVES)))
-#else
-#define LBM_SWEEP_OCC
-#endif
-
 namespace lbmi {
 
 // ---------------------------------------------------------------------------
@@ -152,13 +138,7 @@ template <> __device__ __forceinline__ float ld<BF16S>(const uint16_t* p, uint32
 
 template <class SF> __device__ __forceinline__ void st(typename SF::T* p, uint32_t i, typename SF::R v);
 template <> __device__ __forceinline__ void st<F64S>(double* p, uint32_t i, double v) { p[i] = v; }
-template <> __device__ __forceinline__ void st<F32S>(float* p, uint32_t i, float v) {
-#if LBM_NT_STORE
-    __builtin_nontemporal_store(v, p + i);
-#else
-    p[i] = v;
-#endif
-}
+template <> __device__ __forceinline__ void st<F32S>(float* p, uint32_t i, float v) { p[i] = v; }
 template <> __device__ __forceinline__ void st<F16S>(uint16_t* p, uint32_t i, float v) {
     p[i] = __builtin_bit_cast(uint16_t, (_Float16)v);  // round to nearest even
 }
@@ -274,6 +254,7 @@ struct Geo {
     int NX, NY, NZ;
     int hx, hy, hz, n0, n1, n2;
     uint32_t plane;
+    uint32_t wave_fluid;  // offset in the flag array of one byte per 64 nodes: 1 = all fluid
     FastDiv dx, dy;
 };
 
@@ -373,6 +354,19 @@ __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R
 //     streamed x*_alpha'(E) = [alpha', A]; target [alpha, A]
 // with E = A + e_alpha and B = A - e_alpha.  No other link of the launch
 // reads a target slot, so the kernel is race-free.
+// a link record into registers with 16-byte loads (the fields are then read
+// from registers, not fetched one by one inside the dependent chain)
+template <class R>
+__device__ __forceinline__ DevLink<R> load_link(const DevLink<R>* __restrict__ p) {
+    static_assert(sizeof(DevLink<R>) % 16 == 0, "link records are whole 16-byte words");
+    DevLink<R> L;
+    const uint4* s = reinterpret_cast<const uint4*>(p);
+    uint4* d = reinterpret_cast<uint4*>(&L);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(DevLink<R>) / 16); ++i) d[i] = s[i];
+    return L;
+}
+
 template <class C, int ODD>
 __device__ __forceinline__ void link_update(const Geo& G, const Phys<typename C::R>& P, typename C::T* __restrict__ S,
                                             const DevLink<typename C::R>& L, const typename C::R* __restrict__ M,
@@ -439,7 +433,7 @@ __global__ __launch_bounds__(256) void k_links(Geo G, Phys<typename C::R> P, typ
                                                const uint32_t* __restrict__ tbase, uint32_t tstep) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nlinks) return;
-    link_update<C, ODD>(G, P, S, links[k], M, C::SCALED ? step_time(tbase, tstep) : 0u);
+    link_update<C, ODD>(G, P, S, load_link(links + k), M, C::SCALED ? step_time(tbase, tstep) : 0u);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,20 +447,22 @@ struct NodeRes {
 
 // MODE 0: full step (gather, moments, collide, scatter)
 // MODE 1: observe (gather, moments)
+// The node is fluid (checked by node_update).
 template <class C, int ODD, int MODE>
-__device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C::R>& P,
-                                            typename C::T* __restrict__ S,
-                                            const uint8_t* __restrict__ flags,
-                                            typename C::R* __restrict__ M, uint32_t n,
-                                            NodeRes<C>& res, uint32_t seed = 0u) {
+__device__ __forceinline__ void node_body(const Geo& G, const Phys<typename C::R>& P,
+                                          typename C::T* __restrict__ S,
+                                          const uint8_t* __restrict__ flags,
+                                          typename C::R* __restrict__ M, uint32_t n,
+                                          NodeRes<C>& res, uint32_t seed) {
     using R = typename C::R;
     using SF = typename C::S;
     using FL = typename C::FL;
     using HL = typename C::HL;
     using GL = typename C::GL;
     constexpr int QF = C::QF, QH = C::QH, QG = C::QG, NCP = C::NCOMP, QT = C::QT;
-    const uint8_t fl = flags[n];
-    if (!(fl & NF_FLUID)) return false;
+    // The 64 nodes of a wave are contiguous and 64-aligned.  Where all of them
+    // are fluid (one wave-uniform byte), the gathers do not wait for the
+    // per-node flag, which is then needed only for the moment stores.
     const uint32_t PL = G.plane;
 
     // coordinates and wrapped neighbour offsets (fluid nodes never touch a
@@ -579,10 +575,10 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
     m.dB[0] = dB[0];
     m.dB[1] = dB[1];
     m.dB[2] = dB[2];
-    if (MODE != 0) return true;
+    if (MODE != 0) return;
 
     // moments of link nodes for the next step's extrapolations (Eq. 13)
-    if (fl & NF_MOM) {
+    if (flags[n] & NF_MOM) {
         R* Mc = M + (size_t)ODD * 8 * PL;
         Mc[0 * (size_t)PL + n] = drho;
         Mc[1 * (size_t)PL + n] = ux;
@@ -683,6 +679,26 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
             if (ODD) put(b + i, nb(GL::ex(i), GL::ey(i), GL::ez(i)), v);
             else put(b + GL::opp(i), n, v);
         }
+}
+
+// Updates node n if it is fluid; returns whether it is.  The 64 nodes of a
+// wave are contiguous and 64-aligned; where all of them are fluid (one
+// wave-uniform byte of the flag array, a scalar load), the gathers are issued
+// without waiting for the per-node flag.
+template <class C, int ODD, int MODE>
+__device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C::R>& P,
+                                            typename C::T* __restrict__ S,
+                                            const uint8_t* __restrict__ flags,
+                                            typename C::R* __restrict__ M, uint32_t n,
+                                            NodeRes<C>& res, uint32_t seed = 0u) {
+    const uint32_t wg = __builtin_amdgcn_readfirstlane(n >> 6);
+    const uint32_t wword = reinterpret_cast<const uint32_t*>(flags + G.wave_fluid)[wg >> 2];
+    if ((wword >> (8 * (wg & 3))) & 0xFFu) {
+        node_body<C, ODD, MODE>(G, P, S, flags, M, n, res, seed);
+        return true;
+    }
+    if (!(flags[n] & NF_FLUID)) return false;
+    node_body<C, ODD, MODE>(G, P, S, flags, M, n, res, seed);
     return true;
 }
 
@@ -690,7 +706,7 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
 // kernels
 // ---------------------------------------------------------------------------
 template <class C, int ODD>
-__global__ __launch_bounds__(LBM_SWEEP_BLOCK) LBM_SWEEP_OCC void k_step(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
+__global__ __launch_bounds__(256) void k_step(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
                                               const uint8_t* __restrict__ flags,
                                               typename C::R* __restrict__ M, uint32_t nnodes,
                                               const uint32_t* __restrict__ tbase, uint32_t tstep) {
@@ -935,7 +951,7 @@ __global__ __launch_bounds__(256) void kb_links(const BItem<C>* __restrict__ ite
     const BItem<C>& I = items[it];
     const uint32_t k = ltiles[2 * b + 1] + threadIdx.x;
     if (k >= I.nlinks) return;
-    link_update<C, ODD>(I.G, I.P, I.S, I.links[k], I.M, C::SCALED ? step_time(I.tbase, tstep) : 0u);
+    link_update<C, ODD>(I.G, I.P, I.S, load_link(I.links + k), I.M, C::SCALED ? step_time(I.tbase, tstep) : 0u);
 }
 
 // item time bases: set from the descriptors (all items), or advanced for the
@@ -972,14 +988,14 @@ __global__ __launch_bounds__(512) void kb_resident(const BItem<C>* __restrict__ 
     const uint32_t t0 = C::SCALED ? step_time(I.tbase, tstep) : 0u;
     for (int s = 0; s < nsteps; s += 2) {
         const uint32_t te = t0 + (uint32_t)s, to = te + 1u;
-        for (uint32_t k = threadIdx.x; k < nl; k += bd) link_update<C, 0>(G, P, S, links[k], M, te);
+        for (uint32_t k = threadIdx.x; k < nl; k += bd) link_update<C, 0>(G, P, S, load_link(links + k), M, te);
         __syncthreads();
         for (uint32_t n = threadIdx.x; n < nn; n += bd) {
             NodeRes<C> r;
             node_update<C, 0, 0>(G, P, S, flags, M, n, r, te);
         }
         __syncthreads();
-        for (uint32_t k = threadIdx.x; k < nl; k += bd) link_update<C, 1>(G, P, S, links[k], M, to);
+        for (uint32_t k = threadIdx.x; k < nl; k += bd) link_update<C, 1>(G, P, S, load_link(links + k), M, to);
         __syncthreads();
         for (uint32_t n = threadIdx.x; n < nn; n += bd) {
             NodeRes<C> r;
@@ -1071,6 +1087,7 @@ inline Geo make_geo(const KArgs& a) {
     g.n1 = a.n1;
     g.n2 = a.n2;
     g.plane = (uint32_t)a.plane;
+    g.wave_fluid = (uint32_t)a.wave_fluid;
     g.dx = make_fastdiv((uint32_t)a.NX);
     g.dy = make_fastdiv((uint32_t)a.NY);
     return g;
@@ -1101,7 +1118,7 @@ struct Launch {
     }
     static hipError_t sweep(const KArgs& a) {
         const uint32_t nn = (uint32_t)((size_t)a.NX * a.NY * a.NZ);
-        const int bs = LBM_SWEEP_BLOCK;
+        const int bs = 256;
         dim3 grid((nn + bs - 1) / bs);
         const Phys<R> P = make_phys<R>(a, cg2());
         const Geo G = make_geo(a);

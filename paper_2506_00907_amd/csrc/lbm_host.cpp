@@ -398,7 +398,7 @@ void layout(const lbm_params* p, size_t n_links, size_t sz[LBM_NBUF]) {
     const Pad d = padding(p);
     const size_t vb = value_bytes(p->storage), cb = compute_bytes(p->storage);
     sz[0] = round_up((size_t)total_planes(p) * d.plane * vb, kAlign);          // populations
-    sz[1] = round_up(d.plane, kAlign);                                          // node flags
+    sz[1] = round_up(d.plane, kAlign) + round_up(d.plane / 64, kAlign);        // node flags, wave summary
     sz[2] = round_up(std::max<size_t>(n_links, 1) * link_bytes(p->storage), kAlign);  // link records
     sz[3] = round_up(2 * 8 * d.plane * cb, kAlign) + kAlign;                   // moment planes, time base
     sz[4] = round_up(7 * d.plane * cb, kAlign) + round_up(lbmi::NACC * sizeof(double), kAlign);  // reductions
@@ -420,6 +420,7 @@ lbmi::KArgs base_args(const lbm_ctx* c) {
     a.plane = c->pad.plane;
     a.S = c->buf[0];
     a.flags = (const uint8_t*)c->buf[1];
+    a.wave_fluid = round_up(c->pad.plane, kAlign);
     a.links = c->buf[2];
     a.M = c->buf[3];
     a.n_links = c->n_links;
@@ -440,7 +441,6 @@ lbmi::KArgs base_args(const lbm_ctx* c) {
     a.links_ready = c->t > 0 ? 1 : 0;
     a.tbase = nullptr;
     a.tstep = (uint32_t)c->t;
-    a.block = 256;
     a.stream = c->stream;
     return a;
 }
@@ -744,7 +744,7 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
         sE[i] = padE[order[i]];
         sB[i] = padB[order[i]];
     }
-    std::vector<uint8_t> flags(d.plane, 0);
+    std::vector<uint8_t> flags(round_up(d.plane, kAlign) + d.plane / 64, 0);
     for (size_t i = 0; i < N; ++i)
         if (c->mask[i]) {
             int q[3];
@@ -754,6 +754,13 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
     for (size_t i = 0; i < n; ++i) {
         flags[sA[i]] |= lbmi::NF_LINKS | lbmi::NF_MOM;
         if (!(sl[i].flags & 2)) flags[sE[i]] |= lbmi::NF_MOM;
+    }
+    // one byte per 64 padded nodes: 1 when every node of the group is fluid
+    const size_t wf0 = round_up(d.plane, kAlign);
+    for (size_t g = 0; g < d.plane / 64; ++g) {
+        bool all = true;
+        for (size_t k = 64 * g; k < 64 * g + 64 && all; ++k) all = k < d.nodes && (flags[k] & lbmi::NF_FLUID);
+        flags[wf0 + g] = all ? 1 : 0;
     }
 
     std::vector<unsigned char> dl;

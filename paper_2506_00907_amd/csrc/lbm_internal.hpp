@@ -45,6 +45,7 @@ struct KArgs {
     int hx, hy, hz;        // halo widths (0 periodic, 1 otherwise)
     int n0, n1, n2;        // domain extents
     size_t plane;          // padded node count rounded up (population plane stride)
+    size_t wave_fluid;     // offset in flags of one byte per 64 nodes (1 = all fluid)
     void* S;               // populations [QT][plane]
     const uint8_t* flags;  // [plane]
     const void* links;     // DevLink<R>[n_links]
@@ -66,7 +67,6 @@ struct KArgs {
     void* snap;            // OBS_REDUCE: R[7][plane] snapshot of u, C - C0, B - B_ext
     int snap_valid;
     const double *init_rho, *init_u, *init_C, *init_B;
-    int block;             // threads per block
     hipStream_t stream;
     hipEvent_t ev[3];      // optional: recorded before links, between, after sweep
 };
