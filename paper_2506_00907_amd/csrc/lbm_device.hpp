@@ -126,27 +126,39 @@ struct F32S { using T = float; using R = float; };
 struct F16S { using T = uint16_t; using R = float; };
 struct BF16S { using T = uint16_t; using R = float; };
 
+// Element i of a plane.  The byte offset is formed in 32 bits (a plane is
+// below 4 GiB, checked on the host), so the access is a uniform 64-bit base
+// plus a 32-bit per-lane offset: one VGPR of address per access, not two.
+template <class T>
+__device__ __forceinline__ const T& at(const T* p, uint32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ T& at(T* p, uint32_t i) {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+
 template <class SF> __device__ __forceinline__ typename SF::R ld(const typename SF::T* p, uint32_t i);
-template <> __device__ __forceinline__ double ld<F64S>(const double* p, uint32_t i) { return p[i]; }
-template <> __device__ __forceinline__ float ld<F32S>(const float* p, uint32_t i) { return p[i]; }
+template <> __device__ __forceinline__ double ld<F64S>(const double* p, uint32_t i) { return at(p, i); }
+template <> __device__ __forceinline__ float ld<F32S>(const float* p, uint32_t i) { return at(p, i); }
 template <> __device__ __forceinline__ float ld<F16S>(const uint16_t* p, uint32_t i) {
-    return (float)__builtin_bit_cast(_Float16, p[i]);
+    return (float)__builtin_bit_cast(_Float16, at(p, i));
 }
 template <> __device__ __forceinline__ float ld<BF16S>(const uint16_t* p, uint32_t i) {
-    return __builtin_bit_cast(float, (uint32_t)p[i] << 16);
+    return __builtin_bit_cast(float, (uint32_t)at(p, i) << 16);
 }
 
 template <class SF> __device__ __forceinline__ void st(typename SF::T* p, uint32_t i, typename SF::R v);
-template <> __device__ __forceinline__ void st<F64S>(double* p, uint32_t i, double v) { p[i] = v; }
-template <> __device__ __forceinline__ void st<F32S>(float* p, uint32_t i, float v) { p[i] = v; }
+template <> __device__ __forceinline__ void st<F64S>(double* p, uint32_t i, double v) { at(p, i) = v; }
+template <> __device__ __forceinline__ void st<F32S>(float* p, uint32_t i, float v) { at(p, i) = v; }
 template <> __device__ __forceinline__ void st<F16S>(uint16_t* p, uint32_t i, float v) {
-    p[i] = __builtin_bit_cast(uint16_t, (_Float16)v);  // round to nearest even
+    at(p, i) = __builtin_bit_cast(uint16_t, (_Float16)v);  // round to nearest even
 }
 template <> __device__ __forceinline__ void st<BF16S>(uint16_t* p, uint32_t i, float v) {
     // round to nearest even on the upper 16 bits (finite inputs)
     uint32_t b = __builtin_bit_cast(uint32_t, v);
     b += 0x7FFFu + ((b >> 16) & 1u);
-    p[i] = (uint16_t)(b >> 16);
+    at(p, i) = (uint16_t)(b >> 16);
 }
 
 // Stores with stochastic rounding for the 16-bit formats: a dither drawn
@@ -174,12 +186,12 @@ template <> __device__ __forceinline__ void st_sr<F16S>(uint16_t* p, uint32_t i,
     const uint32_t e = (b >> 23) & 0xFFu;
     // normal FP16 range below the largest binade: dither the 13 dropped bits
     if (e >= 113u && e < 142u) b = (b + (r & 0x1FFFu)) & ~0x1FFFu;
-    p[i] = __builtin_bit_cast(uint16_t, (_Float16)__builtin_bit_cast(float, b));
+    at(p, i) = __builtin_bit_cast(uint16_t, (_Float16)__builtin_bit_cast(float, b));
 }
 template <> __device__ __forceinline__ void st_sr<BF16S>(uint16_t* p, uint32_t i, float v, uint32_t r) {
     uint32_t b = __builtin_bit_cast(uint32_t, v);
     if (((b >> 23) & 0xFFu) < 0xFEu) b += r & 0xFFFFu;  // finite and not next to overflow
-    p[i] = (uint16_t)(b >> 16);
+    at(p, i) = (uint16_t)(b >> 16);
 }
 
 // ---------------------------------------------------------------------------
@@ -445,58 +457,57 @@ struct NodeRes {
     Mom<typename C::R> m;
 };
 
-// MODE 0: full step (gather, moments, collide, scatter)
-// MODE 1: observe (gather, moments)
-// The node is fluid (checked by node_update).
-template <class C, int ODD, int MODE>
-__device__ __forceinline__ void node_body(const Geo& G, const Phys<typename C::R>& P,
-                                          typename C::T* __restrict__ S,
-                                          const uint8_t* __restrict__ flags,
-                                          typename C::R* __restrict__ M, uint32_t n,
-                                          NodeRes<C>& res, uint32_t seed) {
-    using R = typename C::R;
-    using SF = typename C::S;
-    using FL = typename C::FL;
-    using HL = typename C::HL;
-    using GL = typename C::GL;
-    constexpr int QF = C::QF, QH = C::QH, QG = C::QG, NCP = C::NCOMP, QT = C::QT;
-    // The 64 nodes of a wave are contiguous and 64-aligned.  Where all of them
-    // are fluid (one wave-uniform byte), the gathers do not wait for the
-    // per-node flag, which is then needed only for the moment stores.
-    const uint32_t PL = G.plane;
+// Padded node and its wrapped neighbour offsets (fluid nodes never touch a
+// non-periodic edge of the padded grid, so wrapping only ever applies on
+// periodic axes).
+struct Nbr {
+    uint32_t n;
+    int oxm, oxp, oym, oyp, ozm, ozp;
+    __device__ __forceinline__ uint32_t at(int ex, int ey, int ez) const {
+        return (uint32_t)((int)n + (ex > 0 ? oxp : (ex < 0 ? oxm : 0)) + (ey > 0 ? oyp : (ey < 0 ? oym : 0)) +
+                          (ez > 0 ? ozp : (ez < 0 ? ozm : 0)));
+    }
+};
 
-    // coordinates and wrapped neighbour offsets (fluid nodes never touch a
-    // non-periodic edge of the padded grid, so wrapping only ever applies on
-    // periodic axes)
+__device__ __forceinline__ Nbr nbr_of(const Geo& G, uint32_t n) {
+    Nbr q;
+    q.n = n;
     const uint32_t t1 = fdiv(n, G.dx);
     const int x = (int)(n - t1 * (uint32_t)G.NX);
     const uint32_t zz = fdiv(t1, G.dy);
     const int y = (int)(t1 - zz * (uint32_t)G.NY);
     const int z = (int)zz;
     const int sx = G.NX * G.NY;
-    const int oxm = x == 0 ? G.NX - 1 : -1;
-    const int oxp = x == G.NX - 1 ? -(G.NX - 1) : 1;
-    const int oym = y == 0 ? (G.NY - 1) * G.NX : -G.NX;
-    const int oyp = y == G.NY - 1 ? -(G.NY - 1) * G.NX : G.NX;
-    const int ozm = z == 0 ? (G.NZ - 1) * sx : -sx;
-    const int ozp = z == G.NZ - 1 ? -(G.NZ - 1) * sx : sx;
-    auto nb = [&](int ex, int ey, int ez) -> uint32_t {
-        return (uint32_t)((int)n + (ex > 0 ? oxp : (ex < 0 ? oxm : 0)) + (ey > 0 ? oyp : (ey < 0 ? oym : 0)) +
-                          (ez > 0 ? ozp : (ez < 0 ? ozm : 0)));
-    };
+    q.oxm = x == 0 ? G.NX - 1 : -1;
+    q.oxp = x == G.NX - 1 ? -(G.NX - 1) : 1;
+    q.oym = y == 0 ? (G.NY - 1) * G.NX : -G.NX;
+    q.oyp = y == G.NY - 1 ? -(G.NY - 1) * G.NX : G.NX;
+    q.ozm = z == 0 ? (G.NZ - 1) * sx : -sx;
+    q.ozp = z == G.NZ - 1 ? -(G.NZ - 1) * sx : sx;
+    return q;
+}
+
+// gather (streaming) of one fluid node's populations, unscaled deviations
+template <class C, int ODD>
+__device__ __forceinline__ void gather(const Geo& G, const Phys<typename C::R>& P, typename C::T* __restrict__ S,
+                                       const Nbr& q, typename C::R* x_) {
+    using R = typename C::R;
+    using SF = typename C::S;
+    using FL = typename C::FL;
+    using HL = typename C::HL;
+    using GL = typename C::GL;
+    constexpr int QF = C::QF, QH = C::QH, QG = C::QG, NCP = C::NCOMP;
+    const uint32_t PL = G.plane, n = q.n;
     // plane p as a wave-uniform base pointer; per-lane 32-bit element index
     auto plane = [&](int p) -> typename C::T* { return S + (size_t)p * PL; };
-
-    R* x_ = res.x;
-    // ---- gather (streaming) ----
 #pragma unroll
     for (int i = 0; i < QF; ++i) {
-        R v = ODD ? ld<SF>(plane(FL::opp(i)), nb(-FL::ex(i), -FL::ey(i), -FL::ez(i))) : ld<SF>(plane(i), n);
+        R v = ODD ? ld<SF>(plane(FL::opp(i)), q.at(-FL::ex(i), -FL::ey(i), -FL::ez(i))) : ld<SF>(plane(i), n);
         x_[i] = C::SCALED ? v * P.isc[0] : v;
     }
 #pragma unroll
     for (int i = 0; i < QH; ++i) {
-        R v = ODD ? ld<SF>(plane(C::H0 + HL::opp(i)), nb(-HL::ex(i), -HL::ey(i), -HL::ez(i)))
+        R v = ODD ? ld<SF>(plane(C::H0 + HL::opp(i)), q.at(-HL::ex(i), -HL::ey(i), -HL::ez(i)))
                   : ld<SF>(plane(C::H0 + i), n);
         x_[C::H0 + i] = C::SCALED ? v * P.isc[1] : v;
     }
@@ -505,11 +516,28 @@ __device__ __forceinline__ void node_body(const Geo& G, const Phys<typename C::R
 #pragma unroll
         for (int i = 0; i < QG; ++i) {
             const int b = C::G0 + c * QG;
-            R v = ODD ? ld<SF>(plane(b + GL::opp(i)), nb(-GL::ex(i), -GL::ey(i), -GL::ez(i)))
+            R v = ODD ? ld<SF>(plane(b + GL::opp(i)), q.at(-GL::ex(i), -GL::ey(i), -GL::ez(i)))
                       : ld<SF>(plane(b + i), n);
             x_[b + i] = C::SCALED ? v * P.isc[2] : v;
         }
+}
 
+// Everything after the gather: moments, moment store of link nodes,
+// collision, scatter.  MODE 0: full step; MODE 1: observe (moments only).
+template <class C, int ODD, int MODE>
+__device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& P, typename C::T* __restrict__ S,
+                                       uint8_t fl, typename C::R* __restrict__ M,
+                                       const Nbr& q, NodeRes<C>& res, uint32_t seed) {
+    using R = typename C::R;
+    using SF = typename C::S;
+    using FL = typename C::FL;
+    using HL = typename C::HL;
+    using GL = typename C::GL;
+    constexpr int QF = C::QF, QH = C::QH, QG = C::QG, NCP = C::NCOMP;
+    const uint32_t PL = G.plane, n = q.n;
+    auto plane = [&](int p) -> typename C::T* { return S + (size_t)p * PL; };
+    auto nb = [&](int ex, int ey, int ez) -> uint32_t { return q.at(ex, ey, ez); };
+    R* x_ = res.x;
     // ---- moments ----
     Mom<R>& m = res.m;
     R jx = 0, jy = 0, jz = 0, drho = 0;
@@ -578,7 +606,7 @@ __device__ __forceinline__ void node_body(const Geo& G, const Phys<typename C::R
     if (MODE != 0) return;
 
     // moments of link nodes for the next step's extrapolations (Eq. 13)
-    if (flags[n] & NF_MOM) {
+    if (fl & NF_MOM) {
         R* Mc = M + (size_t)ODD * 8 * PL;
         Mc[0 * (size_t)PL + n] = drho;
         Mc[1 * (size_t)PL + n] = ux;
@@ -693,12 +721,17 @@ __device__ __forceinline__ bool node_update(const Geo& G, const Phys<typename C:
                                             NodeRes<C>& res, uint32_t seed = 0u) {
     const uint32_t wg = __builtin_amdgcn_readfirstlane(n >> 6);
     const uint32_t wword = reinterpret_cast<const uint32_t*>(flags + G.wave_fluid)[wg >> 2];
-    if ((wword >> (8 * (wg & 3))) & 0xFFu) {
-        node_body<C, ODD, MODE>(G, P, S, flags, M, n, res, seed);
+    const uint8_t fl = flags[n];  // issued before the gathers, used after them
+    if ((wword >> (8 * (wg & 3))) & 0xFFu) {  // uniform branch: no wait for the node's flag
+        const Nbr q = nbr_of(G, n);
+        gather<C, ODD>(G, P, S, q, res.x);
+        finish<C, ODD, MODE>(G, P, S, fl, M, q, res, seed);
         return true;
     }
-    if (!(flags[n] & NF_FLUID)) return false;
-    node_body<C, ODD, MODE>(G, P, S, flags, M, n, res, seed);
+    if (!(fl & NF_FLUID)) return false;
+    const Nbr q = nbr_of(G, n);
+    gather<C, ODD>(G, P, S, q, res.x);
+    finish<C, ODD, MODE>(G, P, S, fl, M, q, res, seed);
     return true;
 }
 
@@ -711,7 +744,7 @@ __global__ __launch_bounds__(256) void k_step(Geo G, Phys<typename C::R> P, type
                                               typename C::R* __restrict__ M, uint32_t nnodes,
                                               const uint32_t* __restrict__ tbase, uint32_t tstep) {
     const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t n = b * blockDim.x + threadIdx.x;
+    const uint32_t n = b * 256u + threadIdx.x;
     if (n >= nnodes) return;
     NodeRes<C> r;
     node_update<C, ODD, 0>(G, P, S, flags, M, n, r, C::SCALED ? step_time(tbase, tstep) : 0u);

@@ -159,7 +159,7 @@ def cmd_eval(a):
             params = np.load(a.weights)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            net = lbm.Network(16, a.size)
+            net = lbm.Network(16, a.size, in_ch=ws.IN_CH, out_ch=ws.OUT_CH)
             net.set_params(params)
             X = torch.empty((len(items), a.size, a.size, ws.IN_CH), dtype=torch.float32, device="cuda")
             for i, it in enumerate(items):

@@ -1,12 +1,16 @@
 """Learned warm start for batches of duct / pipe cross-sections.
 
-The network of lbm_nn_* sees four maps of a cross-section on a fixed S x S
+The network of lbm_nn_* sees six maps of a cross-section on a fixed S x S
 canvas (the section at the top-left corner, rows = z, columns = y): the fluid
 mask, the distance to the nearest solid node over the half-width L, the
-Hartmann number / 50 and log10 of the wall conductance ratio / 3 on fluid
-nodes.  It predicts the axial velocity and the induced axial field scaled in
-the manner of Eq. 47, with the reference velocity U_ref = g L^2 / nu known
-from the inputs in place of the mean velocity (not known before solving):
+Hartmann number / 50, log10 of the wall conductance ratio / 3, and the
+position relative to the section's centre over L along y (the applied field's
+direction, across which the induced field changes sign) and along z, all on
+fluid nodes.  It predicts the axial velocity and the induced axial field
+scaled in the manner of Eq. 47, with a reference velocity known from the
+inputs in place of the mean velocity (not known before solving),
+U_ref = g L^2 / (nu (2 + Ha)), which follows the centre speed from the
+Poiseuille limit (Ha = 0) to the Hartmann limit (u ~ g L^2 / (nu Ha)):
 
     u* = u_x / U_ref,      B* = b_x / (U_ref sqrt(rho0 nu mu / eta)).
 
@@ -25,7 +29,7 @@ from typing import List, Optional
 
 import numpy as np
 
-IN_CH, OUT_CH = 4, 2
+IN_CH, OUT_CH = 6, 2
 
 
 def _nu_eta(sc):
@@ -46,7 +50,7 @@ def scales(item):
     sc = item.scene
     nu, eta = _nu_eta(sc)
     L = half_width(item)
-    U = sc.accel[0] * L * L / nu
+    U = sc.accel[0] * L * L / (nu * (2.0 + item.Ha))
     return U, U * math.sqrt(sc.rho0 * nu * sc.mu / eta)
 
 
@@ -67,10 +71,13 @@ def features(item, mask: np.ndarray, size: int = 256) -> np.ndarray:
     L = half_width(item)
     dist = ndimage.distance_transform_edt(np.pad(m, 1))[1:-1, 1:-1]
     c = float(np.exp(np.mean(np.log(item.c_eff))))
+    zz, yy = np.meshgrid(np.arange(nz), np.arange(ny), indexing="ij")
     x[:nz, :ny, 0] = m
     x[:nz, :ny, 1] = np.where(m, dist / L, 0.0)
     x[:nz, :ny, 2] = np.where(m, item.Ha / 50.0, 0.0)
     x[:nz, :ny, 3] = np.where(m, math.log10(c) / 3.0, 0.0)
+    x[:nz, :ny, 4] = np.where(m, (yy - (ny - 1) / 2.0) / L, 0.0)
+    x[:nz, :ny, 5] = np.where(m, (zz - (nz - 1) / 2.0) / L, 0.0)
     return x
 
 
@@ -194,7 +201,7 @@ def train(X, T, Wt, epochs: int = 20, batch: int = 16, lr: float = 1e-3, seed: i
     from scenes import SplitMix64
     n = X.shape[0]
     if net is None:
-        net = lbm.Network(batch, size)
+        net = lbm.Network(batch, size, in_ch=IN_CH, out_ch=OUT_CH)
         net.set_params(he_init(seed))
     rng = SplitMix64(seed + 1)
     hist = []

@@ -486,3 +486,23 @@ def developed(sc: Scene, seed: int = BASE_SEED + 7, u_amp: float = 0.02, b_amp: 
         B[..., c] += b_amp * smooth()
     Cf = sc.init_C + C_amp * smooth() if sc.scalar_lattice else None
     return sc.with_(init_rho=rho, init_u=u, init_B=B if sc.mag_lattice else None, init_Cf=Cf)
+
+
+def axial_start(sc: Scene, seed: int = BASE_SEED + 9, u_amp: float = 0.01, b_rel: float = 0.3) -> Scene:
+    """A duct / pipe item (axial extent 1) started from smooth axial fields
+    only, the form a warm start takes: u = (u_x, 0, 0), B = B_ext + (b_x, 0, 0),
+    rho = rho0.  u_x is a seeded multiple of a sine bump over the box (~u_amp),
+    b_x a seeded multiple of b_rel |B_ext| times the bump, odd in y.  In-plane
+    velocities and density changes are left out: started from those, the BGK
+    update keeps a row-alternating in-plane velocity that never decays."""
+    rng = SplitMix64(seed)
+    nx, ny, nz = sc.n
+    z, y = np.meshgrid(np.arange(nz), np.arange(ny), indexing="ij")
+    bump = np.sin(math.pi * (y + 0.5) / ny) * np.sin(math.pi * (z + 0.5) / nz)
+    a, c = rng.uniform(0.5, 1.5), rng.uniform(-1.0, 1.0)
+    u = np.zeros((nz, ny, nx, 3))
+    u[..., 0] = (u_amp * a * bump * (1.0 + 0.3 * np.cos(math.pi * y / ny)))[..., None]
+    B = np.broadcast_to(np.asarray(sc.B_ext, float), (nz, ny, nx, 3)).copy()
+    B0 = max(abs(b) for b in sc.B_ext)
+    B[..., 0] += (b_rel * c * B0 * bump * np.sin(2.0 * math.pi * y / ny))[..., None]
+    return sc.with_(init_u=u, init_B=B if sc.mag_lattice else None)

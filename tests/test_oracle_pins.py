@@ -580,3 +580,56 @@ def test_open_boundaries_keep_uniform_flow(qi, qo):
     assert np.abs(m[..., 0] - rho_out).max() < 1e-14
     assert np.abs(m[..., 1] - u_in[0]).max() < 1e-14
     assert np.abs(m[..., 2] - u_in[1]).max() < 1e-14
+
+
+def _half_way_ducts():
+    import dataclasses
+    ducts = [it.scene for it in scenes.batch_items(12, side_lo=14, side_hi=20, storage="f64", seed=91, Ha_hi=4.0)
+             if it.shape == "duct"][:3]
+    return [sc.with_(boundaries=[dataclasses.replace(b, q=0.5) for b in sc.boundaries]) for sc in ducts]
+
+
+def _run_to_steady(sc, tol, max_steps=50000):
+    """oracle steps until the relative change of u and B per step, over a
+    window of 100 steps, is below tol; returns (moments, steps)."""
+    o = oracle.OracleSim(sc, "f64")
+    o.step(2)
+    prev, t = o.moments().copy(), 2
+    while t < max_steps:
+        o.step(100)
+        t += 100
+        m = o.moments()
+        r = max(np.linalg.norm((m - prev)[..., s]) / (100 * np.linalg.norm(m[..., s]))
+                for s in (slice(1, 4), slice(5, 8)))
+        if r < tol:
+            return m, t
+        prev = m.copy()
+    raise AssertionError("no steady state")
+
+
+def test_axial_warm_start_reaches_the_rest_state():
+    """The steady state of a half-way-walled duct does not depend on a start
+    of the warm-start form (axial u_x and b_x only)."""
+    sc = _half_way_ducts()[1]
+    a, _ = _run_to_steady(sc, 3e-12)
+    b, _ = _run_to_steady(scenes.axial_start(sc, seed=701), 3e-12)
+    for q in (1, 5):
+        ref = np.abs(a[..., q] - sc.B_ext[0] * (q == 5)).max()
+        assert np.abs(a[..., q] - b[..., q]).max() / ref < 1e-7
+
+
+def test_in_plane_start_keeps_a_row_alternating_mode():
+    """Equilibria of a smooth in-plane velocity excite a mode that the BGK
+    update keeps: u_z alternates in sign from one z row to the next and its
+    size does not decay, so the steady state then depends on the start."""
+    sc = scenes.developed(_half_way_ducts()[1], seed=501, u_amp=0.01, b_amp=0.0, rho_amp=0.0)
+    o = oracle.OracleSim(sc, "f64")
+    mask = o.mask()[:, :, 0]
+    amp = []
+    for t in (3000, 3000):
+        o.step(t)
+        uz = o.moments()[:, :, 0, 3]
+        rows = np.array([uz[z][mask[z]].mean() for z in range(uz.shape[0])])
+        assert np.all(np.sign(rows[1:]) == -np.sign(rows[:-1]))
+        amp.append(np.abs(rows).mean())
+    assert amp[0] > 1e-5 and abs(amp[1] / amp[0] - 1.0) < 0.01

@@ -1,0 +1,60 @@
+"""Host-side pieces of the warm start: the network's input maps and the
+scaling of its targets (no GPU)."""
+import math
+
+import numpy as np
+
+import scenes
+from paper_2506_00907_amd import lbm
+from paper_2506_00907_amd import warmstart as ws
+
+
+def _item(shape):
+    its = scenes.batch_items(12, side_lo=20, side_hi=40)
+    return next(it for it in its if it.shape == shape)
+
+
+def test_features_mark_the_fluid_section_only():
+    for shape in ("duct", "pipe"):
+        it = _item(shape)
+        mask, _ = lbm.build_links(it.scene)
+        x = ws.features(it, mask, 64)
+        m = mask[:, :, 0].astype(bool)
+        nz, ny = m.shape
+        assert x.shape == (64, 64, ws.IN_CH)
+        assert np.array_equal(x[:nz, :ny, 0].astype(bool), m)
+        assert not x[nz:].any() and not x[:, ny:].any()
+        assert not x[:nz, :ny][~m].any()
+        # wall distance: 1 lattice unit next to a wall, largest near the centre
+        d = x[:nz, :ny, 1][m] * ws.half_width(it)
+        assert abs(d.min() - 1.0) < 1e-5 and d.max() > 0.8 * ws.half_width(it) - 1
+        assert np.allclose(x[:nz, :ny, 2][m], it.Ha / 50.0)
+        # centred coordinates: antisymmetric about the centre
+        assert abs(x[:nz, :ny, 4][m].mean()) < 1e-6 and abs(x[:nz, :ny, 5][m].mean()) < 1e-6
+
+
+def test_targets_and_initial_fields_are_inverse():
+    it = _item("pipe")
+    mask, _ = lbm.build_links(it.scene)
+    nz, ny = it.nz, it.ny
+    rng = scenes.SplitMix64(3)
+    mom = np.zeros((nz, ny, 1, 8))
+    m = mask.astype(bool)
+    mom[..., 1] = np.where(m, rng.uniform_array(nz * ny).reshape(nz, ny, 1) * 0.01, 0.0)
+    mom[..., 5] = np.where(m, it.scene.B_ext[0] + rng.uniform_array(nz * ny).reshape(nz, ny, 1) * 1e-3, 0.0)
+    t, w = ws.targets(it, mask, mom, 64)
+    assert math.isclose(float(w.sum()), 1.0, rel_tol=1e-6)
+    u, B = ws.init_fields(it, mask, t.astype(np.float64))
+    assert np.allclose(u[..., 0][m], mom[..., 1][m], rtol=1e-6, atol=1e-12)
+    assert np.allclose(B[..., 0][m], mom[..., 5][m], rtol=1e-6, atol=1e-12)
+    assert np.array_equal(B[..., 1], np.full((nz, ny, 1), it.scene.B_ext[1]))
+    assert not u[..., 1:].any()
+
+
+def test_scales_follow_the_hartmann_limit():
+    it = _item("duct")
+    U, Bs = ws.scales(it)
+    nu = (it.scene.tau_f - 0.5) / 3.0
+    L = ws.half_width(it)
+    assert math.isclose(U, it.scene.accel[0] * L * L / (nu * (2.0 + it.Ha)))
+    assert math.isclose(Bs, U)  # nu = eta and rho0 = mu = 1 for these items
