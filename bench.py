@@ -145,8 +145,9 @@ def time_gpu(lat, steps: int, warmup: int):
 
 def time_launches(lat, n: int = 200):
     """Mean durations (ms) of the boundary-link kernel and of the fused sweep
-    kernel: HIP events recorded around each launch on the stream the kernels
-    run on (lbm_step_timed)."""
+    kernel (lbm_step_timed): n launches of each kernel back to back in a HIP
+    graph, timed with HIP events on the stream the kernels run on; the state
+    is restored afterwards."""
     return lat.step_timed(n)
 
 

@@ -194,11 +194,16 @@ lbm_status lbm_init(lbm_ctx* ctx, const double* dev_rho, const double* dev_u, co
 /* Advances n >= 0 steps (asynchronous). */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
-/* As lbm_step, with HIP events recorded on the context's stream around the
- * two launches of every step (the boundary-link kernel, then the fused
- * sweep); synchronises the stream and returns their mean durations in ms in
- * ms_out[0] (links; 0 when a step has no link launch) and ms_out[1]
- * (sweep).  Steps run as single launches (no graph replay). */
+/* Durations of the two kernels of a step, for measurement: n (even, 2 to
+ * 4096) launches of the boundary-link kernel back to back, captured in one
+ * HIP graph and timed with HIP events on the context's stream, then n
+ * launches of the fused sweep the same way (parities alternating from the
+ * context's time).  Returns the mean duration per launch in ms in ms_out[0]
+ * (links; 0 without links) and ms_out[1] (sweep).  These launches are not
+ * steps: the populations and moments are copied aside first (one hipMalloc of
+ * their size, freed before returning) and restored afterwards, so the state
+ * and the time are unchanged.  Synchronises the stream.  Not for items of a
+ * batch. */
 lbm_status lbm_step_timed(lbm_ctx* ctx, int64_t n, float ms_out[2]);
 
 /* Moments at the current time into dev_out, SoA [8][N] of rho, u_x, u_y, u_z,

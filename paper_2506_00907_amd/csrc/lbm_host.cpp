@@ -892,51 +892,91 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     return step_launches(c, n);
 }
 
+namespace {
+
+// One graph of n launches of a single kernel of the step (links or sweep),
+// parities alternating from the context's time.
+lbm_status capture_kernel(lbm_ctx* c, int64_t n, bool links, hipGraphExec_t* out) {
+    *out = nullptr;
+    if (!c->capture_stream && hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->capture_stream = nullptr;
+        return set_err(c, LBM_EDEVICE, "capture stream");
+    }
+    lbmi::KArgs a = base_args(c);
+    a.stream = c->capture_stream;
+    a.links_ready = 1;
+    if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return set_err(c, LBM_EDEVICE, "begin capture");
+    hipError_t le = hipSuccess;
+    for (int64_t i = 0; i < n && le == hipSuccess; ++i) {
+        a.parity = (int)((c->t + i) & 1);
+        a.tstep = (uint32_t)(c->t + i);
+        le = links ? c->ks.links(a) : c->ks.sweep(a);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(c->capture_stream, &g);
+    if (le != hipSuccess || ee != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return set_err(c, LBM_EDEVICE, "kernel capture");
+    }
+    hipError_t ie = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        *out = nullptr;
+        return set_err(c, LBM_EDEVICE, "graph instantiate");
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
 lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, float ms_out[2]) {
     if (!c || !ms_out) return LBM_EINVAL;
-    if (n < 1) return set_err(c, LBM_EINVAL, "step count must be positive");
+    if (n < 2 || n > 4096 || (n & 1)) return set_err(c, LBM_EINVAL, "launch count must be even, 2 to 4096");
     if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
-    std::vector<hipEvent_t> ev((size_t)n * 3, nullptr);
-    lbm_status st = LBM_OK;
-    for (auto& e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            st = set_err(c, LBM_EDEVICE, "event create");
-            break;
-        }
-    lbmi::KArgs a = base_args(c);
-    int64_t with_links = 0;
-    for (int64_t i = 0; i < n && st == LBM_OK; ++i) {
-        a.parity = (int)(c->t & 1);
-        a.links_ready = c->t > 0 ? 1 : 0;
-        a.tstep = (uint32_t)c->t;
-        if (a.links_ready && a.n_links) ++with_links;
-        hipEvent_t* e = &ev[(size_t)i * 3];
-        if ((st = hip_check(c, hipEventRecord(e[0], c->stream), "event record"))) break;
-        if ((st = hip_check(c, c->ks.links(a), "link launch"))) break;
-        if ((st = hip_check(c, hipEventRecord(e[1], c->stream), "event record"))) break;
-        if ((st = hip_check(c, c->ks.sweep(a), "sweep launch"))) break;
-        if ((st = hip_check(c, hipEventRecord(e[2], c->stream), "event record"))) break;
-        c->t++;
+    if (c->batch_owned) return set_err(c, LBM_EINVAL, "an item of a batch is timed through the batch");
+    ms_out[0] = ms_out[1] = 0.f;
+    // the launches below do not form steps: populations and moments (with the
+    // time base word) are saved first and restored afterwards
+    const size_t s0 = c->size[0], s3 = c->size[3];
+    void* save = nullptr;
+    if (hipMalloc(&save, s0 + s3) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(c, LBM_EDEVICE, "state copy allocation");
     }
-    if (st == LBM_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "timed step sync");
-    double sl = 0.0, ss = 0.0;
-    if (st == LBM_OK)
-        for (int64_t i = 0; i < n; ++i) {
-            float t0 = 0.f, t1 = 0.f;
-            hipEvent_t* e = &ev[(size_t)i * 3];
-            if (hipEventElapsedTime(&t0, e[0], e[1]) != hipSuccess || hipEventElapsedTime(&t1, e[1], e[2]) != hipSuccess) {
-                st = set_err(c, LBM_EDEVICE, "event elapsed time");
-                break;
-            }
-            sl += t0;
-            ss += t1;
-        }
-    for (auto& e : ev)
-        if (e) (void)hipEventDestroy(e);
-    if (st != LBM_OK) return st;
-    ms_out[0] = with_links ? (float)(sl / (double)with_links) : 0.f;
-    ms_out[1] = (float)(ss / (double)n);
-    return LBM_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipGraphExec_t g[2] = {nullptr, nullptr};
+    lbm_status st = hip_check(c, hipMemcpyAsync(save, c->buf[0], s0, hipMemcpyDeviceToDevice, c->stream), "state save");
+    if (!st) st = hip_check(c, hipMemcpyAsync((char*)save + s0, c->buf[3], s3, hipMemcpyDeviceToDevice, c->stream),
+                            "state save");
+    if (!st && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        st = set_err(c, LBM_EDEVICE, "event create");
+    for (int k = 0; k < 2 && !st; ++k) {
+        const bool links = k == 0;
+        if (links && c->n_links == 0) continue;
+        if ((st = capture_kernel(c, n, links, &g[k]))) break;
+        // one untimed replay, then the timed one
+        if ((st = hip_check(c, hipGraphLaunch(g[k], c->stream), "graph launch"))) break;
+        if ((st = hip_check(c, hipEventRecord(e0, c->stream), "event record"))) break;
+        if ((st = hip_check(c, hipGraphLaunch(g[k], c->stream), "graph launch"))) break;
+        if ((st = hip_check(c, hipEventRecord(e1, c->stream), "event record"))) break;
+        if ((st = hip_check(c, hipEventSynchronize(e1), "event sync"))) break;
+        float ms = 0.f;
+        if ((st = hip_check(c, hipEventElapsedTime(&ms, e0, e1), "event elapsed time"))) break;
+        ms_out[k] = ms / (float)n;
+    }
+    // the restore runs whatever happened above
+    lbm_status rs = hip_check(c, hipMemcpyAsync(c->buf[0], save, s0, hipMemcpyDeviceToDevice, c->stream), "state restore");
+    if (!rs) rs = hip_check(c, hipMemcpyAsync(c->buf[3], (char*)save + s0, s3, hipMemcpyDeviceToDevice, c->stream),
+                            "state restore");
+    if (!rs) rs = hip_check(c, hipStreamSynchronize(c->stream), "state restore");
+    for (auto& x : g)
+        if (x) (void)hipGraphExecDestroy(x);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(save);
+    return st ? st : rs;
 }
 
 lbm_status lbm_read_moments(lbm_ctx* c, void* dev_out, int32_t out_type) {

@@ -200,6 +200,25 @@ def test_save_load_roundtrip():
     assert np.array_equal(a, b)
 
 
+def test_kernel_timing_leaves_the_state_unchanged():
+    """lbm_step_timed runs graphs of bare link and sweep launches, then
+    restores the populations, moments and time; the run continues exactly as
+    without it."""
+    _case("step_timed")
+    from paper_2506_00907_amd import lbm
+    sc = scenes.hartmann_couette(nx=8, ny=13, storage="f16")
+    a, b = lbm.Lattice(sc), lbm.Lattice(sc)
+    a.step(37)
+    b.step(37)
+    ms_links, ms_sweep = b.step_timed(20)
+    assert ms_links > 0 and ms_sweep > 0
+    assert b.time == 37
+    a.step(21)
+    b.step(21)
+    for f in (0, 2):
+        assert np.array_equal(a.read_populations(f).cpu().numpy(), b.read_populations(f).cpu().numpy())
+
+
 def test_reduce_mass_and_residual():
     _case("reduce")
     sc = scenes.poiseuille(nx=8, ny=12, storage="f64")
