@@ -18,7 +18,10 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-CFLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+# -ffp-contract=on: multiply-adds fuse within one source expression only, so
+# every kernel that inlines the same node or link update rounds it the same
+# way (the default fuses across statements, depending on the surrounding code)
+CFLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-ffp-contract=on",
           f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I" + os.path.join(os.path.dirname(PKG), "include")]
 SOURCES = ["lbm_host.cpp", "lbm_batch.cpp", "lbm_kernels_f64.hip", "lbm_kernels_f32.hip", "lbm_kernels_f16.hip",
