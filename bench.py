@@ -33,13 +33,14 @@ HBM_PEAK = 8.0e12  # bytes/s, MI355X
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes of the commands listed in
 # profiles/, scaled by the same counters of a 1 GiB device copy (FETCH_SIZE
 # reports half of the bytes read, WRITE_SIZE all bytes written): 2 x FETCH +
-# WRITE.  Valid only for the kernel source they were taken with.
+# WRITE.  Valid only for the kernel sources and build flags they were taken
+# with.
 KERNEL_SOURCES = ("paper_2506_00907_amd/csrc/lbm_device.hpp", "paper_2506_00907_amd/csrc/lbm_internal.hpp",
                   "paper_2506_00907_amd/build.py")
 MEASURED_TRAFFIC = {
     # (workload, storage): (kernel source digest, bytes per launch)
-    ("reactive", "f32"): ("e1694ec413e8df2e", 15110144.0),
-    ("hartmann_wide", "f32"): ("e1694ec413e8df2e", 2576588800.0),
+    ("reactive", "f32"): ("34afee037afe26e1", 15146864.0),
+    ("hartmann_wide", "f32"): ("34afee037afe26e1", 2578807181.0),
 }
 
 
