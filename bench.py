@@ -276,8 +276,9 @@ def main():
     }
     if args.extra:
         extra = {}
-        for w, st in (("reactive", "f16"), ("hartmann", "f32"), ("hartmann", "f16"), ("pipe", "f32"),
-                      ("pipe", "bf16"), ("hartmann_wide", "f32"), ("pipe_long", "f32")):
+        for w, st in (("reactive", "f16"), ("reactive", "bf16"), ("hartmann", "f32"), ("hartmann", "f16"),
+                      ("pipe", "f32"), ("pipe", "bf16"), ("hartmann_wide", "f32"), ("hartmann_wide", "f16"),
+                      ("pipe_long", "f32"), ("pipe_long", "f16"), ("pipe_long", "bf16"), ("pipe_long", "f64")):
             s2, d2 = make_scene(w, st)
             l2 = lbm.Lattice(s2)
             a2 = algorithmic_bytes(l2)
