@@ -122,12 +122,19 @@ def inits_from(moms):
     return [(m[..., 1:4], m[..., 5:8]) for m in moms]
 
 
-def summary(sol, moms, ref_m, items, masks):
+def summary(sol, moms, ref_m, items, masks, ref_ok=None):
+    """timing, statuses and field errors; with ref_ok (items whose reference
+    reached its tolerance) also the error statistics over those items."""
     e = field_error(items, moms, ref_m, masks)
-    return dict(seconds=sol["seconds"], steps=sol["steps"].tolist(), status=sol["status"],
-                n_not_steady=int(sum(s != "steady" for s in sol["status"])),
-                n_stalled=int(sum(s == "stalled" for s in sol["status"])),
-                error_median=float(np.median(e)), error_max=float(np.max(e)), tuned=sol.get("tuned"))
+    out = dict(seconds=sol["seconds"], steps=sol["steps"].tolist(), status=sol["status"],
+               n_not_steady=int(sum(s != "steady" for s in sol["status"])),
+               n_stalled=int(sum(s == "stalled" for s in sol["status"])),
+               error_median=float(np.median(e)), error_max=float(np.max(e)), errors=e.tolist(),
+               tuned=sol.get("tuned"))
+    if ref_ok is not None and ref_ok.any():
+        out["error_median_ref_steady"] = float(np.median(e[ref_ok]))
+        out["error_max_ref_steady"] = float(np.max(e[ref_ok]))
+    return out
 
 
 def cmd_eval(a):
@@ -149,9 +156,10 @@ def cmd_eval(a):
     rsol = ws.solve(items, "f64", tol=a.ref_tol, inits=inits_from(b_m), **kw)
     ref_m = ws.moments_of(rsol["batch"])
     res["reference"] = dict(seconds=rsol["seconds"], steps=rsol["steps"].tolist(), status=rsol["status"])
+    ref_ok = np.array([st == "steady" for st in rsol["status"]])
     del rsol
     torch.cuda.empty_cache()
-    res["batch"] = summary(bsol, b_m, ref_m, items, masks)
+    res["batch"] = summary(bsol, b_m, ref_m, items, masks, ref_ok)
 
     for label in ("cold", "warm"):
         inits, t_inf = None, 0.0
@@ -185,18 +193,20 @@ def cmd_eval(a):
         mp = ws.moments_of(p["batch"])
         del p["batch"]
         torch.cuda.empty_cache()
-        r = summary(p, mp, ref_m, items, masks)
-        r16 = summary(s16, m16, ref_m, items, masks)
+        r = summary(p, mp, ref_m, items, masks, ref_ok)
+        r16 = summary(s16, m16, ref_m, items, masks, ref_ok)
         res[label] = dict(inference_seconds=t_inf, fp16=r16, polish=r,
                           total_seconds=t_inf + s16["seconds"] + p["seconds"],
-                          error_median=r["error_median"], error_max=r["error_max"])
+                          error_median=r["error_median"], error_max=r["error_max"],
+                          error_median_ref_steady=r.get("error_median_ref_steady"))
         log(f"[eval] {label}: {res[label]['total_seconds']:.1f} s, error median {r['error_median']:.2e}")
     if a.plain:
         log("[eval] plain FP32, one item at a time")
         pl = plain(items, a.tol, a.interval, a.max_steps)
         e = field_error(items, pl["moments"], ref_m, masks)
         res["plain"] = dict(seconds=pl["seconds"], steps=pl["steps"].tolist(), error_median=float(np.median(e)),
-                            error_max=float(np.max(e)))
+                            error_max=float(np.max(e)), errors=e.tolist(),
+                            error_median_ref_steady=float(np.median(e[ref_ok])) if ref_ok.any() else None)
         for label in ("batch", "cold", "warm"):
             tot = res[label]["seconds"] if label == "batch" else res[label]["total_seconds"]
             res[label]["speedup_vs_plain"] = pl["seconds"] / tot
@@ -205,10 +215,11 @@ def cmd_eval(a):
     brief = {k: v for k, v in res.items() if k != "reference"}
     for k in ("batch", "cold", "warm", "plain"):
         if k in brief:
-            brief[k] = {kk: vv for kk, vv in brief[k].items() if kk not in ("steps", "status")}
+            brief[k] = {kk: vv for kk, vv in brief[k].items() if kk not in ("steps", "status", "errors")}
             for sub in ("fp16", "polish"):
                 if sub in brief[k]:
-                    brief[k][sub] = {kk: vv for kk, vv in brief[k][sub].items() if kk not in ("steps", "status")}
+                    brief[k][sub] = {kk: vv for kk, vv in brief[k][sub].items()
+                                     if kk not in ("steps", "status", "errors")}
     log(json.dumps(brief, default=str))
 
 
