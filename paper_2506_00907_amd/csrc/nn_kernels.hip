@@ -201,6 +201,109 @@ __global__ __launch_bounds__(256) void k_wgrad(const T* __restrict__ X, const T*
     }
 }
 
+// BF16 weight gradient of one (output, input) channel tile for one row of
+// taps (NT = 3: the taps dx = -1, 0, 1 of row dy = blockIdx.z - 1 of a 3 x 3
+// kernel; NT = 1: the 1 x 1 kernel).  Per chunk of 16 pixels, lane
+// (px = l % 16, g = l / 16) loads 8 channels of one pixel in one 16-byte
+// access: of dZ (shared by the taps of the row) and of X at the pixel shifted
+// by each tap (zero outside the image).  The values go to LDS as
+// [channel][pixel], where each lane then reads the 8 pixels of its channel in
+// one 16-byte access, the operand layout of the matrix instruction above
+// (K = pixels).  The next chunk's loads are issued before the current chunk's
+// barrier and products.  Every wave runs the same number of chunk iterations
+// (chunks past the block's range contribute zeros), so the block barriers are
+// uniform.  cin and coutp are multiples of 16 and 32: each 8-channel group is
+// wholly inside or outside the tensor and 16-byte aligned.
+template <int NT>
+__global__ __launch_bounds__(256) void k_wgrad_lds(const __bf16* __restrict__ X, const __bf16* __restrict__ dZ, int N,
+                                                   int H, int W, int cin, int coutp, int64_t chunks_per_block,
+                                                   float* __restrict__ dWt) {
+    constexpr int RS = 16;  // LDS row: 16 pixels of one channel
+    __shared__ uint16_t sA[4][32 * RS];
+    __shared__ uint16_t sB[4][NT][32 * RS];
+    __shared__ float red[16 * 256];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 31, lh = lane >> 5;
+    const int px = lane & 15, grp = lane >> 4;
+    const int nci = (cin + 31) / 32;
+    const int cib = (blockIdx.y % nci) * 32, cob = (blockIdx.y / nci) * 32;
+    const int dy = NT == 3 ? (int)blockIdx.z - 1 : 0;
+    const int64_t npix = (int64_t)N * H * W;
+    const int64_t nchunks = (npix + 15) / 16;
+    const int64_t c_begin = (int64_t)blockIdx.x * chunks_per_block;
+    int64_t c_end = c_begin + chunks_per_block;
+    if (c_end > nchunks) c_end = nchunks;
+    const int64_t iters = (chunks_per_block + 3) / 4;
+    const int ci0 = cib + 8 * grp;  // this lane's channel group
+    const bool cin_ok = ci0 < cin;
+    // this lane's values of chunk c: dZ at its pixel, X at the shifted pixels
+    auto load = [&](int64_t c, u16x8& va, u16x8 (&vb)[NT]) {
+        const int64_t q = c * 16 + px;
+        const bool qv = c < c_end && q < npix;
+        int x = 0, y = 0, n = 0;
+        if (qv) {
+            x = (int)(q % W);
+            const int64_t t1 = q / W;
+            y = (int)(t1 % H);
+            n = (int)(t1 / H);
+        }
+        va = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (qv) va = *(const u16x8*)(dZ + q * coutp + cob + 8 * grp);
+        const int yy = y + dy;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int xx = x + (NT == 3 ? t - 1 : 0);
+            const bool in = qv && cin_ok && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
+            vb[t] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            if (in) vb[t] = *(const u16x8*)(X + (((int64_t)n * H + yy) * W + xx) * cin + ci0);
+        }
+    };
+    f32x16 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+    u16x8 va, vb[NT];
+    load(c_begin + wv, va, vb);
+    for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sA[wv][(8 * grp + j) * RS + px] = va[j];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sB[wv][t][(8 * grp + j) * RS + px] = vb[t][j];
+        if (it + 1 < iters) load(c_begin + wv + 4 * (it + 1), va, vb);  // in flight during the products
+        __syncthreads();
+        const u16x8 ra = *(const u16x8*)&sA[wv][li * RS + 8 * lh];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const u16x8 rb = *(const u16x8*)&sB[wv][t][li * RS + 8 * lh];
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ra), __builtin_bit_cast(bf16x8, rb),
+                                                             acc[t], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // sum the four waves through LDS (one tap at a time), one FP32 atomic per weight
+    const int ci = cib + li;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {  // unrolled: acc[t] stays in registers
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[r * 256 + threadIdx.x] = acc[t][r];
+        __syncthreads();
+        if (wv == 0 && ci < cin) {
+            const int tap = NT == 3 ? (dy + 1) * 3 + t : 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float sum = red[r * 256 + lane] + red[r * 256 + 64 + lane] + red[r * 256 + 128 + lane] +
+                                  red[r * 256 + 192 + lane];
+                const int row = 8 * (r >> 2) + 4 * lh + (r & 3);
+                atomicAdd(&dWt[((int64_t)tap * coutp + cob + row) * cin + ci], sum);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // bias gradient: db[co] += sum_p dZ[p][co]   (coutp divides the block size)
 template <class T>
 __global__ __launch_bounds__(256) void k_bgrad(const T* __restrict__ dZ, int64_t npix, int coutp, int cout,
@@ -425,8 +528,25 @@ struct L {
         int64_t per = (nchunks + want - 1) / want;
         if (per < 16) per = 16;
         const unsigned gx = (unsigned)((nchunks + per - 1) / per);
-        hipLaunchKernelGGL((k_wgrad<T>), dim3(gx, gy), dim3(256), 0, s, (const T*)X, (const T*)dZ, N, H, W, cin, coutp,
-                           taps, per, dWt);
+        if (sizeof(T) == 2 && cin % 16 == 0 && coutp % 32 == 0 && (taps == 9 || taps == 1)) {
+            // about 2048 blocks in all; a 3 x 3 kernel takes one block row per
+            // row of taps (grid z)
+            const unsigned gt = (unsigned)((coutp / 32) * ((cin + 31) / 32));
+            const unsigned gz = taps == 9 ? 3u : 1u;
+            int64_t want2 = 2048 / (gt * gz) + 1;
+            int64_t per2 = (nchunks + want2 - 1) / want2;
+            if (per2 < 16) per2 = 16;
+            const unsigned gx2 = (unsigned)((nchunks + per2 - 1) / per2);
+            if (taps == 9)
+                hipLaunchKernelGGL((k_wgrad_lds<3>), dim3(gx2, gt, 3), dim3(256), 0, s, (const __bf16*)X,
+                                   (const __bf16*)dZ, N, H, W, cin, coutp, per2, dWt);
+            else
+                hipLaunchKernelGGL((k_wgrad_lds<1>), dim3(gx2, gt, 1), dim3(256), 0, s, (const __bf16*)X,
+                                   (const __bf16*)dZ, N, H, W, cin, coutp, per2, dWt);
+        } else {
+            hipLaunchKernelGGL((k_wgrad<T>), dim3(gx, gy), dim3(256), 0, s, (const T*)X, (const T*)dZ, N, H, W, cin,
+                               coutp, taps, per, dWt);
+        }
         return hipGetLastError();
     }
     static hipError_t bgrad(const void* dZ, int64_t npix, int coutp, int cout, float* db, hipStream_t s) {

@@ -55,6 +55,15 @@ def test_batch_item_equals_item_alone(storage, mode):
 
 
 @pytest.mark.parametrize("mode", [MODES[0], MODES[3]], ids=["tiled", "resident"])
+def test_bf16_batch_item_equals_item_alone(mode):
+    scs = duct_pipe_items("bf16", n=3)
+    B = lbm.Batch(scs)
+    B.configure(*mode)
+    B.step(130)
+    assert_items_equal_alone(B, scs, 130)
+
+
+@pytest.mark.parametrize("mode", [MODES[0], MODES[3]], ids=["tiled", "resident"])
 def test_batch_of_2d_channels_equals_alone(mode):
     scs = reactive_items("f32")
     B = lbm.Batch(scs)
