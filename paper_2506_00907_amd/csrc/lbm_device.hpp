@@ -439,7 +439,7 @@ __device__ __forceinline__ uint32_t step_time(const uint32_t* tbase, uint32_t ts
 }
 
 template <class C, int ODD>
-__global__ __launch_bounds__(64) void k_links(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
+__global__ __launch_bounds__(256) void k_links(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
                                                const DevLink<typename C::R>* __restrict__ links,
                                                const typename C::R* __restrict__ M, uint32_t nlinks,
                                                const uint32_t* __restrict__ tbase, uint32_t tstep) {
@@ -1130,12 +1130,13 @@ template <class C>
 struct Launch {
     using R = typename C::R;
     static double cg2() { return C::QG ? 0.25 : 1.0; }
-    // 64 threads per block: the few thousand links of a 2D channel spread
-    // over four times as many CUs (measured: 3.1 -> 2.8 us per launch on the
-    // 512 x 256 reactive channel)
+    // Few links (a 2D channel's few thousand): 64 threads per block, so they
+    // spread over four times as many CUs (3.1 -> 2.8 us per launch on the
+    // 512 x 256 reactive channel).  Millions of links: 256 (with 64, the
+    // pipe 1024 x 128 x 128 took 48 us instead of 37).
     static hipError_t links(const KArgs& a, const Geo& G, const Phys<R>& P) {
         if (!a.links_ready || a.n_links == 0) return hipSuccess;
-        constexpr int LB = 64;
+        const int LB = a.n_links < 65536 ? 64 : 256;
         dim3 grid((unsigned)((a.n_links + LB - 1) / LB));
         if (a.parity)
             hipLaunchKernelGGL((k_links<C, 1>), grid, dim3(LB), 0, a.stream, G, P, (typename C::T*)a.S,
