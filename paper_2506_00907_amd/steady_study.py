@@ -234,7 +234,7 @@ def main(argv=None):
         p.add_argument("--interval", type=int, default=1000)
         p.add_argument("--max-steps", type=int, default=2_000_000)
         p.add_argument("--chunk", type=int, default=50_000)
-        p.add_argument("--out", default="gpurun_out/steady")
+        p.add_argument("--out", default="steady_out")
         if name == "train":
             p.add_argument("--max-seconds", type=float, default=float("inf"))
             p.add_argument("--epochs", type=int, default=20)
