@@ -224,6 +224,18 @@ lbm_status lbm_read_populations(lbm_ctx* ctx, int32_t field, double* dev_out);
  * Returns LBM_EUNSTABLE when out[7] > 0. */
 lbm_status lbm_reduce(lbm_ctx* ctx, double out[8]);
 
+/* FP64 net inflow through the boundary links over the last step, by field:
+ * out[0] f (mass), out[1] h (solute), out[2..4] g (B_x, B_y, B_z).  A link
+ * (A, alpha) adds the value it sets, f_alpha(A) at the current time (the
+ * link updates of Sections 3-4), minus the post-collision population that A
+ * sent toward the wall in the step before, f*_alpha'(A).  Collision and
+ * streaming conserve each field's total, so the change of sum(rho), sum(C)
+ * and sum(B_k) over a step (lbm_reduce) equals these sums, up to rounding.
+ * The links of the current step are written as lbm_step would write them
+ * (the state is otherwise unchanged).  Synchronises the stream.
+ * LBM_ESTATE before the first step. */
+lbm_status lbm_boundary_flux(lbm_ctx* ctx, double out[5]);
+
 /* Checkpoint: lbm_state_bytes() bytes of host memory hold the populations,
  * moment planes and time.  lbm_save synchronises the stream. */
 size_t lbm_state_bytes(const lbm_ctx* ctx);

@@ -379,10 +379,13 @@ __device__ __forceinline__ DevLink<R> load_link(const DevLink<R>* __restrict__ p
     return L;
 }
 
+// Returns the link's net inflow into A over the step: the value it sets
+// minus the post-collision population A sent toward the wall, x*_alpha'(A).
 template <class C, int ODD>
-__device__ __forceinline__ void link_update(const Geo& G, const Phys<typename C::R>& P, typename C::T* __restrict__ S,
-                                            const DevLink<typename C::R>& L, const typename C::R* __restrict__ M,
-                                            uint32_t seed) {
+__device__ __forceinline__ typename C::R link_update(const Geo& G, const Phys<typename C::R>& P,
+                                                     typename C::T* __restrict__ S,
+                                                     const DevLink<typename C::R>& L,
+                                                     const typename C::R* __restrict__ M, uint32_t seed) {
     using R = typename C::R;
     using SF = typename C::S;
     const size_t PL = G.plane;
@@ -431,6 +434,7 @@ __device__ __forceinline__ void link_update(const Geo& G, const Phys<typename C:
     const R v = link_value<R>(L, P, x_a, x_apA, xs, mA, mE, w, c2);
     if (ODD) st_sr<SF>(Sp, L.B, C::SCALED ? v * sc : v, C::SCALED ? dither(L.B, L.pap, seed) : 0u);
     else st_sr<SF>(Sa, L.A, C::SCALED ? v * sc : v, C::SCALED ? dither(L.A, L.pa, seed) : 0u);
+    return v - x_apA;
 }
 
 // time of the step being taken: base word (if any) plus offset
@@ -446,6 +450,41 @@ __global__ __launch_bounds__(256) void k_links(Geo G, Phys<typename C::R> P, typ
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nlinks) return;
     link_update<C, ODD>(G, P, S, load_link(links + k), M, C::SCALED ? step_time(tbase, tstep) : 0u);
+}
+
+// sum over the 64 lanes of a wave (lane 0 holds the total)
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// The links of the current step as k_links, plus the FP64 sums of their net
+// inflows by field slot: 0 f (mass), 1 h (solute), 2 + axis g (B_x, B_y,
+// B_z), one FP64 atomic per slot and block.
+template <class C, int ODD>
+__global__ __launch_bounds__(256) void k_flux(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
+                                              const DevLink<typename C::R>* __restrict__ links,
+                                              const typename C::R* __restrict__ M, uint32_t nlinks, uint32_t tstep,
+                                              double* __restrict__ acc) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[5] = {0, 0, 0, 0, 0};
+    if (k < nlinks) {
+        const DevLink<typename C::R> L = load_link(links + k);
+        const double net = (double)link_update<C, ODD>(G, P, S, L, M, C::SCALED ? tstep : 0u);
+        const int slot = L.field == 2 ? 2 + L.caxis : L.field;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) v[q] = q == slot ? net : 0.0;
+    }
+    __shared__ double red[5][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const double sum = wave_sum(v[q]);
+        if (lane == 0) red[q][wv] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) atomicAdd(&acc[threadIdx.x], red[threadIdx.x][0] + red[threadIdx.x][1] +
+                                                          red[threadIdx.x][2] + red[threadIdx.x][3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -758,11 +797,6 @@ __global__ void k_time(uint32_t* tbase, uint32_t t, int add) {
         if (add) atomicAdd(tbase, t);
         else atomicExch(tbase, t);
     }
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return v;
 }
 
 // Per-node terms of the FP64 reductions: sums of rho, C, B (0..4); squared
@@ -1146,6 +1180,19 @@ struct Launch {
                                (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links, a.tbase, a.tstep);
         return hipGetLastError();
     }
+    static hipError_t flux(const KArgs& a) {
+        if (a.n_links == 0) return hipSuccess;
+        dim3 grid((unsigned)((a.n_links + 255) / 256));
+        const Phys<R> P = make_phys<R>(a, cg2());
+        const Geo G = make_geo(a);
+        if (a.parity)
+            hipLaunchKernelGGL((k_flux<C, 1>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S,
+                               (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links, a.tstep, a.acc);
+        else
+            hipLaunchKernelGGL((k_flux<C, 0>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S,
+                               (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links, a.tstep, a.acc);
+        return hipGetLastError();
+    }
     static hipError_t links_only(const KArgs& a) {
         return links(a, make_geo(a), make_phys<R>(a, cg2()));
     }
@@ -1303,6 +1350,7 @@ struct Launch {
         k.links = &links_only;
         k.sweep = &sweep;
         k.step = &step;
+        k.flux = &flux;
         k.observe = &observe;
         k.init = &init;
         k.QT = C::QT;

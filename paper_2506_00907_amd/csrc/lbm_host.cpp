@@ -1006,6 +1006,29 @@ lbm_status lbm_read_populations(lbm_ctx* c, int32_t field, double* dev_out) {
     return hip_check(c, c->ks.observe(a), "populations launch");
 }
 
+lbm_status lbm_boundary_flux(lbm_ctx* c, double out[5]) {
+    if (!c || !out) return LBM_EINVAL;
+    if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
+    if (c->t == 0) return set_err(c, LBM_ESTATE, "no step has been taken");
+    for (int q = 0; q < 5; ++q) out[q] = 0.0;
+    if (c->n_links == 0) return LBM_OK;
+    const size_t cb = compute_bytes(c->p.storage);
+    char* aux = (char*)c->buf[4];
+    double* acc = (double*)(aux + round_up(7 * c->pad.plane * cb, kAlign));  // the reduction accumulators
+    lbm_status st;
+    if ((st = hip_check(c, hipMemsetAsync(acc, 0, lbmi::NACC * sizeof(double), c->stream), "accumulator clear")))
+        return st;
+    lbmi::KArgs a = base_args(c);
+    a.acc = acc;
+    if ((st = hip_check(c, c->ks.flux(a), "flux launch"))) return st;
+    double h[5];
+    if ((st = hip_check(c, hipMemcpyAsync(h, acc, sizeof h, hipMemcpyDeviceToHost, c->stream), "flux copy")))
+        return st;
+    if ((st = hip_check(c, hipStreamSynchronize(c->stream), "flux sync"))) return st;
+    for (int q = 0; q < 5; ++q) out[q] = h[q];
+    return LBM_OK;
+}
+
 lbm_status lbm_reduce(lbm_ctx* c, double out[8]) {
     if (!c || !out) return LBM_EINVAL;
     if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");

@@ -108,6 +108,7 @@ struct KernelSet {
     Launcher sweep = nullptr;    // the fused sweep of a step
     Launcher step = nullptr;     // links then sweep
     Launcher observe = nullptr;  // moments / populations / reductions at the current time
+    Launcher flux = nullptr;     // links of the current step with their FP64 net inflows by field
     Launcher init = nullptr;     // equilibrium initialisation
     Launcher set_time = nullptr; // *tbase = tstep
     Launcher tick = nullptr;     // *tbase += tstep

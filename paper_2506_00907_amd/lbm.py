@@ -236,6 +236,13 @@ class Lattice:
         L.check(code, self.ctx)
         return vals
 
+    def boundary_flux(self) -> np.ndarray:
+        """lbm_boundary_flux: net inflow through the boundary links over the
+        last step: mass, solute, B_x, B_y, B_z."""
+        out = (C.c_double * 5)()
+        self._call("lbm_boundary_flux", out)
+        return np.array(out[:])
+
     def save(self) -> bytes:
         nb = L.lib().lbm_state_bytes(self.ctx)
         buf = (C.c_char * nb)()

@@ -234,6 +234,36 @@ def test_reduce_mass_and_residual():
     assert all(b < a for a, b in zip(res, res[1:])), res
 
 
+@pytest.mark.parametrize("which", ["reactive", "hartmann"])
+def test_boundary_flux_accounts_for_the_change_of_every_total(which):
+    """Collision and streaming conserve sum(rho), sum(C) and sum(B_k), so over
+    a step each total changes by exactly the net inflow the boundary links
+    report (FP64 storage, rounding aside): a pin of lbm_boundary_flux, and a
+    check that no population crosses a wall without a link."""
+    _case(f"boundary flux {which}")
+    from paper_2506_00907_amd import lbm
+    if which == "reactive":
+        sc = scenes.reactive_channel(nx=40, ny=21, q=0.3, k_range=(1e-3, 1e-1), storage="f64")
+        slots = [(1, 0), (2, 1)]  # (lbm_reduce index, flux slot): mass, solute
+    else:
+        sc = scenes.hartmann_couette(nx=12, ny=17, c_top=0.1, storage="f64")
+        slots = [(1, 0), (3, 2), (4, 3)]  # mass, B_x, B_y
+    lat = lbm.Lattice(sc)
+    lat.step(7)
+    for _ in range(3):
+        before = lat.reduce()
+        lat.step(1)
+        flux = lat.boundary_flux()
+        after = lat.reduce()
+        for r, f in slots:
+            change = after[r] - before[r]
+            assert abs(change - flux[f]) < 1e-11 * max(abs(before[r]), 1.0), (which, r, change, flux[f])
+        # a second call writes the same link values: the same sums (up to the
+        # order in which the FP64 atomics add the block partial sums)
+        assert np.allclose(flux, lat.boundary_flux(), rtol=1e-12, atol=1e-15)
+    assert any(abs(lat.boundary_flux()[f]) > 1e-10 for _, f in slots)
+
+
 def test_nonfinite_state_is_reported():
     _case("nan detection")
     from paper_2506_00907_amd import _lib as L
