@@ -224,6 +224,15 @@ lbm_status lbm_read_populations(lbm_ctx* ctx, int32_t field, double* dev_out);
  * Returns LBM_EUNSTABLE when out[7] > 0. */
 lbm_status lbm_reduce(lbm_ctx* ctx, double out[8]);
 
+/* The dimensionless fields of Eqs. 46-47 along one Cartesian axis (0..2),
+ * FP64 into dev_out as [2][N]: u* = u_axis / U and
+ * B* = (B_axis - B_ext,axis) / (U mu sqrt(rho0 nu sigma)), with
+ * sigma = 1 / (mu eta) in lattice units; 0 at solid nodes.  U > 0 is the
+ * velocity scale (Eq. 46: the wall speed); U = 0 takes the mean of u_axis
+ * over the fluid nodes (Eq. 47: the mean flow velocity), which synchronises
+ * the stream and fails with LBM_EINVAL when that mean is zero. */
+lbm_status lbm_read_normalised(lbm_ctx* ctx, int32_t axis, double U, double* dev_out);
+
 /* FP64 net inflow through the boundary links over the last step, by field:
  * out[0] f (mass), out[1] h (solute), out[2..4] g (B_x, B_y, B_z).  A link
  * (A, alpha) adds the value it sets, f_alpha(A) at the current time (the

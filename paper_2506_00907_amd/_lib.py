@@ -84,6 +84,7 @@ SIGNATURES = {
     "lbm_read_populations": (C.c_int, [_VP, C.c_int32, _VP]),
     "lbm_reduce": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "lbm_boundary_flux": (C.c_int, [_VP, C.POINTER(C.c_double)]),
+    "lbm_read_normalised": (C.c_int, [_VP, C.c_int32, C.c_double, _VP]),
     "lbm_state_bytes": (C.c_size_t, [_VP]),
     "lbm_save": (C.c_int, [_VP, _VP]),
     "lbm_load": (C.c_int, [_VP, _VP]),

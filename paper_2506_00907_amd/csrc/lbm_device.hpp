@@ -904,10 +904,37 @@ __global__ __launch_bounds__(256) void k_observe(Geo G, Phys<typename C::R> P, t
         }
         return;
     }
+    if (mode == OBS_NORM) {
+        // u and B - B_ext along one axis, raw (k_scale divides them), and the
+        // sums of u and of the fluid nodes for a mean velocity
+        double v[NACC];
+        for (int q = 0; q < NACC; ++q) v[q] = 0.0;
+        if (dom >= 0) {
+            double* o = (double*)out;
+            o[dom] = fluid ? (double)r.m.u[field] : 0.0;
+            o[N + dom] = fluid ? (double)r.m.dB[field] : 0.0;
+            if (fluid) {
+                v[0] = r.m.u[field];
+                v[1] = 1.0;
+            }
+        }
+        block_accumulate(v, acc);
+        return;
+    }
     // OBS_REDUCE
     double v[NACC];
     reduce_node<C>(P, r, fluid, snap, snap_valid, G.plane, n, v);
     block_accumulate(v, acc);
+}
+
+// the normalisation of the OBS_NORM output: out[0][i] /= U,
+// out[1][i] /= U * bfac
+template <class C>
+__global__ __launch_bounds__(256) void k_scale(double* __restrict__ out, uint32_t N, double U, double bfac) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    out[i] /= U;
+    out[N + i] /= U * bfac;
 }
 
 // equilibrium initialisation: canonical layout slot i at node n holds x_i
@@ -1193,6 +1220,12 @@ struct Launch {
                                (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links, a.tstep, a.acc);
         return hipGetLastError();
     }
+    static hipError_t scale(const KArgs& a) {
+        const uint32_t N = (uint32_t)((size_t)a.n0 * a.n1 * a.n2);
+        hipLaunchKernelGGL((k_scale<C>), dim3((N + 255) / 256), dim3(256), 0, a.stream, (double*)a.out, N, a.norm_u,
+                           a.norm_b);
+        return hipGetLastError();
+    }
     static hipError_t links_only(const KArgs& a) {
         return links(a, make_geo(a), make_phys<R>(a, cg2()));
     }
@@ -1351,6 +1384,7 @@ struct Launch {
         k.sweep = &sweep;
         k.step = &step;
         k.flux = &flux;
+        k.scale = &scale;
         k.observe = &observe;
         k.init = &init;
         k.QT = C::QT;

@@ -1006,6 +1006,39 @@ lbm_status lbm_read_populations(lbm_ctx* c, int32_t field, double* dev_out) {
     return hip_check(c, c->ks.observe(a), "populations launch");
 }
 
+lbm_status lbm_read_normalised(lbm_ctx* c, int32_t axis, double U, double* dev_out) {
+    if (!c) return LBM_EINVAL;
+    if (!dev_out || axis < 0 || axis > 2 || !(U >= 0.0) || !std::isfinite(U))
+        return set_err(c, LBM_EINVAL, "bad axis, velocity scale or output");
+    if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
+    const size_t cb = compute_bytes(c->p.storage);
+    double* acc = (double*)((char*)c->buf[4] + round_up(7 * c->pad.plane * cb, kAlign));
+    lbm_status st;
+    if ((st = hip_check(c, hipMemsetAsync(acc, 0, lbmi::NACC * sizeof(double), c->stream), "accumulator clear")))
+        return st;
+    lbmi::KArgs a = base_args(c);
+    a.mode = lbmi::OBS_NORM;
+    a.field = axis;
+    a.out = dev_out;
+    a.acc = acc;
+    if ((st = hip_check(c, c->ks.observe(a), "normalised moments launch"))) return st;
+    if (U == 0.0) {  // the mean velocity over the fluid nodes
+        double h[2];
+        if ((st = hip_check(c, hipMemcpyAsync(h, acc, sizeof h, hipMemcpyDeviceToHost, c->stream), "mean copy")))
+            return st;
+        if ((st = hip_check(c, hipStreamSynchronize(c->stream), "mean sync"))) return st;
+        U = h[1] > 0.0 ? h[0] / h[1] : 0.0;
+        if (!(U != 0.0) || !std::isfinite(U)) return set_err(c, LBM_EINVAL, "the mean velocity is zero or not finite");
+    }
+    // B* = B / (U mu sqrt(rho0 nu sigma)), sigma = 1 / (mu eta): sqrt(rho0 nu mu / eta)
+    const double nu = (c->p.tau_f - 0.5) / 3.0;
+    const double eta = c->p.magnetic ? (c->p.tau_m - 0.5) / 4.0 : 1.0;
+    const double mu = c->p.magnetic ? c->p.mu : 1.0;
+    a.norm_u = U;
+    a.norm_b = std::sqrt(c->p.rho0 * nu * mu / eta);
+    return hip_check(c, c->ks.scale(a), "normalisation launch");
+}
+
 lbm_status lbm_boundary_flux(lbm_ctx* c, double out[5]) {
     if (!c || !out) return LBM_EINVAL;
     if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");

@@ -13,7 +13,7 @@ namespace lbmi {
 enum : uint8_t { NF_FLUID = 1, NF_LINKS = 2, NF_MOM = 4 };
 
 // kernel modes of the observe kernel
-enum : int { OBS_MOMENTS = 0, OBS_POPS = 1, OBS_REDUCE = 2 };
+enum : int { OBS_MOMENTS = 0, OBS_POPS = 1, OBS_REDUCE = 2, OBS_NORM = 3 };
 
 // number of FP64 accumulators used by the reduction
 constexpr int NACC = 16;
@@ -60,7 +60,8 @@ struct KArgs {
     int links_ready;       // 0 at t = 0: populations are the initial state
     // observe / init
     int mode;              // OBS_*
-    int field;             // OBS_POPS: 0 f, 1 h, 2 g
+    int field;             // OBS_POPS: 0 f, 1 h, 2 g; OBS_NORM: Cartesian axis
+    double norm_u, norm_b; // scale: u /= norm_u, B - B_ext /= norm_u * norm_b
     void* out;             // OBS_MOMENTS: [8][N] (out_f64 ? double : float); OBS_POPS: double
     int out_f64;
     double* acc;           // OBS_REDUCE: FP64 accumulators [NACC]
@@ -109,6 +110,7 @@ struct KernelSet {
     Launcher step = nullptr;     // links then sweep
     Launcher observe = nullptr;  // moments / populations / reductions at the current time
     Launcher flux = nullptr;     // links of the current step with their FP64 net inflows by field
+    Launcher scale = nullptr;    // OBS_NORM output [2][N] divided by norm_u and norm_u * norm_b
     Launcher init = nullptr;     // equilibrium initialisation
     Launcher set_time = nullptr; // *tbase = tstep
     Launcher tick = nullptr;     // *tbase += tstep

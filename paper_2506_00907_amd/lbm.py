@@ -236,6 +236,14 @@ class Lattice:
         L.check(code, self.ctx)
         return vals
 
+    def read_normalised(self, axis: int = 0, U: float = 0.0):
+        """lbm_read_normalised: [2, nz, ny, nx] FP64 tensor of u* and B* along
+        `axis` (U = 0: scaled by the mean velocity over the fluid nodes)."""
+        torch = self.torch
+        out = torch.empty((2,) + self.shape, dtype=torch.float64, device=self.device)
+        self._call("lbm_read_normalised", int(axis), float(U), C.c_void_p(out.data_ptr()))
+        return out
+
     def boundary_flux(self) -> np.ndarray:
         """lbm_boundary_flux: net inflow through the boundary links over the
         last step: mass, solute, B_x, B_y, B_z."""

@@ -264,6 +264,30 @@ def test_boundary_flux_accounts_for_the_change_of_every_total(which):
     assert any(abs(lat.boundary_flux()[f]) > 1e-10 for _, f in slots)
 
 
+def test_normalised_fields_follow_eqs_46_and_47():
+    """lbm_read_normalised against the same quotients of lbm_read_moments:
+    u* = u_1 / U and B* = B_1 / (U mu sqrt(rho0 nu sigma)), sigma = 1/(mu eta),
+    with U the wall speed (Eq. 46) or the mean of u_1 over the fluid (Eq. 47)."""
+    _case("normalised readback")
+    from paper_2506_00907_amd import lbm
+    sc = scenes.hartmann_couette(nx=12, ny=17, c_top=0.1, storage="f64")
+    lat = lbm.Lattice(sc)
+    lat.step(300)
+    m = lat.read_moments("f64").cpu().numpy()
+    fluid = m[0] > 0
+    nu, eta = (sc.tau_f - 0.5) / 3.0, (sc.tau_m - 0.5) / 4.0
+    bfac = math.sqrt(sc.rho0 * nu * sc.mu / eta)
+    for U in (0.01, None):
+        out = lat.read_normalised(0, 0.0 if U is None else U).cpu().numpy()
+        Ue = m[1][fluid].mean() if U is None else U
+        assert abs(Ue) > 1e-6
+        eu = np.where(fluid, m[1] / Ue, 0.0)
+        eb = np.where(fluid, (m[5] - sc.B_ext[0]) / (Ue * bfac), 0.0)
+        assert np.allclose(out[0], eu, rtol=1e-11, atol=1e-14)
+        assert np.allclose(out[1], eb, rtol=1e-11, atol=1e-14 * np.abs(eb).max())
+        assert np.abs(out[1]).max() > 0
+
+
 def test_nonfinite_state_is_reported():
     _case("nan detection")
     from paper_2506_00907_amd import _lib as L
