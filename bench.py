@@ -184,21 +184,54 @@ def bench_batch(n_items: int, steps: int, storage: str = "f16", tune: bool = Tru
                 config=B.config, tuning=tuned)
 
 
-def cpu_baseline(sc, budget_s: float = 12.0):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n: int) -> bool:
+    """Sets the OpenMP thread count of the process (the oracle's runtime)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except (OSError, AttributeError):
+        return False
+
+
+def cpu_baseline(sc, budget_s: float = 12.0, single_budget_s: float = 4.0):
+    """The FP64 oracle on the host cores (OpenMP over nodes), then on one
+    thread, each on a bounded number of steps of the same workload."""
     import oracle
     o = oracle.OracleSim(sc)
     n_fluid = int(o.mask().sum())
-    o.step(1)
-    t = time.perf_counter()
-    o.step(2)
-    per = (time.perf_counter() - t) / 2
-    k = max(2, int(budget_s / max(per, 1e-6)))
-    t = time.perf_counter()
-    o.step(k)
-    el = time.perf_counter() - t
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=n_fluid * k / el / 1e6, unit="MLUPS", cores=cores, kind="oracle",
-                sample=f"{k} steps of the full {sc.n[0]}x{sc.n[1]}x{sc.n[2]} workload, FP64, OpenMP over nodes")
+
+    def rate(budget):
+        o.step(1)
+        t = time.perf_counter()
+        o.step(2)
+        per = (time.perf_counter() - t) / 2
+        k = max(2, int(budget / max(per, 1e-6)))
+        t = time.perf_counter()
+        o.step(k)
+        return n_fluid * k / (time.perf_counter() - t) / 1e6, k
+
+    value, k = rate(budget_s)
+    out = dict(value=value, unit="MLUPS", cores=cores, kind="oracle",
+               sample=f"{k} steps of the full {sc.n[0]}x{sc.n[1]}x{sc.n[2]} workload, FP64, OpenMP over nodes",
+               cpu_model=_cpu_model(), nproc=os.cpu_count())
+    if _omp_threads(1):
+        v1, k1 = rate(single_budget_s)
+        _omp_threads(cores)
+        out["single_thread"] = dict(value=v1, steps=k1)
+    return out
 
 
 def main():
