@@ -90,6 +90,7 @@ typedef struct {
     double B_ext[3];             /* applied field; non-evolved components stay at B_ext */
     double accel[3];             /* body force per unit mass */
     double store_scale[3];       /* F16/BF16: power-of-two scale of f, h, g deviations */
+    double wall_omega;           /* angular frequency (rad per step) of oscillating boundary velocities */
 } lbm_params;
 
 /* One boundary link: the population entering fluid node A along e_alpha, whose
@@ -103,7 +104,12 @@ typedef struct {
     uint8_t kind;    /* lbm_link_kind */
     uint8_t comp;    /* magnetic slot */
     uint8_t flags;   /* bit 0: u_w is the boundary velocity (else extrapolated, Eq. 13);
-                        bit 1: E is not fluid, A stands in for E */
+                        bit 1: E is not fluid, A stands in for E;
+                        bit 2 (with bit 0): the boundary velocity oscillates,
+                        u_w cos(wall_omega t'), evaluated at the time t' the
+                        bounced population meets the boundary: t' = t - d for
+                        the value entering A at time t (Section 3.1, the
+                        arrival time between t - 1 and t; Eq. 45) */
     uint8_t pad[3];
     double d;        /* boundary-to-node distance |AX| / |AE| in (0, 1] */
     double value;    /* PRES: rho_w; CONC: C_w; MAG_DIR: B_k */
@@ -132,6 +138,8 @@ typedef struct {
     double radius;    /* cylinder radius; nodes strictly inside are fluid */
     double u_w[3];    /* boundary velocity */
     lbm_bc f, h, g[3];
+    int32_t u_osc;    /* 1: the boundary velocity is u_w cos(wall_omega t') (link flag bit 2) */
+    int32_t reserved;
 } lbm_boundary;
 
 typedef struct lbm_ctx lbm_ctx;

@@ -47,7 +47,7 @@ class _Boundary(C.Structure):
     _fields_ = [("type", C.c_int32), ("axis", C.c_int32), ("side", C.c_int32),
                 ("is_open", C.c_int32), ("q", C.c_double), ("center", C.c_double * 3),
                 ("radius", C.c_double), ("u_w", C.c_double * 3), ("f", _BC), ("h", _BC),
-                ("g", _BC * 3)]
+                ("g", _BC * 3), ("omega", C.c_double)]
 
 
 class _Scene(C.Structure):
@@ -64,7 +64,7 @@ class Link(C.Structure):
                 ("dir", C.c_int32), ("kind", C.c_int32), ("bnd", C.c_int32),
                 ("u_given", C.c_int32), ("d", C.c_double), ("value", C.c_double),
                 ("a1", C.c_double), ("a3", C.c_double), ("weight", C.c_double),
-                ("u_w", C.c_double * 3)]
+                ("u_w", C.c_double * 3), ("omega", C.c_double)]
 
 
 class LinkIn(C.Structure):
@@ -198,6 +198,7 @@ class _SceneHolder:
             for k in range(3):
                 cb.center[k] = b.center[k]
                 cb.u_w[k] = b.u_w[k]
+            cb.omega = sc.wall_omega if b.u_osc else 0.0
             self._bc(cb.f, b.f)
             self._bc(cb.h, b.h)
             for k in range(3):
@@ -290,7 +291,7 @@ class OracleSim:
         dt = np.dtype([("A", "i4"), ("E", "i4"), ("field", "i4"), ("comp", "i4"), ("dir", "i4"),
                        ("kind", "i4"), ("bnd", "i4"), ("u_given", "i4"), ("d", "f8"),
                        ("value", "f8"), ("a1", "f8"), ("a3", "f8"), ("weight", "f8"),
-                       ("u_w", "f8", 3)])
+                       ("u_w", "f8", 3), ("omega", "f8")])
         assert dt.itemsize == C.sizeof(Link)
         return np.frombuffer(bytes(out), dtype=dt, count=n).copy()
 

@@ -301,3 +301,13 @@ def polar_sample(r, t, F, x2, x3):
     j0 = j0 % nt
     return ((1 - wi) * (1 - wj) * F[i0, j0] + wi * (1 - wj) * F[i1, j0]
             + (1 - wi) * wj * F[i0, j1] + wi * wj * F[i1, j1])
+
+
+def stokes_second(y: np.ndarray, t: float, U: float, omega: float, nu: float, H: float) -> np.ndarray:
+    """Stokes' second problem between a static wall at y = 0 and a wall at
+    y = H moving tangentially at U cos(omega t) (Eq. 45): the periodic state
+    u(y, t) = Re[U exp(i omega t) sinh(k y) / sinh(k H)], k = (1 + i) sqrt(omega / (2 nu)),
+    the solution of u_t = nu u_yy with those wall values once the start has
+    decayed."""
+    k = (1.0 + 1.0j) * np.sqrt(omega / (2.0 * nu))
+    return np.real(U * np.exp(1j * omega * t) * np.sinh(k * np.asarray(y)) / np.sinh(k * H))

@@ -193,6 +193,7 @@ typedef struct {
     double radius;
     double u_w[3];
     or_bc f, h, g[3];
+    double omega; /* the boundary velocity is u_w cos(omega t') (0: steady) */
 } or_boundary;
 
 typedef struct {
@@ -219,6 +220,7 @@ typedef struct {
     int32_t u_given;
     double d, value, a1, a3, weight;
     double u_w[3];
+    double omega; /* of the boundary velocity, 0 = steady */
 } or_link;
 
 /* ------------------------------------------------------------------------- */
@@ -475,6 +477,7 @@ static int build_field_links(or_sim* S, int field, const or_lattice* L, int ncom
                         }
                         lk->a3 = bc->a3;
                         for (int j = 0; j < 3; ++j) lk->u_w[j] = b->u_w[j];
+                        lk->omega = b->omega;
                         lk->weight = 1.0;
                         if (b->type == 1 && (bc->kind == K_FLUX || bc->kind == K_MAG_FLUX)) {
                             if (!seg[best]) {
@@ -759,7 +762,11 @@ static void apply_links(or_sim* S) {
         in.a1 = lk->a1;
         in.a3 = lk->a3;
         in.weight = lk->weight;
-        for (int k = 0; k < 3; ++k) in.u_w[k] = lk->u_w[k];
+        /* a time-dependent boundary velocity at the arrival time at the
+         * boundary, t' = t + (1 - d) for the value at t + 1 from the
+         * post-collision state at t (Section 3.1) */
+        const double wall = lk->omega != 0.0 ? cos(lk->omega * ((double)S->t + 1.0 - lk->d)) : 1.0;
+        for (int k = 0; k < 3; ++k) in.u_w[k] = lk->u_w[k] * wall;
         in.x_ap_E = xs[base + (size_t)ap * S->N + E];
         in.x_ap_A = xs[base + (size_t)ap * S->N + lk->A];
         in.x_a_A = xs[base + (size_t)a * S->N + lk->A];

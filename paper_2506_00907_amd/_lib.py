@@ -31,7 +31,8 @@ class lbm_params(C.Structure):
                 ("mag_ncomp", C.c_int32), ("mag_comp", C.c_int32 * 3), ("storage", C.c_int32),
                 ("reserved", C.c_int32), ("tau_f", C.c_double), ("tau_c", C.c_double),
                 ("tau_m", C.c_double), ("rho0", C.c_double), ("C0", C.c_double), ("mu", C.c_double),
-                ("B_ext", C.c_double * 3), ("accel", C.c_double * 3), ("store_scale", C.c_double * 3)]
+                ("B_ext", C.c_double * 3), ("accel", C.c_double * 3), ("store_scale", C.c_double * 3),
+                ("wall_omega", C.c_double)]
 
 
 class lbm_link(C.Structure):
@@ -50,7 +51,8 @@ class lbm_bc(C.Structure):
 class lbm_boundary(C.Structure):
     _fields_ = [("type", C.c_int32), ("axis", C.c_int32), ("side", C.c_int32), ("is_open", C.c_int32),
                 ("q", C.c_double), ("center", C.c_double * 3), ("radius", C.c_double),
-                ("u_w", C.c_double * 3), ("f", lbm_bc), ("h", lbm_bc), ("g", lbm_bc * 3)]
+                ("u_w", C.c_double * 3), ("f", lbm_bc), ("h", lbm_bc), ("g", lbm_bc * 3),
+                ("u_osc", C.c_int32), ("reserved", C.c_int32)]
 
 
 class lbm_batch_config(C.Structure):

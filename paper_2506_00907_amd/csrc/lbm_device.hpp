@@ -222,6 +222,7 @@ struct Phys {
     R rho0, C0, inv_mu, grad_c;    // grad_c = 1/(tau_m c_g^2)
     R Bext[3], acc[3];
     R sc[3], isc[3];               // storage scale and inverse (f, h, g)
+    double womega;                 // angular frequency of oscillating boundary velocities
 };
 
 template <class R>
@@ -232,6 +233,7 @@ __host__ Phys<R> make_phys(const KArgs& a, double cg2) {
     p.omm = (R)(1.0 / a.tau_m);
     p.guo = (R)(1.0 - 0.5 / a.tau_f);
     p.rho0 = (R)a.rho0;
+    p.womega = a.wall_omega;
     p.C0 = (R)a.C0;
     p.inv_mu = (R)(1.0 / a.mu);
     p.grad_c = (R)(1.0 / (a.tau_m * cg2));
@@ -292,9 +294,11 @@ struct Mom {
 // x_apA: post-collision deviation of A along alpha'
 // x_apE: post-collision deviation of E along alpha' (streamed value)
 // mA, mE: moments at A and E at the previous time (deviations + u)
+// t: time of the value being set (the bounced population meets the boundary
+// at t - d, where an oscillating boundary velocity is evaluated)
 template <class R>
 __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R x_a, R x_apA,
-                                        R x_apE, const R* mA, const R* mE, R w, R c2) {
+                                        R x_apE, const R* mA, const R* mE, R w, R c2, uint32_t t) {
     const R d = L.d;
     const R one = (R)1, two = (R)2, half = (R)0.5;
     const R cE = -d, cA = d + one;  // Eq. 13 coefficients
@@ -305,6 +309,12 @@ __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R
         ux = L.uw0;
         uy = L.uw1;
         uz = L.uw2;
+        if (L.flags & 4) {  // u_w cos(omega t'), t' = t - d
+            const R c = (R)cos(P.womega * ((double)t - (double)L.d));
+            ux *= c;
+            uy *= c;
+            uz *= c;
+        }
     } else {
         ux = cE * mE[1] + cA * mA[1];
         uy = cE * mE[2] + cA * mA[2];
@@ -379,13 +389,15 @@ __device__ __forceinline__ DevLink<R> load_link(const DevLink<R>* __restrict__ p
     return L;
 }
 
+// t: time of the value being set (also the dither seed of 16-bit storage).
 // Returns the link's net inflow into A over the step: the value it sets
 // minus the post-collision population A sent toward the wall, x*_alpha'(A).
 template <class C, int ODD>
 __device__ __forceinline__ typename C::R link_update(const Geo& G, const Phys<typename C::R>& P,
                                                      typename C::T* __restrict__ S,
                                                      const DevLink<typename C::R>& L,
-                                                     const typename C::R* __restrict__ M, uint32_t seed) {
+                                                     const typename C::R* __restrict__ M, uint32_t t) {
+    const uint32_t seed = t;
     using R = typename C::R;
     using SF = typename C::S;
     const size_t PL = G.plane;
@@ -431,7 +443,7 @@ __device__ __forceinline__ typename C::R link_update(const Geo& G, const Phys<ty
         w = (R)0.125;
         c2 = (R)0.25;
     }
-    const R v = link_value<R>(L, P, x_a, x_apA, xs, mA, mE, w, c2);
+    const R v = link_value<R>(L, P, x_a, x_apA, xs, mA, mE, w, c2, t);
     if (ODD) st_sr<SF>(Sp, L.B, C::SCALED ? v * sc : v, C::SCALED ? dither(L.B, L.pap, seed) : 0u);
     else st_sr<SF>(Sa, L.A, C::SCALED ? v * sc : v, C::SCALED ? dither(L.A, L.pa, seed) : 0u);
     return v - x_apA;
@@ -449,7 +461,7 @@ __global__ __launch_bounds__(256) void k_links(Geo G, Phys<typename C::R> P, typ
                                                const uint32_t* __restrict__ tbase, uint32_t tstep) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nlinks) return;
-    link_update<C, ODD>(G, P, S, load_link(links + k), M, C::SCALED ? step_time(tbase, tstep) : 0u);
+    link_update<C, ODD>(G, P, S, load_link(links + k), M, step_time(tbase, tstep));
 }
 
 // sum over the 64 lanes of a wave (lane 0 holds the total)
@@ -470,7 +482,7 @@ __global__ __launch_bounds__(256) void k_flux(Geo G, Phys<typename C::R> P, type
     double v[5] = {0, 0, 0, 0, 0};
     if (k < nlinks) {
         const DevLink<typename C::R> L = load_link(links + k);
-        const double net = (double)link_update<C, ODD>(G, P, S, L, M, C::SCALED ? tstep : 0u);
+        const double net = (double)link_update<C, ODD>(G, P, S, L, M, tstep);
         const int slot = L.field == 2 ? 2 + L.caxis : L.field;
 #pragma unroll
         for (int q = 0; q < 5; ++q) v[q] = q == slot ? net : 0.0;
@@ -1045,7 +1057,7 @@ __global__ __launch_bounds__(256) void kb_links(const BItem<C>* __restrict__ ite
     const BItem<C>& I = items[it];
     const uint32_t k = ltiles[2 * b + 1] + threadIdx.x;
     if (k >= I.nlinks) return;
-    link_update<C, ODD>(I.G, I.P, I.S, load_link(I.links + k), I.M, C::SCALED ? step_time(I.tbase, tstep) : 0u);
+    link_update<C, ODD>(I.G, I.P, I.S, load_link(I.links + k), I.M, step_time(I.tbase, tstep));
 }
 
 // item time bases: set from the descriptors (all items), or advanced for the
@@ -1079,7 +1091,7 @@ __global__ __launch_bounds__(512) void kb_resident(const BItem<C>* __restrict__ 
     const uint8_t* flags = I.flags;
     const DevLink<typename C::R>* links = I.links;
     const uint32_t nn = I.nnodes, nl = I.nlinks, bd = blockDim.x;
-    const uint32_t t0 = C::SCALED ? step_time(I.tbase, tstep) : 0u;
+    const uint32_t t0 = step_time(I.tbase, tstep);
     for (int s = 0; s < nsteps; s += 2) {
         const uint32_t te = t0 + (uint32_t)s, to = te + 1u;
         for (uint32_t k = threadIdx.x; k < nl; k += bd) link_update<C, 0>(G, P, S, load_link(links + k), M, te);

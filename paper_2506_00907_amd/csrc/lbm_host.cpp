@@ -88,6 +88,7 @@ bool valid_params(const lbm_params* p, std::string* why) {
     if (p->storage < LBM_F64 || p->storage > LBM_BF16) return fail("unknown storage");
     for (int k = 0; k < 3; ++k)
         if (!(p->store_scale[k] > 0.0) || !std::isfinite(p->store_scale[k])) return fail("store_scale must be positive");
+    if (!std::isfinite(p->wall_omega)) return fail("wall_omega must be finite");
     const double nn = (double)(p->n[0] + 2) * (p->n[1] + 2) * (p->n[2] + 2);
     if (nn > 2.0e9) return fail("lattice too large for 32-bit node indices");
     return true;
@@ -210,7 +211,8 @@ class LinkBuilder {
                                 lk.dir = (uint8_t)a;
                                 lk.kind = (uint8_t)bc.kind;
                                 lk.comp = (uint8_t)(field == 2 ? c : 0);
-                                lk.flags = (uint8_t)((bc.u_given ? 1 : 0) | (e_ok ? 0 : 2));
+                                lk.flags = (uint8_t)((bc.u_given ? 1 : 0) | (e_ok ? 0 : 2) |
+                                                     (bc.u_given && bd.u_osc ? 4 : 0));
                                 lk.d = best.d;
                                 lk.value = bc.value;
                                 lk.a1 = bc.a1;
@@ -428,6 +430,7 @@ lbmi::KArgs base_args(const lbm_ctx* c) {
     a.tau_c = c->p.scalar ? c->p.tau_c : 1.0;
     a.tau_m = c->p.magnetic ? c->p.tau_m : 1.0;
     a.rho0 = c->p.rho0;
+    a.wall_omega = c->p.wall_omega;
     a.C0 = c->p.C0;
     a.mu = c->p.magnetic ? c->p.mu : 1.0;
     for (int k = 0; k < 3; ++k) {
@@ -491,7 +494,7 @@ void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::
         d.B = padB[i];
         d.mE = (s.flags & 2) ? padA[i] : padE[i];
         d.kind = s.kind;
-        d.flags = s.flags & 3;
+        d.flags = s.flags & 7;
         d.pa = (uint8_t)(base + s.dir);
         d.pap = (uint8_t)(base + lat.opp[s.dir]);
         d.field = s.field;
@@ -666,6 +669,8 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
                                            : (k.kind == LBM_LK_MAG_DIR || k.kind == LBM_LK_MAG_FLUX || k.kind == LBM_LK_BB0);
         if (!okkind) return bad("kind not allowed for this field");
         if (!(k.d > 0.0 && k.d <= 1.0)) return bad("d outside (0, 1]");
+        if (k.flags & ~7u) return bad("unknown flag bits");
+        if ((k.flags & 4) && !(k.flags & 1)) return bad("an oscillating boundary velocity needs flag bit 0 (u_w given)");
         if (!std::isfinite(k.value) || !std::isfinite(k.a1) || !std::isfinite(k.a3) || !std::isfinite(k.weight))
             return bad("non-finite wall data");
         int q[3];

@@ -26,7 +26,7 @@ struct alignas(16) DevLink {
     uint32_t E, B;        // A + e_alpha and A - e_alpha (periodic wrap), fluid or not
     uint32_t mE;          // node whose moments stand for E: E if fluid, else A
     uint8_t kind;         // lbm_link_kind
-    uint8_t flags;        // bit 0: u_w given; bit 1: E not fluid
+    uint8_t flags;        // bit 0: u_w given; bit 1: E not fluid; bit 2: u_w cos(omega t') (oscillating)
     uint8_t pa, pap;      // population planes of alpha and of its opposite alpha'
     uint8_t field;        // 0 f, 1 h, 2 g
     uint8_t caxis;        // Cartesian axis of the magnetic component (g links)
@@ -52,6 +52,7 @@ struct KArgs {
     void* M;               // R[2][8][plane]
     size_t n_links;
     double tau_f, tau_c, tau_m, rho0, C0, mu;
+    double wall_omega;     // angular frequency of oscillating boundary velocities (link flag bit 2)
     double Bext[3], accel[3], scale[3];
     int comp[3];           // Cartesian axis of each evolved magnetic component
     uint32_t* tbase;       // device word: the time at the start of a captured run (null: use tstep alone)

@@ -42,6 +42,7 @@ def params_from_scene(sc) -> L.lbm_params:
     p.storage = STORAGES[sc.storage]
     p.tau_f, p.tau_c, p.tau_m = sc.tau_f, sc.tau_c, sc.tau_m
     p.rho0, p.C0, p.mu = sc.rho0, sc.C0, sc.mu
+    p.wall_omega = sc.wall_omega
     return p
 
 
@@ -67,6 +68,7 @@ def boundaries_from_scene(sc):
         d = arr[i]
         d.type = 0 if b.type == "plane" else 1
         d.axis, d.side, d.is_open, d.q, d.radius = b.axis, b.side, int(b.is_open), b.q, b.radius
+        d.u_osc = int(b.u_osc)
         for k in range(3):
             d.center[k] = b.center[k]
             d.u_w[k] = b.u_w[k]

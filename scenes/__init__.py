@@ -133,6 +133,7 @@ class Boundary:
     radius: float = 0.0
     is_open: bool = False
     u_w: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    u_osc: bool = False          # the velocity is u_w cos(wall_omega t') (Scene.wall_omega)
     f: Optional[BC] = None
     h: Optional[BC] = None
     g: List[Optional[BC]] = field(default_factory=list)   # one per evolved component
@@ -160,6 +161,7 @@ class Scene:
     storage: str = "f64"
     store_scale: Tuple[float, float, float] = (1.0, 1.0, 1.0)
     steps: int = 1000
+    wall_omega: float = 0.0               # rad per step of the boundaries with u_osc
     init_C: float = 0.0                   # initial uniform concentration
     # optional initial fields (fluid-domain arrays, shape (nz, ny, nx[, 3]))
     init_rho: Optional[np.ndarray] = None
@@ -203,6 +205,25 @@ def poiseuille(nx: int = 64, ny: int = 32, tau: float = 0.8, g: float = 1e-6,
                  periodic=(True, False, True), fluid_lattice=D2Q9, tau_f=tau,
                  accel=(g, 0.0, 0.0), boundaries=[wall(0, 0.0), wall(1, u_top)],
                  storage=storage, steps=steps)
+
+
+def stokes_second(nx: int = 4, ny: int = 40, tau: float = 0.8, U: float = 0.01, period: int = 2000,
+                  q: float = 0.5, storage: str = "f64", steps: int = 6000, dim: int = 2) -> Scene:
+    """Stokes' second problem (the oscillating-wall validation of Section 5,
+    Eq. 45): fluid at rest between a static wall below and a wall above that
+    moves tangentially at U cos(omega t), omega = 2 pi / period, with walls
+    at distance q outside the first and last node rows.  2D: D2Q9, walls
+    normal to y, nx nodes periodic in x.  3D: D3Q19, walls normal to z,
+    nx x nx nodes periodic in x and y, ny rows between the walls."""
+    ax = 1 if dim == 2 else 2
+    bottom = Boundary("plane", axis=ax, side=0, q=q, f=BC(VEL))
+    top = Boundary("plane", axis=ax, side=1, q=q, u_w=(U, 0.0, 0.0), u_osc=True, f=BC(VEL))
+    if dim == 2:
+        n, per, lat = (nx, ny, 1), (True, False, True), D2Q9
+    else:
+        n, per, lat = (nx, nx, ny), (True, True, False), D3Q19
+    return Scene(name=f"stokes_{dim}d_{nx}x{ny}", dim=dim, n=n, periodic=per, fluid_lattice=lat, tau_f=tau,
+                 boundaries=[bottom, top], storage=storage, steps=steps, wall_omega=2.0 * math.pi / period)
 
 
 def reactive_channel(nx: int = 512, ny: int = 256, k: float = 1e-2, q: float = 0.3,

@@ -64,6 +64,17 @@ def test_bf16_batch_item_equals_item_alone(mode):
 
 
 @pytest.mark.parametrize("mode", [MODES[0], MODES[3]], ids=["tiled", "resident"])
+def test_oscillating_walls_in_a_batch(mode):
+    """Time-dependent wall data take each item's own time in the batch."""
+    scs = [scenes.stokes_second(nx=5, ny=17, period=150, q=0.3, storage="f32"),
+           scenes.stokes_second(nx=4, ny=23, period=90, q=0.7, U=0.02, storage="f32")]
+    B = lbm.Batch(scs)
+    B.configure(*mode)
+    B.step(130)
+    assert_items_equal_alone(B, scs, 130)
+
+
+@pytest.mark.parametrize("mode", [MODES[0], MODES[3]], ids=["tiled", "resident"])
 def test_batch_of_2d_channels_equals_alone(mode):
     scs = reactive_items("f32")
     B = lbm.Batch(scs)

@@ -55,6 +55,8 @@ FP64_CASES = {
     "diffreact_full": lambda: scenes.diffusion_reaction(layout="full", Da=48.0, W_nodes=12),
     "duct_item": lambda: scenes.batch_items(4, side_lo=48, side_hi=64, storage="f64")[0].scene,
     "pipe_item": lambda: scenes.batch_items(4, side_lo=48, side_hi=64, storage="f64")[1].scene,
+    # oscillating wall (time-dependent wall data), 1.5 periods in 300 steps
+    "stokes_d03": lambda: scenes.stokes_second(nx=5, ny=17, period=200, q=0.3, storage="f64"),
 }
 
 
@@ -88,7 +90,7 @@ def test_fp64_parity(key):
 
 
 @pytest.mark.parametrize("key", ["reactive", "hartmann_c01", "hartmann_cinf", "pipe_shercliff", "pipe_insulating3",
-                                 "diffreact_full", "pipe_item", "periodic_box"])
+                                 "diffreact_full", "pipe_item", "periodic_box", "stokes_d03"])
 def test_fp32_parity(key):
     """FP32 storage, 128 steps from a developed seeded state."""
     _case("fp32 " + key)

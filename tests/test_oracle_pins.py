@@ -633,3 +633,49 @@ def test_in_plane_start_keeps_a_row_alternating_mode():
         assert np.all(np.sign(rows[1:]) == -np.sign(rows[:-1]))
         amp.append(np.abs(rows).mean())
     assert amp[0] > 1e-5 and abs(amp[1] / amp[0] - 1.0) < 0.01
+
+
+def _stokes_error(ny, period, q, periods=3):
+    """largest relative L2 error of u_x against the closed form over a period
+    that starts after `periods` periods from rest"""
+    sc = scenes.stokes_second(ny=ny, period=period, q=q)
+    o = oracle.OracleSim(sc)
+    o.step(periods * period)
+    nu = (sc.tau_f - 0.5) / 3.0
+    H = ny - 1 + 2 * q
+    y = np.arange(ny) + q
+    errs = []
+    for k in range(4):
+        if k:
+            o.step(period // 4)
+        t = periods * period + k * (period // 4)
+        u = o.moments()[0, :, 0, 1]
+        ua = an.stokes_second(y, t, 0.01, sc.wall_omega, nu, H)
+        errs.append(np.linalg.norm(u - ua) / np.linalg.norm(ua))
+    return max(errs)
+
+
+@pytest.mark.parametrize("q", [0.5, 0.3])
+def test_stokes_second_problem_against_closed_form(q):
+    """An oscillating wall (Eq. 45) over a static one: the periodic state
+    follows u = Re[U e^{i w t} sinh(k y)/sinh(k H)] to discretisation error,
+    which falls with the resolution at a fixed Womersley number."""
+    e40 = _stokes_error(40, 2000, q)
+    assert e40 < 5e-3, e40
+    if q == 0.5:
+        e20 = _stokes_error(20, 500, q)
+        assert e20 / e40 > 2.5, (e20, e40)
+
+
+def test_stokes_closed_form_solves_the_diffusion_problem():
+    """the closed form itself: u_t = nu u_yy by finite differences, u = 0 at
+    y = 0 and U cos(w t) at y = H"""
+    U, w, nu, H = 0.01, 2 * math.pi / 2000, 0.1, 40.0
+    y = np.linspace(0.0, H, 401)
+    t, dt = 123.0, 1e-3
+    u = an.stokes_second(y, t, U, w, nu, H)
+    ut = (an.stokes_second(y, t + dt, U, w, nu, H) - an.stokes_second(y, t - dt, U, w, nu, H)) / (2 * dt)
+    h = y[1] - y[0]
+    uyy = (u[2:] - 2 * u[1:-1] + u[:-2]) / h ** 2
+    assert np.abs(ut[1:-1] - nu * uyy).max() < 1e-4 * np.abs(ut).max()
+    assert abs(u[0]) < 1e-15 and abs(u[-1] - U * math.cos(w * t)) < 1e-14
