@@ -23,9 +23,10 @@
  *    before any work is queued, so a call that fails has no effect.  The text
  *    of the last error of a context is lbm_last_error(ctx).
  *  - Memory: every device buffer is allocated and owned by the caller (the
- *    library never allocates device memory, never frees caller memory); the
- *    library owns only its host-side context.  "dev" pointers are device
- *    pointers, "host" pointers are host pointers.
+ *    library never frees caller memory and allocates no device memory, with
+ *    one exception: the measurement call lbm_step_timed keeps a temporary
+ *    copy of the state); the library owns only its host-side context.  "dev"
+ *    pointers are device pointers, "host" pointers are host pointers.
  *  - Streams: all device work of a context is queued on the hipStream_t given
  *    at creation (or lbm_set_stream).  lbm_reduce and lbm_save synchronise
  *    that stream; everything else is asynchronous.  Asynchronous device errors
@@ -108,7 +109,7 @@ typedef struct {
                         bit 2 (with bit 0): the boundary velocity oscillates,
                         u_w cos(wall_omega t'), evaluated at the time t' the
                         bounced population meets the boundary: t' = t - d for
-                        the value entering A at time t (Section 3.1, the
+                        the value entering A at time t (Section 4.1, the
                         arrival time between t - 1 and t; Eq. 45) */
     uint8_t pad[3];
     double d;        /* boundary-to-node distance |AX| / |AE| in (0, 1] */
@@ -140,6 +141,10 @@ typedef struct {
     lbm_bc f, h, g[3];
     int32_t u_osc;    /* 1: the boundary velocity is u_w cos(wall_omega t') (link flag bit 2) */
     int32_t reserved;
+    double d_scheme;  /* 0: each link uses the distance d measured from the geometry. In (0, 1]:
+                         every link of this boundary uses this d in its update instead (the
+                         deliberate layout/scheme mismatch of Section 5.2, e.g. the d = 0.5
+                         scheme on walls that sit on the nodes, d = 1). Other values: LBM_EINVAL */
 } lbm_boundary;
 
 typedef struct lbm_ctx lbm_ctx;

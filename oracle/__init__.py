@@ -47,7 +47,7 @@ class _Boundary(C.Structure):
     _fields_ = [("type", C.c_int32), ("axis", C.c_int32), ("side", C.c_int32),
                 ("is_open", C.c_int32), ("q", C.c_double), ("center", C.c_double * 3),
                 ("radius", C.c_double), ("u_w", C.c_double * 3), ("f", _BC), ("h", _BC),
-                ("g", _BC * 3), ("omega", C.c_double)]
+                ("g", _BC * 3), ("omega", C.c_double), ("d_used", C.c_double)]
 
 
 class _Scene(C.Structure):
@@ -199,6 +199,7 @@ class _SceneHolder:
                 cb.center[k] = b.center[k]
                 cb.u_w[k] = b.u_w[k]
             cb.omega = sc.wall_omega if b.u_osc else 0.0
+            cb.d_used = b.d_scheme
             self._bc(cb.f, b.f)
             self._bc(cb.h, b.h)
             for k in range(3):

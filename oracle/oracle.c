@@ -52,7 +52,7 @@ typedef struct {
 static void lattice_fill(or_lattice* L, int code) {
     memset(L, 0, sizeof(*L));
     if (code == OR_D2Q9) {
-        /* ordering with opposite pairs 1-3, 2-4, 5-7, 6-8 (Section 3.1 text) */
+        /* ordering with opposite pairs 1-3, 2-4, 5-7, 6-8 (Sections 3 and 4.1) */
         static const int e[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1},
                                     {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
         L->Q = 9;
@@ -194,6 +194,7 @@ typedef struct {
     double u_w[3];
     or_bc f, h, g[3];
     double omega; /* the boundary velocity is u_w cos(omega t') (0: steady) */
+    double d_used; /* > 0: the links take this d in their update, not the measured one */
 } or_boundary;
 
 typedef struct {
@@ -467,7 +468,7 @@ static int build_field_links(or_sim* S, int field, const or_lattice* L, int ncom
                         lk->kind = bc->kind;
                         lk->bnd = best;
                         lk->u_given = bc->u_given;
-                        lk->d = best_d;
+                        lk->d = b->d_used > 0.0 ? b->d_used : best_d;
                         lk->value = bc->value;
                         lk->a1 = bc->a1;
                         if (bc->a1_profile && bc->profile_len > 0) {
@@ -764,7 +765,7 @@ static void apply_links(or_sim* S) {
         in.weight = lk->weight;
         /* a time-dependent boundary velocity at the arrival time at the
          * boundary, t' = t + (1 - d) for the value at t + 1 from the
-         * post-collision state at t (Section 3.1) */
+         * post-collision state at t (Section 4.1) */
         const double wall = lk->omega != 0.0 ? cos(lk->omega * ((double)S->t + 1.0 - lk->d)) : 1.0;
         for (int k = 0; k < 3; ++k) in.u_w[k] = lk->u_w[k] * wall;
         in.x_ap_E = xs[base + (size_t)ap * S->N + E];

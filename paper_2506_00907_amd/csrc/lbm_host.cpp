@@ -213,7 +213,7 @@ class LinkBuilder {
                                 lk.comp = (uint8_t)(field == 2 ? c : 0);
                                 lk.flags = (uint8_t)((bc.u_given ? 1 : 0) | (e_ok ? 0 : 2) |
                                                      (bc.u_given && bd.u_osc ? 4 : 0));
-                                lk.d = best.d;
+                                lk.d = bd.d_scheme > 0.0 ? bd.d_scheme : best.d;
                                 lk.value = bc.value;
                                 lk.a1 = bc.a1;
                                 if (bc.a1_profile && bc.profile_len > 0) {
@@ -553,6 +553,7 @@ lbm_status lbm_build_links(const lbm_params* p, const lbm_boundary* bnds, int32_
         if (b.axis < 0 || b.axis > 2) return LBM_EINVAL;
         if (b.type == 0 && !(b.q > 0.0 && b.q <= 1.0)) return LBM_EINVAL;
         if (b.type == 1 && !(b.radius > 0.0)) return LBM_EINVAL;
+        if (!(b.d_scheme == 0.0 || (b.d_scheme > 0.0 && b.d_scheme <= 1.0))) return LBM_EINVAL;
     }
     LinkBuilder lb(*p, bnds, nb);
     std::vector<lbm_link> links;

@@ -69,6 +69,7 @@ def boundaries_from_scene(sc):
         d.type = 0 if b.type == "plane" else 1
         d.axis, d.side, d.is_open, d.q, d.radius = b.axis, b.side, int(b.is_open), b.q, b.radius
         d.u_osc = int(b.u_osc)
+        d.d_scheme = b.d_scheme
         for k in range(3):
             d.center[k] = b.center[k]
             d.u_w[k] = b.u_w[k]

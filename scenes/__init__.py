@@ -134,6 +134,7 @@ class Boundary:
     is_open: bool = False
     u_w: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     u_osc: bool = False          # the velocity is u_w cos(wall_omega t') (Scene.wall_omega)
+    d_scheme: float = 0.0        # > 0: the links use this d, not the measured one (Section 5.2 mismatch)
     f: Optional[BC] = None
     h: Optional[BC] = None
     g: List[Optional[BC]] = field(default_factory=list)   # one per evolved component
@@ -208,16 +209,21 @@ def poiseuille(nx: int = 64, ny: int = 32, tau: float = 0.8, g: float = 1e-6,
 
 
 def stokes_second(nx: int = 4, ny: int = 40, tau: float = 0.8, U: float = 0.01, period: int = 2000,
-                  q: float = 0.5, storage: str = "f64", steps: int = 6000, dim: int = 2) -> Scene:
+                  q: float = 0.5, storage: str = "f64", steps: int = 6000, dim: int = 2,
+                  d_scheme: float = 0.0) -> Scene:
     """Stokes' second problem (the oscillating-wall validation of Section 5,
     Eq. 45): fluid at rest between a static wall below and a wall above that
     moves tangentially at U cos(omega t), omega = 2 pi / period, with walls
     at distance q outside the first and last node rows.  2D: D2Q9, walls
     normal to y, nx nodes periodic in x.  3D: D3Q19, walls normal to z,
-    nx x nx nodes periodic in x and y, ny rows between the walls."""
+    nx x nx nodes periodic in x and y, ny rows between the walls.
+    d_scheme > 0 makes both walls use the scheme for that d whatever q is
+    (the paper runs the d = 0.5 scheme on walls at q = 1 to show the error
+    a layout/scheme mismatch brings)."""
     ax = 1 if dim == 2 else 2
-    bottom = Boundary("plane", axis=ax, side=0, q=q, f=BC(VEL))
-    top = Boundary("plane", axis=ax, side=1, q=q, u_w=(U, 0.0, 0.0), u_osc=True, f=BC(VEL))
+    bottom = Boundary("plane", axis=ax, side=0, q=q, d_scheme=d_scheme, f=BC(VEL))
+    top = Boundary("plane", axis=ax, side=1, q=q, u_w=(U, 0.0, 0.0), u_osc=True, d_scheme=d_scheme,
+                   f=BC(VEL))
     if dim == 2:
         n, per, lat = (nx, ny, 1), (True, False, True), D2Q9
     else:

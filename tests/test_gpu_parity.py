@@ -57,6 +57,9 @@ FP64_CASES = {
     "pipe_item": lambda: scenes.batch_items(4, side_lo=48, side_hi=64, storage="f64")[1].scene,
     # oscillating wall (time-dependent wall data), 1.5 periods in 300 steps
     "stokes_d03": lambda: scenes.stokes_second(nx=5, ny=17, period=200, q=0.3, storage="f64"),
+    "stokes_mismatch": lambda: scenes.stokes_second(nx=5, ny=15, period=150, q=1.0, d_scheme=0.5,
+                                                    storage="f64"),
+    "stokes_3d": lambda: scenes.stokes_second(nx=5, ny=14, period=120, q=0.5, dim=3, storage="f64"),
 }
 
 
@@ -90,7 +93,8 @@ def test_fp64_parity(key):
 
 
 @pytest.mark.parametrize("key", ["reactive", "hartmann_c01", "hartmann_cinf", "pipe_shercliff", "pipe_insulating3",
-                                 "diffreact_full", "pipe_item", "periodic_box", "stokes_d03"])
+                                 "diffreact_full", "pipe_item", "periodic_box", "stokes_d03",
+                                 "stokes_3d"])
 def test_fp32_parity(key):
     """FP32 storage, 128 steps from a developed seeded state."""
     _case("fp32 " + key)

@@ -70,6 +70,9 @@ SCENES = {
     "diffreact_full": lambda: scenes.diffusion_reaction(layout="full", W_nodes=8),
     "duct_item": lambda: scenes.batch_items(3, side_lo=20, side_hi=30)[0].scene,
     "pipe_item": lambda: scenes.batch_items(3, side_lo=20, side_hi=30)[1].scene,
+    "stokes_d03": lambda: scenes.stokes_second(nx=3, ny=9, q=0.3),
+    "stokes_mismatch": lambda: scenes.stokes_second(nx=3, ny=9, q=1.0, d_scheme=0.5),
+    "stokes_3d": lambda: scenes.stokes_second(nx=3, ny=8, q=0.5, dim=3),
 }
 
 
@@ -95,6 +98,7 @@ def compare_link_tables(sc):
         if not e_invalid:
             assert int(r["enode"]) == int(o_["E"])
         assert bool(r["flags"] & 1) == bool(o_["u_given"])
+        assert bool(r["flags"] & 4) == (o_["omega"] != 0.0)
         for fld in ("value", "a1", "a3"):
             assert r[fld] == o_[fld]
         assert abs(r["weight"] - o_["weight"]) < 1e-12 * max(1.0, abs(o_["weight"]))
@@ -226,6 +230,18 @@ def test_buffer_layout():
     assert sizes[3] == ((2 * 8 * plane * 4 + 255) // 256) * 256 + 256   # moment planes (FP32), time base
     assert sizes[5] == sizes[6] == sizes[7] == 0
     assert all(s % 256 == 0 for s in sizes)
+
+
+def test_scheme_distance_override():
+    """d_scheme replaces the measured d of every link of its boundary; values
+    outside (0, 1] are rejected"""
+    _, ll = lbm.build_links(scenes.stokes_second(nx=3, ny=9, q=1.0, d_scheme=0.5))
+    assert np.all(ll["d"] == 0.5)
+    _, ll = lbm.build_links(scenes.stokes_second(nx=3, ny=9, q=1.0))
+    assert np.all(ll["d"] == 1.0)
+    for bad in (-0.5, 1.5, math.nan):
+        with pytest.raises(L.LbmError):
+            lbm.build_links(scenes.stokes_second(nx=3, ny=9, q=1.0, d_scheme=bad))
 
 
 def test_builder_rejects_uncovered_boundary():

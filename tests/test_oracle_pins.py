@@ -44,7 +44,7 @@ def test_lattice_moments(name):
 
 
 def test_d2q9_ordering_pairs():
-    """The paper's D2Q9 indices pair 1-3, 2-4, 5-7, 6-8 (Section 3.1 text)."""
+    """The paper's D2Q9 indices pair 1-3, 2-4, 5-7, 6-8 (Sections 3 and 4.1)."""
     e, w, c2, opp = oracle.lattice_table("D2Q9")
     assert list(opp) == [0, 3, 4, 1, 2, 7, 8, 5, 6]
     assert tuple(e[1, :2]) == (1, 0) and tuple(e[5, :2]) == (1, 1)
@@ -101,7 +101,7 @@ def test_heq_geq_moments_eq9_eq10(name):
 
 def test_moving_increment_identity():
     """f^eq_a(u) - f^eq_a'(u) = f^eq_a'(-u) - f^eq_a(-u) = 2 rho w_a (e_a.u)/c_s^2
-    (Sections 3.1 and 4.2.2)."""
+    (Sections 4.1 and 4.2.2)."""
     e, w, c2, opp = oracle.lattice_table("D2Q9")
     rho, u = 1.03, np.array([0.02, -0.013, 0.0])
     fp, _, _ = oracle.equilibria("D2Q9", rho, u)
@@ -635,15 +635,16 @@ def test_in_plane_start_keeps_a_row_alternating_mode():
     assert amp[0] > 1e-5 and abs(amp[1] / amp[0] - 1.0) < 0.01
 
 
-def _stokes_error(ny, period, q, periods=3):
+def _stokes_error(ny, period, q, periods=3, d_scheme=0.0, H=None, y0=None):
     """largest relative L2 error of u_x against the closed form over a period
-    that starts after `periods` periods from rest"""
-    sc = scenes.stokes_second(ny=ny, period=period, q=q)
+    that starts after `periods` periods from rest; by default the walls of the
+    closed form are where the geometry puts them (H = ny - 1 + 2q)"""
+    sc = scenes.stokes_second(ny=ny, period=period, q=q, d_scheme=d_scheme)
     o = oracle.OracleSim(sc)
     o.step(periods * period)
     nu = (sc.tau_f - 0.5) / 3.0
-    H = ny - 1 + 2 * q
-    y = np.arange(ny) + q
+    H = ny - 1 + 2 * q if H is None else H
+    y = np.arange(ny) + (q if y0 is None else y0)
     errs = []
     for k in range(4):
         if k:
@@ -665,6 +666,22 @@ def test_stokes_second_problem_against_closed_form(q):
     if q == 0.5:
         e20 = _stokes_error(20, 500, q)
         assert e20 / e40 > 2.5, (e20, e40)
+
+
+def test_stokes_full_grid_layout_and_the_d_mismatch():
+    """Section 5.2, full-grid layout (walls on the nodes, d = 1, Eq. 43): the
+    periodic state follows the closed form and converges with resolution.
+    Running the d = 0.5 scheme on the same layout instead (the paper's
+    deliberate mismatch) is several times less accurate, and the error is
+    exactly a misplaced wall: the result then matches the closed form for
+    walls half a spacing from the outer nodes (H one spacing shorter)."""
+    e39 = _stokes_error(39, 2000, 1.0)
+    e19 = _stokes_error(19, 500, 1.0)
+    assert e39 < 1.5e-2 and e19 / e39 > 2.5, (e19, e39)
+    mis = _stokes_error(39, 2000, 1.0, d_scheme=0.5)
+    assert mis > 5 * e39, (mis, e39)
+    moved = _stokes_error(39, 2000, 1.0, d_scheme=0.5, H=39.0, y0=0.5)
+    assert moved < 5e-3, moved
 
 
 def test_stokes_closed_form_solves_the_diffusion_problem():
