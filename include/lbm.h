@@ -130,7 +130,7 @@ typedef struct {
 } lbm_bc;
 
 typedef struct {
-    int32_t type;     /* 0 = plane, 1 = cylinder */
+    int32_t type;     /* 0 = plane, 1 = cylinder, 2 = box */
     int32_t axis;     /* plane: normal axis; cylinder: its axis */
     int32_t side;     /* plane: 0 below node 0, 1 above node n-1 */
     int32_t is_open;  /* open boundary (inlet/outlet): loses corner ties to walls */
@@ -145,6 +145,13 @@ typedef struct {
                          every link of this boundary uses this d in its update instead (the
                          deliberate layout/scheme mismatch of Section 5.2, e.g. the d = 0.5
                          scheme on walls that sit on the nodes, d = 1). Other values: LBM_EINVAL */
+    double lo[3], hi[3]; /* box: the closed solid block lo <= x <= hi in node coordinates;
+                            bounds may be infinite, lo[k] <= hi[k] (else LBM_EINVAL).
+                            Nodes inside or on a face are solid; a link's d is where
+                            it enters the block (walls of voxel geometries, e.g. a
+                            channel between reservoirs, Section 5.1).  Along a
+                            periodic axis a box must be unbounded or stay clear of
+                            the domain's ends. */
 } lbm_boundary;
 
 typedef struct lbm_ctx lbm_ctx;

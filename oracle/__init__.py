@@ -47,7 +47,8 @@ class _Boundary(C.Structure):
     _fields_ = [("type", C.c_int32), ("axis", C.c_int32), ("side", C.c_int32),
                 ("is_open", C.c_int32), ("q", C.c_double), ("center", C.c_double * 3),
                 ("radius", C.c_double), ("u_w", C.c_double * 3), ("f", _BC), ("h", _BC),
-                ("g", _BC * 3), ("omega", C.c_double), ("d_used", C.c_double)]
+                ("g", _BC * 3), ("omega", C.c_double), ("d_used", C.c_double),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
 
 
 class _Scene(C.Structure):
@@ -193,13 +194,15 @@ class _SceneHolder:
         arr = (_Boundary * max(1, len(sc.boundaries)))()
         for i, b in enumerate(sc.boundaries):
             cb = arr[i]
-            cb.type = 0 if b.type == "plane" else 1
+            cb.type = {"plane": 0, "cylinder": 1, "box": 2}[b.type]
             cb.axis, cb.side, cb.is_open, cb.q, cb.radius = b.axis, b.side, int(b.is_open), b.q, b.radius
             for k in range(3):
                 cb.center[k] = b.center[k]
                 cb.u_w[k] = b.u_w[k]
             cb.omega = sc.wall_omega if b.u_osc else 0.0
             cb.d_used = b.d_scheme
+            for k in range(3):
+                cb.lo[k], cb.hi[k] = b.lo[k], b.hi[k]
             self._bc(cb.f, b.f)
             self._bc(cb.h, b.h)
             for k in range(3):

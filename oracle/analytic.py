@@ -311,3 +311,24 @@ def stokes_second(y: np.ndarray, t: float, U: float, omega: float, nu: float, H:
     decayed."""
     k = (1.0 + 1.0j) * np.sqrt(omega / (2.0 * nu))
     return np.real(U * np.exp(1j * omega * t) * np.sinh(k * np.asarray(y)) / np.sinh(k * H))
+
+
+def duct_poiseuille(x: np.ndarray, y: np.ndarray, a: float, b: float, G: float, mu: float,
+                    nterms: int = 200) -> np.ndarray:
+    """Fully developed flow along a rectangular duct -a < x < a, -b < y < b
+    driven by G = -dp/dz: the solution of mu (u_xx + u_yy) = -G with u = 0 on
+    the walls, as the cosine series in x (odd n) whose y-dependence meets the
+    walls at y = +-b:
+        u = (16 a^2 G / (mu pi^3)) sum_n (-1)^((n-1)/2) / n^3
+            [1 - cosh(n pi y / 2a) / cosh(n pi b / 2a)] cos(n pi x / 2a).
+    The far field of the channel of Section 5.1."""
+    x = np.asarray(x, dtype=float)
+    y = np.asarray(y, dtype=float)
+    u = np.zeros(np.broadcast(x, y).shape)
+    for j in range(nterms):
+        n = 2 * j + 1
+        k = n * math.pi / (2.0 * a)
+        # cosh ratio written with exponentials that cannot overflow
+        ratio = (np.exp(k * (np.abs(y) - b)) + np.exp(-k * (np.abs(y) + b))) / (1.0 + math.exp(-2.0 * k * b))
+        u += (-1.0) ** j / n ** 3 * (1.0 - ratio) * np.cos(k * x)
+    return 16.0 * a * a * G / (mu * math.pi ** 3) * u

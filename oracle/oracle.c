@@ -186,7 +186,7 @@ typedef struct {
 } or_bc;
 
 typedef struct {
-    int32_t type; /* 0 plane, 1 cylinder */
+    int32_t type; /* 0 plane, 1 cylinder, 2 box */
     int32_t axis, side, is_open;
     double q;
     double center[3];
@@ -195,6 +195,7 @@ typedef struct {
     or_bc f, h, g[3];
     double omega; /* the boundary velocity is u_w cos(omega t') (0: steady) */
     double d_used; /* > 0: the links take this d in their update, not the measured one */
+    double lo[3], hi[3]; /* box: closed solid block lo <= x <= hi (bounds may be infinite) */
 } or_boundary;
 
 typedef struct {
@@ -253,7 +254,38 @@ static int inside_cylinder(const or_boundary* b, const int* c) {
     return dy * dy + dz * dz < b->radius * b->radius;
 }
 
-/* fluid iff inside every cylinder (flat planes lie outside the node range) */
+/* closed solid block: a node on a face belongs to it */
+static int inside_box(const or_boundary* b, const int* c) {
+    for (int k = 0; k < 3; ++k)
+        if (c[k] < b->lo[k] || c[k] > b->hi[k]) return 0;
+    return 1;
+}
+
+/* fraction d in (0,1] of the link A -> A - e at which it enters the block:
+ * the points A - s e inside the block form the s-interval where every
+ * coordinate lies in [lo, hi]; d is that interval's lower end. */
+static double box_d(const or_boundary* b, const int* A, const int* e) {
+    double s_lo = 0.0, s_hi = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        if (e[k] == 0) {
+            if (A[k] < b->lo[k] || A[k] > b->hi[k]) return -1.0;
+            continue;
+        }
+        /* coordinate A[k] - s e[k] in [lo, hi] for s between these two */
+        double s1 = (A[k] - b->lo[k]) / e[k], s2 = (A[k] - b->hi[k]) / e[k];
+        if (s1 > s2) {
+            double t = s1;
+            s1 = s2;
+            s2 = t;
+        }
+        if (s1 > s_lo) s_lo = s1;
+        if (s2 < s_hi) s_hi = s2;
+    }
+    return s_lo <= s_hi ? s_lo : -1.0;
+}
+
+/* fluid iff inside every cylinder and outside every block (flat planes lie
+ * outside the node range) */
 int or_fluid_mask(const or_scene* s, uint8_t* mask) {
     int c[3];
     for (c[2] = 0; c[2] < s->n[2]; ++c[2])
@@ -261,7 +293,9 @@ int or_fluid_mask(const or_scene* s, uint8_t* mask) {
             for (c[0] = 0; c[0] < s->n[0]; ++c[0]) {
                 int fl = 1;
                 for (int i = 0; i < s->nb; ++i)
-                    if (s->b[i].type == 1 && !inside_cylinder(&s->b[i], c)) fl = 0;
+                    if ((s->b[i].type == 1 && !inside_cylinder(&s->b[i], c)) ||
+                        (s->b[i].type == 2 && inside_box(&s->b[i], c)))
+                        fl = 0;
                 mask[node_index(s, c)] = (uint8_t)fl;
             }
     return 0;
@@ -428,8 +462,10 @@ static int build_field_links(or_sim* S, int field, const or_lattice* L, int ncom
                             int ax = b->axis;
                             int crossed = b->side == 0 ? (Bc[ax] < 0) : (Bc[ax] >= s->n[ax]);
                             if (crossed && !s->periodic[ax]) d = b->q;
-                        } else {
+                        } else if (b->type == 1) {
                             if (!inside_cylinder(b, Bc)) d = cylinder_d(b, c, L->e[a]);
+                        } else if (inside_box(b, Bc)) {
+                            d = box_d(b, c, L->e[a]);
                         }
                         if (d <= 0.0) continue;
                         const or_bc* bc0 = bc_of(b, field, 0);

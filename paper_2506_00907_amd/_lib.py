@@ -52,7 +52,8 @@ class lbm_boundary(C.Structure):
     _fields_ = [("type", C.c_int32), ("axis", C.c_int32), ("side", C.c_int32), ("is_open", C.c_int32),
                 ("q", C.c_double), ("center", C.c_double * 3), ("radius", C.c_double),
                 ("u_w", C.c_double * 3), ("f", lbm_bc), ("h", lbm_bc), ("g", lbm_bc * 3),
-                ("u_osc", C.c_int32), ("reserved", C.c_int32), ("d_scheme", C.c_double)]
+                ("u_osc", C.c_int32), ("reserved", C.c_int32), ("d_scheme", C.c_double),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
 
 
 class lbm_batch_config(C.Structure):

@@ -143,7 +143,7 @@ class LinkBuilder {
         N_ = (size_t)p.n[0] * p.n[1] * p.n[2];
     }
 
-    // fluid iff strictly inside every cylinder
+    // fluid iff strictly inside every cylinder and outside every box
     void classify() {
         mask_.assign(N_, 1);
         for (int z = 0; z < p_.n[2]; ++z)
@@ -151,7 +151,8 @@ class LinkBuilder {
                 for (int x = 0; x < p_.n[0]; ++x) {
                     const int c[3] = {x, y, z};
                     for (const auto& bd : b_)
-                        if (bd.type == 1 && !inside(bd, c)) mask_[index(c)] = 0;
+                        if ((bd.type == 1 && !inside(bd, c)) || (bd.type == 2 && in_box(bd, c)))
+                            mask_[index(c)] = 0;
                 }
     }
 
@@ -182,8 +183,10 @@ class LinkBuilder {
                                     const int ax = bd.axis;
                                     const bool crossed = bd.side == 0 ? raw[ax] < 0 : raw[ax] >= p_.n[ax];
                                     if (crossed && !p_.periodic[ax]) d = bd.q;
-                                } else if (!inside(bd, raw)) {
-                                    d = cylinder_fraction(bd, A, L.e[a]);
+                                } else if (bd.type == 1) {
+                                    if (!inside(bd, raw)) d = cylinder_fraction(bd, A, L.e[a]);
+                                } else if (in_box(bd, raw)) {
+                                    d = box_fraction(bd, A, L.e[a]);
                                 }
                                 if (!(d > 0.0)) continue;
                                 const bool open = bd.is_open != 0;
@@ -268,6 +271,28 @@ class LinkBuilder {
         plane_axes(c.axis, &u, &v);
         const double du = q[u] - c.center[u], dv = q[v] - c.center[v];
         return du * du + dv * dv < c.radius * c.radius;
+    }
+
+    // closed axis-aligned box (bounds may be infinite): a node on a face is solid
+    static bool in_box(const lbm_boundary& b, const int* q) {
+        for (int k = 0; k < 3; ++k)
+            if (!(q[k] >= b.lo[k] && q[k] <= b.hi[k])) return false;
+        return true;
+    }
+
+    // fraction s in (0, 1] of the link A -> A - e (A outside, A - e inside the
+    // box) where the segment A - s e enters the box: the latest of its slab
+    // entries
+    static double box_fraction(const lbm_boundary& b, const int* A, const int* e) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double a = A[k];
+            if (a >= b.lo[k] && a <= b.hi[k]) continue;
+            if (e[k] == 0) return -1.0;
+            const double face = a < b.lo[k] ? b.lo[k] : b.hi[k];
+            s = std::max(s, (a - face) / (double)e[k]);
+        }
+        return s;
     }
 
     // fraction s in (0, 1] of the link A -> A - e where the ray meets the
@@ -549,10 +574,13 @@ lbm_status lbm_build_links(const lbm_params* p, const lbm_boundary* bnds, int32_
     if (!valid_params(p, &why) || nb < 0 || (nb > 0 && !bnds) || !n_out) return LBM_EINVAL;
     for (int i = 0; i < nb; ++i) {
         const lbm_boundary& b = bnds[i];
-        if (b.type != 0 && b.type != 1) return LBM_EINVAL;
+        if (b.type < 0 || b.type > 2) return LBM_EINVAL;
         if (b.axis < 0 || b.axis > 2) return LBM_EINVAL;
         if (b.type == 0 && !(b.q > 0.0 && b.q <= 1.0)) return LBM_EINVAL;
         if (b.type == 1 && !(b.radius > 0.0)) return LBM_EINVAL;
+        if (b.type == 2)
+            for (int k = 0; k < 3; ++k)
+                if (!(b.lo[k] <= b.hi[k])) return LBM_EINVAL;
         if (!(b.d_scheme == 0.0 || (b.d_scheme > 0.0 && b.d_scheme <= 1.0))) return LBM_EINVAL;
     }
     LinkBuilder lb(*p, bnds, nb);

@@ -16,6 +16,7 @@ from . import _lib as L
 
 LATTICES = {"D2Q9": 1, "D3Q19": 2, "D2Q5": 3, "D3Q7": 4}
 KINDS = {"VEL": 1, "PRES": 2, "CONC": 3, "FLUX": 4, "BB0": 5, "MAG_DIR": 6, "MAG_FLUX": 7}
+BOUNDARY_TYPES = {"plane": 0, "cylinder": 1, "box": 2}
 STORAGES = {"f64": L.LBM_F64, "f32": L.LBM_F32, "f16": L.LBM_F16, "bf16": L.LBM_BF16}
 
 LINK_DTYPE = np.dtype([("node", "<u4"), ("enode", "<u4"), ("field", "u1"), ("dir", "u1"), ("kind", "u1"),
@@ -66,10 +67,12 @@ def boundaries_from_scene(sc):
 
     for i, b in enumerate(sc.boundaries):
         d = arr[i]
-        d.type = 0 if b.type == "plane" else 1
+        d.type = BOUNDARY_TYPES[b.type]
         d.axis, d.side, d.is_open, d.q, d.radius = b.axis, b.side, int(b.is_open), b.q, b.radius
         d.u_osc = int(b.u_osc)
         d.d_scheme = b.d_scheme
+        for k in range(3):
+            d.lo[k], d.hi[k] = b.lo[k], b.hi[k]
         for k in range(3):
             d.center[k] = b.center[k]
             d.u_w[k] = b.u_w[k]

@@ -125,7 +125,7 @@ class Boundary:
               radius ``radius`` about ``center`` (the axis coordinate of
               ``center`` is ignored).
     """
-    type: str                    # "plane" | "cylinder"
+    type: str                    # "plane" | "cylinder" | "box"
     axis: int
     side: int = 0
     q: float = 0.5
@@ -135,6 +135,8 @@ class Boundary:
     u_w: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     u_osc: bool = False          # the velocity is u_w cos(wall_omega t') (Scene.wall_omega)
     d_scheme: float = 0.0        # > 0: the links use this d, not the measured one (Section 5.2 mismatch)
+    lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # box: closed solid block lo <= x <= hi
+    hi: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     f: Optional[BC] = None
     h: Optional[BC] = None
     g: List[Optional[BC]] = field(default_factory=list)   # one per evolved component
@@ -230,6 +232,39 @@ def stokes_second(nx: int = 4, ny: int = 40, tau: float = 0.8, U: float = 0.01, 
         n, per, lat = (nx, nx, ny), (True, True, False), D3Q19
     return Scene(name=f"stokes_{dim}d_{nx}x{ny}", dim=dim, n=n, periodic=per, fluid_lattice=lat, tau_f=tau,
                  boundaries=[bottom, top], storage=storage, steps=steps, wall_omega=2.0 * math.pi / period)
+
+
+def channel_reservoirs(layout: str = "half", width: int = 20, res_len: int = 20, ch_len: int = 60,
+                       tau: float = 0.7, u_in: float = 0.01, storage: str = "f64",
+                       steps: int = 20000) -> Scene:
+    """The 3D channel of Section 5.1: a square channel between two reservoirs,
+    D3Q19, driven by a uniform normal velocity u_in at the inlet (z = 0 end)
+    and held at rho = 1 at the outlet (z = end).  The reservoirs' lateral
+    sides are periodic; the channel's four walls are solid blocks (static,
+    the velocity scheme with u = 0, i.e. Bouzidi's bounceback).
+
+    layout "half": walls half a spacing outside the fluid nodes (d = 0.5),
+    width + 2 nodes across; "full": walls on the outer grid layers (d = 1),
+    width + 1 nodes across.  Lengths in lattice spacings (the paper: width
+    20, reservoirs 20, channel 60, tau 0.7, u_in = 0.01)."""
+    q = {"half": 0.5, "full": 1.0}[layout]
+    n_lat = width + (2 if layout == "half" else 1)
+    nz = 2 * res_len + ch_len + (0 if layout == "half" else -1)
+    w_lo, w_hi = 1.0 - q, 1.0 - q + width
+    z0 = -q + res_len
+    z1 = z0 + ch_len
+    inf = math.inf
+    walls = []
+    for ax in (0, 1):
+        for lo_c, hi_c in ((-inf, w_lo), (w_hi, inf)):
+            lo, hi = [-inf, -inf, z0], [inf, inf, z1]
+            lo[ax], hi[ax] = lo_c, hi_c
+            walls.append(Boundary("box", axis=2, lo=tuple(lo), hi=tuple(hi), f=BC(VEL)))
+    inlet = Boundary("plane", axis=2, side=0, q=q, is_open=True, u_w=(0.0, 0.0, u_in), f=BC(VEL))
+    outlet = Boundary("plane", axis=2, side=1, q=q, is_open=True, f=BC(PRES, value=1.0))
+    return Scene(name=f"channel_{layout}_{n_lat}x{n_lat}x{nz}", dim=3, n=(n_lat, n_lat, nz),
+                 periodic=(True, True, False), fluid_lattice=D3Q19, tau_f=tau, rho0=1.0,
+                 boundaries=walls + [inlet, outlet], storage=storage, steps=steps)
 
 
 def reactive_channel(nx: int = 512, ny: int = 256, k: float = 1e-2, q: float = 0.3,

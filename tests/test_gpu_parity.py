@@ -60,6 +60,9 @@ FP64_CASES = {
     "stokes_mismatch": lambda: scenes.stokes_second(nx=5, ny=15, period=150, q=1.0, d_scheme=0.5,
                                                     storage="f64"),
     "stokes_3d": lambda: scenes.stokes_second(nx=5, ny=14, period=120, q=0.5, dim=3, storage="f64"),
+    # channel between reservoirs: solid blocks, normal-velocity inlet, pressure outlet
+    "channel_half": lambda: scenes.channel_reservoirs("half", width=6, res_len=4, ch_len=12),
+    "channel_full": lambda: scenes.channel_reservoirs("full", width=6, res_len=4, ch_len=12),
 }
 
 
@@ -94,7 +97,7 @@ def test_fp64_parity(key):
 
 @pytest.mark.parametrize("key", ["reactive", "hartmann_c01", "hartmann_cinf", "pipe_shercliff", "pipe_insulating3",
                                  "diffreact_full", "pipe_item", "periodic_box", "stokes_d03",
-                                 "stokes_3d"])
+                                 "stokes_3d", "channel_half", "channel_full"])
 def test_fp32_parity(key):
     """FP32 storage, 128 steps from a developed seeded state."""
     _case("fp32 " + key)

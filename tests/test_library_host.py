@@ -73,7 +73,18 @@ SCENES = {
     "stokes_d03": lambda: scenes.stokes_second(nx=3, ny=9, q=0.3),
     "stokes_mismatch": lambda: scenes.stokes_second(nx=3, ny=9, q=1.0, d_scheme=0.5),
     "stokes_3d": lambda: scenes.stokes_second(nx=3, ny=8, q=0.5, dim=3),
+    "channel_half": lambda: scenes.channel_reservoirs("half", width=4, res_len=3, ch_len=6),
+    "channel_full": lambda: scenes.channel_reservoirs("full", width=4, res_len=3, ch_len=6),
+    "box_offgrid": lambda: _offgrid_box(),
 }
+
+
+def _offgrid_box():
+    """a finite block at off-grid faces inside a periodic box: every link
+    distance differs (diagonal entries through faces, edges and corners)"""
+    sc = scenes.channel_reservoirs("half", width=4, res_len=3, ch_len=6)
+    blk = scenes.Boundary("box", axis=2, lo=(2.3, 1.6, 4.2), hi=(3.7, 2.45, 6.9), f=scenes.BC(scenes.VEL))
+    return sc.with_(boundaries=sc.boundaries + [blk])
 
 
 def compare_link_tables(sc):
@@ -242,6 +253,19 @@ def test_scheme_distance_override():
     for bad in (-0.5, 1.5, math.nan):
         with pytest.raises(L.LbmError):
             lbm.build_links(scenes.stokes_second(nx=3, ny=9, q=1.0, d_scheme=bad))
+
+
+def test_box_distances_and_validation():
+    """a block's links enter it where the segment crosses its first face;
+    inverted bounds are rejected"""
+    _, ll = lbm.build_links(_offgrid_box())
+    d = np.round(ll["d"], 6)
+    assert {0.5}.issubset(set(d)) and len(set(d)) > 4, sorted(set(d))
+    assert np.all((ll["d"] > 0) & (ll["d"] <= 1))
+    sc = scenes.channel_reservoirs("half", width=4, res_len=3, ch_len=6)
+    bad = scenes.Boundary("box", axis=2, lo=(1.0, 0.0, 0.0), hi=(0.0, 1.0, 1.0), f=scenes.BC(scenes.VEL))
+    with pytest.raises(L.LbmError):
+        lbm.build_links(sc.with_(boundaries=sc.boundaries + [bad]))
 
 
 def test_builder_rejects_uncovered_boundary():

@@ -696,3 +696,93 @@ def test_stokes_closed_form_solves_the_diffusion_problem():
     uyy = (u[2:] - 2 * u[1:-1] + u[:-2]) / h ** 2
     assert np.abs(ut[1:-1] - nu * uyy).max() < 1e-4 * np.abs(ut).max()
     assert abs(u[0]) < 1e-15 and abs(u[-1] - U * math.cos(w * t)) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Section 5.1: the channel between reservoirs (normal-velocity inlet,
+# pressure outlet, walls as solid blocks)
+# ---------------------------------------------------------------------------
+_CHANNEL = {}
+
+
+def _channel(layout, W):
+    """steady state of the channel of width W (reservoirs 3W/4, channel 3W)"""
+    key = (layout, W)
+    if key not in _CHANNEL:
+        sc = scenes.channel_reservoirs(layout, width=W, res_len=3 * W // 4, ch_len=3 * W)
+        o = oracle.OracleSim(sc)
+        o.step(int(6000 * (W / 8) ** 2))
+        _CHANNEL[key] = (sc, o.moments())
+    return _CHANNEL[key]
+
+
+def _far_field_error(layout, W):
+    """u_z on the channel's middle plane against the duct solution driven by
+    the pressure gradient measured there (no fitted scale)"""
+    sc, m = _channel(layout, W)
+    rho, uz = m[..., 0], m[..., 3]
+    zc = m.shape[0] // 2
+    w_lo = 0.0 if layout == "full" else 0.5
+    xs = np.arange(sc.n[0]) - w_lo - W / 2
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    fl = (np.abs(X) < W / 2) & (np.abs(Y) < W / 2)
+    G = -(rho[zc + 1][fl] - rho[zc - 1][fl]).mean() / 2.0 / 3.0
+    nu = (sc.tau_f - 0.5) / 3.0
+    us = an.duct_poiseuille(X, Y, W / 2, W / 2, G, rho[zc][fl].mean() * nu)
+    ul = uz[zc].T
+    return np.linalg.norm((ul - us)[fl]) / np.linalg.norm(us[fl])
+
+
+@pytest.mark.parametrize("layout", ["half", "full"])
+def test_channel_inlet_mass_flux(layout):
+    """The velocity inlet adds rho(X) u_n per inlet node and step (the
+    increments f^eq_a - f^eq_a' of Section 4.1 sum to it), so at the steady
+    state the first plane carries u_in times the sum of rho(X) (Eq. 13) over
+    the inlet: the number of inlet nodes sets the flow (Section 5.1).  With
+    half-way walls and outlet the mass flux is the same on every plane; on
+    full-grid walls the node sum is only the trapezoid rule of the flux, and
+    the interpolated wall updates lose a little mass."""
+    sc, m = _channel(layout, 6)
+    rho, uz = m[..., 0], m[..., 3]
+    flux = (rho * uz).sum(axis=(1, 2))
+    q = 0.5 if layout == "half" else 1.0
+    rho_x = rho[0] + q * (rho[0] - rho[1])  # Eq. 13 at the inlet
+    inflow = 0.01 * rho_x.sum()
+    assert abs(flux[0] / inflow - 1) < 1e-6, (flux[0], inflow)
+    if layout == "half":
+        assert np.abs(flux / inflow - 1).max() < 1e-6, flux / inflow
+    else:
+        # interpolated walls (d = 1) do not conserve mass exactly: the far
+        # reservoir carries slightly less than the inflow
+        assert abs(flux[-1] / inflow - 1) < 1e-2, flux / inflow
+        assert np.abs(flux / inflow - 1).max() < 0.12, flux / inflow
+
+
+def test_channel_far_field_is_duct_poiseuille():
+    """Section 5.1: away from its ends the channel carries fully developed
+    duct flow.  Against the series solution at the measured pressure
+    gradient, the error falls at second order with the width for both
+    layouts (d = 0.5 walls are the more accurate)."""
+    e6, e8 = _far_field_error("half", 6), _far_field_error("half", 8)
+    assert e8 < 0.03 and e6 / e8 > 1.5, (e6, e8)
+    f6, f8 = _far_field_error("full", 6), _far_field_error("full", 8)
+    assert f8 < 0.12 and f6 / f8 > 1.5, (f6, f8)
+
+
+def test_duct_series_solves_the_poisson_problem():
+    """the duct series against a finite-difference solve of
+    mu (u_xx + u_yy) = -G with u = 0 on the walls (second order)"""
+    from scipy import sparse
+    from scipy.sparse import linalg as spla
+    a, b, G, mu = 1.0, 0.7, 2.0, 0.5
+    nx, ny = 161, 113
+    x, y = np.linspace(-a, a, nx), np.linspace(-b, b, ny)
+    hx, hy = x[1] - x[0], y[1] - y[0]
+    mx, my = nx - 2, ny - 2
+    Dx = sparse.diags([1, -2, 1], [-1, 0, 1], shape=(mx, mx)) / hx ** 2
+    Dy = sparse.diags([1, -2, 1], [-1, 0, 1], shape=(my, my)) / hy ** 2
+    A = mu * (sparse.kron(Dx, sparse.identity(my)) + sparse.kron(sparse.identity(mx), Dy))
+    u_fd = spla.spsolve(A.tocsc(), -G * np.ones(mx * my)).reshape(mx, my)
+    X, Y = np.meshgrid(x[1:-1], y[1:-1], indexing="ij")
+    u = an.duct_poiseuille(X, Y, a, b, G, mu)
+    assert np.abs(u - u_fd).max() < 1e-4 * u.max()
