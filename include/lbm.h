@@ -70,7 +70,13 @@ typedef enum {
     LBM_LK_FLUX = 4,     /* scalar flux F(C) = a1 C_X - a3, M scheme: Eqs. 23-27 */
     LBM_LK_BB0 = 5,      /* zero normal gradient, static: Eqs. 21-22 */
     LBM_LK_MAG_DIR = 6,  /* given magnetic component B_k: Eqs. 34-35 */
-    LBM_LK_MAG_FLUX = 7  /* magnetic flux F(B_k) = a1 B_X,k - a3 (Shercliff, Eq. 30), M scheme */
+    LBM_LK_MAG_FLUX = 7, /* magnetic flux F(B_k) = a1 B_X,k - a3 (Shercliff, Eq. 30), M scheme */
+    LBM_LK_MAG_THETA = 8 /* comparison scheme: the link-based theta form of Eq. 39 (d = 0.5)
+                            and Eq. 40 (d = 1) for a magnetic component.  The bounced
+                            value x becomes ((theta - 1) x + theta dg_move) / (theta + 1),
+                            theta = a1 >= 0 (Section 4.3: c_w H / (tau_m - 1/2));
+                            combined as Eq. 43 for d >= 0.5 and applied to the Y value
+                            of Eq. 35 for d < 0.5 */
 } lbm_link_kind;
 
 #define LBM_NBUF 8
@@ -110,7 +116,14 @@ typedef struct {
                         u_w cos(wall_omega t'), evaluated at the time t' the
                         bounced population meets the boundary: t' = t - d for
                         the value entering A at time t (Section 4.1, the
-                        arrival time between t - 1 and t; Eq. 45) */
+                        arrival time between t - 1 and t; Eq. 45);
+                        bit 3: the comparison form of Section 5 instead of the
+                        method's: VEL and PRES take the extrapolated form
+                        (Eqs. 15-16 and the pressure pair form) at every d, the
+                        form Section 5.1 finds unstable beyond d of about 0.8;
+                        FLUX and MAG_FLUX add the flux at X instead of M (Eq. 33,
+                        and Y + flux + correction for d < 0.5).  Other kinds:
+                        LBM_EINVAL */
     uint8_t pad[3];
     double d;        /* boundary-to-node distance |AX| / |AE| in (0, 1] */
     double value;    /* PRES: rho_w; CONC: C_w; MAG_DIR: B_k */
@@ -125,6 +138,9 @@ typedef struct {
     int32_t u_given;       /* 1: use the boundary velocity; 0: extrapolate u (Eq. 13) */
     int32_t profile_axis;  /* axis of a1_profile */
     int32_t profile_len;   /* 0 = no profile */
+    int32_t alt;           /* 1: the comparison form of the kind (link flag bit 3); only for
+                              VEL, PRES, FLUX and MAG_FLUX, else LBM_EINVAL */
+    int32_t reserved;
     double value, a1, a3;
     const double* a1_profile; /* host: a1 per coordinate of A along profile_axis, or NULL */
 } lbm_bc;

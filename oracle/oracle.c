@@ -174,13 +174,14 @@ void or_equilibria(int code, double rho, const double* u, double C, const double
 /* ------------------------------------------------------------------------- */
 /* scene description (mirrors the Python scene objects)                       */
 /* ------------------------------------------------------------------------- */
-enum { K_NONE = 0, K_VEL = 1, K_PRES, K_CONC, K_FLUX, K_BB0, K_MAG_DIR, K_MAG_FLUX };
+enum { K_NONE = 0, K_VEL = 1, K_PRES, K_CONC, K_FLUX, K_BB0, K_MAG_DIR, K_MAG_FLUX, K_MAG_THETA };
 
 typedef struct {
     int32_t kind;
     int32_t u_given;
     int32_t profile_axis;
     int32_t profile_len;
+    int32_t alt; /* the comparison form of Section 5 (VEL, PRES, FLUX, MAG_FLUX) */
     double value, a1, a3;
     const double* a1_profile;
 } or_bc;
@@ -223,6 +224,8 @@ typedef struct {
     double d, value, a1, a3, weight;
     double u_w[3];
     double omega; /* of the boundary velocity, 0 = steady */
+    int32_t compare; /* comparison form of the kind (Section 5) */
+    int32_t pad;
 } or_link;
 
 /* ------------------------------------------------------------------------- */
@@ -515,6 +518,7 @@ static int build_field_links(or_sim* S, int field, const or_lattice* L, int ncom
                         lk->a3 = bc->a3;
                         for (int j = 0; j < 3; ++j) lk->u_w[j] = b->u_w[j];
                         lk->omega = b->omega;
+                        lk->compare = bc->alt;
                         lk->weight = 1.0;
                         if (b->type == 1 && (bc->kind == K_FLUX || bc->kind == K_MAG_FLUX)) {
                             if (!seg[best]) {
@@ -683,6 +687,7 @@ typedef struct {
     double x_ap_A;  /* post-collision, direction alpha', at A */
     double x_a_A;   /* post-collision, direction alpha, at A */
     double mA[8], mE[8]; /* rho, u(3), C, B(3) at A and E at time t */
+    int32_t compare;     /* the comparison form of the kind (Section 5) */
 } or_link_in;
 
 /* Eq. 13: phi(X) = -d phi(E) + (d+1) phi(A) */
@@ -695,6 +700,7 @@ typedef struct {
     real u_w[3];
     real x_ap_E, x_ap_A, x_a_A;
     real mA[8], mE[8];
+    int32_t compare;
 } or_link_in_r;
 
 static real link_eval_r(const or_link_in_r* in) {
@@ -713,14 +719,15 @@ static real link_eval_r(const or_link_in_r* in) {
         case K_VEL: {
             real rhoX = extrap(d, in->mE[0], in->mA[0]);
             real inc = feq(&L, a, rhoX, in->u_w) - feq(&L, ap, rhoX, in->u_w);
-            if (d < (real)0.5) return xY + inc;                                         /* Eq. 15 */
+            /* Eq. 15; the comparison run of Section 5.1 keeps it for d >= 0.5 */
+            if (d < (real)0.5 || in->compare) return xY + inc;
             return ((2 * d - 1) * in->x_a_A + in->x_ap_A + inc) / (2 * d); /* Eq. 43 */
         }
         case K_PRES: {
             real uXp[3];
             for (int k = 0; k < 3; ++k) uXp[k] = extrap(d, in->mE[1 + k], in->mA[1 + k]);
             real sum = feq(&L, a, in->value, uXp) + feq(&L, ap, in->value, uXp);
-            if (d < (real)0.5) return sum - xY;                                         /* zeroth-moment pair */
+            if (d < (real)0.5 || in->compare) return sum - xY;                          /* zeroth-moment pair */
             return ((2 * d - 1) * in->x_a_A - in->x_ap_A + sum) / (2 * d); /* Eq. 44 */
         }
         case K_CONC: /* Eqs. 19-20 */
@@ -734,7 +741,8 @@ static real link_eval_r(const or_link_in_r* in) {
             if (d < (real)0.5) return xY;
             return ((2 * d - 1) * in->x_a_A + in->x_ap_A) / (2 * d);
         case K_FLUX:
-        case K_MAG_FLUX: {
+        case K_MAG_FLUX:
+        case K_MAG_THETA: {
             real phiX, dmove;
             real mu_[3] = {-uX[0], -uX[1], -uX[2]};
             if (in->kind == K_FLUX) {
@@ -744,7 +752,19 @@ static real link_eval_r(const or_link_in_r* in) {
                 phiX = BX[in->comp_axis];
                 dmove = geq(&L, ap, in->comp_axis, BX, mu_) - geq(&L, a, in->comp_axis, BX, mu_);
             }
+            if (in->kind == K_MAG_THETA) {
+                /* Eqs. 39-40: theta = a1; the bounced population x is replaced
+                 * by ((theta - 1) x + theta dmove) / (theta + 1) */
+                real th = in->a1;
+                if (d < (real)0.5) return ((th - 1) * xY + th * dmove) / (th + 1);
+                real bounced = ((th - 1) * in->x_ap_A + th * dmove) / (th + 1);
+                return ((2 * d - 1) * in->x_a_A + bounced) / (2 * d);
+            }
             real dflux = (in->a1 * phiX - in->a3) * in->weight;              /* Eq. 23, Eq. 48 */
+            if (in->compare) { /* Eq. 33: the flux joins the bounced population at X */
+                if (d < (real)0.5) return xY + dflux + dmove;
+                return ((2 * d - 1) * in->x_a_A + in->x_ap_A + dflux + dmove) / (2 * d);
+            }
             real xM = ((real)0.5 - d) * in->x_ap_E + ((real)0.5 + d) * in->x_ap_A;      /* Eq. 25 */
             real xM1 = xM + dflux + dmove;                                    /* Eq. 26 */
             return ((d - (real)0.5) * in->x_a_A + xM1) / (d + (real)0.5);                  /* Eq. 27 */
@@ -769,6 +789,7 @@ double or_link_eval(const or_link_in* in) {
     r.x_ap_E = in->x_ap_E;
     r.x_ap_A = in->x_ap_A;
     r.x_a_A = in->x_a_A;
+    r.compare = in->compare;
     for (int k = 0; k < 3; ++k) r.u_w[k] = in->u_w[k];
     for (int k = 0; k < 8; ++k) {
         r.mA[k] = in->mA[k];
@@ -794,6 +815,7 @@ static void apply_links(or_sim* S) {
         in.dir = a;
         in.comp_axis = lk->field == 2 ? s->comps[lk->comp] : 0;
         in.u_given = lk->u_given;
+        in.compare = lk->compare;
         in.d = lk->d;
         in.value = lk->value;
         in.a1 = lk->a1;

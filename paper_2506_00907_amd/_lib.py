@@ -44,7 +44,8 @@ class lbm_link(C.Structure):
 
 class lbm_bc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("u_given", C.c_int32), ("profile_axis", C.c_int32),
-                ("profile_len", C.c_int32), ("value", C.c_double), ("a1", C.c_double),
+                ("profile_len", C.c_int32), ("alt", C.c_int32), ("reserved", C.c_int32),
+                ("value", C.c_double), ("a1", C.c_double),
                 ("a3", C.c_double), ("a1_profile", C.POINTER(C.c_double))]
 
 

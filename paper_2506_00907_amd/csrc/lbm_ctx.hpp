@@ -41,6 +41,7 @@ struct lbm_ctx {
     void* buf[LBM_NBUF];
     size_t size[LBM_NBUF];
     size_t cap_links = 0, n_links = 0;
+    bool cmp_links = false;  // some link takes a comparison form (flag bit 3 or kind 8)
     hipStream_t stream = nullptr;
     int64_t t = 0, t_snap = 0;
     bool have_geometry = false, have_links = false, initialized = false, snap_valid = false;

@@ -296,7 +296,9 @@ struct Mom {
 // mA, mE: moments at A and E at the previous time (deviations + u)
 // t: time of the value being set (the bounced population meets the boundary
 // at t - d, where an oscillating boundary velocity is evaluated)
-template <class R>
+// CMP: the comparison forms (link flag bit 3, kind 8) are compiled in; the
+// method-only instantiation keeps the link kernel of the hot path lean.
+template <class R, bool CMP = true>
 __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R x_a, R x_apA,
                                         R x_apE, const R* mA, const R* mE, R w, R c2, uint32_t t) {
     const R d = L.d;
@@ -322,18 +324,20 @@ __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R
     }
     const R Y = (one - two * d) * x_apE + two * d * x_apA;  // Eqs. 16, 20, 35
     const bool lo = d < half;
+    const bool alt = CMP && (L.flags & 8) != 0;  // the comparison forms of Section 5
     switch (L.kind) {
         case 1: {  // VEL
             R rhoX = P.rho0 + cE * mE[0] + cA * mA[0];
             R inc = two * w * rhoX * (ex * ux + ey * uy + ez * uz) / c2;
-            return lo ? Y + inc : ((two * d - one) * x_a + x_apA + inc) / (two * d);  // Eq. 15 / 43
+            // Eq. 15 (at every d with the comparison flag) / Eq. 43
+            return (lo || alt) ? Y + inc : ((two * d - one) * x_a + x_apA + inc) / (two * d);
         }
         case 2: {  // PRES: u_X always extrapolated
             R vx = cE * mE[1] + cA * mA[1], vy = cE * mE[2] + cA * mA[2], vz = cE * mE[3] + cA * mA[3];
             R eu = ex * vx + ey * vy + ez * vz;
             R rw = P.rho0 + L.value;  // value holds rho_w - rho0
             R sdev = two * w * (L.value + rw * (eu * eu / (two * c2 * c2) - (vx * vx + vy * vy + vz * vz) / (two * c2)));
-            return lo ? sdev - Y : ((two * d - one) * x_a - x_apA + sdev) / (two * d);  // pair form / Eq. 44
+            return (lo || alt) ? sdev - Y : ((two * d - one) * x_a - x_apA + sdev) / (two * d);  // pair / Eq. 44
         }
         case 3:  // CONC (Eqs. 19-20); the velocity terms of the pair cancel; value = C_w - C0
         case 6:  // MAG_DIR (Eqs. 34-35); value = B_k - B_ext,k
@@ -341,7 +345,8 @@ __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R
         case 5:  // BB0 (Eqs. 21-22)
             return lo ? Y : ((two * d - one) * x_a + x_apA) / (two * d);
         case 4:
-        case 7: {  // FLUX / MAG_FLUX: M scheme (Eqs. 23-27) with the moving correction (Eq. 24)
+        case 7:
+        case 8: {  // FLUX / MAG_FLUX: M scheme (Eqs. 23-27) with the moving correction (Eq. 24)
             R phiX, dmove;
             const R eu = ex * ux + ey * uy + ez * uz;
             if (L.kind == 4) {
@@ -356,7 +361,18 @@ __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R
                 R uk = k == 0 ? ux : (k == 1 ? uy : uz);
                 dmove = two * w * (eu * phiX - (ex * Bx + ey * By + ez * Bz) * uk) / c2;
             }
+            if (CMP && L.kind == 8) {
+                // link-based theta form (Eqs. 39-40): the bounced value x
+                // becomes ((theta - 1) x + theta dmove) / (theta + 1), written
+                // for deviations from w B_ext,k; theta = a1
+                const R th = L.a1, Bk = P.Bext[L.caxis];
+                const R bx = lo ? Y : x_apA;
+                const R tb = ((th - one) * bx + th * dmove - two * w * Bk) / (th + one);
+                return lo ? tb : ((two * d - one) * x_a + tb) / (two * d);
+            }
             R dflux = (L.a1 * phiX - L.a3) * L.weight;
+            if (alt)  // flux added at X, not at M (Eq. 33 and its d < 0.5 analogue)
+                return lo ? Y + dflux + dmove : ((two * d - one) * x_a + x_apA + dflux + dmove) / (two * d);
             R xM = (half - d) * x_apE + (half + d) * x_apA + dflux + dmove;
             return ((d - half) * x_a + xM) / (d + half);
         }
@@ -392,7 +408,7 @@ __device__ __forceinline__ DevLink<R> load_link(const DevLink<R>* __restrict__ p
 // t: time of the value being set (also the dither seed of 16-bit storage).
 // Returns the link's net inflow into A over the step: the value it sets
 // minus the post-collision population A sent toward the wall, x*_alpha'(A).
-template <class C, int ODD>
+template <class C, int ODD, bool CMP = true>
 __device__ __forceinline__ typename C::R link_update(const Geo& G, const Phys<typename C::R>& P,
                                                      typename C::T* __restrict__ S,
                                                      const DevLink<typename C::R>& L,
@@ -443,7 +459,7 @@ __device__ __forceinline__ typename C::R link_update(const Geo& G, const Phys<ty
         w = (R)0.125;
         c2 = (R)0.25;
     }
-    const R v = link_value<R>(L, P, x_a, x_apA, xs, mA, mE, w, c2, t);
+    const R v = link_value<R, CMP>(L, P, x_a, x_apA, xs, mA, mE, w, c2, t);
     if (ODD) st_sr<SF>(Sp, L.B, C::SCALED ? v * sc : v, C::SCALED ? dither(L.B, L.pap, seed) : 0u);
     else st_sr<SF>(Sa, L.A, C::SCALED ? v * sc : v, C::SCALED ? dither(L.A, L.pa, seed) : 0u);
     return v - x_apA;
@@ -454,14 +470,14 @@ __device__ __forceinline__ uint32_t step_time(const uint32_t* tbase, uint32_t ts
     return (tbase ? *tbase : 0u) + tstep;
 }
 
-template <class C, int ODD>
+template <class C, int ODD, bool CMP>
 __global__ __launch_bounds__(256) void k_links(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
                                                const DevLink<typename C::R>* __restrict__ links,
                                                const typename C::R* __restrict__ M, uint32_t nlinks,
                                                const uint32_t* __restrict__ tbase, uint32_t tstep) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nlinks) return;
-    link_update<C, ODD>(G, P, S, load_link(links + k), M, step_time(tbase, tstep));
+    link_update<C, ODD, CMP>(G, P, S, load_link(links + k), M, step_time(tbase, tstep));
 }
 
 // sum over the 64 lanes of a wave (lane 0 holds the total)
@@ -1211,12 +1227,14 @@ struct Launch {
         if (!a.links_ready || a.n_links == 0) return hipSuccess;
         const int LB = a.n_links < 65536 ? 64 : 256;
         dim3 grid((unsigned)((a.n_links + LB - 1) / LB));
-        if (a.parity)
-            hipLaunchKernelGGL((k_links<C, 1>), grid, dim3(LB), 0, a.stream, G, P, (typename C::T*)a.S,
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, dim3(LB), 0, a.stream, G, P, (typename C::T*)a.S,
                                (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links, a.tbase, a.tstep);
+        };
+        if (a.cmp_links)
+            a.parity ? go(k_links<C, 1, true>) : go(k_links<C, 0, true>);
         else
-            hipLaunchKernelGGL((k_links<C, 0>), grid, dim3(LB), 0, a.stream, G, P, (typename C::T*)a.S,
-                               (const DevLink<R>*)a.links, (const R*)a.M, (uint32_t)a.n_links, a.tbase, a.tstep);
+            a.parity ? go(k_links<C, 1, false>) : go(k_links<C, 0, false>);
         return hipGetLastError();
     }
     static hipError_t flux(const KArgs& a) {

@@ -215,7 +215,7 @@ class LinkBuilder {
                                 lk.kind = (uint8_t)bc.kind;
                                 lk.comp = (uint8_t)(field == 2 ? c : 0);
                                 lk.flags = (uint8_t)((bc.u_given ? 1 : 0) | (e_ok ? 0 : 2) |
-                                                     (bc.u_given && bd.u_osc ? 4 : 0));
+                                                     (bc.u_given && bd.u_osc ? 4 : 0) | (bc.alt ? 8 : 0));
                                 lk.d = bd.d_scheme > 0.0 ? bd.d_scheme : best.d;
                                 lk.value = bc.value;
                                 lk.a1 = bc.a1;
@@ -451,6 +451,7 @@ lbmi::KArgs base_args(const lbm_ctx* c) {
     a.links = c->buf[2];
     a.M = c->buf[3];
     a.n_links = c->n_links;
+    a.cmp_links = c->cmp_links ? 1 : 0;
     a.tau_f = c->p.tau_f;
     a.tau_c = c->p.scalar ? c->p.tau_c : 1.0;
     a.tau_m = c->p.magnetic ? c->p.tau_m : 1.0;
@@ -496,6 +497,9 @@ uint8_t moments_needed(const lbm_link& k, const int* e) {
         case LBM_LK_MAG_FLUX:
             if (uw_zero) return (uint8_t)(0x20 << k.comp);
             return (uint8_t)(0xE0 | (u_given ? 0 : U));
+        case LBM_LK_MAG_THETA:  // B only through the moving correction
+            if (uw_zero) return 0;
+            return (uint8_t)(0xE0 | (u_given ? 0 : U));
         default: return 0;  // CONC, BB0, MAG_DIR: no moments
     }
 }
@@ -519,7 +523,7 @@ void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::
         d.B = padB[i];
         d.mE = (s.flags & 2) ? padA[i] : padE[i];
         d.kind = s.kind;
-        d.flags = s.flags & 7;
+        d.flags = s.flags & 15;
         d.pa = (uint8_t)(base + s.dir);
         d.pap = (uint8_t)(base + lat.opp[s.dir]);
         d.field = s.field;
@@ -582,6 +586,11 @@ lbm_status lbm_build_links(const lbm_params* p, const lbm_boundary* bnds, int32_
             for (int k = 0; k < 3; ++k)
                 if (!(b.lo[k] <= b.hi[k])) return LBM_EINVAL;
         if (!(b.d_scheme == 0.0 || (b.d_scheme > 0.0 && b.d_scheme <= 1.0))) return LBM_EINVAL;
+        const lbm_bc* bcs[5] = {&b.f, &b.h, &b.g[0], &b.g[1], &b.g[2]};
+        for (const lbm_bc* bc : bcs)
+            if (bc->alt && !(bc->kind == LBM_LK_VEL || bc->kind == LBM_LK_PRES || bc->kind == LBM_LK_FLUX ||
+                             bc->kind == LBM_LK_MAG_FLUX))
+                return LBM_EINVAL;
     }
     LinkBuilder lb(*p, bnds, nb);
     std::vector<lbm_link> links;
@@ -695,10 +704,15 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
         if (k.field == 2 ? k.comp >= p.mag_ncomp : k.comp != 0) return bad("component out of range");
         const bool okkind = k.field == 0 ? (k.kind == LBM_LK_VEL || k.kind == LBM_LK_PRES)
                             : k.field == 1 ? (k.kind == LBM_LK_CONC || k.kind == LBM_LK_FLUX || k.kind == LBM_LK_BB0)
-                                           : (k.kind == LBM_LK_MAG_DIR || k.kind == LBM_LK_MAG_FLUX || k.kind == LBM_LK_BB0);
+                                           : (k.kind == LBM_LK_MAG_DIR || k.kind == LBM_LK_MAG_FLUX || k.kind == LBM_LK_BB0 ||
+                                              k.kind == LBM_LK_MAG_THETA);
         if (!okkind) return bad("kind not allowed for this field");
         if (!(k.d > 0.0 && k.d <= 1.0)) return bad("d outside (0, 1]");
-        if (k.flags & ~7u) return bad("unknown flag bits");
+        if (k.flags & ~15u) return bad("unknown flag bits");
+        if ((k.flags & 8) && !(k.kind == LBM_LK_VEL || k.kind == LBM_LK_PRES || k.kind == LBM_LK_FLUX ||
+                               k.kind == LBM_LK_MAG_FLUX))
+            return bad("flag bit 3 (comparison form) needs kind VEL, PRES, FLUX or MAG_FLUX");
+        if (k.kind == LBM_LK_MAG_THETA && !(k.a1 >= 0.0)) return bad("theta (a1) must be >= 0");
         if ((k.flags & 4) && !(k.flags & 1)) return bad("an oscillating boundary velocity needs flag bit 0 (u_w given)");
         if (!std::isfinite(k.value) || !std::isfinite(k.a1) || !std::isfinite(k.a3) || !std::isfinite(k.weight))
             return bad("non-finite wall data");
@@ -813,6 +827,9 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
     if ((st = hip_check(c, hipMemsetAsync(c->buf[3], 0, c->size[3], c->stream), "moment clear"))) return st;
     if ((st = hip_check(c, hipStreamSynchronize(c->stream), "link upload sync"))) return st;
     c->n_links = n;
+    c->cmp_links = false;
+    for (size_t i = 0; i < n; ++i)
+        if ((L[i].flags & 8) || L[i].kind == LBM_LK_MAG_THETA) c->cmp_links = true;
     drop_graph(c);
     c->have_links = true;
     c->initialized = false;

@@ -26,7 +26,8 @@ struct alignas(16) DevLink {
     uint32_t E, B;        // A + e_alpha and A - e_alpha (periodic wrap), fluid or not
     uint32_t mE;          // node whose moments stand for E: E if fluid, else A
     uint8_t kind;         // lbm_link_kind
-    uint8_t flags;        // bit 0: u_w given; bit 1: E not fluid; bit 2: u_w cos(omega t') (oscillating)
+    uint8_t flags;        // bit 0: u_w given; bit 1: E not fluid; bit 2: u_w cos(omega t') (oscillating);
+                          // bit 3: the comparison form of the kind
     uint8_t pa, pap;      // population planes of alpha and of its opposite alpha'
     uint8_t field;        // 0 f, 1 h, 2 g
     uint8_t caxis;        // Cartesian axis of the magnetic component (g links)
@@ -59,6 +60,7 @@ struct KArgs {
     uint32_t tstep;        // time of this step, counted from *tbase (or absolute without tbase)
     int parity;            // parity of the current time (t % 2)
     int links_ready;       // 0 at t = 0: populations are the initial state
+    int cmp_links;         // some link takes a comparison form (flag bit 3 or kind 8)
     // observe / init
     int mode;              // OBS_*
     int field;             // OBS_POPS: 0 f, 1 h, 2 g; OBS_NORM: Cartesian axis

@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib as L
 
 LATTICES = {"D2Q9": 1, "D3Q19": 2, "D2Q5": 3, "D3Q7": 4}
-KINDS = {"VEL": 1, "PRES": 2, "CONC": 3, "FLUX": 4, "BB0": 5, "MAG_DIR": 6, "MAG_FLUX": 7}
+KINDS = {"VEL": 1, "PRES": 2, "CONC": 3, "FLUX": 4, "BB0": 5, "MAG_DIR": 6, "MAG_FLUX": 7, "MAG_THETA": 8}
 BOUNDARY_TYPES = {"plane": 0, "cylinder": 1, "box": 2}
 STORAGES = {"f64": L.LBM_F64, "f32": L.LBM_F32, "f16": L.LBM_F16, "bf16": L.LBM_BF16}
 
@@ -57,6 +57,7 @@ def boundaries_from_scene(sc):
             return
         dst.kind = KINDS[bc.kind]
         dst.u_given = int(bc.u_given)
+        dst.alt = int(bc.alt)
         dst.value, dst.a1, dst.a3 = bc.value, bc.a1, bc.a3
         dst.profile_axis = bc.profile_axis
         if bc.a1_profile is not None:

@@ -86,9 +86,9 @@ class SplitMix64:
 # lattice names
 D2Q9, D3Q19, D2Q5, D3Q7 = "D2Q9", "D3Q19", "D2Q5", "D3Q7"
 # boundary-condition kinds (per lattice, per boundary)
-VEL, PRES, CONC, FLUX, BB0, MAG_DIR, MAG_FLUX = (
-    "VEL", "PRES", "CONC", "FLUX", "BB0", "MAG_DIR", "MAG_FLUX")
-KIND_CODES = {VEL: 1, PRES: 2, CONC: 3, FLUX: 4, BB0: 5, MAG_DIR: 6, MAG_FLUX: 7}
+VEL, PRES, CONC, FLUX, BB0, MAG_DIR, MAG_FLUX, MAG_THETA = (
+    "VEL", "PRES", "CONC", "FLUX", "BB0", "MAG_DIR", "MAG_FLUX", "MAG_THETA")
+KIND_CODES = {VEL: 1, PRES: 2, CONC: 3, FLUX: 4, BB0: 5, MAG_DIR: 6, MAG_FLUX: 7, MAG_THETA: 8}
 LATTICE_CODES = {D2Q9: 1, D3Q19: 2, D2Q5: 3, D3Q7: 4}
 STORAGE_CODES = {"f64": 1, "f32": 2, "f16": 3, "bf16": 4}
 
@@ -104,6 +104,9 @@ class BC:
              velocity at the boundary point is extrapolated from the fluid
     a1_profile: optional per-position a1 along ``profile_axis`` (indexed by
              the first fluid node's coordinate on that axis)
+    alt    : the comparison form of Section 5 instead of the method's: VEL
+             and PRES extrapolated at every d (Eqs. 15-16), FLUX and MAG_FLUX
+             with the flux added at the wall (Eq. 33)
     """
     kind: str
     value: float = 0.0
@@ -112,6 +115,7 @@ class BC:
     u_given: bool = True
     a1_profile: Optional[np.ndarray] = None
     profile_axis: int = 0
+    alt: bool = False
 
 
 @dataclass
@@ -236,7 +240,7 @@ def stokes_second(nx: int = 4, ny: int = 40, tau: float = 0.8, U: float = 0.01, 
 
 def channel_reservoirs(layout: str = "half", width: int = 20, res_len: int = 20, ch_len: int = 60,
                        tau: float = 0.7, u_in: float = 0.01, storage: str = "f64",
-                       steps: int = 20000) -> Scene:
+                       steps: int = 20000, q_io: Optional[float] = None, alt_io: bool = False) -> Scene:
     """The 3D channel of Section 5.1: a square channel between two reservoirs,
     D3Q19, driven by a uniform normal velocity u_in at the inlet (z = 0 end)
     and held at rho = 1 at the outlet (z = end).  The reservoirs' lateral
@@ -246,7 +250,10 @@ def channel_reservoirs(layout: str = "half", width: int = 20, res_len: int = 20,
     layout "half": walls half a spacing outside the fluid nodes (d = 0.5),
     width + 2 nodes across; "full": walls on the outer grid layers (d = 1),
     width + 1 nodes across.  Lengths in lattice spacings (the paper: width
-    20, reservoirs 20, channel 60, tau 0.7, u_in = 0.01)."""
+    20, reservoirs 20, channel 60, tau 0.7, u_in = 0.01).  ``q_io`` moves the
+    inlet and outlet planes to that distance from the end nodes (default: the
+    layout's); ``alt_io`` gives them the extrapolated forms at every d (the
+    comparison of Section 5.1, unstable at large d)."""
     q = {"half": 0.5, "full": 1.0}[layout]
     n_lat = width + (2 if layout == "half" else 1)
     nz = 2 * res_len + ch_len + (0 if layout == "half" else -1)
@@ -260,11 +267,24 @@ def channel_reservoirs(layout: str = "half", width: int = 20, res_len: int = 20,
             lo, hi = [-inf, -inf, z0], [inf, inf, z1]
             lo[ax], hi[ax] = lo_c, hi_c
             walls.append(Boundary("box", axis=2, lo=tuple(lo), hi=tuple(hi), f=BC(VEL)))
-    inlet = Boundary("plane", axis=2, side=0, q=q, is_open=True, u_w=(0.0, 0.0, u_in), f=BC(VEL))
-    outlet = Boundary("plane", axis=2, side=1, q=q, is_open=True, f=BC(PRES, value=1.0))
+    qi = q if q_io is None else q_io
+    inlet = Boundary("plane", axis=2, side=0, q=qi, is_open=True, u_w=(0.0, 0.0, u_in), f=BC(VEL, alt=alt_io))
+    outlet = Boundary("plane", axis=2, side=1, q=qi, is_open=True, f=BC(PRES, value=1.0, alt=alt_io))
     return Scene(name=f"channel_{layout}_{n_lat}x{n_lat}x{nz}", dim=3, n=(n_lat, n_lat, nz),
                  periodic=(True, True, False), fluid_lattice=D3Q19, tau_f=tau, rho0=1.0,
                  boundaries=walls + [inlet, outlet], storage=storage, steps=steps)
+
+
+def open_box(nx: int = 24, ny: int = 5, q_in: float = 0.5, q_out: float = 0.5, alt_in: bool = False,
+             alt_out: bool = False, u_in: float = 0.01, tau: float = 0.7, storage: str = "f64") -> Scene:
+    """Uniform D2Q9 flow through a box periodic in y: velocity inlet at
+    x = -q_in, pressure outlet (rho = 1) at nx - 1 + q_out.  With alt_in /
+    alt_out the inlet / outlet take the extrapolated forms at every d (the
+    comparison of Section 5.1, which loses stability at large d)."""
+    inlet = Boundary("plane", axis=0, side=0, q=q_in, is_open=True, u_w=(u_in, 0.0, 0.0), f=BC(VEL, alt=alt_in))
+    outlet = Boundary("plane", axis=0, side=1, q=q_out, is_open=True, f=BC(PRES, value=1.0, alt=alt_out))
+    return Scene(name=f"open_box_{nx}x{ny}", dim=2, n=(nx, ny, 1), periodic=(False, True, True),
+                 fluid_lattice=D2Q9, tau_f=tau, rho0=1.0, boundaries=[inlet, outlet], storage=storage)
 
 
 def reactive_channel(nx: int = 512, ny: int = 256, k: float = 1e-2, q: float = 0.3,
@@ -301,7 +321,7 @@ def hartmann_couette(nx: int = 1024, ny: int = 512, Ha: float = 5.0, c_top: floa
                      u_top: float = 0.01, v0: float = 0.002, qb: Optional[float] = None,
                      qt: Optional[float] = None, tau_f: float = 0.8, tau_m: float = 0.9,
                      storage: str = "f32", steps: int = 2000, seed: int = BASE_SEED + 3,
-                     accel: float = 0.0) -> Scene:
+                     accel: float = 0.0, top_scheme: str = "M") -> Scene:
     """Sheared MHD channel with transverse field B_ext = (0, B0).
 
     Bottom wall: insulating (B1 = 0), velocity (0, v0).  Top wall: velocity
@@ -309,6 +329,9 @@ def hartmann_couette(nx: int = 1024, ny: int = 512, Ha: float = 5.0, c_top: floa
     inf -> perfectly conducting (zero flux), otherwise the Shercliff flux
     F(B1) = -eta B1/(c H).  B2 = B0 is given on both walls.  With v0 != 0 both
     walls transpire uniformly, which keeps the flow x-invariant.
+    ``top_scheme`` for a finite c_top: "M" (the method, flux at the point M),
+    "X" (the simplified Eq. 33, flux at the wall) or "theta" (the link-based
+    form of Eqs. 39-40, theta = c H / (tau_m - 1/2)).
     """
     rng = SplitMix64(seed)
     qb = rng.uniform(0.1, 0.9) if qb is None else qb
@@ -320,9 +343,11 @@ def hartmann_couette(nx: int = 1024, ny: int = 512, Ha: float = 5.0, c_top: floa
         top_b1 = BC(MAG_DIR, value=0.0)
     elif math.isinf(c_top):
         top_b1 = BC(MAG_FLUX, a1=0.0, a3=0.0)
+    elif top_scheme == "theta":
+        top_b1 = BC(MAG_THETA, a1=c_top * H / (tau_m - 0.5))
     else:
         a1 = -eta / (c_top * H)
-        top_b1 = BC(MAG_FLUX, a1=a1, a3=a1 * 0.0)
+        top_b1 = BC(MAG_FLUX, a1=a1, a3=a1 * 0.0, alt=top_scheme == "X")
     bottom = Boundary("plane", axis=1, side=0, q=qb, u_w=(0.0, v0, 0.0), f=BC(VEL),
                       g=[BC(MAG_DIR, value=0.0), BC(MAG_DIR, value=B0)])
     top = Boundary("plane", axis=1, side=1, q=qt, u_w=(u_top, v0, 0.0), f=BC(VEL),

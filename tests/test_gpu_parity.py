@@ -3,6 +3,7 @@ same seeded scenes.  Bars: FP64 storage 1e-12 relative L2 per moment field
 (populations to 1e-13 absolute); FP32 storage 1e-5 relative L2 on u, C, B;
 FP16/BF16 storage has no parity bound and is checked against loose error
 bounds only."""
+import dataclasses
 import math
 
 import numpy as np
@@ -63,7 +64,24 @@ FP64_CASES = {
     # channel between reservoirs: solid blocks, normal-velocity inlet, pressure outlet
     "channel_half": lambda: scenes.channel_reservoirs("half", width=6, res_len=4, ch_len=12),
     "channel_full": lambda: scenes.channel_reservoirs("full", width=6, res_len=4, ch_len=12),
+    # comparison forms: flux at the wall (Eq. 33), theta form (Eqs. 39-40),
+    # extrapolated inlet / outlet above d = 0.5, scalar flux at the wall
+    "hartmann_X": lambda: scenes.hartmann_couette(nx=5, ny=17, c_top=0.1, qb=1.0, qt=1.0, top_scheme="X",
+                                                  storage="f64"),
+    "hartmann_theta": lambda: scenes.hartmann_couette(nx=5, ny=17, c_top=0.5, qb=1.0, qt=0.7,
+                                                      top_scheme="theta", storage="f64"),
+    "hartmann_theta_d03": lambda: scenes.hartmann_couette(nx=5, ny=17, c_top=0.5, qb=0.5, qt=0.3,
+                                                          top_scheme="theta", storage="f64"),
+    "open_box_alt": lambda: scenes.open_box(nx=24, ny=5, q_in=0.52, q_out=0.7, alt_in=True, alt_out=True),
+    "reactive_alt": lambda: _reactive_alt(),
 }
+
+
+def _reactive_alt():
+    sc = scenes.reactive_channel(nx=33, ny=11, q=0.3, k_range=(1e-3, 1e-1), storage="f64")
+    for b in sc.boundaries[:2]:
+        b.h = dataclasses.replace(b.h, alt=True)
+    return sc
 
 
 def _developed(key, storage=None):
@@ -97,7 +115,8 @@ def test_fp64_parity(key):
 
 @pytest.mark.parametrize("key", ["reactive", "hartmann_c01", "hartmann_cinf", "pipe_shercliff", "pipe_insulating3",
                                  "diffreact_full", "pipe_item", "periodic_box", "stokes_d03",
-                                 "stokes_3d", "channel_half", "channel_full"])
+                                 "stokes_3d", "channel_half", "channel_full", "hartmann_X", "hartmann_theta",
+                                 "open_box_alt"])
 def test_fp32_parity(key):
     """FP32 storage, 128 steps from a developed seeded state."""
     _case("fp32 " + key)

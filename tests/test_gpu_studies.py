@@ -1,0 +1,53 @@
+"""The paper's validation cases at the paper's resolution, run on the GPU
+through the C ABI and compared with closed forms (properties that hold at
+any size, where the oracle would take minutes)."""
+import math
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle import analytic as an
+from paper_2506_00907_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+C_W = (0.1, 0.5, 1.0, 5.0, 1e4)
+
+
+def test_hartmann_couette_schemes_at_paper_resolution():
+    """Section 5.4 at the paper's resolution (101 grid points across the
+    full-grid channel, 102 across the half-grid one), Ha = 5, every c_w of the
+    paper: the M scheme matches the closed form at d = 1 and d = 0.5; adding
+    the flux at the wall (Eq. 33) errs at small c_w and converges to the M
+    scheme as c_w grows; the theta form (Eq. 40) behaves like Eq. 33.  All
+    items run as one FP64 batch from rest for 8 H^2 / nu steps."""
+    cases = [(c, s, 1.0) for c in C_W for s in ("M", "X", "theta")] + [(c, "M", 0.5) for c in C_W]
+    scs = []
+    for c, s, q in cases:
+        ny = 99 if q == 1.0 else 100
+        scs.append(scenes.hartmann_couette(nx=4, ny=ny, Ha=5.0, c_top=c, u_top=1e-3, v0=0.0, qb=q, qt=q,
+                                           storage="f64", top_scheme=s))
+    B = lbm.Batch(scs)
+    B.configure("tiled", 64, 1, 64)
+    H = scs[0].meta["H"]
+    assert H == 50.0
+    B.step(int(8 * H * H / 0.1))
+    errs = {}
+    for (c, s, q), sc, it in zip(cases, scs, B.items):
+        m = it.read_moments("f64").cpu().numpy()
+        ny = sc.n[1]
+        y = np.arange(ny) - (ny - 1) / 2
+        u_ex, b_ex = an.hartmann_couette(y, H, sc.meta["B0"], 0.1, 0.1, U_top=1e-3, c_top=c)
+        u, b = m[1, 0, :, 0], m[5, 0, :, 0]
+        errs[c, s, q] = (np.linalg.norm(u - u_ex) / np.linalg.norm(u_ex), np.linalg.norm(b - b_ex) / np.linalg.norm(b_ex))
+    for key in sorted(errs, key=lambda k: (k[2], k[1], k[0])):
+        print("c_w=%g scheme=%s d=%g  u %.2e  B1 %.2e" % (key[0], key[1], key[2], *errs[key]), flush=True)
+    for c in C_W:
+        assert max(errs[c, "M", 1.0]) < 4e-3 and max(errs[c, "M", 0.5]) < 2e-3, (c, errs[c, "M", 1.0])
+    assert errs[0.1, "X", 1.0][0] > 10 * errs[0.1, "M", 1.0][0]
+    ex = [errs[c, "X", 1.0][0] for c in C_W]
+    assert all(a > b for a, b in zip(ex, ex[1:])), ex
+    assert np.allclose(errs[1e4, "X", 1.0], errs[1e4, "M", 1.0], rtol=1e-2)
+    for c in C_W[:3]:
+        assert np.allclose(errs[c, "theta", 1.0], errs[c, "X", 1.0], rtol=0.1)

@@ -76,6 +76,9 @@ SCENES = {
     "channel_half": lambda: scenes.channel_reservoirs("half", width=4, res_len=3, ch_len=6),
     "channel_full": lambda: scenes.channel_reservoirs("full", width=4, res_len=3, ch_len=6),
     "box_offgrid": lambda: _offgrid_box(),
+    "hartmann_X": lambda: scenes.hartmann_couette(nx=3, ny=7, c_top=0.1, qb=1.0, qt=1.0, top_scheme="X"),
+    "hartmann_theta": lambda: scenes.hartmann_couette(nx=3, ny=7, c_top=0.1, qb=1.0, qt=1.0, top_scheme="theta"),
+    "open_box_alt": lambda: scenes.open_box(nx=6, ny=3, q_in=0.52, q_out=0.7, alt_in=True, alt_out=True),
 }
 
 
@@ -110,6 +113,7 @@ def compare_link_tables(sc):
             assert int(r["enode"]) == int(o_["E"])
         assert bool(r["flags"] & 1) == bool(o_["u_given"])
         assert bool(r["flags"] & 4) == (o_["omega"] != 0.0)
+        assert bool(r["flags"] & 8) == bool(o_["compare"])
         for fld in ("value", "a1", "a3"):
             assert r[fld] == o_[fld]
         assert abs(r["weight"] - o_["weight"]) < 1e-12 * max(1.0, abs(o_["weight"]))
@@ -266,6 +270,32 @@ def test_box_distances_and_validation():
     bad = scenes.Boundary("box", axis=2, lo=(1.0, 0.0, 0.0), hi=(0.0, 1.0, 1.0), f=scenes.BC(scenes.VEL))
     with pytest.raises(L.LbmError):
         lbm.build_links(sc.with_(boundaries=sc.boundaries + [bad]))
+
+
+def test_comparison_forms_validation():
+    """the comparison flag only exists for VEL, PRES, FLUX and MAG_FLUX;
+    theta must not be negative"""
+    sc = scenes.hartmann_couette(nx=3, ny=7, c_top=0.0)
+    sc.boundaries[1].g[0] = scenes.BC(scenes.MAG_DIR, value=0.0, alt=True)
+    with pytest.raises(L.LbmError):
+        lbm.build_links(sc)
+    _, ll = lbm.build_links(scenes.hartmann_couette(nx=3, ny=7, c_top=0.1, top_scheme="X"))
+    assert np.any(ll["flags"] & 8)
+    sc = scenes.hartmann_couette(nx=3, ny=7, c_top=0.1, top_scheme="theta")
+    mask, ll = lbm.build_links(sc)
+    fc = _FakeCtx(sc, len(ll))
+    assert L.lib().lbm_set_geometry(fc.ctx, mask.ctypes.data_as(C.c_void_p)) == 0
+    assert fc.set_links(ll) != -1  # passes validation (no device here to upload to)
+    th = ll.copy()
+    th["a1"][th["kind"] == lbm.KINDS["MAG_THETA"]] = -1.0
+    assert fc.set_links(th) == -1 and "theta" in fc.err()
+    bad = ll.copy()
+    i = int(np.nonzero(bad["kind"] == lbm.KINDS["MAG_DIR"])[0][0])
+    bad["flags"][i] |= 8
+    assert fc.set_links(bad) == -1 and "flag bit 3" in fc.err()
+    bad = ll.copy()
+    bad["flags"][0] |= 16
+    assert fc.set_links(bad) == -1 and "unknown flag" in fc.err()
 
 
 def test_builder_rejects_uncovered_boundary():

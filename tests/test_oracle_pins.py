@@ -786,3 +786,111 @@ def test_duct_series_solves_the_poisson_problem():
     X, Y = np.meshgrid(x[1:-1], y[1:-1], indexing="ij")
     u = an.duct_poiseuille(X, Y, a, b, G, mu)
     assert np.abs(u - u_fd).max() < 1e-4 * u.max()
+
+
+# ---------------------------------------------------------------------------
+# comparison schemes of Sections 4.3 and 5 (Eqs. 33, 39-40; extrapolated
+# velocity and pressure forms at large d)
+# ---------------------------------------------------------------------------
+def test_comparison_link_forms():
+    """Eq. 33 is the flux added at X: (x_a + x_ap + flux + move)/2 at d = 1,
+    the M scheme itself at d = 0.5.  The theta form of Eq. 39 gives the
+    conducting wall (Eq. 36) as theta -> inf and the insulating one (Eq. 37)
+    at theta = 0; Eq. 40 is its d = 1 interpolation.  The extrapolated
+    velocity and pressure forms equal the method's below d = 0.5 and are
+    Eq. 15 and the pressure pair form with Y of Eq. 16 above it."""
+    rng = np.random.default_rng(11)
+    e, w, c2, opp = oracle.lattice_table("D2Q5")
+    U1 = 0.01
+    for a in range(1, 5):
+        x = _rand_inputs(rng)
+        BA, BE = np.array([0.003, 0.02, 0.0]), np.array([0.002, 0.02, 0.0])
+        mA, mE = [1, 0, 0, 0, 0, *BA], [1, 0, 0, 0, 0, *BE]
+        kw = dict(lattice="D2Q5", dir=a, comp_axis=0, u_w=(U1, 0, 0), mA=mA, mE=mE, **x)
+        # Eq. 33 at d = 1
+        a1 = -0.05
+        v = oracle.link_eval(kind="MAG_FLUX", d=1.0, a1=a1, compare=True, **kw)
+        BX = 2.0 * BA - BE
+        dmove = 2 * w[a] * ((e[a] @ np.array([U1, 0, 0])) * BX[0] - (e[a] @ BX) * U1) / c2
+        assert np.isclose(v, 0.5 * (x["x_a_A"] + x["x_ap_A"] + a1 * BX[0] + dmove), rtol=1e-13)
+        m05 = oracle.link_eval(kind="MAG_FLUX", d=0.5, a1=a1, **kw)
+        assert np.isclose(oracle.link_eval(kind="MAG_FLUX", d=0.5, a1=a1, compare=True, **kw), m05, rtol=1e-14)
+        # theta form (Eqs. 39-40)
+        cond = oracle.link_eval(kind="MAG_FLUX", d=0.5, a1=0.0, **kw)
+        assert np.isclose(oracle.link_eval(kind="MAG_THETA", d=0.5, a1=1e12, **kw), cond, rtol=1e-10)
+        assert np.isclose(oracle.link_eval(kind="MAG_THETA", d=0.5, a1=0.0, **kw), -x["x_ap_A"], rtol=1e-14)
+        th = 3.7
+        BX5 = 1.5 * BA - 0.5 * BE
+        dm5 = 2 * w[a] * ((e[a] @ np.array([U1, 0, 0])) * BX5[0] - (e[a] @ BX5) * U1) / c2
+        ref39 = ((th - 1) * x["x_ap_A"] + th * dm5) / (th + 1)
+        assert np.isclose(oracle.link_eval(kind="MAG_THETA", d=0.5, a1=th, **kw), ref39, rtol=1e-13)
+        ref40 = 0.5 * (x["x_a_A"] + ((th - 1) * x["x_ap_A"] + th * dmove) / (th + 1))
+        assert np.isclose(oracle.link_eval(kind="MAG_THETA", d=1.0, a1=th, **kw), ref40, rtol=1e-13)
+    # extrapolated velocity / pressure forms
+    x = dict(x_ap_E=0.31, x_ap_A=0.27, x_a_A=0.12)
+    for kind in ("VEL", "PRES"):
+        extra = dict(value=1.001) if kind == "PRES" else dict(u_w=(0.01, 0, 0))
+        for d in (0.2, 0.45):
+            assert oracle.link_eval(kind=kind, dir=1, d=d, compare=True, **x, **extra) == \
+                oracle.link_eval(kind=kind, dir=1, d=d, **x, **extra)
+        d = 0.8
+        Y = (1 - 2 * d) * x["x_ap_E"] + 2 * d * x["x_ap_A"]
+        v = oracle.link_eval(kind=kind, dir=1, d=d, compare=True, **x, **extra)
+        # the wall terms do not depend on the populations: v = +-Y + terms
+        terms = oracle.link_eval(kind=kind, dir=1, d=d, compare=True, x_ap_E=0.0, x_ap_A=0.0, x_a_A=0.0,
+                                 **extra)
+        assert np.isclose(v, (Y if kind == "VEL" else -Y) + terms, rtol=1e-13)
+        assert not np.isclose(v, oracle.link_eval(kind=kind, dir=1, d=d, **x, **extra))
+
+
+def _hartmann_d1_error(c, scheme, ny=48):
+    sc = scenes.hartmann_couette(nx=1, ny=ny, Ha=5.0, c_top=c, u_top=1e-3, v0=0.0, qb=1.0, qt=1.0,
+                                 storage="f64", top_scheme=scheme)
+    H, B0 = sc.meta["H"], sc.meta["B0"]
+    o = oracle.OracleSim(sc)
+    o.step(int(8 * H * H / 0.1))
+    m = o.moments()
+    y = np.arange(ny) - (ny - 1) / 2
+    u_ex, b_ex = an.hartmann_couette(y, H, B0, 0.1, 0.1, U_top=1e-3, c_top=c)
+    return (np.linalg.norm(m[0, :, 0, 1] - u_ex) / np.linalg.norm(u_ex),
+            np.linalg.norm(m[0, :, 0, 5] - b_ex) / np.linalg.norm(b_ex))
+
+
+def test_flux_at_the_wall_errs_at_small_conductance():
+    """Section 5.4 (full-grid layout, d = 1): the M scheme matches the closed
+    form at every c_w; adding the flux at the wall (Eq. 33) errs where the
+    flux matters, at small c_w, and the error vanishes as c_w grows; the
+    theta form (Eq. 40) behaves like Eq. 33."""
+    errs = {}
+    for c in (0.1, 1.0, 1e4):
+        for s in ("M", "X", "theta"):
+            errs[c, s] = _hartmann_d1_error(c, s)
+    for c in (0.1, 1.0, 1e4):
+        assert errs[c, "M"][0] < 5e-3 and errs[c, "M"][1] < 1.5e-2, errs[c, "M"]
+    assert errs[0.1, "X"][0] > 10 * errs[0.1, "M"][0]
+    assert errs[0.1, "X"][0] > errs[1.0, "X"][0] > errs[1e4, "X"][0]
+    assert np.allclose(errs[1e4, "X"], errs[1e4, "M"], rtol=1e-2)
+    for c in (0.1, 1.0):
+        assert np.allclose(errs[c, "theta"], errs[c, "X"], rtol=0.05), (errs[c, "theta"], errs[c, "X"])
+
+
+def _stays_bounded(sc, steps):
+    o = oracle.OracleSim(sc)
+    for _ in range(steps // 500):
+        o.step(500)
+        m = o.moments()
+        if not np.all(np.isfinite(m)) or np.abs(m[..., 1]).max() > 1.0:
+            return False
+    return True
+
+
+def test_extrapolated_forms_lose_stability_at_large_d():
+    """Section 5.1: the extrapolated velocity and pressure forms become
+    unstable at large d, which is why the method switches to Eqs. 43-44 for
+    d >= 0.5.  The pressure form holds to d = 0.7 and fails from about 0.8
+    (tau = 0.7); the velocity form fails just above 0.5.  Eqs. 43-44 hold at
+    d = 1."""
+    assert _stays_bounded(scenes.open_box(q_out=0.7, alt_out=True), 10000)
+    assert not _stays_bounded(scenes.open_box(q_out=0.9, alt_out=True), 10000)
+    assert not _stays_bounded(scenes.open_box(q_in=0.6, alt_in=True), 2000)
+    assert _stays_bounded(scenes.open_box(q_in=1.0, q_out=1.0), 10000)
