@@ -87,7 +87,10 @@ typedef struct {
     int32_t periodic[3];  /* 1 = periodic axis (2D: periodic[2] must be 1) */
     int32_t fluid;        /* LBM_D2Q9 (2D) or LBM_D3Q19 (3D) */
     int32_t scalar;       /* LBM_NONE, LBM_D2Q5 (2D) or LBM_D3Q7 (3D) */
-    int32_t magnetic;     /* LBM_NONE, LBM_D2Q5 (2D) or LBM_D3Q7 (3D) */
+    int32_t magnetic;     /* LBM_NONE, LBM_D2Q5 (2D), LBM_D3Q7 (3D), or LBM_D3Q19 (3D, one
+                             component, no scalar lattice, c_g^2 = 1/3: the richer magnetic
+                             lattice Section 6.1 suggests for conducting walls; its links
+                             may be MAG_DIR, BB0 or zero-flux MAG_FLUX only) */
     int32_t mag_ncomp;    /* evolved B components: 0 (no magnetic lattice), 1..3 */
     int32_t mag_comp[3];  /* Cartesian axis (0..2) of each evolved component */
     int32_t storage;      /* lbm_storage */

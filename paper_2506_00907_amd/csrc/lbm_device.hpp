@@ -455,7 +455,10 @@ __device__ __forceinline__ typename C::R link_update(const Geo& G, const Phys<ty
     if (L.field == 0) {
         w = (R)(C::QF == 9 ? (e2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0) : (e2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0));
         c2 = (R)(1.0 / 3.0);
-    } else {
+    } else if (L.field == 2 && C::QG == 19) {  // D3Q19 magnetic lattice
+        w = (R)(e2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+        c2 = (R)(1.0 / 3.0);
+    } else {  // D2Q5 / D3Q7
         w = (R)0.125;
         c2 = (R)0.25;
     }
@@ -741,7 +744,7 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
             const R ex = (R)GL::ex(a), ey = (R)GL::ey(a), ez = (R)GL::ez(a);
             const R w = (R)GL::w(a);
             const R s = (ex * ux + ey * uy + ez * uz) * Bk - (ex * B[0] + ey * B[1] + ez * B[2]) * uk;
-            const R ev = w * dB[c], od = (R)4 * w * s;
+            const R ev = w * dB[c], od = (R)(1.0 / GL::c2) * w * s;
             const R xa = x_[p0 + a], xb = x_[p0 + b];
             x_[p0 + a] = xa + omm * (ev + od - xa);
             x_[p0 + b] = xb + omm * (ev - od - xb);
@@ -1019,7 +1022,7 @@ __global__ __launch_bounds__(256) void k_init(Geo G, Phys<typename C::R> P, type
         for (int i = 0; i < C::QG; ++i) {
             const R ex = (R)GL::ex(i), ey = (R)GL::ey(i), ez = (R)GL::ez(i);
             const R s = (ex * u[0] + ey * u[1] + ez * u[2]) * B[c] - (ex * B[0] + ey * B[1] + ez * B[2]) * uk;
-            const R v = (R)GL::w(i) * (dB[c] + s * (R)4);
+            const R v = (R)GL::w(i) * (dB[c] + s * (R)(1.0 / GL::c2));
             st<typename C::S>(S + (size_t)(C::G0 + c * C::QG + i) * PL, (uint32_t)n, C::SCALED ? v * P.sc[2] : v);
         }
     }
@@ -1218,7 +1221,7 @@ inline Geo make_geo(const KArgs& a) {
 template <class C>
 struct Launch {
     using R = typename C::R;
-    static double cg2() { return C::QG ? 0.25 : 1.0; }
+    static double cg2() { return C::QG == 19 ? 1.0 / 3.0 : (C::QG ? 0.25 : 1.0); }
     // Few links (a 2D channel's few thousand): 64 threads per block, so they
     // spread over four times as many CUs (3.1 -> 2.8 us per launch on the
     // 512 x 256 reactive channel).  Millions of links: 256 (with 64, the
@@ -1440,6 +1443,7 @@ KernelSet select_kernels(int fl, int sl, int ml, int nc) {
     LBM_CASE(2, 0, 4, 3)
     LBM_CASE(2, 4, 4, 1)
     LBM_CASE(2, 4, 4, 3)
+    LBM_CASE(2, 0, 2, 1)
 #undef LBM_CASE
     return KernelSet{};
 }

@@ -75,7 +75,10 @@ bool valid_params(const lbm_params* p, std::string* why) {
     } else {
         if (p->fluid != LBM_D3Q19) return fail("3D flow lattice must be D3Q19");
         if (p->scalar != LBM_NONE && p->scalar != LBM_D3Q7) return fail("3D scalar lattice must be D3Q7");
-        if (p->magnetic != LBM_NONE && p->magnetic != LBM_D3Q7) return fail("3D magnetic lattice must be D3Q7");
+        if (p->magnetic != LBM_NONE && p->magnetic != LBM_D3Q7 && p->magnetic != LBM_D3Q19)
+            return fail("3D magnetic lattice must be D3Q7 or D3Q19");
+        if (p->magnetic == LBM_D3Q19 && (p->scalar || p->mag_ncomp != 1))
+            return fail("a D3Q19 magnetic lattice: one component, no scalar lattice");
         if (p->magnetic && p->mag_ncomp != 1 && p->mag_ncomp != 3) return fail("3D magnetic components: 1 or 3");
     }
     if (!p->magnetic && p->mag_ncomp != 0) return fail("mag_ncomp must be 0 without a magnetic lattice");
@@ -713,6 +716,12 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
                                k.kind == LBM_LK_MAG_FLUX))
             return bad("flag bit 3 (comparison form) needs kind VEL, PRES, FLUX or MAG_FLUX");
         if (k.kind == LBM_LK_MAG_THETA && !(k.a1 >= 0.0)) return bad("theta (a1) must be >= 0");
+        // the flux split over a wall node's links (weight) is derived for one
+        // crossing link per flat-wall node (D2Q5 / D3Q7): a D3Q19 magnetic
+        // lattice takes given-B and zero-flux walls only
+        if (k.field == 2 && p.magnetic == LBM_D3Q19 &&
+            (k.kind == LBM_LK_MAG_THETA || (k.kind == LBM_LK_MAG_FLUX && (k.a1 != 0.0 || k.a3 != 0.0))))
+            return bad("a D3Q19 magnetic lattice takes MAG_DIR, BB0 and zero-flux MAG_FLUX links only");
         if ((k.flags & 4) && !(k.flags & 1)) return bad("an oscillating boundary velocity needs flag bit 0 (u_w given)");
         if (!std::isfinite(k.value) || !std::isfinite(k.a1) || !std::isfinite(k.a3) || !std::isfinite(k.weight))
             return bad("non-finite wall data");
@@ -1083,7 +1092,8 @@ lbm_status lbm_read_normalised(lbm_ctx* c, int32_t axis, double U, double* dev_o
     }
     // B* = B / (U mu sqrt(rho0 nu sigma)), sigma = 1 / (mu eta): sqrt(rho0 nu mu / eta)
     const double nu = (c->p.tau_f - 0.5) / 3.0;
-    const double eta = c->p.magnetic ? (c->p.tau_m - 0.5) / 4.0 : 1.0;
+    const double cg2 = c->p.magnetic == LBM_D3Q19 ? 1.0 / 3.0 : 0.25;
+    const double eta = c->p.magnetic ? cg2 * (c->p.tau_m - 0.5) : 1.0;
     const double mu = c->p.magnetic ? c->p.mu : 1.0;
     a.norm_u = U;
     a.norm_b = std::sqrt(c->p.rho0 * nu * mu / eta);

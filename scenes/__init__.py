@@ -364,14 +364,18 @@ def hartmann_couette(nx: int = 1024, ny: int = 512, Ha: float = 5.0, c_top: floa
 def mhd_pipe(nx: int = 64, side: int = 128, R: float = 60.0, wall: str = "insulating",
              c_w: float = 0.05, Ha: float = 10.0, g: float = 1e-6, tau_f: float = 0.8,
              tau_m: float = 0.9, storage: str = "f32", steps: int = 2000,
-             ncomp: int = 1) -> Scene:
+             ncomp: int = 1, mag_lattice: str = D3Q7) -> Scene:
     """Pipe along x (periodic), circular cross-section in (y, z), B_ext along y.
 
     ``wall``: "insulating" (given B1 = 0), "conducting" (zero flux) or
     "shercliff" (F(B1) = -eta B1/(c_w R)).  With ``ncomp`` = 3 the transverse
     components are also evolved with given-B walls (B2 = B0, B3 = 0).
+    ``mag_lattice`` D3Q19 solves B1 on the 19-velocity lattice (c_g^2 = 1/3,
+    eta = (tau_m - 1/2)/3), the option Section 6.1 suggests for conducting
+    walls.
     """
-    nu, eta, rho, mu = _nu(tau_f), _diff(tau_m), 1.0, 1.0
+    nu, rho, mu = _nu(tau_f), 1.0, 1.0
+    eta = _nu(tau_m) if mag_lattice == D3Q19 else _diff(tau_m)
     B0 = hartmann_B0(Ha, R, rho, nu, eta, mu)
     c = (side - 1) / 2.0
     if wall == "insulating":
@@ -386,7 +390,7 @@ def mhd_pipe(nx: int = 64, side: int = 128, R: float = 60.0, wall: str = "insula
     cyl = Boundary("cylinder", axis=0, center=(0.0, c, c), radius=R, f=BC(VEL), g=gbc)
     comps = (0,) if ncomp == 1 else (0, 1, 2)
     sc = Scene(name=f"pipe_{nx}x{side}x{side}_{wall}", dim=3, n=(nx, side, side),
-               periodic=(True, False, False), fluid_lattice=D3Q19, mag_lattice=D3Q7,
+               periodic=(True, False, False), fluid_lattice=D3Q19, mag_lattice=mag_lattice,
                mag_comps=comps, tau_f=tau_f, tau_m=tau_m, rho0=rho, mu=mu,
                B_ext=(0.0, B0, 0.0), accel=(g, 0.0, 0.0), boundaries=[cyl], storage=storage,
                store_scale=(1024.0, 1.0, 1024.0), steps=steps)

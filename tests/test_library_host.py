@@ -79,6 +79,7 @@ SCENES = {
     "hartmann_X": lambda: scenes.hartmann_couette(nx=3, ny=7, c_top=0.1, qb=1.0, qt=1.0, top_scheme="X"),
     "hartmann_theta": lambda: scenes.hartmann_couette(nx=3, ny=7, c_top=0.1, qb=1.0, qt=1.0, top_scheme="theta"),
     "open_box_alt": lambda: scenes.open_box(nx=6, ny=3, q_in=0.52, q_out=0.7, alt_in=True, alt_out=True),
+    "pipe_conducting_q19": lambda: scenes.mhd_pipe(nx=2, side=17, R=6.3, wall="conducting", mag_lattice="D3Q19"),
 }
 
 
@@ -296,6 +297,21 @@ def test_comparison_forms_validation():
     bad = ll.copy()
     bad["flags"][0] |= 16
     assert fc.set_links(bad) == -1 and "unknown flag" in fc.err()
+
+
+def test_d3q19_magnetic_lattice_takes_no_wall_flux():
+    """given-B and zero-flux walls only on a D3Q19 magnetic lattice"""
+    for wall, ok in (("conducting", True), ("insulating", True), ("shercliff", False)):
+        sc = scenes.mhd_pipe(nx=1, side=17, R=6.3, wall=wall, mag_lattice="D3Q19")
+        mask, ll = lbm.build_links(sc)
+        fc = _FakeCtx(sc, len(ll))
+        assert L.lib().lbm_set_geometry(fc.ctx, mask.ctypes.data_as(C.c_void_p)) == 0
+        code = fc.set_links(ll)
+        assert (code != -1) == ok, (wall, code, fc.err())
+    p = lbm.params_from_scene(scenes.mhd_pipe(nx=1, side=17, R=6.3, mag_lattice="D3Q19"))
+    p.mag_ncomp = 3
+    with pytest.raises(L.LbmError):
+        lbm.required_bytes(p, 10)
 
 
 def test_builder_rejects_uncovered_boundary():
