@@ -89,8 +89,8 @@ typedef struct {
     int32_t scalar;       /* LBM_NONE, LBM_D2Q5 (2D) or LBM_D3Q7 (3D) */
     int32_t magnetic;     /* LBM_NONE, LBM_D2Q5 (2D), LBM_D3Q7 (3D), or LBM_D3Q19 (3D, one
                              component, no scalar lattice, c_g^2 = 1/3: the richer magnetic
-                             lattice Section 6.1 suggests for conducting walls; its links
-                             may be MAG_DIR, BB0 or zero-flux MAG_FLUX only) */
+                             lattice Section 6.1 suggests for conducting walls; every link
+                             kind but LBM_LK_MAG_THETA) */
     int32_t mag_ncomp;    /* evolved B components: 0 (no magnetic lattice), 1..3 */
     int32_t mag_comp[3];  /* Cartesian axis (0..2) of each evolved component */
     int32_t storage;      /* lbm_storage */
@@ -131,7 +131,9 @@ typedef struct {
     double d;        /* boundary-to-node distance |AX| / |AE| in (0, 1] */
     double value;    /* PRES: rho_w; CONC: C_w; MAG_DIR: B_k */
     double a1, a3;   /* FLUX / MAG_FLUX: F(phi) = a1 phi_X - a3 (lattice units) */
-    double weight;   /* flux share of this link: 1 on flat walls, S_i e.n / sum e.n on curved walls (Eq. 48) */
+    double weight;   /* flux share of this link (Eq. 48): on flat walls 1 / (links crossing the wall per
+                        node: 1 on D2Q5 / D3Q7, 5 on D3Q19); on curved walls S_i e.n / sum e.n over
+                        the links of the outer-layer node B_i */
     double u_w[3];   /* boundary velocity */
 } lbm_link;
 

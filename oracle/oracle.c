@@ -408,7 +408,9 @@ static double split_weight(const or_scene* s, const or_boundary* b, const or_lat
     double sum = 0.0, best = -1e300;
     int best_a = -1;
     for (int g = 1; g < L->Q; ++g) {
-        if (L->e[g][b->axis] != 0) continue;
+        /* all links of B_i across the wall: directions with an in-plane part
+         * (on D3Q19 also those with an axial component) */
+        if (L->e[g][p] == 0 && L->e[g][q] == 0) continue;
         int cc[3] = {Bc[0] + L->e[g][0], Bc[1] + L->e[g][1], Bc[2] + L->e[g][2]};
         cc[b->axis] = 0;
         if (cc[p] < 0 || cc[p] >= np || cc[q] < 0 || cc[q] >= nq) continue;
@@ -519,7 +521,15 @@ static int build_field_links(or_sim* S, int field, const or_lattice* L, int ncom
                         for (int j = 0; j < 3; ++j) lk->u_w[j] = b->u_w[j];
                         lk->omega = b->omega;
                         lk->compare = bc->alt;
+                        /* Eq. 48 on a flat face: the node's share is spread evenly
+                         * over its links through the face, as many as the lattice
+                         * directions with component +1 along an axis */
                         lk->weight = 1.0;
+                        if (bc->kind == K_FLUX || bc->kind == K_MAG_FLUX) {
+                            int through = 0;
+                            for (int g = 0; g < L->Q; ++g) through += L->e[g][0] == 1;
+                            lk->weight = 1.0 / through;
+                        }
                         if (b->type == 1 && (bc->kind == K_FLUX || bc->kind == K_MAG_FLUX)) {
                             if (!seg[best]) {
                                 int no;

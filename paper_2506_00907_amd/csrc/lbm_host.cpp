@@ -27,6 +27,7 @@ struct HostLat {
     double w[19] = {};
     double c2 = 1.0;
     int opp[19] = {};
+    int cross = 1;  // directions crossing a flat face from one side (1 on D2Q5 / D3Q7, 5 on D3Q19)
 };
 
 template <class L>
@@ -41,6 +42,8 @@ HostLat host_lat() {
         h.w[a] = L::w(a);
         h.opp[a] = L::opp(a);
     }
+    h.cross = 0;
+    for (int a = 0; a < L::Q; ++a) h.cross += L::ex(a) == 1 ? 1 : 0;
     return h;
 }
 
@@ -228,9 +231,11 @@ class LinkBuilder {
                                     lk.a1 = bc.a1_profile[pos];
                                 }
                                 lk.a3 = bc.a3;
-                                lk.weight = 1.0;
                                 for (int k = 0; k < 3; ++k) lk.u_w[k] = bd.u_w[k];
                                 const bool flux = bc.kind == LBM_LK_FLUX || bc.kind == LBM_LK_MAG_FLUX;
+                                // flat faces: a node's flux split evenly over the
+                                // links crossing the face (one on D2Q5 / D3Q7)
+                                lk.weight = flux ? 1.0 / L.cross : 1.0;
                                 if (bd.type == 1 && flux) {
                                     if (segs[best.bnd].empty()) segs[best.bnd] = segments(bd, L);
                                     lk.weight = split(bd, L, segs[best.bnd], raw, a);
@@ -381,7 +386,9 @@ class LinkBuilder {
         double total = 0.0, top = -1e300;
         int arg = -1;
         for (int g = 1; g < L.Q; ++g) {
-            if (L.e[g][c.axis] != 0) continue;
+            // every direction with an in-plane part (D3Q19: also those with an
+            // axial component); the axial directions never cross the wall
+            if (L.e[g][u] == 0 && L.e[g][v] == 0) continue;
             int s[3] = {B[0] + L.e[g][0], B[1] + L.e[g][1], B[2] + L.e[g][2]};
             s[c.axis] = 0;
             if (s[u] < 0 || s[u] >= nu || s[v] < 0 || s[v] >= nv || !inside(c, s)) continue;
@@ -716,12 +723,9 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
                                k.kind == LBM_LK_MAG_FLUX))
             return bad("flag bit 3 (comparison form) needs kind VEL, PRES, FLUX or MAG_FLUX");
         if (k.kind == LBM_LK_MAG_THETA && !(k.a1 >= 0.0)) return bad("theta (a1) must be >= 0");
-        // the flux split over a wall node's links (weight) is derived for one
-        // crossing link per flat-wall node (D2Q5 / D3Q7): a D3Q19 magnetic
-        // lattice takes given-B and zero-flux walls only
-        if (k.field == 2 && p.magnetic == LBM_D3Q19 &&
-            (k.kind == LBM_LK_MAG_THETA || (k.kind == LBM_LK_MAG_FLUX && (k.a1 != 0.0 || k.a3 != 0.0))))
-            return bad("a D3Q19 magnetic lattice takes MAG_DIR, BB0 and zero-flux MAG_FLUX links only");
+        // the theta form assumes one crossing link per wall node (D2Q5 / D3Q7)
+        if (k.field == 2 && p.magnetic == LBM_D3Q19 && k.kind == LBM_LK_MAG_THETA)
+            return bad("the theta form needs a D2Q5 or D3Q7 magnetic lattice");
         if ((k.flags & 4) && !(k.flags & 1)) return bad("an oscillating boundary velocity needs flag bit 0 (u_w given)");
         if (!std::isfinite(k.value) || !std::isfinite(k.a1) || !std::isfinite(k.a3) || !std::isfinite(k.weight))
             return bad("non-finite wall data");

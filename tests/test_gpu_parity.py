@@ -77,6 +77,8 @@ FP64_CASES = {
     # B1 on the D3Q19 lattice (conducting wall)
     "pipe_conducting_q19": lambda: scenes.mhd_pipe(nx=2, side=21, R=8.1, wall="conducting", tau_m=0.8,
                                                    mag_lattice="D3Q19", storage="f64"),
+    "pipe_shercliff_q19": lambda: scenes.mhd_pipe(nx=2, side=23, R=9.37, wall="shercliff", tau_m=0.8,
+                                                  mag_lattice="D3Q19", storage="f64"),
 }
 
 
@@ -119,7 +121,7 @@ def test_fp64_parity(key):
 @pytest.mark.parametrize("key", ["reactive", "hartmann_c01", "hartmann_cinf", "pipe_shercliff", "pipe_insulating3",
                                  "diffreact_full", "pipe_item", "periodic_box", "stokes_d03",
                                  "stokes_3d", "channel_half", "channel_full", "hartmann_X", "hartmann_theta",
-                                 "open_box_alt", "pipe_conducting_q19"])
+                                 "open_box_alt", "pipe_conducting_q19", "pipe_shercliff_q19"])
 def test_fp32_parity(key):
     """FP32 storage, 128 steps from a developed seeded state."""
     _case("fp32 " + key)

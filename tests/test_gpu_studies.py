@@ -53,15 +53,17 @@ def test_hartmann_couette_schemes_at_paper_resolution():
         assert np.allclose(errs[c, "theta", 1.0], errs[c, "X", 1.0], rtol=0.1)
 
 
-def test_conducting_pipe_magnetic_lattices_at_full_size():
-    """Section 6.1's conducting pipe at R = 60 (Ha = 10): B1 on the D3Q7 and
-    on the D3Q19 lattice (same eta), each run from rest for 5 R^2 / nu steps
-    and compared with the polar finite-difference solution.  The richer
-    lattice the paper suggests for dB1/dn = 0 is at least as accurate."""
+@pytest.mark.parametrize("wall", ["conducting", "shercliff"])
+def test_pipe_magnetic_lattices_at_full_size(wall):
+    """Section 6's pipe at R = 60 (Ha = 10): B1 on the D3Q7 and on the D3Q19
+    lattice (same eta), each run from rest for 5 R^2 / nu steps and compared
+    with the polar finite-difference solution.  For the conducting wall
+    (dB1/dn = 0) the richer lattice the paper suggests is at least as
+    accurate; the Shercliff wall (c_w = 0.05) is reported."""
     R, side, g = 60.0, 128, 1e-6
     errs = {}
     for lat, tau_m in (("D3Q7", 0.9), ("D3Q19", 0.8)):
-        sc = scenes.mhd_pipe(nx=1, side=side, R=R, wall="conducting", Ha=10.0, g=g, tau_m=tau_m,
+        sc = scenes.mhd_pipe(nx=1, side=side, R=R, wall=wall, c_w=0.05, Ha=10.0, g=g, tau_m=tau_m,
                              mag_lattice=lat, storage="f64")
         assert abs(sc.meta["eta"] - 0.1) < 1e-12
         lat_ = lbm.Lattice(sc)
@@ -69,13 +71,15 @@ def test_conducting_pipe_magnetic_lattices_at_full_size():
         m = lat_.read_moments("f64").cpu().numpy()
         mask = lat_.mask.reshape(sc.n[2], sc.n[1], sc.n[0])[:, :, 0] == 1
         u, b = m[1, :, :, 0], m[5, :, :, 0]
-        rg, tg, U, Bf = an.pipe_mhd_polar(R, sc.meta["B0"], 0.1, 0.1, g, "conducting", nr=96, nt=256)
+        rg, tg, U, Bf = an.pipe_mhd_polar(R, sc.meta["B0"], 0.1, 0.1, g, wall, c_w=0.05, nr=96, nt=256)
         c = (side - 1) / 2
         Y, Z = np.meshgrid(np.arange(side) - c, np.arange(side) - c, indexing="xy")
         uex, bex = an.polar_sample(rg, tg, U, Y, Z), an.polar_sample(rg, tg, Bf, Y, Z)
-        b, bex = b - b[mask].mean(), bex - bex[mask].mean()
+        if wall == "conducting":  # B1 is fixed only up to a constant
+            b, bex = b - b[mask].mean(), bex - bex[mask].mean()
         errs[lat] = (np.linalg.norm((u - uex)[mask]) / np.linalg.norm(uex[mask]),
                      np.linalg.norm((b - bex)[mask]) / np.linalg.norm(bex[mask]))
-        print("conducting pipe R=60, B on %s: u %.2e  B1 %.2e" % (lat, *errs[lat]), flush=True)
-    assert max(errs["D3Q7"]) < 0.02 and max(errs["D3Q19"]) < 0.02, errs
-    assert errs["D3Q19"][0] <= errs["D3Q7"][0] * 1.05, errs
+        print("%s pipe R=60, B on %s: u %.2e  B1 %.2e" % (wall, lat, *errs[lat]), flush=True)
+    assert max(errs["D3Q7"]) < 0.02 and max(errs["D3Q19"]) < 0.03, errs
+    if wall == "conducting":
+        assert errs["D3Q19"][0] <= errs["D3Q7"][0] * 1.05, errs

@@ -331,6 +331,24 @@ def test_magnetic_linear_profile_exact(qb, qt):
     assert np.abs(o.moments()[0, :, 0, 5] - (0.01 + s * y)).max() < 1e-13
 
 
+@pytest.mark.parametrize("qb,qt", [(0.5, 0.5), (0.25, 1.0)])
+def test_magnetic_linear_profile_exact_d3q19(qb, qt):
+    """The same on a D3Q19 magnetic lattice, where five links cross each
+    wall node and the node's flux is split evenly over them (Eq. 48 on a
+    flat face): still exactly linear for any d."""
+    ny, eta, a1 = 12, (0.8 - 0.5) / 3, -0.02
+    bot = Boundary("plane", axis=2, side=0, q=qb, f=BC("VEL"), g=[BC("MAG_DIR", value=0.01)])
+    top = Boundary("plane", axis=2, side=1, q=qt, f=BC("VEL"), g=[BC("MAG_FLUX", a1=a1, a3=0.0)])
+    sc = Scene(name="m1d3", dim=3, n=(1, 1, ny), periodic=(True, True, False), fluid_lattice="D3Q19",
+               mag_lattice="D3Q19", mag_comps=(0,), tau_m=0.8, mu=1e15, boundaries=[bot, top])
+    o = oracle.OracleSim(sc)
+    o.step(60000)
+    y = np.arange(ny) + qb
+    W = ny - 1 + qb + qt
+    s = a1 * 0.01 / (eta - a1 * W)
+    assert np.abs(o.moments()[:, 0, 0, 5] - (0.01 + s * y)).max() < 1e-13
+
+
 # ---------------------------------------------------------------------------
 # Hartmann-Couette flow (Section 5.4): second-order convergence to the closed form
 # ---------------------------------------------------------------------------
@@ -535,6 +553,15 @@ def test_conducting_pipe_on_the_d3q19_magnetic_lattice():
     assert e19[0] < 0.85 * e7[0] and e19[1] < 0.95 * e7[1], (e7, e19)
     e19b = _mhd_pipe_error(16.6, "conducting", mag_lattice="D3Q19")
     assert e19[0] / e19b[0] > 1.6 and e19[1] / e19b[1] > 1.6, (e19, e19b)
+
+
+def test_shercliff_pipe_on_the_d3q19_magnetic_lattice():
+    """A Shercliff wall on the D3Q19 magnetic lattice (Eq. 48 over all links
+    of each outer-layer node): the error falls with R, more slowly than on
+    D3Q7, and stays a few per cent at these sizes."""
+    a = _mhd_pipe_error(10.3, "shercliff", mag_lattice="D3Q19")
+    b = _mhd_pipe_error(16.6, "shercliff", mag_lattice="D3Q19")
+    assert max(b) < 0.04 and a[0] / b[0] > 1.2 and a[1] / b[1] > 1.3, (a, b)
 
 
 @pytest.mark.slow
