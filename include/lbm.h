@@ -67,7 +67,7 @@ typedef enum {
     LBM_LK_VEL = 1,      /* given velocity u_w: Eqs. 15-16 (d < 0.5), Eq. 43 (d >= 0.5) */
     LBM_LK_PRES = 2,     /* given density: zeroth-moment pair (d < 0.5), Eq. 44 (d >= 0.5) */
     LBM_LK_CONC = 3,     /* given concentration: Eqs. 19-20 */
-    LBM_LK_FLUX = 4,     /* scalar flux F(C) = a1 C_X - a3, M scheme: Eqs. 23-27 */
+    LBM_LK_FLUX = 4,     /* scalar flux F(C) = a1 C_X + a2 C_X^2 - a3, M scheme: Eqs. 23-27 */
     LBM_LK_BB0 = 5,      /* zero normal gradient, static: Eqs. 21-22 */
     LBM_LK_MAG_DIR = 6,  /* given magnetic component B_k: Eqs. 34-35 */
     LBM_LK_MAG_FLUX = 7, /* magnetic flux F(B_k) = a1 B_X,k - a3 (Shercliff, Eq. 30), M scheme */
@@ -135,6 +135,9 @@ typedef struct {
                         node: 1 on D2Q5 / D3Q7, 5 on D3Q19); on curved walls S_i e.n / sum e.n over
                         the links of the outer-layer node B_i */
     double u_w[3];   /* boundary velocity */
+    double a2;       /* FLUX / MAG_FLUX: quadratic term of the flux law, F(phi) = a1 phi_X + a2 phi_X^2
+                        - a3, evaluated explicitly from the extrapolated phi_X (Eq. 13; a nonlinear
+                        surface reaction, Section 4.2.2); 0 for the other kinds (else LBM_EINVAL) */
 } lbm_link;
 
 /* Boundary description consumed by lbm_build_links. */
@@ -148,6 +151,7 @@ typedef struct {
     int32_t reserved;
     double value, a1, a3;
     const double* a1_profile; /* host: a1 per coordinate of A along profile_axis, or NULL */
+    double a2;                /* FLUX / MAG_FLUX: quadratic coefficient of F (see lbm_link.a2) */
 } lbm_bc;
 
 typedef struct {

@@ -40,7 +40,7 @@ def build(force: bool = False) -> str:
 class _BC(C.Structure):
     _fields_ = [("kind", C.c_int32), ("u_given", C.c_int32), ("profile_axis", C.c_int32),
                 ("profile_len", C.c_int32), ("alt", C.c_int32), ("value", C.c_double), ("a1", C.c_double),
-                ("a3", C.c_double), ("a1_profile", C.POINTER(C.c_double))]
+                ("a3", C.c_double), ("a1_profile", C.POINTER(C.c_double)), ("a2", C.c_double)]
 
 
 class _Boundary(C.Structure):
@@ -65,7 +65,8 @@ class Link(C.Structure):
                 ("dir", C.c_int32), ("kind", C.c_int32), ("bnd", C.c_int32),
                 ("u_given", C.c_int32), ("d", C.c_double), ("value", C.c_double),
                 ("a1", C.c_double), ("a3", C.c_double), ("weight", C.c_double),
-                ("u_w", C.c_double * 3), ("omega", C.c_double), ("compare", C.c_int32), ("pad", C.c_int32)]
+                ("u_w", C.c_double * 3), ("omega", C.c_double), ("compare", C.c_int32), ("pad", C.c_int32),
+                ("a2", C.c_double)]
 
 
 class LinkIn(C.Structure):
@@ -74,7 +75,7 @@ class LinkIn(C.Structure):
                 ("value", C.c_double), ("a1", C.c_double), ("a3", C.c_double),
                 ("weight", C.c_double), ("u_w", C.c_double * 3), ("x_ap_E", C.c_double),
                 ("x_ap_A", C.c_double), ("x_a_A", C.c_double), ("mA", C.c_double * 8),
-                ("mE", C.c_double * 8), ("compare", C.c_int32)]
+                ("mE", C.c_double * 8), ("compare", C.c_int32), ("a2", C.c_double)]
 
 
 _libs = {}
@@ -160,7 +161,7 @@ def link_eval(**kw) -> float:
     li.u_given = int(kw.get("u_given", True))
     li.compare = int(kw.get("compare", False))
     li.d = kw["d"]
-    for k in ("value", "a1", "a3", "x_ap_E", "x_ap_A", "x_a_A"):
+    for k in ("value", "a1", "a2", "a3", "x_ap_E", "x_ap_A", "x_a_A"):
         setattr(li, k, float(kw.get(k, 0.0)))
     li.weight = float(kw.get("weight", 1.0))
     for i, v in enumerate(kw.get("u_w", (0.0, 0.0, 0.0))):
@@ -221,6 +222,7 @@ class _SceneHolder:
         dst.u_given = int(bc.u_given)
         dst.alt = int(bc.alt)
         dst.value, dst.a1, dst.a3 = bc.value, bc.a1, bc.a3
+        dst.a2 = bc.a2
         dst.profile_axis = bc.profile_axis
         if bc.a1_profile is not None:
             p = np.ascontiguousarray(bc.a1_profile, dtype=np.float64)
@@ -297,7 +299,8 @@ class OracleSim:
         dt = np.dtype([("A", "i4"), ("E", "i4"), ("field", "i4"), ("comp", "i4"), ("dir", "i4"),
                        ("kind", "i4"), ("bnd", "i4"), ("u_given", "i4"), ("d", "f8"),
                        ("value", "f8"), ("a1", "f8"), ("a3", "f8"), ("weight", "f8"),
-                       ("u_w", "f8", 3), ("omega", "f8"), ("compare", "i4"), ("pad", "i4")])
+                       ("u_w", "f8", 3), ("omega", "f8"), ("compare", "i4"), ("pad", "i4"),
+                       ("a2", "f8")])
         assert dt.itemsize == C.sizeof(Link)
         return np.frombuffer(bytes(out), dtype=dt, count=n).copy()
 

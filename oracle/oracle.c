@@ -184,6 +184,7 @@ typedef struct {
     int32_t alt; /* the comparison form of Section 5 (VEL, PRES, FLUX, MAG_FLUX) */
     double value, a1, a3;
     const double* a1_profile;
+    double a2; /* F = a1 phi + a2 phi^2 - a3 */
 } or_bc;
 
 typedef struct {
@@ -226,6 +227,7 @@ typedef struct {
     double omega; /* of the boundary velocity, 0 = steady */
     int32_t compare; /* comparison form of the kind (Section 5) */
     int32_t pad;
+    double a2;       /* quadratic term of the flux law */
 } or_link;
 
 /* ------------------------------------------------------------------------- */
@@ -518,6 +520,7 @@ static int build_field_links(or_sim* S, int field, const or_lattice* L, int ncom
                             lk->a1 = bc->a1_profile[pos];
                         }
                         lk->a3 = bc->a3;
+                        lk->a2 = bc->a2;
                         for (int j = 0; j < 3; ++j) lk->u_w[j] = b->u_w[j];
                         lk->omega = b->omega;
                         lk->compare = bc->alt;
@@ -698,6 +701,7 @@ typedef struct {
     double x_a_A;   /* post-collision, direction alpha, at A */
     double mA[8], mE[8]; /* rho, u(3), C, B(3) at A and E at time t */
     int32_t compare;     /* the comparison form of the kind (Section 5) */
+    double a2;           /* quadratic term of the flux law */
 } or_link_in;
 
 /* Eq. 13: phi(X) = -d phi(E) + (d+1) phi(A) */
@@ -711,6 +715,7 @@ typedef struct {
     real x_ap_E, x_ap_A, x_a_A;
     real mA[8], mE[8];
     int32_t compare;
+    real a2;
 } or_link_in_r;
 
 static real link_eval_r(const or_link_in_r* in) {
@@ -770,7 +775,8 @@ static real link_eval_r(const or_link_in_r* in) {
                 real bounced = ((th - 1) * in->x_ap_A + th * dmove) / (th + 1);
                 return ((2 * d - 1) * in->x_a_A + bounced) / (2 * d);
             }
-            real dflux = (in->a1 * phiX - in->a3) * in->weight;              /* Eq. 23, Eq. 48 */
+            /* Eq. 23 with F(phi_X) = a1 phi_X + a2 phi_X^2 - a3, Eq. 48 */
+            real dflux = (in->a1 * phiX + in->a2 * phiX * phiX - in->a3) * in->weight;
             if (in->compare) { /* Eq. 33: the flux joins the bounced population at X */
                 if (d < (real)0.5) return xY + dflux + dmove;
                 return ((2 * d - 1) * in->x_a_A + in->x_ap_A + dflux + dmove) / (2 * d);
@@ -800,6 +806,7 @@ double or_link_eval(const or_link_in* in) {
     r.x_ap_A = in->x_ap_A;
     r.x_a_A = in->x_a_A;
     r.compare = in->compare;
+    r.a2 = in->a2;
     for (int k = 0; k < 3; ++k) r.u_w[k] = in->u_w[k];
     for (int k = 0; k < 8; ++k) {
         r.mA[k] = in->mA[k];
@@ -826,6 +833,7 @@ static void apply_links(or_sim* S) {
         in.comp_axis = lk->field == 2 ? s->comps[lk->comp] : 0;
         in.u_given = lk->u_given;
         in.compare = lk->compare;
+        in.a2 = lk->a2;
         in.d = lk->d;
         in.value = lk->value;
         in.a1 = lk->a1;

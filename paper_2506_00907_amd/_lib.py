@@ -39,14 +39,14 @@ class lbm_link(C.Structure):
     _fields_ = [("node", C.c_uint32), ("enode", C.c_uint32), ("field", C.c_uint8), ("dir", C.c_uint8),
                 ("kind", C.c_uint8), ("comp", C.c_uint8), ("flags", C.c_uint8), ("pad", C.c_uint8 * 3),
                 ("d", C.c_double), ("value", C.c_double), ("a1", C.c_double), ("a3", C.c_double),
-                ("weight", C.c_double), ("u_w", C.c_double * 3)]
+                ("weight", C.c_double), ("u_w", C.c_double * 3), ("a2", C.c_double)]
 
 
 class lbm_bc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("u_given", C.c_int32), ("profile_axis", C.c_int32),
                 ("profile_len", C.c_int32), ("alt", C.c_int32), ("reserved", C.c_int32),
                 ("value", C.c_double), ("a1", C.c_double),
-                ("a3", C.c_double), ("a1_profile", C.POINTER(C.c_double))]
+                ("a3", C.c_double), ("a1_profile", C.POINTER(C.c_double)), ("a2", C.c_double)]
 
 
 class lbm_boundary(C.Structure):

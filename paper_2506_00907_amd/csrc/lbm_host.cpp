@@ -231,6 +231,7 @@ class LinkBuilder {
                                     lk.a1 = bc.a1_profile[pos];
                                 }
                                 lk.a3 = bc.a3;
+                                lk.a2 = bc.a2;
                                 for (int k = 0; k < 3; ++k) lk.u_w[k] = bd.u_w[k];
                                 const bool flux = bc.kind == LBM_LK_FLUX || bc.kind == LBM_LK_MAG_FLUX;
                                 // flat faces: a node's flux split evenly over the
@@ -551,6 +552,7 @@ void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::
         d.value = (R)(s.value - rest);
         d.a1 = (R)s.a1;
         d.a3 = (R)s.a3;
+        d.a2 = (R)s.a2;
         d.weight = (R)s.weight;
         d.uw0 = (R)s.u_w[0];
         d.uw1 = (R)s.u_w[1];
@@ -727,8 +729,11 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
         if (k.field == 2 && p.magnetic == LBM_D3Q19 && k.kind == LBM_LK_MAG_THETA)
             return bad("the theta form needs a D2Q5 or D3Q7 magnetic lattice");
         if ((k.flags & 4) && !(k.flags & 1)) return bad("an oscillating boundary velocity needs flag bit 0 (u_w given)");
-        if (!std::isfinite(k.value) || !std::isfinite(k.a1) || !std::isfinite(k.a3) || !std::isfinite(k.weight))
+        if (!std::isfinite(k.value) || !std::isfinite(k.a1) || !std::isfinite(k.a3) || !std::isfinite(k.weight) ||
+            !std::isfinite(k.a2))
             return bad("non-finite wall data");
+        if (k.a2 != 0.0 && k.kind != LBM_LK_FLUX && k.kind != LBM_LK_MAG_FLUX)
+            return bad("a2 (quadratic flux term) needs kind FLUX or MAG_FLUX");
         int q[3];
         coords(k.node, q);
         int s[3] = {q[0] - lat.e[k.dir][0], q[1] - lat.e[k.dir][1], q[2] - lat.e[k.dir][2]};

@@ -21,7 +21,7 @@ STORAGES = {"f64": L.LBM_F64, "f32": L.LBM_F32, "f16": L.LBM_F16, "bf16": L.LBM_
 
 LINK_DTYPE = np.dtype([("node", "<u4"), ("enode", "<u4"), ("field", "u1"), ("dir", "u1"), ("kind", "u1"),
                        ("comp", "u1"), ("flags", "u1"), ("pad", "u1", 3), ("d", "<f8"), ("value", "<f8"),
-                       ("a1", "<f8"), ("a3", "<f8"), ("weight", "<f8"), ("u_w", "<f8", 3)])
+                       ("a1", "<f8"), ("a3", "<f8"), ("weight", "<f8"), ("u_w", "<f8", 3), ("a2", "<f8")])
 assert LINK_DTYPE.itemsize == C.sizeof(L.lbm_link)
 
 
@@ -59,6 +59,7 @@ def boundaries_from_scene(sc):
         dst.u_given = int(bc.u_given)
         dst.alt = int(bc.alt)
         dst.value, dst.a1, dst.a3 = bc.value, bc.a1, bc.a3
+        dst.a2 = bc.a2
         dst.profile_axis = bc.profile_axis
         if bc.a1_profile is not None:
             prof = np.ascontiguousarray(bc.a1_profile, dtype=np.float64)

@@ -99,7 +99,8 @@ class BC:
 
     kind   : one of VEL, PRES, CONC, FLUX, BB0, MAG_DIR, MAG_FLUX
     value  : given rho (PRES), C (CONC) or B_k (MAG_DIR)
-    a1, a3 : flux law F(phi) = a1*phi_X - a3 (FLUX, MAG_FLUX), lattice units
+    a1, a3 : flux law F(phi) = a1*phi_X + a2*phi_X**2 - a3 (FLUX, MAG_FLUX), lattice units
+    a2     : quadratic term of that law (a nonlinear surface reaction)
     u_given: the wall velocity is used in the moving-wall terms; False means the
              velocity at the boundary point is extrapolated from the fluid
     a1_profile: optional per-position a1 along ``profile_axis`` (indexed by
@@ -116,6 +117,7 @@ class BC:
     a1_profile: Optional[np.ndarray] = None
     profile_axis: int = 0
     alt: bool = False
+    a2: float = 0.0
 
 
 @dataclass

@@ -79,7 +79,15 @@ FP64_CASES = {
                                                    mag_lattice="D3Q19", storage="f64"),
     "pipe_shercliff_q19": lambda: scenes.mhd_pipe(nx=2, side=23, R=9.37, wall="shercliff", tau_m=0.8,
                                                   mag_lattice="D3Q19", storage="f64"),
+    # second-order surface reaction F = -k C^2 on the walls
+    "reactive_quadratic": lambda: _quadratic(scenes.reactive_channel(nx=33, ny=11, q=0.7, storage="f64")),
 }
+
+
+def _quadratic(sc, k=0.02):
+    for b in sc.boundaries[:2]:
+        b.h = BC("FLUX", a1=-0.001, a2=-k)
+    return sc
 
 
 def _reactive_alt():
@@ -121,7 +129,8 @@ def test_fp64_parity(key):
 @pytest.mark.parametrize("key", ["reactive", "hartmann_c01", "hartmann_cinf", "pipe_shercliff", "pipe_insulating3",
                                  "diffreact_full", "pipe_item", "periodic_box", "stokes_d03",
                                  "stokes_3d", "channel_half", "channel_full", "hartmann_X", "hartmann_theta",
-                                 "open_box_alt", "pipe_conducting_q19", "pipe_shercliff_q19"])
+                                 "open_box_alt", "pipe_conducting_q19", "pipe_shercliff_q19",
+                                 "reactive_quadratic"])
 def test_fp32_parity(key):
     """FP32 storage, 128 steps from a developed seeded state."""
     _case("fp32 " + key)

@@ -80,7 +80,15 @@ SCENES = {
     "hartmann_theta": lambda: scenes.hartmann_couette(nx=3, ny=7, c_top=0.1, qb=1.0, qt=1.0, top_scheme="theta"),
     "open_box_alt": lambda: scenes.open_box(nx=6, ny=3, q_in=0.52, q_out=0.7, alt_in=True, alt_out=True),
     "pipe_conducting_q19": lambda: scenes.mhd_pipe(nx=2, side=17, R=6.3, wall="conducting", mag_lattice="D3Q19"),
+    "reactive_quadratic": lambda: _quadratic_walls(scenes.reactive_channel(nx=9, ny=6, q=0.3)),
 }
+
+
+def _quadratic_walls(sc, k=0.02):
+    """the channel's walls with a second-order surface reaction F = -k C^2"""
+    for b in sc.boundaries[:2]:
+        b.h = scenes.BC(scenes.FLUX, a1=0.0, a2=-k)
+    return sc
 
 
 def _offgrid_box():
@@ -115,7 +123,7 @@ def compare_link_tables(sc):
         assert bool(r["flags"] & 1) == bool(o_["u_given"])
         assert bool(r["flags"] & 4) == (o_["omega"] != 0.0)
         assert bool(r["flags"] & 8) == bool(o_["compare"])
-        for fld in ("value", "a1", "a3"):
+        for fld in ("value", "a1", "a2", "a3"):
             assert r[fld] == o_[fld]
         assert abs(r["weight"] - o_["weight"]) < 1e-12 * max(1.0, abs(o_["weight"]))
         assert np.array_equal(r["u_w"], o_["u_w"])
@@ -321,6 +329,21 @@ def test_d3q19_magnetic_lattice_walls():
     p.mag_ncomp = 3
     with pytest.raises(L.LbmError):
         lbm.required_bytes(p, 10)
+
+
+def test_quadratic_flux_term_validation(small):
+    """a2 is copied to the links of flux walls and rejected elsewhere"""
+    sc, mask, links, fc = small
+    bad = links.copy()
+    i = int(np.nonzero(bad["kind"] == lbm.KINDS["VEL"])[0][0])
+    bad["a2"][i] = 0.1
+    assert fc.set_links(bad) == -1 and "a2" in fc.err()
+    ok = links.copy()
+    ok["a2"][ok["kind"] == lbm.KINDS["FLUX"]] = -0.01
+    assert fc.set_links(ok) != -1
+    bad = links.copy()
+    bad["a2"][0] = float("nan")
+    assert fc.set_links(bad) == -1
 
 
 def test_builder_rejects_uncovered_boundary():
