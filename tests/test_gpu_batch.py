@@ -75,6 +75,41 @@ def test_oscillating_walls_in_a_batch(mode):
 
 
 @pytest.mark.parametrize("mode", [MODES[0], MODES[3]], ids=["tiled", "resident"])
+def test_d3q19_magnetic_items_in_a_batch(mode):
+    """pipes whose B1 lives on the D3Q19 lattice (conducting and Shercliff
+    walls), batched: each equals the same pipe alone"""
+    scs = [scenes.developed(scenes.mhd_pipe(nx=2, side=side, R=R, wall=w, tau_m=0.8, mag_lattice="D3Q19",
+                                            storage="f32"), seed=3000 + i, u_amp=0.005)
+           for i, (side, R, w) in enumerate([(21, 8.1, "conducting"), (25, 10.6, "shercliff")])]
+    B = lbm.Batch(scs)
+    B.configure(*mode)
+    B.step(66)
+    assert_items_equal_alone(B, scs, 66)
+
+
+@pytest.mark.parametrize("mode", [MODES[0], MODES[3]], ids=["tiled", "resident"])
+def test_comparison_and_quadratic_forms_in_a_batch(mode):
+    """items with the comparison link forms, the theta form and a quadratic
+    surface reaction, batched: each equals the same item alone"""
+    def quad(sc):
+        for b in sc.boundaries[:2]:
+            b.h = scenes.BC(scenes.FLUX, a1=-0.001, a2=-0.02)
+        return sc
+    scs = [scenes.hartmann_couette(nx=4, ny=19, c_top=0.1, qb=1.0, qt=1.0, top_scheme="X", storage="f32"),
+           scenes.hartmann_couette(nx=4, ny=23, c_top=0.5, qb=0.6, qt=1.0, top_scheme="theta", storage="f32")]
+    B = lbm.Batch([scenes.developed(sc, seed=4000 + i, u_amp=0.005) for i, sc in enumerate(scs)])
+    B.configure(*mode)
+    B.step(66)
+    assert_items_equal_alone(B, B.scenes, 66)
+    rc = [scenes.developed(quad(scenes.reactive_channel(nx=nx, ny=ny, q=q, storage="f32")), seed=5000 + i,
+                           u_amp=0.005) for i, (nx, ny, q) in enumerate([(33, 12, 0.3), (41, 15, 0.8)])]
+    B = lbm.Batch(rc)
+    B.configure(*mode)
+    B.step(66)
+    assert_items_equal_alone(B, rc, 66)
+
+
+@pytest.mark.parametrize("mode", [MODES[0], MODES[3]], ids=["tiled", "resident"])
 def test_batch_of_2d_channels_equals_alone(mode):
     scs = reactive_items("f32")
     B = lbm.Batch(scs)
