@@ -243,6 +243,8 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", action="store_true", help="add throughput of the other workloads")
+    ap.add_argument("--no-hbm", action="store_true",
+                    help="leave out the sweep of the 32768x512 lattice that streams from HBM")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--batch", type=int, default=0, metavar="N",
@@ -307,6 +309,25 @@ def main():
                      "bytes_per_launch": ab["sweep"], "mean_launch_ms": sweep_ms,
                      "link_kernel": {"bytes_per_launch": ab["links"], "mean_launch_ms": link_ms}},
     }
+    if not args.no_hbm and args.workload != "hartmann_wide":
+        # The 512 x 256 channel (15 MB) stays in the 256 MB Infinity Cache and
+        # is bound by launch latency; the same sweep over a 1.28 GB state
+        # streams from HBM.  Same timing as the main roofline.
+        s2, d2 = make_scene("hartmann_wide", "f32")
+        l2 = lbm.Lattice(s2)
+        a2 = algorithmic_bytes(l2)
+        m2 = time_gpu(l2, 200, 20)
+        lk2, sw2 = time_launches(l2, 50)
+        ach2 = a2["sweep"] / (sw2 / 1e3)
+        out["roofline_hbm"] = {"workload": d2, "storage": "f32", "bound": "hbm", "achieved": ach2 / 1e9,
+                               "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": ach2 / HBM_PEAK,
+                               "traffic": measured_traffic("hartmann_wide", "f32"),
+                               "kernel": "k_step (fused stream-collide sweep), both parities",
+                               "bytes_per_launch": a2["sweep"], "mean_launch_ms": sw2,
+                               "mlups": round(a2["fluid_nodes"] * 200 / (m2 / 1e3) / 1e6, 1),
+                               "link_kernel": {"bytes_per_launch": a2["links"], "mean_launch_ms": lk2}}
+        del l2
+        torch.cuda.empty_cache()
     if args.extra:
         extra = {}
         for w, st in (("reactive", "f16"), ("reactive", "bf16"), ("hartmann", "f32"), ("hartmann", "f16"),
