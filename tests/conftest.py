@@ -4,6 +4,13 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# Under pytest-xdist every worker loads the OpenMP oracle; share the cores
+# among the workers instead of starting one thread per core in each (set
+# before the oracle's OpenMP runtime starts).
+if os.environ.get("PYTEST_XDIST_WORKER") and "OMP_NUM_THREADS" not in os.environ:
+    _workers = max(1, int(os.environ.get("PYTEST_XDIST_WORKER_COUNT", "1")))
+    os.environ["OMP_NUM_THREADS"] = str(max(1, (os.cpu_count() or 1) // _workers))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
