@@ -39,8 +39,8 @@ KERNEL_SOURCES = ("paper_2506_00907_amd/csrc/lbm_device.hpp", "paper_2506_00907_
                   "paper_2506_00907_amd/build.py")
 MEASURED_TRAFFIC = {
     # (workload, storage): (kernel source digest, bytes per launch)
-    ("reactive", "f32"): ("a362b458c4dded53", 15161326.0),
-    ("hartmann_wide", "f32"): ("a362b458c4dded53", 2578994871.0),
+    ("reactive", "f32"): ("2eda05abf08b7b4f", 15163064.0),
+    ("hartmann_wide", "f32"): ("2eda05abf08b7b4f", 2578816534.0),
 }
 
 

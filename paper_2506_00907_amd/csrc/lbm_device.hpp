@@ -161,12 +161,14 @@ template <> __device__ __forceinline__ void st<BF16S>(uint16_t* p, uint32_t i, f
     at(p, i) = (uint16_t)(b >> 16);
 }
 
-// Stores with stochastic rounding for the 16-bit formats: a dither drawn
-// from (destination slot, destination node, time) is added below the last
-// kept mantissa bit before truncation, so increments smaller than half a unit
-// in the last place survive on average instead of being rounded away.  The
-// dither is a counter-based hash (the 32-bit finaliser of MurmurHash3), so a
-// slot written at a given time gets the same rounding on every path.
+// Stores with stochastic rounding for the 16-bit formats: a dither is added
+// below the last kept mantissa bit before truncation, so increments smaller
+// than half a unit in the last place survive on average instead of being
+// rounded away.  The dither is a counter-based hash (the 32-bit finaliser of
+// MurmurHash3): a link store hashes (slot, node, time); the sweep hashes
+// (writing node, time) once per node and mixes in each slot with one more
+// multiply-xorshift round.  Either way a slot written at a given time gets the
+// same rounding on every path.
 __device__ __forceinline__ uint32_t dither(uint32_t node, uint32_t slot, uint32_t t) {
     uint32_t h = node * 0x9E3779B1u + slot * 0x85EBCA77u + t * 0xC2B2AE3Du;
     h ^= h >> 16;
@@ -753,8 +755,14 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
 
     // ---- scatter (streaming); 16-bit formats round stochastically with a
     // dither of (slot, destination node, time) ----
+    // one full hash of (node, time), then one multiply per store mixes in the slot
+    const uint32_t hn = C::SCALED ? dither(n, 0u, seed) : 0u;
     auto put = [&](int slot, uint32_t dest, R v) {
-        st_sr<SF>(plane(slot), dest, v, C::SCALED ? dither(dest, (uint32_t)slot, seed) : 0u);
+        uint32_t h = hn + (uint32_t)slot * 0x9E3779B9u;
+        h ^= h >> 16;
+        h *= 0x7FEB352Du;
+        h ^= h >> 15;
+        st_sr<SF>(plane(slot), dest, v, C::SCALED ? h : 0u);
     };
 #pragma unroll
     for (int i = 0; i < QF; ++i) {
