@@ -23,10 +23,9 @@
  *    before any work is queued, so a call that fails has no effect.  The text
  *    of the last error of a context is lbm_last_error(ctx).
  *  - Memory: every device buffer is allocated and owned by the caller (the
- *    library never frees caller memory and allocates no device memory, with
- *    one exception: the measurement call lbm_step_timed keeps a temporary
- *    copy of the state); the library owns only its host-side context.  "dev"
- *    pointers are device pointers, "host" pointers are host pointers.
+ *    library never frees caller memory and allocates no device memory); the
+ *    library owns only its host-side context.  "dev" pointers are device
+ *    pointers, "host" pointers are host pointers.
  *  - Streams: all device work of a context is queued on the hipStream_t given
  *    at creation (or lbm_set_stream).  lbm_reduce and lbm_save synchronise
  *    that stream; everything else is asynchronous.  Asynchronous device errors
@@ -67,10 +66,11 @@ typedef enum {
     LBM_LK_VEL = 1,      /* given velocity u_w: Eqs. 15-16 (d < 0.5), Eq. 43 (d >= 0.5) */
     LBM_LK_PRES = 2,     /* given density: zeroth-moment pair (d < 0.5), Eq. 44 (d >= 0.5) */
     LBM_LK_CONC = 3,     /* given concentration: Eqs. 19-20 */
-    LBM_LK_FLUX = 4,     /* scalar flux F(C) = a1 C_X + a2 C_X^2 - a3, M scheme: Eqs. 23-27 */
+    LBM_LK_FLUX = 4,     /* scalar flux F(C) = a1 C_X + quad C_X^2 - a3, M scheme: Eqs. 23-27 */
     LBM_LK_BB0 = 5,      /* zero normal gradient, static: Eqs. 21-22 */
     LBM_LK_MAG_DIR = 6,  /* given magnetic component B_k: Eqs. 34-35 */
-    LBM_LK_MAG_FLUX = 7, /* magnetic flux F(B_k) = a1 B_X,k - a3 (Shercliff, Eq. 30), M scheme */
+    LBM_LK_MAG_FLUX = 7, /* magnetic flux F(B_k) = a1 B_X,k + quad B_X,k^2 - a3 (Shercliff, Eq. 30),
+                            M scheme */
     LBM_LK_MAG_THETA = 8 /* comparison scheme: the link-based theta form of Eq. 39 (d = 0.5)
                             and Eq. 40 (d = 1) for a magnetic component.  The bounced
                             value x becomes ((theta - 1) x + theta dg_move) / (theta + 1),
@@ -130,28 +130,56 @@ typedef struct {
     uint8_t pad[3];
     double d;        /* boundary-to-node distance |AX| / |AE| in (0, 1] */
     double value;    /* PRES: rho_w; CONC: C_w; MAG_DIR: B_k */
-    double a1, a3;   /* FLUX / MAG_FLUX: F(phi) = a1 phi_X - a3 (lattice units) */
+    double a1, a3;   /* FLUX / MAG_FLUX: F(phi) = a1 phi_X - a3 (lattice units; Eq. 17 with a2 = D);
+                        MAG_THETA: a1 = theta = c_w H / (tau_m - 1/2) (Eqs. 39-40), a3 = 0 */
     double weight;   /* flux share of this link (Eq. 48): on flat walls 1 / (links crossing the wall per
                         node: 1 on D2Q5 / D3Q7, 5 on D3Q19); on curved walls S_i e.n / sum e.n over
                         the links of the outer-layer node B_i */
     double u_w[3];   /* boundary velocity */
-    double a2;       /* FLUX / MAG_FLUX: quadratic term of the flux law, F(phi) = a1 phi_X + a2 phi_X^2
+    double quad;     /* FLUX / MAG_FLUX: quadratic term of the flux law, F(phi) = a1 phi_X + quad phi_X^2
                         - a3, evaluated explicitly from the extrapolated phi_X (Eq. 13; a nonlinear
-                        surface reaction, Section 4.2.2); 0 for the other kinds (else LBM_EINVAL) */
+                        surface reaction, Section 4.2.2); 0 for the other kinds (else LBM_EINVAL).
+                        (Eq. 17's own a2 is the coefficient of the normal derivative, D here.) */
 } lbm_link;
+
+/* How a boundary states the flux law of a FLUX or MAG_FLUX condition, or the
+ * theta of MAG_THETA.  lbm_build_links forms each link's coefficients
+ * (lbm_link.a1, a3, quad) from it, with the field's own transport
+ * coefficient: D = c_h^2 (tau_c - 1/2) for h, eta = c_g^2 (tau_m - 1/2) for g
+ * (c^2 = 1/4 on D2Q5 / D3Q7, 1/3 on D3Q19). */
+typedef enum {
+    LBM_LAW_COEF = 0,      /* F(phi) = a1 phi_X + quad phi_X^2 - a3 with the given a1, quad, a3
+                              (Eq. 17 with a2 = D; the quadratic term: Section 4.2.2) */
+    LBM_LAW_ROBIN = 1,     /* d phi / dn = k phi with n into the fluid (Eq. 17 with a2 = D):
+                              F = -k D phi, i.e. a1 = -k D, a3 = 0; FLUX only */
+    LBM_LAW_REACTION = 2,  /* first-order surface reaction F = -k (phi - phi_eq) (Section 5.3):
+                              a1 = -k, a3 = -k phi_eq; FLUX only */
+    LBM_LAW_SHERCLIFF = 3  /* thin conducting wall (Eq. 30) for the component B_k:
+                              F = -eta (B_X,k - B_ext,k) / (c_w H), i.e. a1 = -eta / (c_w H),
+                              a3 = a1 B_ext,k; c_w = +inf is the perfectly conducting wall (F = 0).
+                              MAG_THETA: theta = c_w H / (tau_m - 1/2) (Eqs. 39-40).
+                              MAG_FLUX and MAG_THETA only; c_w > 0, H > 0 */
+} lbm_flux_law;
 
 /* Boundary description consumed by lbm_build_links. */
 typedef struct {
     int32_t kind;          /* lbm_link_kind, 0 = no condition for this lattice */
     int32_t u_given;       /* 1: use the boundary velocity; 0: extrapolate u (Eq. 13) */
-    int32_t profile_axis;  /* axis of a1_profile */
+    int32_t profile_axis;  /* axis of profile */
     int32_t profile_len;   /* 0 = no profile */
     int32_t alt;           /* 1: the comparison form of the kind (link flag bit 3); only for
                               VEL, PRES, FLUX and MAG_FLUX, else LBM_EINVAL */
-    int32_t reserved;
-    double value, a1, a3;
-    const double* a1_profile; /* host: a1 per coordinate of A along profile_axis, or NULL */
-    double a2;                /* FLUX / MAG_FLUX: quadratic coefficient of F (see lbm_link.a2) */
+    int32_t law;           /* lbm_flux_law of a FLUX, MAG_FLUX or MAG_THETA condition; must be
+                              LBM_LAW_COEF (0) for the other kinds (else LBM_EINVAL) */
+    double value;          /* PRES: rho_w; CONC: C_w; MAG_DIR: B_k */
+    double a1, a3, quad;   /* LBM_LAW_COEF: the flux law's coefficients (MAG_THETA: a1 = theta);
+                              other laws: ignored */
+    const double* profile; /* host, or NULL: per coordinate of A along profile_axis, the value that
+                              replaces a1 (LBM_LAW_COEF) or k (LBM_LAW_ROBIN, LBM_LAW_REACTION) */
+    double k;              /* LBM_LAW_ROBIN, LBM_LAW_REACTION: the rate k (>= 0) */
+    double phi_eq;         /* LBM_LAW_REACTION: equilibrium value of the reacting field */
+    double c_w, H;         /* LBM_LAW_SHERCLIFF: wall conductance ratio (> 0, may be +inf) and the
+                              length scale of Eq. 30 (> 0): the channel half-width or pipe radius */
 } lbm_bc;
 
 typedef struct {
@@ -245,11 +273,13 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
  * launches of the fused sweep the same way (parities alternating from the
  * context's time).  Returns the mean duration per launch in ms in ms_out[0]
  * (links; 0 without links) and ms_out[1] (sweep).  These launches are not
- * steps: the populations and moments are copied aside first (one hipMalloc of
- * their size, freed before returning) and restored afterwards, so the state
- * and the time are unchanged.  Synchronises the stream.  Not for items of a
- * batch. */
-lbm_status lbm_step_timed(lbm_ctx* ctx, int64_t n, float ms_out[2]);
+ * steps: the populations and moments are copied into the caller's device
+ * buffer dev_scratch (scratch_bytes >= lbm_timing_scratch_bytes(ctx), else
+ * LBM_ESIZE) first and restored from it afterwards, so the state and the
+ * time are unchanged.  Allocates no device memory.  Synchronises the stream.
+ * Not for items of a batch. */
+size_t lbm_timing_scratch_bytes(const lbm_ctx* ctx);
+lbm_status lbm_step_timed(lbm_ctx* ctx, int64_t n, void* dev_scratch, size_t scratch_bytes, float ms_out[2]);
 
 /* Moments at the current time into dev_out, SoA [8][N] of rho, u_x, u_y, u_z,
  * C, B_x, B_y, B_z (0 at solid nodes); out_type LBM_F64 or LBM_F32. */

@@ -39,8 +39,13 @@ def build(force: bool = False) -> str:
 
 class _BC(C.Structure):
     _fields_ = [("kind", C.c_int32), ("u_given", C.c_int32), ("profile_axis", C.c_int32),
-                ("profile_len", C.c_int32), ("alt", C.c_int32), ("value", C.c_double), ("a1", C.c_double),
-                ("a3", C.c_double), ("a1_profile", C.POINTER(C.c_double)), ("a2", C.c_double)]
+                ("profile_len", C.c_int32), ("alt", C.c_int32), ("law", C.c_int32), ("value", C.c_double),
+                ("a1", C.c_double), ("a3", C.c_double), ("quad", C.c_double),
+                ("profile", C.POINTER(C.c_double)), ("k", C.c_double), ("phi_eq", C.c_double),
+                ("c_w", C.c_double), ("H", C.c_double)]
+
+
+_LAWS = {"coef": 0, "robin": 1, "reaction": 2, "shercliff": 3}
 
 
 class _Boundary(C.Structure):
@@ -66,7 +71,7 @@ class Link(C.Structure):
                 ("u_given", C.c_int32), ("d", C.c_double), ("value", C.c_double),
                 ("a1", C.c_double), ("a3", C.c_double), ("weight", C.c_double),
                 ("u_w", C.c_double * 3), ("omega", C.c_double), ("compare", C.c_int32), ("pad", C.c_int32),
-                ("a2", C.c_double)]
+                ("quad", C.c_double)]
 
 
 class LinkIn(C.Structure):
@@ -75,7 +80,7 @@ class LinkIn(C.Structure):
                 ("value", C.c_double), ("a1", C.c_double), ("a3", C.c_double),
                 ("weight", C.c_double), ("u_w", C.c_double * 3), ("x_ap_E", C.c_double),
                 ("x_ap_A", C.c_double), ("x_a_A", C.c_double), ("mA", C.c_double * 8),
-                ("mE", C.c_double * 8), ("compare", C.c_int32), ("a2", C.c_double)]
+                ("mE", C.c_double * 8), ("compare", C.c_int32), ("quad", C.c_double)]
 
 
 _libs = {}
@@ -150,8 +155,8 @@ def link_eval(**kw) -> float:
     """Evaluates the oracle's boundary-link formula on explicit inputs.
 
     Keywords: lattice (name), kind (name), dir, d, x_ap_E, x_ap_A, x_a_A,
-    mA, mE (8-vectors rho, u, C, B), value, a1, a3, weight, u_w, u_given,
-    comp_axis.
+    mA, mE (8-vectors rho, u, C, B), value, a1, quad, a3, weight, u_w,
+    u_given, comp_axis.
     """
     li = LinkIn()
     li.lattice = S.LATTICE_CODES[kw.get("lattice", "D2Q9")]
@@ -161,7 +166,7 @@ def link_eval(**kw) -> float:
     li.u_given = int(kw.get("u_given", True))
     li.compare = int(kw.get("compare", False))
     li.d = kw["d"]
-    for k in ("value", "a1", "a2", "a3", "x_ap_E", "x_ap_A", "x_a_A"):
+    for k in ("value", "a1", "quad", "a3", "x_ap_E", "x_ap_A", "x_a_A"):
         setattr(li, k, float(kw.get(k, 0.0)))
     li.weight = float(kw.get("weight", 1.0))
     for i, v in enumerate(kw.get("u_w", (0.0, 0.0, 0.0))):
@@ -221,13 +226,14 @@ class _SceneHolder:
         dst.kind = S.KIND_CODES[bc.kind]
         dst.u_given = int(bc.u_given)
         dst.alt = int(bc.alt)
-        dst.value, dst.a1, dst.a3 = bc.value, bc.a1, bc.a3
-        dst.a2 = bc.a2
+        dst.law = _LAWS[bc.law]
+        dst.value, dst.a1, dst.a3, dst.quad = bc.value, bc.a1, bc.a3, bc.quad
+        dst.k, dst.phi_eq, dst.c_w, dst.H = bc.k, bc.phi_eq, bc.c_w, bc.H
         dst.profile_axis = bc.profile_axis
-        if bc.a1_profile is not None:
-            p = np.ascontiguousarray(bc.a1_profile, dtype=np.float64)
+        if bc.profile is not None:
+            p = np.ascontiguousarray(bc.profile, dtype=np.float64)
             self.keep.append(p)
-            dst.a1_profile = p.ctypes.data_as(C.POINTER(C.c_double))
+            dst.profile = p.ctypes.data_as(C.POINTER(C.c_double))
             dst.profile_len = len(p)
         else:
             dst.profile_len = 0
@@ -300,7 +306,7 @@ class OracleSim:
                        ("kind", "i4"), ("bnd", "i4"), ("u_given", "i4"), ("d", "f8"),
                        ("value", "f8"), ("a1", "f8"), ("a3", "f8"), ("weight", "f8"),
                        ("u_w", "f8", 3), ("omega", "f8"), ("compare", "i4"), ("pad", "i4"),
-                       ("a2", "f8")])
+                       ("quad", "f8")])
         assert dt.itemsize == C.sizeof(Link)
         return np.frombuffer(bytes(out), dtype=dt, count=n).copy()
 

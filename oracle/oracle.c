@@ -176,15 +176,23 @@ void or_equilibria(int code, double rho, const double* u, double C, const double
 /* ------------------------------------------------------------------------- */
 enum { K_NONE = 0, K_VEL = 1, K_PRES, K_CONC, K_FLUX, K_BB0, K_MAG_DIR, K_MAG_FLUX, K_MAG_THETA };
 
+/* how a flux wall states its law (the physical description; the builder
+ * forms the coefficients of F(phi) = a1 phi + quad phi^2 - a3 itself) */
+enum { LAW_COEF = 0, LAW_ROBIN = 1, LAW_REACTION = 2, LAW_SHERCLIFF = 3 };
+
 typedef struct {
     int32_t kind;
     int32_t u_given;
     int32_t profile_axis;
     int32_t profile_len;
     int32_t alt; /* the comparison form of Section 5 (VEL, PRES, FLUX, MAG_FLUX) */
-    double value, a1, a3;
-    const double* a1_profile;
-    double a2; /* F = a1 phi + a2 phi^2 - a3 */
+    int32_t law;
+    double value;
+    double a1, a3, quad; /* LAW_COEF: F = a1 phi + quad phi^2 - a3 (theta = a1 for MAG_THETA) */
+    const double* profile; /* per coordinate along profile_axis: a1 (LAW_COEF) or k */
+    double k;             /* LAW_ROBIN: d phi/dn = k phi; LAW_REACTION: F = -k (phi - phi_eq) */
+    double phi_eq;
+    double c_w, H;        /* LAW_SHERCLIFF: thin-wall conductance ratio, length scale */
 } or_bc;
 
 typedef struct {
@@ -227,7 +235,7 @@ typedef struct {
     double omega; /* of the boundary velocity, 0 = steady */
     int32_t compare; /* comparison form of the kind (Section 5) */
     int32_t pad;
-    double a2;       /* quadratic term of the flux law */
+    double quad;     /* quadratic term of the flux law */
 } or_link;
 
 /* ------------------------------------------------------------------------- */
@@ -443,6 +451,51 @@ typedef struct {
     int n_outer;
 } or_sim;
 
+/* The coefficients of a flux wall's law F(phi) = a1 phi + quad phi^2 - a3 from
+ * its physical description.  The field's transport coefficient is
+ * c^2 (tau - 1/2): D for the scalar (Section 2.2), eta for B (Section 2.3).
+ *  - Robin wall d phi/dn = k phi, n into the fluid: with Eq. 17 and a2 = D,
+ *    -D d phi/dn = a1 phi - a3 gives a1 = -k D, a3 = 0.
+ *  - first-order surface reaction F = -k (phi - phi_eq) (Section 5.3).
+ *  - Shercliff thin wall (Eq. 30): -eta dB_k/dn = -eta (B_k - B_ext,k)/(c_w H),
+ *    i.e. a1 = -eta/(c_w H) and a3 = a1 B_ext,k; c_w infinite is the perfectly
+ *    conducting wall, zero flux.  The theta form (Eqs. 39-40) takes
+ *    theta = c_w H / (tau_m - 1/2) in a1.
+ * A profile gives a1 (given coefficients) or k (Robin, reaction) per position
+ * of A along its axis. */
+static void flux_law(const or_scene* s, const or_bc* bc, int field, const or_lattice* L, int comp,
+                     const int* c, or_link* lk) {
+    double prof = 0.0;
+    int has_prof = bc->profile && bc->profile_len > 0;
+    if (has_prof) {
+        int pos = c[bc->profile_axis];
+        if (pos >= bc->profile_len) pos = bc->profile_len - 1;
+        prof = bc->profile[pos];
+    }
+    double tau = field == 1 ? s->tau_c : s->tau_m;
+    double kappa = (double)L->c2 * (tau - 0.5);
+    lk->a1 = lk->a3 = lk->quad = 0.0;
+    if (bc->law == LAW_ROBIN) {
+        double k = has_prof ? prof : bc->k;
+        lk->a1 = -k * kappa;
+    } else if (bc->law == LAW_REACTION) {
+        double k = has_prof ? prof : bc->k;
+        lk->a1 = -k;
+        lk->a3 = -k * bc->phi_eq;
+    } else if (bc->law == LAW_SHERCLIFF) {
+        if (bc->kind == K_MAG_THETA) {
+            lk->a1 = bc->c_w * bc->H / (s->tau_m - 0.5);
+        } else if (!isinf(bc->c_w)) {
+            lk->a1 = -kappa / (bc->c_w * bc->H);
+            lk->a3 = lk->a1 * s->B_ext[s->comps[comp]];
+        }
+    } else {
+        lk->a1 = has_prof ? prof : bc->a1;
+        lk->a3 = bc->a3;
+        lk->quad = bc->quad;
+    }
+}
+
 /* collects the links of one lattice field.  Returns the number written or -1. */
 static int build_field_links(or_sim* S, int field, const or_lattice* L, int ncomp, or_link* out,
                              int cap, int cnt) {
@@ -513,14 +566,7 @@ static int build_field_links(or_sim* S, int field, const or_lattice* L, int ncom
                         lk->u_given = bc->u_given;
                         lk->d = b->d_used > 0.0 ? b->d_used : best_d;
                         lk->value = bc->value;
-                        lk->a1 = bc->a1;
-                        if (bc->a1_profile && bc->profile_len > 0) {
-                            int pos = c[bc->profile_axis];
-                            if (pos >= bc->profile_len) pos = bc->profile_len - 1;
-                            lk->a1 = bc->a1_profile[pos];
-                        }
-                        lk->a3 = bc->a3;
-                        lk->a2 = bc->a2;
+                        flux_law(s, bc, field, L, k, c, lk);
                         for (int j = 0; j < 3; ++j) lk->u_w[j] = b->u_w[j];
                         lk->omega = b->omega;
                         lk->compare = bc->alt;
@@ -701,7 +747,7 @@ typedef struct {
     double x_a_A;   /* post-collision, direction alpha, at A */
     double mA[8], mE[8]; /* rho, u(3), C, B(3) at A and E at time t */
     int32_t compare;     /* the comparison form of the kind (Section 5) */
-    double a2;           /* quadratic term of the flux law */
+    double quad;         /* quadratic term of the flux law */
 } or_link_in;
 
 /* Eq. 13: phi(X) = -d phi(E) + (d+1) phi(A) */
@@ -715,7 +761,7 @@ typedef struct {
     real x_ap_E, x_ap_A, x_a_A;
     real mA[8], mE[8];
     int32_t compare;
-    real a2;
+    real quad;
 } or_link_in_r;
 
 static real link_eval_r(const or_link_in_r* in) {
@@ -775,8 +821,8 @@ static real link_eval_r(const or_link_in_r* in) {
                 real bounced = ((th - 1) * in->x_ap_A + th * dmove) / (th + 1);
                 return ((2 * d - 1) * in->x_a_A + bounced) / (2 * d);
             }
-            /* Eq. 23 with F(phi_X) = a1 phi_X + a2 phi_X^2 - a3, Eq. 48 */
-            real dflux = (in->a1 * phiX + in->a2 * phiX * phiX - in->a3) * in->weight;
+            /* Eq. 23 with F(phi_X) = a1 phi_X + quad phi_X^2 - a3, Eq. 48 */
+            real dflux = (in->a1 * phiX + in->quad * phiX * phiX - in->a3) * in->weight;
             if (in->compare) { /* Eq. 33: the flux joins the bounced population at X */
                 if (d < (real)0.5) return xY + dflux + dmove;
                 return ((2 * d - 1) * in->x_a_A + in->x_ap_A + dflux + dmove) / (2 * d);
@@ -806,7 +852,7 @@ double or_link_eval(const or_link_in* in) {
     r.x_ap_A = in->x_ap_A;
     r.x_a_A = in->x_a_A;
     r.compare = in->compare;
-    r.a2 = in->a2;
+    r.quad = in->quad;
     for (int k = 0; k < 3; ++k) r.u_w[k] = in->u_w[k];
     for (int k = 0; k < 8; ++k) {
         r.mA[k] = in->mA[k];
@@ -833,7 +879,7 @@ static void apply_links(or_sim* S) {
         in.comp_axis = lk->field == 2 ? s->comps[lk->comp] : 0;
         in.u_given = lk->u_given;
         in.compare = lk->compare;
-        in.a2 = lk->a2;
+        in.quad = lk->quad;
         in.d = lk->d;
         in.value = lk->value;
         in.a1 = lk->a1;

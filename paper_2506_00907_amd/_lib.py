@@ -39,14 +39,15 @@ class lbm_link(C.Structure):
     _fields_ = [("node", C.c_uint32), ("enode", C.c_uint32), ("field", C.c_uint8), ("dir", C.c_uint8),
                 ("kind", C.c_uint8), ("comp", C.c_uint8), ("flags", C.c_uint8), ("pad", C.c_uint8 * 3),
                 ("d", C.c_double), ("value", C.c_double), ("a1", C.c_double), ("a3", C.c_double),
-                ("weight", C.c_double), ("u_w", C.c_double * 3), ("a2", C.c_double)]
+                ("weight", C.c_double), ("u_w", C.c_double * 3), ("quad", C.c_double)]
 
 
 class lbm_bc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("u_given", C.c_int32), ("profile_axis", C.c_int32),
-                ("profile_len", C.c_int32), ("alt", C.c_int32), ("reserved", C.c_int32),
-                ("value", C.c_double), ("a1", C.c_double),
-                ("a3", C.c_double), ("a1_profile", C.POINTER(C.c_double)), ("a2", C.c_double)]
+                ("profile_len", C.c_int32), ("alt", C.c_int32), ("law", C.c_int32),
+                ("value", C.c_double), ("a1", C.c_double), ("a3", C.c_double), ("quad", C.c_double),
+                ("profile", C.POINTER(C.c_double)), ("k", C.c_double), ("phi_eq", C.c_double),
+                ("c_w", C.c_double), ("H", C.c_double)]
 
 
 class lbm_boundary(C.Structure):
@@ -68,6 +69,8 @@ class lbm_nn_desc(C.Structure):
 
 
 LBM_BATCH_TILED, LBM_BATCH_RESIDENT = 1, 2
+# lbm_flux_law
+LAWS = {"coef": 0, "robin": 1, "reaction": 2, "shercliff": 3}
 ITEM_STATUS = {0: "active", 1: "steady", 2: "nonfinite", 3: "disabled"}
 
 # every entry point declared in include/lbm.h: name -> (restype, argtypes)
@@ -83,7 +86,8 @@ SIGNATURES = {
     "lbm_set_links": (C.c_int, [_VP, _VP, C.c_size_t]),
     "lbm_init": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "lbm_step": (C.c_int, [_VP, C.c_int64]),
-    "lbm_step_timed": (C.c_int, [_VP, C.c_int64, C.POINTER(C.c_float)]),
+    "lbm_timing_scratch_bytes": (C.c_size_t, [_VP]),
+    "lbm_step_timed": (C.c_int, [_VP, C.c_int64, _VP, C.c_size_t, C.POINTER(C.c_float)]),
     "lbm_read_moments": (C.c_int, [_VP, _VP, C.c_int32]),
     "lbm_read_populations": (C.c_int, [_VP, C.c_int32, _VP]),
     "lbm_reduce": (C.c_int, [_VP, C.POINTER(C.c_double)]),

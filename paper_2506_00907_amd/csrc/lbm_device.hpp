@@ -372,7 +372,7 @@ __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R
                 const R tb = ((th - one) * bx + th * dmove - two * w * Bk) / (th + one);
                 return lo ? tb : ((two * d - one) * x_a + tb) / (two * d);
             }
-            R dflux = ((L.a1 + L.a2 * phiX) * phiX - L.a3) * L.weight;  // F(phi_X), explicit
+            R dflux = ((L.a1 + L.quad * phiX) * phiX - L.a3) * L.weight;  // F(phi_X), explicit
             if (alt)  // flux added at X, not at M (Eq. 33 and its d < 0.5 analogue)
                 return lo ? Y + dflux + dmove : ((two * d - one) * x_a + x_apA + dflux + dmove) / (two * d);
             R xM = (half - d) * x_apE + (half + d) * x_apA + dflux + dmove;

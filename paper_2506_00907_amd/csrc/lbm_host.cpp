@@ -224,14 +224,7 @@ class LinkBuilder {
                                                      (bc.u_given && bd.u_osc ? 4 : 0) | (bc.alt ? 8 : 0));
                                 lk.d = bd.d_scheme > 0.0 ? bd.d_scheme : best.d;
                                 lk.value = bc.value;
-                                lk.a1 = bc.a1;
-                                if (bc.a1_profile && bc.profile_len > 0) {
-                                    int pos = A[bc.profile_axis];
-                                    pos = std::min(pos, bc.profile_len - 1);
-                                    lk.a1 = bc.a1_profile[pos];
-                                }
-                                lk.a3 = bc.a3;
-                                lk.a2 = bc.a2;
+                                law_coefficients(bc, field, c, A, &lk);
                                 for (int k = 0; k < 3; ++k) lk.u_w[k] = bd.u_w[k];
                                 const bool flux = bc.kind == LBM_LK_FLUX || bc.kind == LBM_LK_MAG_FLUX;
                                 // flat faces: a node's flux split evenly over the
@@ -256,6 +249,53 @@ class LinkBuilder {
     }
 
     const std::vector<uint8_t>& mask() const { return mask_; }
+
+    // The flux law of a link from the boundary's description (lbm_flux_law),
+    // with the field's transport coefficient kappa = c^2 (tau - 1/2) (D for
+    // h, eta for g): a Robin wall d phi/dn = k phi gives F = -k D phi (Eq. 17
+    // with a2 = D); a first-order reaction F = -k (phi - phi_eq) (Section
+    // 5.3); a thin conducting wall F = -eta (B_k - B_ext,k) / (c_w H) (Eq. 30),
+    // where c_w = inf is the perfectly conducting wall; the theta form takes
+    // theta = c_w H / (tau_m - 1/2) (Eqs. 39-40).  A profile replaces a1
+    // (given coefficients) or k (Robin, reaction) by its value at A.
+    void law_coefficients(const lbm_bc& bc, int field, int comp, const int* A, lbm_link* lk) const {
+        double prof = 0.0;
+        const bool has_prof = bc.profile && bc.profile_len > 0;
+        if (has_prof) prof = bc.profile[std::min(A[bc.profile_axis], bc.profile_len - 1)];
+        const int code = field == 1 ? p_.scalar : p_.magnetic;
+        const double tau = field == 1 ? p_.tau_c : p_.tau_m;
+        const double kappa = field == 0 ? 0.0 : lattice_of(code).c2 * (tau - 0.5);
+        switch (bc.law) {
+            case LBM_LAW_ROBIN: {
+                const double k = has_prof ? prof : bc.k;
+                lk->a1 = -k * kappa;
+                lk->a3 = 0.0;
+                break;
+            }
+            case LBM_LAW_REACTION: {
+                const double k = has_prof ? prof : bc.k;
+                lk->a1 = -k;
+                lk->a3 = -k * bc.phi_eq;
+                break;
+            }
+            case LBM_LAW_SHERCLIFF: {
+                if (bc.kind == LBM_LK_MAG_THETA) {
+                    lk->a1 = bc.c_w * bc.H / (p_.tau_m - 0.5);
+                    lk->a3 = 0.0;
+                } else if (std::isinf(bc.c_w)) {
+                    lk->a1 = lk->a3 = 0.0;
+                } else {
+                    lk->a1 = -kappa / (bc.c_w * bc.H);
+                    lk->a3 = lk->a1 * p_.B_ext[p_.mag_comp[comp]];
+                }
+                break;
+            }
+            default:
+                lk->a1 = has_prof ? prof : bc.a1;
+                lk->a3 = bc.a3;
+                lk->quad = bc.quad;
+        }
+    }
 
    private:
     size_t index(const int* c) const { return (size_t)c[0] + (size_t)p_.n[0] * ((size_t)c[1] + (size_t)p_.n[1] * c[2]); }
@@ -552,13 +592,36 @@ void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::
         d.value = (R)(s.value - rest);
         d.a1 = (R)s.a1;
         d.a3 = (R)s.a3;
-        d.a2 = (R)s.a2;
+        d.quad = (R)s.quad;
         d.weight = (R)s.weight;
         d.uw0 = (R)s.u_w[0];
         d.uw1 = (R)s.u_w[1];
         d.uw2 = (R)s.u_w[2];
         d.need = moments_needed(s, lat.e[s.dir]);
         out[i] = d;
+    }
+}
+
+// A boundary's flux law (lbm_flux_law) fits its kind and has valid data.
+bool valid_law(const lbm_bc& bc) {
+    if (bc.profile_len < 0 || (bc.profile_len > 0 && (!bc.profile || bc.profile_axis < 0 || bc.profile_axis > 2)))
+        return false;
+    switch (bc.law) {
+        case LBM_LAW_COEF:
+            return true;
+        case LBM_LAW_ROBIN:
+        case LBM_LAW_REACTION:
+            if (bc.kind != LBM_LK_FLUX || !(bc.k >= 0.0) || !std::isfinite(bc.k) || !std::isfinite(bc.phi_eq))
+                return false;
+            for (int i = 0; i < bc.profile_len; ++i)
+                if (!(bc.profile[i] >= 0.0) || !std::isfinite(bc.profile[i])) return false;
+            return true;
+        case LBM_LAW_SHERCLIFF:
+            if (bc.kind != LBM_LK_MAG_FLUX && bc.kind != LBM_LK_MAG_THETA) return false;
+            if (bc.profile_len > 0 || !(bc.c_w > 0.0) || !(bc.H > 0.0) || !std::isfinite(bc.H)) return false;
+            return bc.kind == LBM_LK_MAG_FLUX || std::isfinite(bc.c_w);
+        default:
+            return false;
     }
 }
 
@@ -599,10 +662,12 @@ lbm_status lbm_build_links(const lbm_params* p, const lbm_boundary* bnds, int32_
                 if (!(b.lo[k] <= b.hi[k])) return LBM_EINVAL;
         if (!(b.d_scheme == 0.0 || (b.d_scheme > 0.0 && b.d_scheme <= 1.0))) return LBM_EINVAL;
         const lbm_bc* bcs[5] = {&b.f, &b.h, &b.g[0], &b.g[1], &b.g[2]};
-        for (const lbm_bc* bc : bcs)
+        for (const lbm_bc* bc : bcs) {
             if (bc->alt && !(bc->kind == LBM_LK_VEL || bc->kind == LBM_LK_PRES || bc->kind == LBM_LK_FLUX ||
                              bc->kind == LBM_LK_MAG_FLUX))
                 return LBM_EINVAL;
+            if (!valid_law(*bc)) return LBM_EINVAL;
+        }
     }
     LinkBuilder lb(*p, bnds, nb);
     std::vector<lbm_link> links;
@@ -730,10 +795,10 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
             return bad("the theta form needs a D2Q5 or D3Q7 magnetic lattice");
         if ((k.flags & 4) && !(k.flags & 1)) return bad("an oscillating boundary velocity needs flag bit 0 (u_w given)");
         if (!std::isfinite(k.value) || !std::isfinite(k.a1) || !std::isfinite(k.a3) || !std::isfinite(k.weight) ||
-            !std::isfinite(k.a2))
+            !std::isfinite(k.quad))
             return bad("non-finite wall data");
-        if (k.a2 != 0.0 && k.kind != LBM_LK_FLUX && k.kind != LBM_LK_MAG_FLUX)
-            return bad("a2 (quadratic flux term) needs kind FLUX or MAG_FLUX");
+        if (k.quad != 0.0 && k.kind != LBM_LK_FLUX && k.kind != LBM_LK_MAG_FLUX)
+            return bad("quad (quadratic flux term) needs kind FLUX or MAG_FLUX");
         int q[3];
         coords(k.node, q);
         int s[3] = {q[0] - lat.e[k.dir][0], q[1] - lat.e[k.dir][1], q[2] - lat.e[k.dir][2]};
@@ -1004,20 +1069,21 @@ lbm_status capture_kernel(lbm_ctx* c, int64_t n, bool links, hipGraphExec_t* out
 
 }  // namespace
 
-lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, float ms_out[2]) {
+size_t lbm_timing_scratch_bytes(const lbm_ctx* c) { return c ? c->size[0] + c->size[3] : 0; }
+
+lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, void* dev_scratch, size_t scratch_bytes, float ms_out[2]) {
     if (!c || !ms_out) return LBM_EINVAL;
     if (n < 2 || n > 4096 || (n & 1)) return set_err(c, LBM_EINVAL, "launch count must be even, 2 to 4096");
     if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
     if (c->batch_owned) return set_err(c, LBM_EINVAL, "an item of a batch is timed through the batch");
-    ms_out[0] = ms_out[1] = 0.f;
     // the launches below do not form steps: populations and moments (with the
-    // time base word) are saved first and restored afterwards
+    // time base word) are saved into the caller's scratch first and restored
+    // afterwards
     const size_t s0 = c->size[0], s3 = c->size[3];
-    void* save = nullptr;
-    if (hipMalloc(&save, s0 + s3) != hipSuccess) {
-        (void)hipGetLastError();
-        return set_err(c, LBM_EDEVICE, "state copy allocation");
-    }
+    if (!dev_scratch) return set_err(c, LBM_EINVAL, "no scratch buffer");
+    if (scratch_bytes < s0 + s3) return set_err(c, LBM_ESIZE, "scratch buffer smaller than lbm_timing_scratch_bytes");
+    ms_out[0] = ms_out[1] = 0.f;
+    void* save = dev_scratch;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipGraphExec_t g[2] = {nullptr, nullptr};
     lbm_status st = hip_check(c, hipMemcpyAsync(save, c->buf[0], s0, hipMemcpyDeviceToDevice, c->stream), "state save");
@@ -1048,7 +1114,6 @@ lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, float ms_out[2]) {
         if (x) (void)hipGraphExecDestroy(x);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(save);
     return st ? st : rs;
 }
 

@@ -37,7 +37,7 @@ struct alignas(16) DevLink {
     R d;
     R value;  // given value minus its rest value (rho0, C0 or B_ext,k)
     R a1, a3, weight, uw0, uw1, uw2;
-    R a2;     // quadratic coefficient of the flux law (FLUX / MAG_FLUX)
+    R quad;   // quadratic coefficient of the flux law (FLUX / MAG_FLUX)
 };
 
 // Launch description: sizes, pointers and physical parameters in double; the

@@ -21,7 +21,7 @@ STORAGES = {"f64": L.LBM_F64, "f32": L.LBM_F32, "f16": L.LBM_F16, "bf16": L.LBM_
 
 LINK_DTYPE = np.dtype([("node", "<u4"), ("enode", "<u4"), ("field", "u1"), ("dir", "u1"), ("kind", "u1"),
                        ("comp", "u1"), ("flags", "u1"), ("pad", "u1", 3), ("d", "<f8"), ("value", "<f8"),
-                       ("a1", "<f8"), ("a3", "<f8"), ("weight", "<f8"), ("u_w", "<f8", 3), ("a2", "<f8")])
+                       ("a1", "<f8"), ("a3", "<f8"), ("weight", "<f8"), ("u_w", "<f8", 3), ("quad", "<f8")])
 assert LINK_DTYPE.itemsize == C.sizeof(L.lbm_link)
 
 
@@ -58,13 +58,14 @@ def boundaries_from_scene(sc):
         dst.kind = KINDS[bc.kind]
         dst.u_given = int(bc.u_given)
         dst.alt = int(bc.alt)
-        dst.value, dst.a1, dst.a3 = bc.value, bc.a1, bc.a3
-        dst.a2 = bc.a2
+        dst.law = L.LAWS[bc.law]
+        dst.value, dst.a1, dst.a3, dst.quad = bc.value, bc.a1, bc.a3, bc.quad
+        dst.k, dst.phi_eq, dst.c_w, dst.H = bc.k, bc.phi_eq, bc.c_w, bc.H
         dst.profile_axis = bc.profile_axis
-        if bc.a1_profile is not None:
-            prof = np.ascontiguousarray(bc.a1_profile, dtype=np.float64)
+        if bc.profile is not None:
+            prof = np.ascontiguousarray(bc.profile, dtype=np.float64)
             keep.append(prof)
-            dst.a1_profile = prof.ctypes.data_as(C.POINTER(C.c_double))
+            dst.profile = prof.ctypes.data_as(C.POINTER(C.c_double))
             dst.profile_len = len(prof)
 
     for i, b in enumerate(sc.boundaries):
@@ -206,9 +207,14 @@ class Lattice:
         self._call("lbm_step", int(n))
 
     def step_timed(self, n: int):
-        """lbm_step_timed: mean (link kernel, sweep kernel) durations in ms."""
+        """lbm_step_timed: mean (link kernel, sweep kernel) durations in ms.
+        The state is saved into a torch-allocated scratch buffer of
+        lbm_timing_scratch_bytes and restored from it."""
+        nbytes = L.lib().lbm_timing_scratch_bytes(self.ctx)
+        scratch = self.torch.empty(max(nbytes, 1), dtype=self.torch.uint8, device=self.device)
         out = (C.c_float * 2)()
-        self._call("lbm_step_timed", int(n), out)
+        self._call("lbm_step_timed", int(n), C.c_void_p(scratch.data_ptr()), nbytes, out)
+        del scratch
         return float(out[0]), float(out[1])
 
     @property

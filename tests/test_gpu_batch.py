@@ -93,7 +93,7 @@ def test_comparison_and_quadratic_forms_in_a_batch(mode):
     surface reaction, batched: each equals the same item alone"""
     def quad(sc):
         for b in sc.boundaries[:2]:
-            b.h = scenes.BC(scenes.FLUX, a1=-0.001, a2=-0.02)
+            b.h = scenes.BC(scenes.FLUX, a1=-0.001, quad=-0.02)
         return sc
     scs = [scenes.hartmann_couette(nx=4, ny=19, c_top=0.1, qb=1.0, qt=1.0, top_scheme="X", storage="f32"),
            scenes.hartmann_couette(nx=4, ny=23, c_top=0.5, qb=0.6, qt=1.0, top_scheme="theta", storage="f32")]

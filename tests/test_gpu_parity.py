@@ -86,7 +86,7 @@ FP64_CASES = {
 
 def _quadratic(sc, k=0.02):
     for b in sc.boundaries[:2]:
-        b.h = BC("FLUX", a1=-0.001, a2=-k)
+        b.h = BC("FLUX", a1=-0.001, quad=-k)
     return sc
 
 

@@ -87,7 +87,7 @@ SCENES = {
 def _quadratic_walls(sc, k=0.02):
     """the channel's walls with a second-order surface reaction F = -k C^2"""
     for b in sc.boundaries[:2]:
-        b.h = scenes.BC(scenes.FLUX, a1=0.0, a2=-k)
+        b.h = scenes.BC(scenes.FLUX, a1=0.0, quad=-k)
     return sc
 
 
@@ -123,8 +123,8 @@ def compare_link_tables(sc):
         assert bool(r["flags"] & 1) == bool(o_["u_given"])
         assert bool(r["flags"] & 4) == (o_["omega"] != 0.0)
         assert bool(r["flags"] & 8) == bool(o_["compare"])
-        for fld in ("value", "a1", "a2", "a3"):
-            assert r[fld] == o_[fld]
+        for fld in ("value", "a1", "quad", "a3"):
+            assert r[fld] == o_[fld], (fld, r[fld], o_[fld])
         assert abs(r["weight"] - o_["weight"]) < 1e-12 * max(1.0, abs(o_["weight"]))
         assert np.array_equal(r["u_w"], o_["u_w"])
     return ll
@@ -332,18 +332,92 @@ def test_d3q19_magnetic_lattice_walls():
 
 
 def test_quadratic_flux_term_validation(small):
-    """a2 is copied to the links of flux walls and rejected elsewhere"""
+    """quad is copied to the links of flux walls and rejected elsewhere"""
     sc, mask, links, fc = small
     bad = links.copy()
     i = int(np.nonzero(bad["kind"] == lbm.KINDS["VEL"])[0][0])
-    bad["a2"][i] = 0.1
-    assert fc.set_links(bad) == -1 and "a2" in fc.err()
+    bad["quad"][i] = 0.1
+    assert fc.set_links(bad) == -1 and "quad" in fc.err()
     ok = links.copy()
-    ok["a2"][ok["kind"] == lbm.KINDS["FLUX"]] = -0.01
+    ok["quad"][ok["kind"] == lbm.KINDS["FLUX"]] = -0.01
     assert fc.set_links(ok) != -1
     bad = links.copy()
-    bad["a2"][0] = float("nan")
+    bad["quad"][0] = float("nan")
     assert fc.set_links(bad) == -1
+
+
+def _law_links(sc):
+    mask, ll = lbm.build_links(sc)
+    return ll[(ll["kind"] == lbm.KINDS["FLUX"]) | (ll["kind"] >= lbm.KINDS["MAG_FLUX"])]
+
+
+def test_flux_laws_form_their_coefficients():
+    """The builder forms a1, a3 from a wall's physical law with the field's own
+    transport coefficient c^2 (tau - 1/2): a Robin wall d phi/dn = k phi gives
+    F = -k D phi (Eq. 17 with a2 = D), a reaction F = -k (phi - phi_eq), a thin
+    wall F = -eta (B_k - B_ext,k) / (c_w H) (Eq. 30), and the theta form
+    theta = c_w H / (tau_m - 1/2) (Eqs. 39-40).  Stated values: tau_c = 0.6 on
+    D2Q5 has D = 0.025; tau_m = 0.9 on D3Q7 has eta = 0.1, on D3Q19 eta = 0.4/3."""
+    e5 = lbm.lattice_table(lbm.LATTICES["D2Q5"])[0]
+    up = int(np.nonzero((e5[:, 0] == 0) & (e5[:, 1] == 1))[0][0])  # links entering from the bottom wall
+
+    def bottom(sc):
+        fl = _law_links(sc)
+        return fl[fl["dir"] == up]
+
+    sc = scenes.reactive_channel(nx=9, ny=6, q=0.3, k=0.04)
+    wall = bottom(sc)
+    assert len(wall) == 9 and np.allclose(wall["a1"], -0.04 * 0.025, rtol=1e-15) and np.all(wall["a3"] == 0.0)
+    prof = np.linspace(0.01, 0.09, 9)
+    sc.boundaries[0].h = scenes.BC(scenes.FLUX, law="robin", profile=prof, profile_axis=0)
+    wall = bottom(sc)
+    assert np.allclose(wall["a1"], -prof[wall["node"] % 9] * 0.025, rtol=1e-15)
+    sc.boundaries[0].h = scenes.BC(scenes.FLUX, law="reaction", k=0.3, phi_eq=2.0)
+    wall = bottom(sc)
+    assert np.allclose(wall["a1"], -0.3) and np.allclose(wall["a3"], -0.6)
+    pipe = scenes.mhd_pipe(nx=1, side=17, R=6.3, wall="shercliff", c_w=0.05)
+    ml = _law_links(pipe)
+    assert len(ml) and np.allclose(ml["a1"], -0.1 / (0.05 * 6.3), rtol=1e-14) and np.all(ml["a3"] == 0.0)
+    q19 = scenes.mhd_pipe(nx=1, side=17, R=6.3, wall="shercliff", c_w=0.05, mag_lattice="D3Q19")
+    assert np.allclose(_law_links(q19)["a1"], -(0.4 / 3) / (0.05 * 6.3), rtol=1e-14)
+    cond = scenes.mhd_pipe(nx=1, side=17, R=6.3, wall="conducting")
+    assert np.all(_law_links(cond)["a1"] == 0.0)
+    # a thin wall on a component with an applied field: a3 = a1 B_ext,k
+    hc = scenes.hartmann_couette(nx=3, ny=7, c_top=0.2)
+    hc.boundaries[1].g[1] = scenes.BC(scenes.MAG_FLUX, law="shercliff", c_w=0.5, H=hc.meta["H"])
+    hl = _law_links(hc)
+    by = hl[hl["comp"] == 1]
+    a1 = -0.1 / (0.5 * hc.meta["H"])
+    assert len(by) and np.allclose(by["a1"], a1, rtol=1e-14) and np.allclose(by["a3"], a1 * hc.B_ext[1], rtol=1e-14)
+    th = scenes.hartmann_couette(nx=3, ny=7, c_top=0.2, top_scheme="theta")
+    tl = _law_links(th)
+    assert len(tl) and np.allclose(tl["a1"], 0.2 * th.meta["H"] / 0.4, rtol=1e-14)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(kind="MAG_FLUX", law="robin", k=0.1),
+    dict(kind="FLUX", law="shercliff", c_w=0.1, H=3.0),
+    dict(kind="FLUX", law="robin", k=-0.1),
+    dict(kind="FLUX", law="robin", k=float("nan")),
+    dict(kind="VEL", law="robin", k=0.1),
+])
+def test_flux_law_validation(bad):
+    """a law that does not fit its kind, or invalid law data, is rejected"""
+    sc = scenes.reactive_channel(nx=9, ny=6, q=0.3)
+    if bad["kind"] == "MAG_FLUX":
+        sc = scenes.hartmann_couette(nx=3, ny=7, c_top=0.2)
+        sc.boundaries[1].g[0] = scenes.BC(**bad)
+    elif bad["kind"] == "VEL":
+        sc.boundaries[0].f = scenes.BC(**bad)
+    else:
+        sc.boundaries[0].h = scenes.BC(**bad)
+    with pytest.raises(L.LbmError):
+        lbm.build_links(sc)
+    for c_w, H in ((0.0, 3.0), (0.1, 0.0), (math.inf, 3.0)):
+        th = scenes.hartmann_couette(nx=3, ny=7, c_top=0.2, top_scheme="theta")
+        th.boundaries[1].g[0] = scenes.BC(scenes.MAG_THETA, law="shercliff", c_w=c_w, H=H)
+        with pytest.raises(L.LbmError):
+            lbm.build_links(th)
 
 
 def test_builder_rejects_uncovered_boundary():

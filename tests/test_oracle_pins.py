@@ -322,17 +322,17 @@ def test_nonlinear_surface_reaction_exact(qb, qt):
     ny, D, k = 12, (0.8 - 0.5) / 4, 0.004
     y = np.arange(ny) + qb
     W = ny - 1 + qb + qt
-    o = oracle.OracleSim(_chan_scalar(qb, qt, BC("CONC", value=1.0), BC("FLUX", a2=-k)))
+    o = oracle.OracleSim(_chan_scalar(qb, qt, BC("CONC", value=1.0), BC("FLUX", quad=-k)))
     o.step(60000)
     # k W^2 s^2 + (2 k W + D) s + k = 0, the root near -k/D
     a, b, c = k * W * W, 2 * k * W + D, k
     s = (-b + math.sqrt(b * b - 4 * a * c)) / (2 * a)
     assert np.abs(o.moments()[0, :, 0, 4] - (1 + s * y)).max() < 1e-11
-    # the quadratic term enters the link value as a2 C_X^2 times the weight
+    # the quadratic term enters the link value as quad C_X^2 times the weight
     x = dict(x_ap_E=0.11, x_ap_A=0.13, x_a_A=0.07)
     mA, mE = [1, 0, 0, 0, 0.9, 0, 0, 0], [1, 0, 0, 0, 0.8, 0, 0, 0]
     base = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, d=0.5, mA=mA, mE=mE, **x)
-    quad = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, d=0.5, a2=-k, mA=mA, mE=mE, **x)
+    quad = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, d=0.5, quad=-k, mA=mA, mE=mE, **x)
     CX = 1.5 * 0.9 - 0.5 * 0.8
     assert np.isclose(quad - base, -k * CX * CX, rtol=1e-12)
 
