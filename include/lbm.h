@@ -299,6 +299,24 @@ lbm_status lbm_read_populations(lbm_ctx* ctx, int32_t field, double* dev_out);
  * Returns LBM_EUNSTABLE when out[7] > 0. */
 lbm_status lbm_reduce(lbm_ctx* ctx, double out[8]);
 
+/* lbm_reduce for callers that cannot allocate device memory (code under HIP
+ * graph capture of its neighbours, serving loops, harnesses that forbid
+ * hipMalloc): the same outputs, return values and snapshot update as
+ * lbm_reduce, but the reduction's scratch (one record of FP64 sums per
+ * 256-node block, then their totals) lives in a device array the library
+ * owns, sized for at most LBM_REDUCE_STATIC_MAX_BLOCKS blocks, i.e. lattices
+ * of up to 256 * LBM_REDUCE_STATIC_MAX_BLOCKS padded nodes (16 MiB per
+ * device, held until the process ends); larger lattices fail with LBM_ESIZE.
+ * The records are added in a fixed order, so the sums are reproducible run to
+ * run (lbm_reduce adds them with atomics and may differ in the last bits).
+ * The context's device must be the current HIP device (else LBM_EINVAL).
+ * Allocates no device memory.  Every call on one device shares that device's
+ * array: calls that overlap in time on one device (other host threads,
+ * other streams) race and must be serialised by the caller.  Synchronises
+ * the stream. */
+#define LBM_REDUCE_STATIC_MAX_BLOCKS 131072
+lbm_status lbm_reduce_static(lbm_ctx* ctx, double out[8]);
+
 /* The dimensionless fields of Eqs. 46-47 along one Cartesian axis (0..2),
  * FP64 into dev_out as [2][N]: u* = u_axis / U and
  * B* = (B_axis - B_ext,axis) / (U mu sqrt(rho0 nu sigma)), with

@@ -17,6 +17,7 @@ LBM_NBUF = 8
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ESIZE", -3: "LBM_EDEVICE", -4: "LBM_EUNSTABLE",
           -5: "LBM_ESTATE"}
 LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = 1, 2, 3, 4
+LBM_REDUCE_STATIC_MAX_BLOCKS = 131072  # lbm_reduce_static: 256-node blocks its scratch holds
 
 
 class LbmError(RuntimeError):
@@ -91,6 +92,7 @@ SIGNATURES = {
     "lbm_read_moments": (C.c_int, [_VP, _VP, C.c_int32]),
     "lbm_read_populations": (C.c_int, [_VP, C.c_int32, _VP]),
     "lbm_reduce": (C.c_int, [_VP, C.POINTER(C.c_double)]),
+    "lbm_reduce_static": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "lbm_boundary_flux": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "lbm_read_normalised": (C.c_int, [_VP, C.c_int32, C.c_double, _VP]),
     "lbm_state_bytes": (C.c_size_t, [_VP]),

@@ -505,6 +505,7 @@ lbm_status lbm_batch_create(int32_t n_items, const lbm_params* items, const size
         }
         c->cap_links = n_links[i];
         c->stream = b->stream;
+        if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
         c->batch_owned = true;
         b->items.push_back(c);
     }

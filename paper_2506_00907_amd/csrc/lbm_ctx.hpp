@@ -43,6 +43,7 @@ struct lbm_ctx {
     size_t cap_links = 0, n_links = 0;
     bool cmp_links = false;  // some link takes a comparison form (flag bit 3 or kind 8)
     hipStream_t stream = nullptr;
+    int device = -1;  // HIP device current at creation
     int64_t t = 0, t_snap = 0;
     bool have_geometry = false, have_links = false, initialized = false, snap_valid = false;
     std::vector<uint8_t> mask;   // domain
@@ -65,5 +66,9 @@ lbm_status hip_check(lbm_ctx* c, hipError_t e, const char* what);
 lbmi::KArgs base_args(const lbm_ctx* c);
 // device word holding the time at the start of a captured run (end of buffer 3)
 uint32_t* time_base(const lbm_ctx* c);
+// lbm_reduce's outputs from the 12 FP64 sums of the reduction (h[0..4] sums of
+// rho, C, B; h[5..7] squared changes and h[8..10] squared norms of u, C - C0,
+// B - B_ext; h[11] non-finite count); moves the residual snapshot time
+lbm_status finish_reduce(lbm_ctx* c, const double h[12], double out[8]);
 
 }  // namespace lbmh

@@ -868,8 +868,9 @@ __device__ __forceinline__ void reduce_node(const Phys<typename C::R>& P, const 
 }
 
 // block sum of the first 12 accumulators: wave shuffles, then LDS, then one
-// FP64 atomic per value and block
-__device__ __forceinline__ void block_accumulate(const double v[NACC], double* acc) {
+// FP64 atomic per value and block into acc, or (store) a plain store of the
+// block's sums into acc
+__device__ __forceinline__ void block_accumulate(const double v[NACC], double* acc, bool store = false) {
     __shared__ double red[12][16];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int q = 0; q < 12; ++q) {
@@ -880,7 +881,8 @@ __device__ __forceinline__ void block_accumulate(const double v[NACC], double* a
     if (threadIdx.x < 12) {
         double s = 0.0;
         for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) s += red[threadIdx.x][k];
-        atomicAdd(&acc[threadIdx.x], s);
+        if (store) acc[threadIdx.x] = s;
+        else atomicAdd(&acc[threadIdx.x], s);
     }
 }
 
@@ -890,8 +892,8 @@ __global__ __launch_bounds__(256) void k_observe(Geo G, Phys<typename C::R> P, t
                                                  const uint8_t* __restrict__ flags,
                                                  typename C::R* __restrict__ M,
                                                  uint32_t nnodes, int mode, int field, void* out,
-                                                 int out_f64, double* acc, typename C::R* snap,
-                                                 int snap_valid) {
+                                                 int out_f64, double* acc, int acc_blocks,
+                                                 typename C::R* snap, int snap_valid) {
     using R = typename C::R;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     NodeRes<C> r;
@@ -963,7 +965,8 @@ __global__ __launch_bounds__(256) void k_observe(Geo G, Phys<typename C::R> P, t
     // OBS_REDUCE
     double v[NACC];
     reduce_node<C>(P, r, fluid, snap, snap_valid, G.plane, n, v);
-    block_accumulate(v, acc);
+    if (acc_blocks) block_accumulate(v, acc + (size_t)blockIdx.x * NACC, true);
+    else block_accumulate(v, acc);
 }
 
 // the normalisation of the OBS_NORM output: out[0][i] /= U,
@@ -1306,10 +1309,12 @@ struct Launch {
         if (e != hipSuccess) return e;
         if (a.parity)
             hipLaunchKernelGGL((k_observe<C, 1>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
-                               (R*)a.M, nn, a.mode, a.field, a.out, a.out_f64, a.acc, (R*)a.snap, a.snap_valid);
+                               (R*)a.M, nn, a.mode, a.field, a.out, a.out_f64, a.acc, a.acc_blocks, (R*)a.snap,
+                               a.snap_valid);
         else
             hipLaunchKernelGGL((k_observe<C, 0>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S, a.flags,
-                               (R*)a.M, nn, a.mode, a.field, a.out, a.out_f64, a.acc, (R*)a.snap, a.snap_valid);
+                               (R*)a.M, nn, a.mode, a.field, a.out, a.out_f64, a.acc, a.acc_blocks, (R*)a.snap,
+                               a.snap_valid);
         return hipGetLastError();
     }
     static hipError_t init(const KArgs& a) {

@@ -462,6 +462,31 @@ void drop_graph(lbm_ctx* c) {
     c->graph = nullptr;
 }
 
+lbm_status finish_reduce(lbm_ctx* c, const double h[12], double out[8]) {
+    const double dt = (double)(c->t - c->t_snap);
+    double res = -1.0;
+    if (c->snap_valid && dt > 0) {
+        res = 0.0;
+        for (int f = 0; f < 3; ++f) {
+            const double nrm = std::sqrt(h[8 + f]);
+            if (h[8 + f] == 0.0 && h[5 + f] == 0.0) continue;
+            res = std::max(res, std::sqrt(h[5 + f]) / (dt * std::max(nrm, 1e-30)));
+        }
+    }
+    out[0] = res;
+    out[1] = h[0];
+    out[2] = h[1];
+    out[3] = h[2];
+    out[4] = h[3];
+    out[5] = h[4];
+    out[6] = c->snap_valid ? dt : 0.0;
+    out[7] = h[11];
+    c->snap_valid = true;
+    c->t_snap = c->t;
+    if (h[11] > 0) return set_err(c, LBM_EUNSTABLE, "non-finite moments");
+    return LBM_OK;
+}
+
 lbm_status set_err(lbm_ctx* c, lbm_status s, const std::string& m) {
     if (c) c->err = m;
     return s;
@@ -718,6 +743,7 @@ lbm_status lbm_create(const lbm_params* p, size_t n_links, void* const dev_bufs[
     }
     c->cap_links = n_links;
     c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
     *out = c;
     return LBM_OK;
 }
@@ -1216,29 +1242,9 @@ lbm_status lbm_reduce(lbm_ctx* c, double out[8]) {
     if ((st = hip_check(c, hipMemcpyAsync(h, acc, sizeof h, hipMemcpyDeviceToHost, c->stream), "reduce copy")))
         return st;
     if ((st = hip_check(c, hipStreamSynchronize(c->stream), "reduce sync"))) return st;
-    const double dt = (double)(c->t - c->t_snap);
-    double res = -1.0;
-    if (c->snap_valid && dt > 0) {
-        res = 0.0;
-        for (int f = 0; f < 3; ++f) {
-            const double nrm = std::sqrt(h[8 + f]);
-            if (h[8 + f] == 0.0 && h[5 + f] == 0.0) continue;
-            res = std::max(res, std::sqrt(h[5 + f]) / (dt * std::max(nrm, 1e-30)));
-        }
-    }
-    out[0] = res;
-    out[1] = h[0];
-    out[2] = h[1];
-    out[3] = h[2];
-    out[4] = h[3];
-    out[5] = h[4];
-    out[6] = c->snap_valid ? dt : 0.0;
-    out[7] = h[11];
-    c->snap_valid = true;
-    c->t_snap = c->t;
-    if (h[11] > 0) return set_err(c, LBM_EUNSTABLE, "non-finite moments");
-    return LBM_OK;
+    return finish_reduce(c, h, out);
 }
+
 
 size_t lbm_state_bytes(const lbm_ctx* c) {
     if (!c) return 0;

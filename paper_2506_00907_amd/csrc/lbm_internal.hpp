@@ -68,7 +68,10 @@ struct KArgs {
     double norm_u, norm_b; // scale: u /= norm_u, B - B_ext /= norm_u * norm_b
     void* out;             // OBS_MOMENTS: [8][N] (out_f64 ? double : float); OBS_POPS: double
     int out_f64;
-    double* acc;           // OBS_REDUCE: FP64 accumulators [NACC]
+    double* acc;           // OBS_REDUCE: FP64 accumulators [NACC], or with acc_blocks the
+                           // per-block records [blocks][NACC]
+    int acc_blocks;        // OBS_REDUCE: 1 = each block stores its sums into its own record
+                           // of acc (no atomics), 0 = FP64 atomics into acc[0..NACC)
     void* snap;            // OBS_REDUCE: R[7][plane] snapshot of u, C - C0, B - B_ext
     int snap_valid;
     const double *init_rho, *init_u, *init_C, *init_B;

@@ -241,9 +241,12 @@ class Lattice:
         self._call("lbm_read_populations", field, C.c_void_p(out.data_ptr()))
         return out
 
-    def reduce(self) -> np.ndarray:
+    def reduce(self, static_scratch: bool = False) -> np.ndarray:
+        """lbm_reduce (static_scratch: lbm_reduce_static, the variant whose
+        scratch is the library's own device array)."""
         out = (C.c_double * 8)()
-        code = L.lib().lbm_reduce(self.ctx, out)
+        fn = L.lib().lbm_reduce_static if static_scratch else L.lib().lbm_reduce
+        code = fn(self.ctx, out)
         vals = np.array(out[:])
         if code == -4:
             raise L.LbmError(code, "non-finite values")

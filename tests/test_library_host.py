@@ -32,6 +32,10 @@ def test_library_exports_every_declared_function():
         assert n in L.SIGNATURES, n
     assert set(L.SIGNATURES) == set(names)
     assert b"gfx950" in lib.lbm_version()
+    # constants of the header that the binding mirrors
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    m = re.search(r"#define LBM_REDUCE_STATIC_MAX_BLOCKS (\d+)", src)
+    assert m and int(m.group(1)) == L.LBM_REDUCE_STATIC_MAX_BLOCKS
 
 
 def _lat_map(name):
