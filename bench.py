@@ -3,16 +3,21 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--storage f32]
 
-Default workload: the coupled D2Q9 flow + D2Q5 convection-diffusion channel,
-512 x 256 nodes, Robin-reacting walls at d = 0.3 with a per-position rate
-k ~ log-uniform[1e-3, 1e-1], pressure-driven (rho_in/rho_out = 1.001),
-tau_f = 0.8, tau_c = 0.6, FP32 storage.  One step = one fused sweep over
-every fluid node of both lattices with all boundary links.  Prints ONE JSON
-line: MLUPS (fluid nodes x steps / s / 1e6) with inputs resident in HBM, the
-roofline of the step kernel (algorithmic bytes per launch / mean launch
-duration from HIP events on the launch stream, against 8 TB/s) and the FP64
-oracle's throughput on the host cores on a bounded sample of the same
-workload.
+Default workload: the 3D MHD pipe, D3Q19 flow + D3Q7 magnetic lattice, a
+128 x 128 cross-section with a circular wall of radius 60 (per-link distances
+from the exact geometry), 64 nodes along the periodic axis, transverse field
+at Ha = 10, thin Shercliff walls of conductance ratio 0.05, FP32 storage.
+One step = the boundary-link kernel plus one fused sweep over every fluid
+node of both lattices.  Prints ONE JSON line:
+  value      MLUPS (fluid nodes x steps / s / 1e6), inputs resident in HBM;
+  roofline   the fused sweep of the same pipe 1024 nodes long (a 1.8 GB state
+             that streams from HBM): algorithmic bytes per launch / mean
+             launch duration (HIP events on the launch stream) against 8 TB/s,
+             beside the rate plain 16-byte streaming kernels attain;
+  roofline_config  the same for the benchmark pipe itself (its 0.19 GB state
+             fits the 256 MB Infinity Cache);
+  roofline_hbm_2d  the sweep of the Hartmann-Couette channel 32768 x 512;
+  cpu_baseline     the FP64 oracle on the host cores, on a bounded sample.
 """
 from __future__ import annotations
 
@@ -39,8 +44,9 @@ KERNEL_SOURCES = ("paper_2506_00907_amd/csrc/lbm_device.hpp", "paper_2506_00907_
                   "paper_2506_00907_amd/build.py")
 MEASURED_TRAFFIC = {
     # (workload, storage): (kernel source digest, bytes per launch)
-    ("reactive", "f32"): ("2eda05abf08b7b4f", 15163064.0),
-    ("hartmann_wide", "f32"): ("2eda05abf08b7b4f", 2578816534.0),
+    ("pipe_long", "f32"): ("bd55abde27e2bccb", 2466764519.0),
+    ("pipe", "f32"): ("bd55abde27e2bccb", 153601612.0),
+    ("hartmann_wide", "f32"): ("bd55abde27e2bccb", 2578809092.0),
 }
 
 
@@ -67,14 +73,23 @@ def make_scene(name: str, storage: str):
     if name == "hartmann":
         return scenes.config(3, storage=storage), "Hartmann-Couette 1024x512 (D2Q9 + D2Q5 x2)"
     if name == "pipe":
-        return scenes.config(4, storage=storage, wall="shercliff"), "MHD pipe 64x128x128 (D3Q19 + D3Q7)"
+        return (scenes.config(4, storage=storage, wall="shercliff"),
+                "MHD pipe 128x128 cross-section x 64 periodic, R = 60, Ha = 10, Shercliff c_w = 0.05 "
+                "(D3Q19 + D3Q7)")
     if name == "poiseuille":
         return scenes.config(1, storage=storage), "plane Poiseuille 64x32 (D2Q9)"
     if name == "hartmann_wide":
         return scenes.config(3, storage=storage, nx=32768), "Hartmann-Couette 32768x512 (D2Q9 + D2Q5 x2)"
     if name == "pipe_long":
-        return scenes.config(4, storage=storage, nx=1024, wall="shercliff"), "MHD pipe 1024x128x128 (D3Q19 + D3Q7)"
+        return (scenes.config(4, storage=storage, nx=1024, wall="shercliff"),
+                "MHD pipe 128x128 cross-section x 1024 periodic, R = 60, Ha = 10, Shercliff c_w = 0.05 "
+                "(D3Q19 + D3Q7)")
     raise SystemExit(f"unknown workload {name}")
+
+
+# the lattice of the same workload whose state streams from HBM (periodic
+# axis lengthened; the flow is invariant along it)
+ROOFLINE_VARIANT = {"pipe": "pipe_long", "hartmann": "hartmann_wide"}
 
 
 def links_moment_reads(links, sc) -> np.ndarray:
@@ -132,17 +147,25 @@ def algorithmic_bytes(lat) -> dict:
 
 
 def time_gpu(lat, steps: int, warmup: int):
+    """Runs `warmup` steps, captures the graphs a run of `steps` replays from
+    there (set-up, not a step), then times exactly `steps` steps with HIP
+    events on the lattice's stream.  Returns (ms, launch description)."""
     import torch
     stream = lat.stream
     lat.step(warmup)
+    lat.step_prepare(steps)
     torch.cuda.synchronize()
+    before = lat.step_stats()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
     lat.step(steps)
     t1.record(stream)
     torch.cuda.synchronize()
-    return t0.elapsed_time(t1)  # ms
+    g, gs, plain = (a - b for a, b in zip(lat.step_stats(), before))
+    launch = (f"{gs} steps in {g} hipGraph replays (up to 64 steps each; link kernel + fused sweep "
+              f"per step), {plain} steps launched singly; 256 threads/block")
+    return t0.elapsed_time(t1), launch  # ms
 
 
 def time_launches(lat, n: int = 200):
@@ -151,6 +174,48 @@ def time_launches(lat, n: int = 200):
     graph, timed with HIP events on the stream the kernels run on; the state
     is restored afterwards."""
     return lat.step_timed(n)
+
+
+def sweep_roofline(name: str, storage: str, steps: int, warmup: int, launches: int = 50):
+    """MLUPS of a workload and the roofline of its fused sweep."""
+    import torch
+    from paper_2506_00907_amd import lbm
+    sc, desc = make_scene(name, storage)
+    lat = lbm.Lattice(sc)
+    ab = algorithmic_bytes(lat)
+    ms, _ = time_gpu(lat, steps, warmup)
+    lk, sw = time_launches(lat, launches)
+    ach = ab["sweep"] / (sw / 1e3)
+    out = {"workload": desc, "storage": storage, "bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9,
+           "unit": "GB/s", "frac": ach / HBM_PEAK, "traffic": measured_traffic(name, storage),
+           "kernel": "k_step (fused stream-collide sweep), both parities", "bytes_per_launch": ab["sweep"],
+           "bytes_per_fluid_node": ab["per_fluid_node_populations"], "fluid_nodes": ab["fluid_nodes"],
+           "mean_launch_ms": sw, "state_bytes": int(sum(lat.sizes[:5])),
+           "mlups": round(ab["fluid_nodes"] * steps / (ms / 1e3) / 1e6, 1),
+           "link_kernel": {"bytes_per_launch": ab["links"], "mean_launch_ms": lk, "links": ab["n_links"]}}
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def attainable_bandwidth(nbytes: int = 1 << 31):
+    """Best rate (GB/s) of plain 16-byte-access read, write and copy kernels
+    (lbm_stream_bandwidth) over nbytes, each at 1, 4 and 16 words per
+    thread; copy counts the bytes read plus written."""
+    import torch
+    from paper_2506_00907_amd import lbm
+    out = {}
+    for kind, mult in (("read", 1), ("write", 1), ("copy", 2)):
+        best = None
+        for per in (1, 4, 16):
+            ms = lbm.stream_bandwidth(kind, nbytes, per_thread=per, reps=10)
+            rate = mult * nbytes / (ms / 1e3) / 1e9
+            if best is None or rate > best[0]:
+                best = (rate, per, ms)
+        out[kind] = {"GB/s": round(best[0], 1), "words_per_thread": best[1], "ms": best[2]}
+        torch.cuda.empty_cache()
+    out["bytes"] = nbytes
+    return out
 
 
 def bench_batch(n_items: int, steps: int, storage: str = "f16", tune: bool = True):
@@ -239,12 +304,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="reactive")
+    ap.add_argument("--workload", default="pipe")
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", action="store_true", help="add throughput of the other workloads")
     ap.add_argument("--no-hbm", action="store_true",
-                    help="leave out the sweep of the 32768x512 lattice that streams from HBM")
+                    help="leave out the sweeps of the large lattices that stream from HBM")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--batch", type=int, default=0, metavar="N",
@@ -260,33 +325,35 @@ def main():
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
-        # 1 GiB read + 1 GiB written per copy: the byte counters of this copy
-        # calibrate those of the sweep
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0.record()
-        for _ in range(10):
-            dst.copy_(src)
-        t1.record()
-        torch.cuda.synchronize()
-        ms = t0.elapsed_time(t1) / 10
+        # 1 GiB read + 1 GiB written per launch of the plain 16-byte copy
+        # kernel (k_copy of lbm_stream_bandwidth): the byte counters of this
+        # copy calibrate those of the sweep
+        ms = lbm.stream_bandwidth("copy", 1 << 30, per_thread=4, reps=3)
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "ms": ms,
                           "GB/s": 2 * (1 << 30) / (ms / 1e3) / 1e9}))
         return
     sc, desc = make_scene(args.workload, args.storage)
     lat = lbm.Lattice(sc)
     ab = algorithmic_bytes(lat)
-    ms = time_gpu(lat, args.steps, args.warmup)
+    ms, launch = time_gpu(lat, args.steps, args.warmup)
     mlups = ab["fluid_nodes"] * args.steps / (ms / 1e3) / 1e6
     link_ms, sweep_ms = time_launches(lat)
     achieved = ab["sweep"] / (sweep_ms / 1e3)
     res = lat.reduce()
     if not np.isfinite(res[1:6]).all():
         raise SystemExit("non-finite state")
+    state_bytes = int(sum(lat.sizes[:5]))
+    del lat
+    torch.cuda.empty_cache()
+    own = {"workload": desc, "storage": args.storage, "bound": "hbm", "achieved": achieved / 1e9,
+           "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
+           "traffic": measured_traffic(args.workload, args.storage),
+           "kernel": "k_step (fused stream-collide sweep), both parities",
+           "bytes_per_launch": ab["sweep"], "bytes_per_fluid_node": ab["per_fluid_node_populations"],
+           "fluid_nodes": ab["fluid_nodes"], "mean_launch_ms": sweep_ms, "state_bytes": state_bytes,
+           "regime": ("Infinity-Cache resident (state below 256 MB)" if state_bytes < (256 << 20)
+                      else "streams from HBM"),
+           "link_kernel": {"bytes_per_launch": ab["links"], "mean_launch_ms": link_ms, "links": ab["n_links"]}}
     out = {
         "metric": "MLUPS + HBM GB/s fraction; time-to-steady (fp16-store+warm-start vs plain)",
         "value": round(mlups, 1),
@@ -301,42 +368,30 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32"}[args.storage],
         "data": "synthetic (seeded scene, SplitMix64)",
         "config": {"workload": desc, "storage": args.storage, "fluid_nodes": ab["fluid_nodes"],
-                   "links": ab["n_links"],
-                   "launch": "hipGraph of 64 steps (link kernel + fused sweep each), 256 threads/block"},
-        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": measured_traffic(args.workload, args.storage),
-                     "kernel": "k_step (fused stream-collide sweep), both parities",
-                     "bytes_per_launch": ab["sweep"], "mean_launch_ms": sweep_ms,
-                     "link_kernel": {"bytes_per_launch": ab["links"], "mean_launch_ms": link_ms}},
+                   "links": ab["n_links"], "launch": launch},
     }
+    big = ROOFLINE_VARIANT.get(args.workload)
+    if big and not args.no_hbm:
+        # the same sweep over a state that does not fit the Infinity Cache
+        out["roofline"] = sweep_roofline(big, args.storage, 200, 20)
+        out["roofline"]["attainable"] = attainable_bandwidth()
+        out["roofline"]["frac_of_attainable_copy"] = \
+            out["roofline"]["achieved"] / out["roofline"]["attainable"]["copy"]["GB/s"]
+        out["roofline_config"] = own
+    else:
+        out["roofline"] = own
     if not args.no_hbm and args.workload != "hartmann_wide":
-        # The 512 x 256 channel (15 MB) stays in the 256 MB Infinity Cache and
-        # is bound by launch latency; the same sweep over a 1.28 GB state
-        # streams from HBM.  Same timing as the main roofline.
-        s2, d2 = make_scene("hartmann_wide", "f32")
-        l2 = lbm.Lattice(s2)
-        a2 = algorithmic_bytes(l2)
-        m2 = time_gpu(l2, 200, 20)
-        lk2, sw2 = time_launches(l2, 50)
-        ach2 = a2["sweep"] / (sw2 / 1e3)
-        out["roofline_hbm"] = {"workload": d2, "storage": "f32", "bound": "hbm", "achieved": ach2 / 1e9,
-                               "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": ach2 / HBM_PEAK,
-                               "traffic": measured_traffic("hartmann_wide", "f32"),
-                               "kernel": "k_step (fused stream-collide sweep), both parities",
-                               "bytes_per_launch": a2["sweep"], "mean_launch_ms": sw2,
-                               "mlups": round(a2["fluid_nodes"] * 200 / (m2 / 1e3) / 1e6, 1),
-                               "link_kernel": {"bytes_per_launch": a2["links"], "mean_launch_ms": lk2}}
-        del l2
-        torch.cuda.empty_cache()
+        out["roofline_hbm_2d"] = sweep_roofline("hartmann_wide", "f32", 200, 20)
     if args.extra:
         extra = {}
-        for w, st in (("reactive", "f16"), ("reactive", "bf16"), ("hartmann", "f32"), ("hartmann", "f16"),
+        for w, st in (("reactive", "f32"), ("reactive", "f16"), ("reactive", "bf16"), ("hartmann", "f32"),
+                      ("hartmann", "f16"),
                       ("pipe", "f32"), ("pipe", "bf16"), ("hartmann_wide", "f32"), ("hartmann_wide", "f16"),
                       ("pipe_long", "f32"), ("pipe_long", "f16"), ("pipe_long", "bf16"), ("pipe_long", "f64")):
             s2, d2 = make_scene(w, st)
             l2 = lbm.Lattice(s2)
             a2 = algorithmic_bytes(l2)
-            m2 = time_gpu(l2, 1000, 100)
+            m2, _ = time_gpu(l2, 1000, 100)
             lk2, sw2 = time_launches(l2, 50)
             extra[f"{w}_{st}"] = dict(mlups=round(a2["fluid_nodes"] * 1000 / (m2 / 1e3) / 1e6, 1),
                                       sweep_frac=a2["sweep"] / (sw2 / 1e3) / HBM_PEAK,

@@ -264,8 +264,23 @@ lbm_status lbm_set_links(lbm_ctx* ctx, const lbm_link* host_links, size_t n);
 lbm_status lbm_init(lbm_ctx* ctx, const double* dev_rho, const double* dev_u, const double* dev_C,
                     const double* dev_B);
 
-/* Advances n >= 0 steps (asynchronous). */
+/* Advances n >= 0 steps (asynchronous).  One step is the boundary-link
+ * update followed by the fused stream-collide sweep (Sections 2-4).  The
+ * first step after lbm_init is launched singly; after that the steps run as
+ * replays of captured HIP graphs: runs of 64 steps while they fit, then one
+ * run of the rest (a single remaining step is launched singly).  A graph is
+ * captured the first time a run of its start parity and length is needed;
+ * the runs of 64 and the last shorter run are kept for replay. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Captures, without running anything, the graphs that lbm_step(ctx, n) would
+ * replay from the current time, so that a later lbm_step(n) spends no time in
+ * capture (e.g. before a timed region).  Synchronous on the host. */
+lbm_status lbm_step_prepare(lbm_ctx* ctx, int64_t n);
+
+/* What lbm_step has run since lbm_create, host outputs: out[0] graph
+ * replays, out[1] steps run inside them, out[2] steps launched singly. */
+lbm_status lbm_step_stats(const lbm_ctx* ctx, int64_t out[3]);
 
 /* Durations of the two kernels of a step, for measurement: n (even, 2 to
  * 4096) launches of the boundary-link kernel back to back, captured in one
@@ -343,6 +358,20 @@ lbm_status lbm_boundary_flux(lbm_ctx* ctx, double out[5]);
 size_t lbm_state_bytes(const lbm_ctx* ctx);
 lbm_status lbm_save(lbm_ctx* ctx, void* host);
 lbm_status lbm_load(lbm_ctx* ctx, const void* host);
+
+/* Measurement utility (not a step of the method): the bandwidth a plain
+ * streaming kernel attains on the current device, the ceiling against which
+ * the sweep's share of the HBM peak is read.  kind 0 reads `bytes` from
+ * dev_src (dev_dst: a 16-byte device word the kernel may write), 1 writes
+ * `bytes` to dev_dst, 2 copies `bytes` from dev_src to dev_dst (not
+ * overlapping).  16-byte accesses, consecutive threads on consecutive words,
+ * each thread per_thread (1..1024) words at a grid stride; 256-thread blocks.
+ * One untimed launch, then reps launches back to back on hip_stream between
+ * two HIP events: *ms_out = mean duration per launch.  bytes a nonzero
+ * multiple of 16, pointers 16-byte aligned (else LBM_EINVAL).  Synchronises
+ * the stream. */
+lbm_status lbm_stream_bandwidth(int32_t kind, const void* dev_src, void* dev_dst, size_t bytes, int32_t per_thread,
+                                int32_t reps, void* hip_stream, float* ms_out);
 
 int64_t lbm_time(const lbm_ctx* ctx);
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* hip_stream);

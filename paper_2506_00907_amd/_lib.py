@@ -87,6 +87,8 @@ SIGNATURES = {
     "lbm_set_links": (C.c_int, [_VP, _VP, C.c_size_t]),
     "lbm_init": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "lbm_step": (C.c_int, [_VP, C.c_int64]),
+    "lbm_step_prepare": (C.c_int, [_VP, C.c_int64]),
+    "lbm_step_stats": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "lbm_timing_scratch_bytes": (C.c_size_t, [_VP]),
     "lbm_step_timed": (C.c_int, [_VP, C.c_int64, _VP, C.c_size_t, C.POINTER(C.c_float)]),
     "lbm_read_moments": (C.c_int, [_VP, _VP, C.c_int32]),
@@ -98,6 +100,8 @@ SIGNATURES = {
     "lbm_state_bytes": (C.c_size_t, [_VP]),
     "lbm_save": (C.c_int, [_VP, _VP]),
     "lbm_load": (C.c_int, [_VP, _VP]),
+    "lbm_stream_bandwidth": (C.c_int, [C.c_int32, _VP, _VP, C.c_size_t, C.c_int32, C.c_int32, _VP,
+                                       C.POINTER(C.c_float)]),
     "lbm_time": (C.c_int64, [_VP]),
     "lbm_set_stream": (C.c_int, [_VP, _VP]),
     "lbm_last_error": (C.c_char_p, [_VP]),

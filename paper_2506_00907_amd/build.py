@@ -24,7 +24,7 @@ ARCH = "gfx950"
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-ffp-contract=on",
           f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I" + os.path.join(os.path.dirname(PKG), "include")]
-SOURCES = ["lbm_host.cpp", "lbm_batch.cpp", "lbm_static.hip", "lbm_kernels_f64.hip", "lbm_kernels_f32.hip", "lbm_kernels_f16.hip",
+SOURCES = ["lbm_host.cpp", "lbm_batch.cpp", "lbm_static.hip", "lbm_bandwidth.hip", "lbm_kernels_f64.hip", "lbm_kernels_f32.hip", "lbm_kernels_f16.hip",
            "lbm_kernels_bf16.hip", "nn_host.cpp", "nn_kernels.hip"]
 HEADERS = ["lbm_device.hpp", "lbm_internal.hpp", "lbm_ctx.hpp", "nn_internal.hpp"]
 

@@ -48,12 +48,22 @@ struct lbm_ctx {
     bool have_geometry = false, have_links = false, initialized = false, snap_valid = false;
     std::vector<uint8_t> mask;   // domain
     std::string err;
-    // a captured run of graph_steps steps (even start parity, links ready),
-    // replayed by lbm_step on the caller's stream
-    hipGraphExec_t graph = nullptr;
+    // captured runs of steps (links ready), replayed by lbm_step on the
+    // caller's stream: graph_steps steps from an even (run[0]) or odd (run[1])
+    // time, and the last shorter run lbm_step needed (tail)
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        int parity = 0;
+        int64_t steps = 0;
+    };
+    StepGraph run[2];
+    StepGraph tail;
     hipStream_t capture_stream = nullptr;
     bool graph_failed = false;
     int graph_steps = 64;
+    // what lbm_step ran (lbm_step_stats): graph replays, steps inside them,
+    // steps as single launches
+    int64_t n_graph_launches = 0, n_graph_steps = 0, n_plain_steps = 0;
     // item of a batch: the batch owns the context and its buffers
     bool batch_owned = false;
 };

@@ -458,8 +458,10 @@ using namespace lbmh;
 namespace lbmh {
 
 void drop_graph(lbm_ctx* c) {
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
-    c->graph = nullptr;
+    for (lbm_ctx::StepGraph* g : {&c->run[0], &c->run[1], &c->tail}) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        *g = lbm_ctx::StepGraph();
+    }
 }
 
 lbm_status finish_reduce(lbm_ctx* c, const double h[12], double out[8]) {
@@ -966,31 +968,34 @@ lbm_status lbm_init(lbm_ctx* c, const double* rho, const double* u, const double
 
 namespace {
 
-// Captures graph_steps steps starting at an even time with links ready.
-// The capture runs on a private stream (the caller's stream may be the legacy
-// default stream, which cannot be captured); the launch arguments do not
-// depend on the time beyond its parity.
-lbm_status make_graph(lbm_ctx* c) {
+// Captures `steps` steps starting at a time of the given parity with links
+// ready.  The capture runs on a private stream (the caller's stream may be the
+// legacy default stream, which cannot be captured); the launch arguments do
+// not depend on the time beyond its parity: each launch reads the time of its
+// step from the time-base word, which the run advances at its end.
+lbm_status make_graph(lbm_ctx* c, int parity, int64_t steps, lbm_ctx::StepGraph* out) {
     if (!c->capture_stream) {
         if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
             c->capture_stream = nullptr;
             return LBM_EDEVICE;
         }
     }
+    if (out->exec) (void)hipGraphExecDestroy(out->exec);
+    *out = lbm_ctx::StepGraph();
     lbmi::KArgs a = base_args(c);
     a.stream = c->capture_stream;
     a.links_ready = 1;
     a.tbase = time_base(c);
     if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_EDEVICE;
     hipError_t le = hipSuccess;
-    for (int i = 0; i < c->graph_steps && le == hipSuccess; ++i) {
-        a.parity = i & 1;
+    for (int64_t i = 0; i < steps && le == hipSuccess; ++i) {
+        a.parity = (int)((parity + i) & 1);
         a.tstep = (uint32_t)i;
         le = c->ks.step(a);
     }
     if (le == hipSuccess) {
         // the time base follows the run
-        a.tstep = (uint32_t)c->graph_steps;
+        a.tstep = (uint32_t)steps;
         le = c->ks.tick(a);
     }
     hipGraph_t g = nullptr;
@@ -999,13 +1004,30 @@ lbm_status make_graph(lbm_ctx* c) {
         if (g) (void)hipGraphDestroy(g);
         return LBM_EDEVICE;
     }
-    hipError_t ie = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (ie != hipSuccess) {
-        c->graph = nullptr;
-        return LBM_EDEVICE;
-    }
+    if (ie != hipSuccess) return LBM_EDEVICE;
+    out->exec = exec;
+    out->parity = parity;
+    out->steps = steps;
     return LBM_OK;
+}
+
+// The captured run lbm_step replays next from a time of parity `par` with n
+// steps left (n >= 2): graph_steps steps when n allows, else all n.  Captures
+// it when missing; null when capture failed (lbm_step then launches singly).
+lbm_ctx::StepGraph* run_for(lbm_ctx* c, int par, int64_t n) {
+    if (c->graph_failed) return nullptr;
+    lbm_ctx::StepGraph* g = n >= c->graph_steps ? &c->run[par] : &c->tail;
+    const int64_t steps = n >= c->graph_steps ? c->graph_steps : n;
+    if (g->exec && g->parity == par && g->steps == steps) return g;
+    if (make_graph(c, par, steps, g) != LBM_OK) {
+        c->graph_failed = true;  // fall back to single launches of the same kernels
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return g;
 }
 
 lbm_status step_launches(lbm_ctx* c, int64_t n) {
@@ -1027,33 +1049,58 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     if (!c) return LBM_EINVAL;
     if (n < 0) return set_err(c, LBM_EINVAL, "negative step count");
     if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
-    // single launches until the time is even and positive
-    while (n > 0 && (c->t == 0 || (c->t & 1))) {
-        lbm_status st = step_launches(c, 1);
-        if (st) return st;
+    lbm_status st;
+    // the first step reads the initial populations (no link values yet)
+    if (n > 0 && c->t == 0) {
+        if ((st = step_launches(c, 1))) return st;
+        c->n_plain_steps++;
         --n;
     }
-    const int64_t G = c->graph_steps;
-    if (n >= G && !c->graph_failed) {
-        if (!c->graph && make_graph(c) != LBM_OK) {
-            c->graph_failed = true;  // fall back to plain launches of the same kernels
-            (void)hipGetLastError();
-        }
-        if (c->graph && n >= G) {
-            // runs start from the context's time
+    // captured runs: graph_steps steps while they fit, then one run of the
+    // rest; runs start from the context's time, whatever its parity
+    bool timed = false;
+    while (n >= 2) {
+        lbm_ctx::StepGraph* g = run_for(c, (int)(c->t & 1), n);
+        if (!g) break;
+        if (!timed) {
             lbmi::KArgs a = base_args(c);
             a.tbase = time_base(c);
-            lbm_status st = hip_check(c, c->ks.set_time(a), "time base");
-            if (st) return st;
+            a.tstep = (uint32_t)c->t;
+            if ((st = hip_check(c, c->ks.set_time(a), "time base"))) return st;
+            timed = true;
         }
-        while (c->graph && n >= G) {
-            lbm_status st = hip_check(c, hipGraphLaunch(c->graph, c->stream), "graph launch");
-            if (st) return st;
-            c->t += G;
-            n -= G;
-        }
+        if ((st = hip_check(c, hipGraphLaunch(g->exec, c->stream), "graph launch"))) return st;
+        c->t += g->steps;
+        n -= g->steps;
+        c->n_graph_launches++;
+        c->n_graph_steps += g->steps;
     }
+    c->n_plain_steps += n;
     return step_launches(c, n);
+}
+
+lbm_status lbm_step_prepare(lbm_ctx* c, int64_t n) {
+    if (!c) return LBM_EINVAL;
+    if (n < 0) return set_err(c, LBM_EINVAL, "negative step count");
+    if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
+    int64_t t = c->t;
+    if (n > 0 && t == 0) {
+        ++t;
+        --n;
+    }
+    // graph_steps is even: every full run starts at the same parity
+    if (n >= c->graph_steps && !run_for(c, (int)(t & 1), n)) return set_err(c, LBM_EDEVICE, "graph capture");
+    const int64_t r = n % c->graph_steps;
+    if (r >= 2 && !run_for(c, (int)((t + n - r) & 1), r)) return set_err(c, LBM_EDEVICE, "graph capture");
+    return LBM_OK;
+}
+
+lbm_status lbm_step_stats(const lbm_ctx* c, int64_t out[3]) {
+    if (!c || !out) return LBM_EINVAL;
+    out[0] = c->n_graph_launches;
+    out[1] = c->n_graph_steps;
+    out[2] = c->n_plain_steps;
+    return LBM_OK;
 }
 
 namespace {

@@ -123,6 +123,22 @@ def required_bytes(p: L.lbm_params, n_links: int):
     return list(sizes)
 
 
+def stream_bandwidth(kind: str, nbytes: int, per_thread: int = 4, reps: int = 10, device="cuda:0"):
+    """lbm_stream_bandwidth: mean ms per launch of a plain 16-byte-access
+    read, write or copy kernel over nbytes (torch-allocated buffers)."""
+    import torch
+    k = {"read": 0, "write": 1, "copy": 2}[kind]
+    dev = torch.device(device)
+    src = torch.ones(nbytes // 4 if k != 1 else 1, dtype=torch.int32, device=dev)
+    dst = torch.zeros(nbytes // 4 if k != 0 else 4, dtype=torch.int32, device=dev)
+    out = C.c_float()
+    stream = torch.cuda.current_stream(dev)
+    code = L.lib().lbm_stream_bandwidth(k, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), int(nbytes),
+                                        int(per_thread), int(reps), C.c_void_p(stream.cuda_stream), C.byref(out))
+    L.check(code)
+    return float(out.value)
+
+
 def _torch_device(torch, device):
     if not torch.cuda.is_available():
         raise RuntimeError("liblbm needs a HIP device")
@@ -205,6 +221,16 @@ class Lattice:
 
     def step(self, n: int = 1):
         self._call("lbm_step", int(n))
+
+    def step_prepare(self, n: int):
+        """lbm_step_prepare: capture the graphs a later step(n) replays."""
+        self._call("lbm_step_prepare", int(n))
+
+    def step_stats(self):
+        """lbm_step_stats: (graph replays, steps inside them, single steps)."""
+        out = (C.c_int64 * 3)()
+        self._call("lbm_step_stats", out)
+        return int(out[0]), int(out[1]), int(out[2])
 
     def step_timed(self, n: int):
         """lbm_step_timed: mean (link kernel, sweep kernel) durations in ms.

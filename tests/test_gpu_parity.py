@@ -261,6 +261,31 @@ def test_kernel_timing_leaves_the_state_unchanged():
         assert np.array_equal(a.read_populations(f).cpu().numpy(), b.read_populations(f).cpu().numpy())
 
 
+@pytest.mark.parametrize("storage", ["f16", "f32"])
+def test_graph_runs_of_any_length_match_single_steps(storage):
+    """lbm_step replays captured runs of 64 steps and one run of the rest,
+    from either parity: the state equals that of single launches bit for bit
+    (FP16 also checks each step's time, which its stochastic rounding
+    hashes), and lbm_step_stats counts what ran."""
+    _case(f"graph runs {storage}")
+    from paper_2506_00907_amd import lbm
+    sc = scenes.developed(scenes.hartmann_couette(nx=10, ny=13, c_top=0.1, storage=storage))
+    a, b = lbm.Lattice(sc), lbm.Lattice(sc)
+    chunks = [1, 5, 67, 2, 130, 1, 3]
+    for n in chunks:
+        b.step_prepare(n)
+        b.step(n)
+    for _ in range(sum(chunks)):
+        a.step(1)
+    assert a.time == b.time == sum(chunks)
+    for f in (0, 2):
+        assert np.array_equal(a.read_populations(f).cpu().numpy(), b.read_populations(f).cpu().numpy()), f
+    # runs: 5 (tail), 64 + 3 (tail), 2 (tail), 64 + 64 + 2 (tail), 3 (tail);
+    # single: the first step and the lone step
+    assert b.step_stats() == (8, 1 + 5 + 67 + 2 + 130 + 3 - 1, 2)
+    assert a.step_stats() == (0, 0, sum(chunks))
+
+
 def test_reduce_mass_and_residual():
     _case("reduce")
     sc = scenes.poiseuille(nx=8, ny=12, storage="f64")

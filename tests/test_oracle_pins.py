@@ -959,3 +959,111 @@ def test_extrapolated_forms_lose_stability_at_large_d():
     assert not _stays_bounded(scenes.open_box(q_out=0.9, alt_out=True), 10000)
     assert not _stays_bounded(scenes.open_box(q_in=0.6, alt_in=True), 2000)
     assert _stays_bounded(scenes.open_box(q_in=1.0, q_out=1.0), 10000)
+
+
+# ---------------------------------------------------------------------------
+# Phase of an oscillating wall (Section 4.1, Eq. 45): brute force on a tiny
+# channel.  With a wall speed U ~ 1e-8 the scheme is linear in the deviation
+# from rest to ~1e-8, so its time-periodic state solves one complex linear
+# system: s(t + 1) = M s(t) + b cos(omega t'), s(t) = Re(X e^{i omega t}),
+# X = (e^{i omega} I - M)^{-1} b e^{i omega (t' - t)}.  M (collision,
+# streaming, the static and the moving wall's link forms) is assembled below
+# from the paper's equations, independently of the oracle, and t' is the
+# time the bounced population met the wall: t' = t + 1 - d for the value
+# entering A at t + 1.
+# ---------------------------------------------------------------------------
+_E9 = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]])
+_W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+_OPP9 = [0, 3, 4, 1, 2, 7, 8, 5, 6]
+
+
+def _periodic_channel_state(ny, tau, d, U, omega, phase_lag):
+    """Periodic state X (complex, [9][ny]) of the linearised D2Q9 channel:
+    static wall below row 0, wall above row ny - 1 moving at U cos(omega t'),
+    both at distance d; t' = t + 1 - phase_lag for the link value written in
+    the step from t to t + 1."""
+    n = 9 * ny
+    idx = lambda a, y: a * ny + y
+    cs2 = 1.0 / 3.0
+    # collision (linear in the deviation): x* = x - (x - w (rho + e.j / cs2)) / tau
+    K = np.eye(n) * (1.0 - 1.0 / tau)
+    for y in range(ny):
+        for a in range(9):
+            for b in range(9):
+                K[idx(a, y), idx(b, y)] += _W9[a] * (1.0 + (_E9[a] @ _E9[b]) / cs2) / tau
+    S = np.zeros((n, n))     # streaming and link rows acting on x*
+    bvec = np.zeros(n)       # coefficient of cos(omega t') in the moving wall's links
+    for y in range(ny):
+        for a in range(9):
+            src = y - _E9[a][1]
+            if 0 <= src < ny:
+                S[idx(a, y), idx(a, src)] = 1.0
+                continue
+            ap = _OPP9[a]
+            E = y + _E9[a][1]  # x is periodic (one column)
+            moving = src >= ny
+            delta = 2.0 * _W9[a] * (_E9[a][0] * U) / cs2 if moving else 0.0
+            if d < 0.5:  # Eqs. 15-16
+                S[idx(a, y), idx(ap, E)] += 1.0 - 2.0 * d
+                S[idx(a, y), idx(ap, y)] += 2.0 * d
+                bvec[idx(a, y)] = delta
+            else:  # Eq. 43
+                S[idx(a, y), idx(a, y)] += (2.0 * d - 1.0) / (2.0 * d)
+                S[idx(a, y), idx(ap, y)] += 1.0 / (2.0 * d)
+                bvec[idx(a, y)] = delta / (2.0 * d)
+    M = S @ K
+    X = np.linalg.solve(np.exp(1j * omega) * np.eye(n) - M, bvec * np.exp(1j * omega * (1.0 - phase_lag)))
+    return X.reshape(9, ny)
+
+
+@pytest.mark.parametrize("d", [0.3, 0.5, 0.8])
+def test_oscillating_wall_phase_by_brute_force(d):
+    ny, tau, U, period = 4, 0.8, 1e-8, 20
+    omega = 2 * math.pi / period
+    sc = scenes.stokes_second(nx=1, ny=ny, tau=tau, U=U, period=period, q=d, storage="f64")
+    o = oracle.OracleSim(sc, "ld")
+    T = 40 * period + 7
+    o.step(T)
+    eo, _, _, _ = oracle.lattice_table("D2Q9")
+    m = [[b for b in range(9) if np.array_equal(eo[b][:2], _E9[a])][0] for a in range(9)]
+    P = o.populations(0)[:, 0, :, 0]
+    dev = np.array([P[m[a]] - _W9[a] for a in range(9)])
+    errs = {}
+    for name, lag in (("t+1-d", d), ("t+1", 0.0), ("t", 1.0)):
+        X = _periodic_channel_state(ny, tau, d, U, omega, lag)
+        ref = np.real(X * np.exp(1j * omega * T))
+        errs[name] = np.linalg.norm(dev - ref) / np.linalg.norm(ref)
+    assert errs["t+1-d"] < 1e-6, errs
+    # the other phase conventions are far off: the pin tells them apart
+    assert errs["t+1"] > 1e-2 and errs["t"] > 1e-2, errs
+
+
+@pytest.mark.parametrize("lo,hi", [((2.3, 1.6, 4.2), (3.7, 2.45, 6.9)), ((1.37, 0.81, 3.61), (3.83, 2.29, 7.07))])
+def test_box_link_distances_bruteforce(lo, hi):
+    """Links into an off-grid solid block (faces at fractional node
+    coordinates; links through faces, edges and corners): d is where the
+    segment from A towards A - e_alpha first enters the closed block, found
+    here by bisection."""
+    sc = scenes.channel_reservoirs("half", width=4, res_len=3, ch_len=6)
+    blk = scenes.Boundary("box", axis=2, lo=lo, hi=hi, f=scenes.BC(scenes.VEL))
+    sc = sc.with_(boundaries=sc.boundaries + [blk])
+    o = oracle.OracleSim(sc)
+    e19, _, _, _ = oracle.lattice_table("D3Q19")
+    nx, ny, nz = sc.n
+    L = o.links()
+    mine = L[L["bnd"] == len(sc.boundaries) - 1]
+    assert len(mine) >= 30
+    ds = set()
+    for lk in mine:
+        A = int(lk["A"])
+        p = np.array([A % nx, (A // nx) % ny, A // (nx * ny)], float)
+        e = e19[lk["dir"]]
+        inside = lambda s: all(lo[k] <= p[k] - s * e[k] <= hi[k] for k in range(3))
+        assert not inside(0.0) and inside(1.0)
+        a, b = 0.0, 1.0
+        for _ in range(80):
+            mid = 0.5 * (a + b)
+            a, b = (a, mid) if inside(mid) else (mid, b)
+        assert abs(lk["d"] - b) < 1e-12, (lk["d"], b)
+        ds.add(round(float(lk["d"]), 6))
+    assert len(ds) >= 5, ds
