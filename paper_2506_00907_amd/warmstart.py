@@ -115,15 +115,19 @@ def init_fields(item, mask: np.ndarray, pred: np.ndarray):
 # ---------------------------------------------------------------------------
 def solve(items, storage: str = "f16", tol: float = 1e-8, interval: int = 1000, max_steps: int = 2_000_000,
           chunk: int = 20_000, inits: Optional[list] = None, tune: bool = True, log=print,
-          max_seconds: float = float("inf"), stall: Optional[float] = None):
+          max_seconds: float = float("inf"), stall: Optional[float] = None, retune: bool = True):
     """Runs every item to its steady state with lbm_batch_run in chunks of
     `chunk` steps (items that finish are disabled between chunks).
     inits[i] = (u, B) initial fields or None for rest; the solve also stops
     after max_seconds (checked between chunks).  With stall = s, an item whose
     residual fell by less than the factor s over a chunk (the noise floor of
-    its storage format) stops with status "stalled".  Returns a dict with
-    per-item steps, residuals and statuses, the batch (for readback) and the
-    wall time of the solve (synchronised, excluding set-up)."""
+    its storage format, or the mass drift of interpolated walls) stops with
+    status "stalled".  With tune and retune, the launch configuration is
+    tuned at the start and tuned again whenever the active items have halved
+    (a few large items left run best with other tiles than the full batch).
+    Returns a dict with per-item steps, residuals and statuses, the batch
+    (for readback), the wall time of the solve (synchronised, excluding
+    set-up) and the configurations tuned."""
     import torch
     from . import lbm
     scs = [it.scene.with_(storage=storage) for it in items]
@@ -136,10 +140,11 @@ def solve(items, storage: str = "f16", tol: float = 1e-8, interval: int = 1000, 
             lat.init()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tuned = None
+    tuned = []
     if tune:
-        tuned = B.tune(trial_steps=64)[0]
+        tuned.append(dict(active=len(items), config=B.tune(trial_steps=64)[0]))
     n = len(items)
+    n_tuned = n
     steps = np.zeros(n, np.int64)
     res = np.full(n, -1.0)
     status = ["active"] * n
@@ -161,6 +166,10 @@ def solve(items, storage: str = "f16", tol: float = 1e-8, interval: int = 1000, 
                     status[i] = "stalled"
         done += k
         n_act = sum(s == "active" for s in status)
+        if tune and retune and 0 < n_act <= n_tuned // 2 and done < max_steps:
+            B.set_active([s == "active" for s in status])
+            tuned.append(dict(active=n_act, config=B.tune(trial_steps=64)[0]))
+            n_tuned = n_act
         log(f"  [{storage}] {done} steps: {n - n_act}/{n} items finished, "
             f"max residual of the rest {max([r for r, s in zip(res, status) if s == 'active'] or [0]):.2e}, "
             f"{time.perf_counter() - t0:.1f} s")

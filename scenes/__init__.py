@@ -500,23 +500,29 @@ FLUX_SLOPE_MAX = 0.3
 def batch_items(n_items: int = 256, seed: int = BASE_SEED + 5, side_lo: int = 64,
                 side_hi: int = 256, Ha_hi: float = 50.0, c_lo: float = 1e-3, c_hi: float = 10.0,
                 tau_f: float = 0.8, tau_m: float = 0.9, u_target: float = 0.01,
-                storage: str = "f16") -> List[BatchItem]:
+                storage: str = "f16", ducts_only: bool = False,
+                q_duct: Optional[float] = None) -> List[BatchItem]:
     """Uneven duct / pipe cross-sections (axial extent 1, periodic) for the
     batched solver: D3Q19 fluid + D3Q7 magnetic lattice evolving B1 only,
     B_ext along y, thin walls of conductance ratio c_w everywhere (raised to
-    the stable floor where needed, see FLUX_SLOPE_MAX)."""
+    the stable floor where needed, see FLUX_SLOPE_MAX).  ducts_only makes
+    every item a duct and q_duct puts every duct wall at that distance (the
+    draws are made as usual, so the other parameters do not change)."""
     rng = SplitMix64(seed)
     nu, eta = _nu(tau_f), _diff(tau_m)
     c_min = lambda H: eta / (FLUX_SLOPE_MAX * H)
     items = []
     for i in range(n_items):
         shape = "duct" if rng.uniform() < 0.5 else "pipe"
+        shape = "duct" if ducts_only else shape
         Ha = rng.uniform(0.0, Ha_hi)
         c_w = rng.log_uniform(c_lo, c_hi)
         if shape == "duct":
             a = rng.randint(side_lo, side_hi)
             b = rng.randint(side_lo, side_hi)
             qs = tuple(rng.uniform(0.1, 0.9) for _ in range(4))
+            if q_duct is not None:
+                qs = (q_duct,) * 4
             Hy = (a - 1 + qs[0] + qs[1]) / 2.0
             Hz = (b - 1 + qs[2] + qs[3]) / 2.0
             Hmin = min(Hy, Hz)

@@ -118,10 +118,11 @@ def test_batch_of_2d_channels_equals_alone(mode):
     assert_items_equal_alone(B, scs, 71)
 
 
-def test_batch_fp64_item_matches_oracle():
+@pytest.mark.parametrize("mode", [("resident", 256, 8, 64), ("tiled", 128, 1, 64)])
+def test_batch_fp64_item_matches_oracle(mode):
     scs = duct_pipe_items("f64", n=3, lo=16, hi=24)
     B = lbm.Batch(scs)
-    B.configure("resident", 256, 8, 64)
+    B.configure(*mode)
     B.step(66)
     for i, sc in enumerate(scs):
         o = oracle.OracleSim(sc, "ld")

@@ -212,17 +212,6 @@ def test_full_poiseuille_fp64_matches_oracle_and_closed_form():
     assert np.abs(mg[0, :, :, 1] - ex[:, None]).max() / ex.max() < 1e-7
 
 
-@pytest.mark.parametrize("cfg,steps", [(2, 200), (3, 100), (4, 40)])
-def test_full_size_fp32_parity(cfg, steps):
-    _case(f"full size config {cfg} fp32, {steps} steps")
-    sc = scenes.developed(scenes.config(cfg, storage="f32"))
-    lat, o = run_pair(sc, steps)
-    errs = field_errors(gpu_moments(lat), o.moments(), o.mask(), sc.B_ext)
-    print(cfg, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
-    for f, e in errs.items():
-        assert e < 1e-5, (f, e)
-
-
 # ---------------------------------------------------------------------------
 # state handling, reductions, failure detection
 # ---------------------------------------------------------------------------

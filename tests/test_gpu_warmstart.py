@@ -1,0 +1,114 @@
+"""What the trained warm-start network gains over the method without it.
+
+The network is trained here, on the GPU, by the library's own forward,
+backward and Adam kernels, on steady fields that the batched solver itself
+computes for small seeded duct cross-sections.  On held-out
+sections the lattice update then runs from the network's prediction and
+from rest: the prediction must need fewer steps,
+and both runs must converge to the same fields (the network changes only
+where the iteration starts).  Progress is measured as the field error
+against the FP64 steady state: the steps each start needs to bring it below
+1e-3."""
+import numpy as np
+import pytest
+
+import scenes
+from paper_2506_00907_amd import lbm
+from paper_2506_00907_amd import warmstart as ws
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SIZE = 32          # canvas of the network (sections up to 32 x 32)
+# ducts with half-way walls: mass is conserved exactly (Section 4.1), so every
+# section has a steady state to converge to (interpolated walls drift slowly
+# in mass and have none below a residual floor)
+KW = dict(side_lo=20, side_hi=32, c_lo=1e-2, c_hi=1.0, Ha_hi=20.0, storage="f32", ducts_only=True, q_duct=0.5)
+
+
+def _dataset(items, sol):
+    X = torch.empty((len(items), SIZE, SIZE, ws.IN_CH), dtype=torch.float32, device="cuda")
+    T = torch.empty((len(items), SIZE, SIZE, ws.OUT_CH), dtype=torch.float32, device="cuda")
+    W = torch.empty((len(items), SIZE, SIZE), dtype=torch.float32, device="cuda")
+    moms = ws.moments_of(sol["batch"])
+    for i, it in enumerate(items):
+        m = sol["batch"].items[i].mask
+        X[i] = torch.from_numpy(ws.features(it, m, SIZE))
+        t, w = ws.targets(it, m, moms[i], SIZE)
+        T[i] = torch.from_numpy(t)
+        W[i] = torch.from_numpy(w)
+    return X, T, W
+
+
+def test_trained_network_reaches_the_steady_state_in_fewer_steps():
+    quiet = lambda *_: None
+    print("\n[case] warm start: train on 64 solved sections, evaluate on 12 held-out", flush=True)
+    train_items = scenes.batch_items(64, seed=scenes.BASE_SEED + 60, **KW)
+    sol = ws.solve(train_items, "f32", tol=1e-7, interval=200, max_steps=400_000, chunk=20_000, log=quiet)
+    assert all(s == "steady" for s in sol["status"]), sol["status"]
+    X, T, W = _dataset(train_items, sol)
+    del sol
+    net, hist = ws.train(X, T, W, epochs=60, batch=16, lr=2e-3, size=SIZE, log=quiet)
+    print(f"loss {hist[0]:.3e} -> {hist[-1]:.3e}", flush=True)
+    assert hist[-1] < 0.2 * hist[0]
+
+    held = scenes.batch_items(12, seed=scenes.BASE_SEED + 61, **KW)
+    masks = [lbm.build_links(it.scene)[0] for it in held]
+    Xh = torch.stack([torch.from_numpy(ws.features(it, masks[i], SIZE)) for i, it in enumerate(held)]).cuda()
+    pred = ws.predict(net, Xh).cpu().numpy()
+    inits = [ws.init_fields(it, masks[i], pred[i]) for i, it in enumerate(held)]
+    # reference: the steady state in FP64
+    ref = ws.solve(held, "f64", tol=1e-11, interval=1000, max_steps=1_000_000, tune=False, log=quiet)
+    ok = np.array([s == "steady" for s in ref["status"]])
+    assert ok.all(), ref["status"]
+    ref_m = ws.moments_of(ref["batch"])
+    del ref
+
+    def error(i, m):
+        """relative L2 of (u_x, b_x) over the fluid nodes against the reference"""
+        sel = masks[i].astype(bool).reshape(m.shape[:3])
+        Bx = held[i].scene.B_ext[0]
+        a = np.concatenate([m[..., 1][sel], m[..., 5][sel] - Bx])
+        b = np.concatenate([ref_m[i][..., 1][sel], ref_m[i][..., 5][sel] - Bx])
+        return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+    def steps_to(level, init, chunk=100, cap=40_000):
+        """steps of the FP32 update until each item's error is below level"""
+        B = lbm.Batch([it.scene for it in held], init=False)
+        for i, lat in enumerate(B.items):
+            lat.init(None, *init[i]) if init is not None else lat.init()
+        B.step(2)
+        reached = np.full(len(held), -1)
+        t = 2
+        while (reached < 0).any() and t < cap:
+            B.set_active(reached < 0)
+            B.step(chunk)
+            t += chunk
+            for i in np.where(reached < 0)[0]:
+                if error(i, B.items[i].read_moments("f64").cpu().numpy().transpose(1, 2, 3, 0)) < level:
+                    reached[i] = t
+        return reached, B
+
+    e0 = np.array([error(i, np.concatenate([np.ones(ref_m[i].shape[:3] + (1,)), u, np.zeros(u.shape[:3] + (1,)), B],
+                                           axis=-1)) for i, (u, B) in enumerate(inits)])
+    print("prediction error", np.round(e0, 3).tolist(), flush=True)
+    level = 1e-3
+    sc, Bc = steps_to(level, None)
+    sw, Bw = steps_to(level, inits)
+    print(f"steps to error {level:g}: from rest", sc.tolist(), "from the network", sw.tolist(), flush=True)
+    sc, sw = sc[ok], sw[ok]
+    assert (sc > 0).all() and (sw > 0).all()
+    # fewer steps in total and for most sections
+    assert sw.sum() < 0.7 * sc.sum(), (sw.sum(), sc.sum())
+    assert (sw < sc).mean() >= 0.75, (sw, sc)
+    # the network changes where the iteration starts, not where it ends: both
+    # runs continue to the same steady fields
+    for Bx in (Bc, Bw):
+        Bx.set_active(np.ones(len(held), bool))
+        Bx.step(30_000)
+    for i in np.where(ok)[0]:
+        mc = Bc.items[i].read_moments("f64").cpu().numpy().transpose(1, 2, 3, 0)
+        mw = Bw.items[i].read_moments("f64").cpu().numpy().transpose(1, 2, 3, 0)
+        ec, ew = error(i, mc), error(i, mw)
+        assert ec < 1e-4 and ew < 1e-4, (i, ec, ew)
