@@ -178,22 +178,79 @@ __device__ __forceinline__ uint32_t dither(uint32_t node, uint32_t slot, uint32_
     h ^= h >> 16;
     return h;
 }
-
-template <class SF>
-__device__ __forceinline__ void st_sr(typename SF::T* p, uint32_t i, typename SF::R v, uint32_t r) {
-    st<SF>(p, i, v);
+// the sweep's per-store random bits: the node's hash hn mixed with the slot
+__device__ __forceinline__ uint32_t slot_dither(uint32_t hn, int slot) {
+    uint32_t h = hn + (uint32_t)slot * 0x9E3779B9u;
+    h ^= h >> 16;
+    h *= 0x7FEB352Du;
+    h ^= h >> 15;
+    return h;
 }
-template <> __device__ __forceinline__ void st_sr<F16S>(uint16_t* p, uint32_t i, float v, uint32_t r) {
+
+// the stored form of v (16-bit formats: stochastically rounded with the
+// random bits r)
+template <class SF>
+__device__ __forceinline__ typename SF::T to_store(typename SF::R v, uint32_t r) {
+    return v;
+}
+template <> __device__ __forceinline__ uint16_t to_store<F16S>(float v, uint32_t r) {
     uint32_t b = __builtin_bit_cast(uint32_t, v);
     const uint32_t e = (b >> 23) & 0xFFu;
     // normal FP16 range below the largest binade: dither the 13 dropped bits
     if (e >= 113u && e < 142u) b = (b + (r & 0x1FFFu)) & ~0x1FFFu;
-    at(p, i) = __builtin_bit_cast(uint16_t, (_Float16)__builtin_bit_cast(float, b));
+    return __builtin_bit_cast(uint16_t, (_Float16)__builtin_bit_cast(float, b));
 }
-template <> __device__ __forceinline__ void st_sr<BF16S>(uint16_t* p, uint32_t i, float v, uint32_t r) {
+template <> __device__ __forceinline__ uint16_t to_store<BF16S>(float v, uint32_t r) {
     uint32_t b = __builtin_bit_cast(uint32_t, v);
     if (((b >> 23) & 0xFFu) < 0xFEu) b += r & 0xFFFFu;  // finite and not next to overflow
-    at(p, i) = (uint16_t)(b >> 16);
+    return (uint16_t)(b >> 16);
+}
+template <class SF>
+__device__ __forceinline__ void st_sr(typename SF::T* p, uint32_t i, typename SF::R v, uint32_t r) {
+    if (sizeof(typename SF::T) == 2) at(p, i) = to_store<SF>(v, r);
+    else st<SF>(p, i, v);
+}
+// the value of a stored element
+template <class SF> __device__ __forceinline__ typename SF::R from_store(typename SF::T t) { return t; }
+template <> __device__ __forceinline__ float from_store<F16S>(uint16_t t) {
+    return (float)__builtin_bit_cast(_Float16, t);
+}
+template <> __device__ __forceinline__ float from_store<BF16S>(uint16_t t) {
+    return __builtin_bit_cast(float, (uint32_t)t << 16);
+}
+
+// 8 bytes of consecutive elements of a plane, as two 32-bit words, at the
+// alignment of one element (the odd-step gathers and scatters of the K-node
+// sweep are shifted by one element along x)
+typedef uint32_t u32x2_a2 __attribute__((ext_vector_type(2), aligned(2)));
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+template <class T>
+__device__ __forceinline__ void ld8(const T* p, uint32_t i, uint32_t w[2]) {
+    const char* a = reinterpret_cast<const char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T));
+    if (sizeof(T) == 2) {
+        const u32x2_a2 v = *reinterpret_cast<const u32x2_a2*>(a);
+        w[0] = v.x;
+        w[1] = v.y;
+    } else {
+        const u32x2_a4 v = *reinterpret_cast<const u32x2_a4*>(a);
+        w[0] = v.x;
+        w[1] = v.y;
+    }
+}
+template <class T>
+__device__ __forceinline__ void st8(T* p, uint32_t i, const uint32_t w[2]) {
+    char* a = reinterpret_cast<char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T));
+    if (sizeof(T) == 2) {
+        u32x2_a2 v;
+        v.x = w[0];
+        v.y = w[1];
+        *reinterpret_cast<u32x2_a2*>(a) = v;
+    } else {
+        u32x2_a4 v;
+        v.x = w[0];
+        v.y = w[1];
+        *reinterpret_cast<u32x2_a4*>(a) = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -596,7 +653,7 @@ __device__ __forceinline__ void gather(const Geo& G, const Phys<typename C::R>& 
 
 // Everything after the gather: moments, moment store of link nodes,
 // collision, scatter.  MODE 0: full step; MODE 1: observe (moments only).
-template <class C, int ODD, int MODE>
+template <class C, int ODD, int MODE, bool SCATTER = true>
 __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& P, typename C::T* __restrict__ S,
                                        uint8_t fl, typename C::R* __restrict__ M,
                                        const Nbr& q, NodeRes<C>& res, uint32_t seed) {
@@ -753,16 +810,15 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
         }
     }
 
+    if (!SCATTER) return;  // the K-node sweep stores K nodes' values at once
+
     // ---- scatter (streaming); 16-bit formats round stochastically with a
-    // dither of (slot, destination node, time) ----
-    // one full hash of (node, time), then one multiply per store mixes in the slot
+    // dither of (writing node, time), then the slot ----
+    // one full hash of (writing node n, time), then one multiply-xorshift
+    // round per store mixes in the slot
     const uint32_t hn = C::SCALED ? dither(n, 0u, seed) : 0u;
     auto put = [&](int slot, uint32_t dest, R v) {
-        uint32_t h = hn + (uint32_t)slot * 0x9E3779B9u;
-        h ^= h >> 16;
-        h *= 0x7FEB352Du;
-        h ^= h >> 15;
-        st_sr<SF>(plane(slot), dest, v, C::SCALED ? h : 0u);
+        st_sr<SF>(plane(slot), dest, v, C::SCALED ? slot_dither(hn, slot) : 0u);
     };
 #pragma unroll
     for (int i = 0; i < QF; ++i) {

@@ -77,7 +77,7 @@ def cmd_train(a):
     items = scenes.batch_items(a.items, seed=TRAIN_SEED)
     log(f"[train] solving {len(items)} training items (FP16 batch, tol {a.tol:g})")
     sol = ws.solve(items, "f16", tol=a.tol, interval=a.interval, max_steps=a.max_steps, chunk=a.chunk, log=log,
-                   max_seconds=a.max_seconds)
+                   max_seconds=a.max_seconds, stall=0.5)
     log(f"[train] solved in {sol['seconds']:.1f} s; statuses {dict(zip(*np.unique(sol['status'], return_counts=True)))}")
     mom = ws.moments_of(sol["batch"])
     X, T, W = dataset(items, sol["batch"], mom, a.size)
@@ -339,9 +339,75 @@ def cmd_eval(a):
     log(json.dumps(brief, default=str))
 
 
+def cmd_report(a):
+    """Markdown summary of eval.json (and train.json) for the design notes."""
+    ev = json.load(open(a.eval))
+    tr = json.load(open(a.train)) if a.train else None
+    ref_ok = np.array([st == "steady" for st in ev["reference"]["status"]])
+    raised = np.array([row["raised"] for row in ev["item_table"]])
+    out = []
+    w = out.append
+    w(f"# Time to steady state: {ev['items']} duct / pipe cross-sections (seed {ev['seed']})")
+    w("")
+    w(f"Residual rule: R16 over {ev['interval']} steps below {ev['tol']:g} (FP16 phase: {ev['tol_fp16']:g}). "
+      f"Reference: FP64 from the FP32 batch's state to {ev['ref_tol']:g}; "
+      f"{int(ref_ok.sum())} of {len(ref_ok)} references reach it "
+      f"({int((ref_ok & raised).sum())} of them with a raised wall conductance).")
+    w("")
+    pl = ev.get("plain")
+    w("| Variant | seconds at the residual rule | speed-up | seconds at equal error | speed-up | "
+      "items within the rule (reference-converged, at equal error) | of them not raised | raised | "
+      "median error / plain |")
+    w("|---|---|---|---|---|---|---|---|---|")
+    if pl:
+        w(f"| plain: FP32, one item at a time, rest start | {pl['seconds']:.1f} | 1.00 | {pl['seconds']:.1f} | 1.00 "
+          f"| — | — | — | 1 |")
+    b = ev["batch"]
+    st = b.get("at_residual", {}).get("all", {})
+    w(f"| batch: FP32, all items, rest start | {b['seconds']:.1f} | {b.get('speedup_vs_plain_at_residual', 0):.2f} "
+      f"| — | — | {st.get('equal', float('nan')):.2f} (at the residual rule) | — | — | "
+      f"{st.get('median_ratio', float('nan')):.2f} |")
+    for label, name in (("cold", "cold: FP16 batch, then FP32 polish"),
+                        ("warm", "warm: network, FP16 batch, then FP32 polish")):
+        v = ev[label]
+        eq = v.get("equal_error", {})
+        if not eq:
+            continue
+        w(f"| {name} | {v['total_seconds']:.1f} | {v.get('speedup_vs_plain_at_residual', 0):.2f} | "
+          f"{eq['total_seconds']:.1f} | {eq.get('speedup_vs_plain', 0):.2f} | {eq['all']['equal']:.2f} "
+          f"({eq['all']['not_worse']:.2f} not worse) | {eq['unraised'].get('not_worse', float('nan')):.2f} | "
+          f"{eq['raised'].get('not_worse', float('nan')):.2f} | {eq['all']['median_ratio']:.2f} |")
+    w("")
+    for label in ("cold", "warm"):
+        v = ev[label]
+        if "equal_error" not in v:
+            continue
+        ar = v["at_residual"]
+        w(f"- {label}: at the residual rule {ar['all']['equal']:.2f} of the reference-converged items are within "
+          f"|e - e_plain| <= 0.1 e_plain and {ar['all']['not_worse']:.2f} not worse (median ratio "
+          f"{ar['all']['median_ratio']:.2f}); {v['equal_error']['n_extended']} items ran on for "
+          f"{v['equal_error']['extra_seconds']:.1f} s. Phases: inference {v['inference_seconds']:.1f} s, FP16 "
+          f"{v['fp16']['seconds']:.1f} s, polish {v['polish']['seconds']:.1f} s.")
+    if "prediction_error" in ev:
+        w(f"- network prediction error (relative L2 of the scaled fields): median {ev['prediction_error']['median']:.3f}, "
+          f"max {ev['prediction_error']['max']:.3f}.")
+    w(f"- reference: {ev['reference']['seconds']:.1f} s.")
+    if tr:
+        w(f"- training: {tr['items']} items (seed {tr['seed']}), {tr['epochs']} epochs in {tr['train_seconds']:.1f} s, "
+          f"loss {tr['loss'][0]:.3e} -> {tr['loss'][-1]:.3e}.")
+    text = "\n".join(out) + "\n"
+    if a.out:
+        open(a.out, "w").write(text)
+    print(text)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    rp = sub.add_parser("report")
+    rp.add_argument("--eval", required=True)
+    rp.add_argument("--train", default=None)
+    rp.add_argument("--out", default=None)
     for name in ("train", "eval"):
         p = sub.add_parser(name)
         p.add_argument("--items", type=int, default=4096 if name == "train" else 256)
@@ -367,6 +433,9 @@ def main(argv=None):
             p.add_argument("--equal-chunk", type=int, default=2000,
                            help="steps per round of the equal-error continuation")
     a = ap.parse_args(argv)
+    if a.cmd == "report":
+        cmd_report(a)
+        return
     import torch
     torch.cuda.set_device(0)
     cmd_train(a) if a.cmd == "train" else cmd_eval(a)

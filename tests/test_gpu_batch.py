@@ -258,3 +258,35 @@ def test_converged_fields_do_not_depend_on_the_start():
         for q in (1, 5):
             d = np.abs(a[..., q] - b[..., q]).max() / max(np.abs(a[..., q] - sc.B_ext[0] * (q == 5)).max(), 1e-30)
             assert d < 1e-7, (i, q, d)
+
+
+def test_fp64_batch_steady_state_is_a_fixed_point_of_the_oracle():
+    """The time-to-steady study takes its reference from FP64 batch runs
+    converged to a residual of 1e-11.  Handed to the CPU oracle, such a state
+    must stay put: over 2000 oracle steps u and b change by less than
+    2000 x the residual bound (relative), far below the field errors the
+    study compares."""
+    from .gpu_util import gpu_populations
+    its = scenes.batch_items(3, seed=scenes.BASE_SEED + 62, side_lo=20, side_hi=28, c_lo=0.05, c_hi=1.0,
+                             Ha_hi=20.0, storage="f64", ducts_only=True, q_duct=0.5)
+    scs = [it.scene for it in its]
+    B = lbm.Batch(scs)
+    steps, res, status = B.run(tol=1e-11, interval=1000, max_steps=2_000_000)
+    assert status == ["steady"] * len(scs), (status, res)
+    for i, sc in enumerate(scs):
+        lat = B.items[i]
+        o = oracle.OracleSim(sc, "ld")
+        o.set_populations(0, gpu_populations(lat, 0))
+        o.set_populations(2, gpu_populations(lat, 2))
+        m0 = o.moments()
+        mg = gpu_moments(lat)
+        sel = o.mask().astype(bool)
+        # the handed-over state is the GPU's
+        assert np.abs(m0 - mg)[sel].max() < 1e-13
+        o.step(2000)
+        m1 = o.moments()
+        for q, name in ((1, "u"), (5, "b")):
+            ref = m0[..., q][sel] - (sc.B_ext[0] if q == 5 else 0.0)
+            d = np.linalg.norm((m1 - m0)[..., q][sel]) / np.linalg.norm(ref)
+            print(i, name, f"{d:.1e}", flush=True)
+            assert d < 2000 * 1e-11 * 10, (i, name, d)

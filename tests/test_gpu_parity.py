@@ -355,3 +355,35 @@ def test_nonfinite_state_is_reported():
     lat.step(3)
     with pytest.raises(L.LbmError):
         lat.reduce()
+
+
+def test_fp16_stochastic_rounding_keeps_sub_ulp_increments():
+    """16-bit storage rounds stochastically (reading R19): increments below
+    half a unit in the last place must add up on average.  In a duct at the
+    batch items' FP16 scale, the body force adds about 1/5 of an FP16 ulp of
+    the axial populations per step near the steady state; with
+    round-to-nearest the state freezes about 10 % short of the steady flow.
+    Here the FP16 run reaches the FP64 oracle's steady state to 1e-3."""
+    _case("fp16 sub-ulp increments to steady state")
+    from paper_2506_00907_amd import lbm
+    it = scenes.batch_items(1, side_lo=64, side_hi=70, Ha_hi=5.0, c_lo=0.05, c_hi=0.5, storage="f16",
+                            ducts_only=True, q_duct=0.5)[0]
+    sc = it.scene
+    g = sc.accel[0]
+    # the per-step body-force increment of an axial population (Guo source,
+    # w = 1/18) against the FP16 ulp of its stored deviation at the centre
+    # speed of about 0.01
+    w = 1.0 / 18.0
+    inc = w * 3.0 * g * (1.0 - 1.0 / (2.0 * sc.tau_f)) * sc.store_scale[0]
+    ulp = 2.0 ** (np.floor(np.log2(0.01 * w * 3.0 * sc.store_scale[0])) - 10)
+    assert inc < 0.3 * ulp, (inc, ulp)
+    steps = 30000  # 14 e-folds of the slowest flow mode
+    o = oracle.OracleSim(sc.with_(storage="f64"))
+    o.step(steps)
+    lat = lbm.Lattice(sc)
+    lat.step(steps)
+    mo, mg = o.moments(), gpu_moments(lat)
+    sel = o.mask().astype(bool)
+    e = np.linalg.norm((mg[..., 1] - mo[..., 1])[sel]) / np.linalg.norm(mo[..., 1][sel])
+    print(f"fp16 steady u error {e:.2e}", flush=True)
+    assert e < 1e-3, e
