@@ -42,7 +42,8 @@ class _BC(C.Structure):
                 ("profile_len", C.c_int32), ("alt", C.c_int32), ("law", C.c_int32), ("value", C.c_double),
                 ("a1", C.c_double), ("a3", C.c_double), ("quad", C.c_double),
                 ("profile", C.POINTER(C.c_double)), ("k", C.c_double), ("phi_eq", C.c_double),
-                ("c_w", C.c_double), ("H", C.c_double)]
+                ("c_w", C.c_double), ("H", C.c_double), ("partner", C.c_int32), ("pad", C.c_int32),
+                ("cross", C.c_double)]
 
 
 _LAWS = {"coef": 0, "robin": 1, "reaction": 2, "shercliff": 3}
@@ -51,7 +52,7 @@ _LAWS = {"coef": 0, "robin": 1, "reaction": 2, "shercliff": 3}
 class _Boundary(C.Structure):
     _fields_ = [("type", C.c_int32), ("axis", C.c_int32), ("side", C.c_int32),
                 ("is_open", C.c_int32), ("q", C.c_double), ("center", C.c_double * 3),
-                ("radius", C.c_double), ("u_w", C.c_double * 3), ("f", _BC), ("h", _BC),
+                ("radius", C.c_double), ("u_w", C.c_double * 3), ("f", _BC), ("h", _BC * 3),
                 ("g", _BC * 3), ("omega", C.c_double), ("d_used", C.c_double),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
 
@@ -62,7 +63,8 @@ class _Scene(C.Structure):
                 ("comps", C.c_int32 * 3), ("tau_f", C.c_double), ("tau_c", C.c_double),
                 ("tau_m", C.c_double), ("rho0", C.c_double), ("C0", C.c_double),
                 ("mu", C.c_double), ("B_ext", C.c_double * 3), ("accel", C.c_double * 3),
-                ("init_C", C.c_double), ("nb", C.c_int32), ("b", C.POINTER(_Boundary))]
+                ("init_C", C.c_double), ("nb", C.c_int32), ("b", C.POINTER(_Boundary)),
+                ("ns", C.c_int32), ("pad", C.c_int32), ("tau_s", C.c_double * 3)]
 
 
 class Link(C.Structure):
@@ -71,7 +73,7 @@ class Link(C.Structure):
                 ("u_given", C.c_int32), ("d", C.c_double), ("value", C.c_double),
                 ("a1", C.c_double), ("a3", C.c_double), ("weight", C.c_double),
                 ("u_w", C.c_double * 3), ("omega", C.c_double), ("compare", C.c_int32), ("pad", C.c_int32),
-                ("quad", C.c_double)]
+                ("quad", C.c_double), ("partner", C.c_int32), ("pad2", C.c_int32), ("cross", C.c_double)]
 
 
 class LinkIn(C.Structure):
@@ -79,8 +81,9 @@ class LinkIn(C.Structure):
                 ("comp_axis", C.c_int32), ("u_given", C.c_int32), ("d", C.c_double),
                 ("value", C.c_double), ("a1", C.c_double), ("a3", C.c_double),
                 ("weight", C.c_double), ("u_w", C.c_double * 3), ("x_ap_E", C.c_double),
-                ("x_ap_A", C.c_double), ("x_a_A", C.c_double), ("mA", C.c_double * 8),
-                ("mE", C.c_double * 8), ("compare", C.c_int32), ("quad", C.c_double)]
+                ("x_ap_A", C.c_double), ("x_a_A", C.c_double), ("mA", C.c_double * 10),
+                ("mE", C.c_double * 10), ("compare", C.c_int32), ("quad", C.c_double),
+                ("cslot", C.c_int32), ("pslot", C.c_int32), ("cross", C.c_double)]
 
 
 _libs = {}
@@ -96,6 +99,7 @@ def lib(precision: str = "f64"):
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_step.argtypes = [C.c_void_p, C.c_long]
         L.or_moments.argtypes = [C.c_void_p, C.c_void_p]
+        L.or_moment_width.argtypes = [C.c_void_p]
         L.or_populations.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
         L.or_set_populations.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
         L.or_num_links.argtypes = [C.c_void_p]
@@ -155,8 +159,10 @@ def link_eval(**kw) -> float:
     """Evaluates the oracle's boundary-link formula on explicit inputs.
 
     Keywords: lattice (name), kind (name), dir, d, x_ap_E, x_ap_A, x_a_A,
-    mA, mE (8-vectors rho, u, C, B), value, a1, quad, a3, weight, u_w,
-    u_given, comp_axis.
+    mA, mE (vectors rho, u, C_0, B, C_1, C_2), value, a1, quad, a3, weight,
+    u_w, u_given, comp_axis; FLUX of several components: cslot (moment slot
+    of the link's component, 4 by default), pslot (of the cross term's
+    component, -1 none) and cross.
     """
     li = LinkIn()
     li.lattice = S.LATTICE_CODES[kw.get("lattice", "D2Q9")]
@@ -169,6 +175,9 @@ def link_eval(**kw) -> float:
     for k in ("value", "a1", "quad", "a3", "x_ap_E", "x_ap_A", "x_a_A"):
         setattr(li, k, float(kw.get(k, 0.0)))
     li.weight = float(kw.get("weight", 1.0))
+    li.cslot = int(kw.get("cslot", 4))
+    li.pslot = int(kw.get("pslot", -1))
+    li.cross = float(kw.get("cross", 0.0))
     for i, v in enumerate(kw.get("u_w", (0.0, 0.0, 0.0))):
         li.u_w[i] = v
     for i, v in enumerate(kw.get("mA", [1.0] + [0.0] * 7)):
@@ -197,6 +206,9 @@ class _SceneHolder:
         for i, c in enumerate(sc.mag_comps):
             cs.comps[i] = c
         cs.tau_f, cs.tau_c, cs.tau_m = sc.tau_f, sc.tau_c, sc.tau_m
+        cs.ns = sc.scalar_ncomp if sc.scalar_lattice else 0
+        for k in range(max(cs.ns, 1)):
+            cs.tau_s[k] = sc.tau_scalar(k)
         cs.rho0, cs.C0, cs.mu, cs.init_C = sc.rho0, sc.C0, sc.mu, sc.init_C
         arr = (_Boundary * max(1, len(sc.boundaries)))()
         for i, b in enumerate(sc.boundaries):
@@ -211,7 +223,8 @@ class _SceneHolder:
             for k in range(3):
                 cb.lo[k], cb.hi[k] = b.lo[k], b.hi[k]
             self._bc(cb.f, b.f)
-            self._bc(cb.h, b.h)
+            for k in range(3):
+                self._bc(cb.h[k], b.h_of(k) if k < max(sc.scalar_ncomp, 1) else None)
             for k in range(3):
                 self._bc(cb.g[k], b.g[k] if k < len(b.g) else None)
         cs.nb = len(sc.boundaries)
@@ -230,6 +243,7 @@ class _SceneHolder:
         dst.value, dst.a1, dst.a3, dst.quad = bc.value, bc.a1, bc.a3, bc.quad
         dst.k, dst.phi_eq, dst.c_w, dst.H = bc.k, bc.phi_eq, bc.c_w, bc.H
         dst.profile_axis = bc.profile_axis
+        dst.partner, dst.cross = bc.partner, bc.cross
         if bc.profile is not None:
             p = np.ascontiguousarray(bc.profile, dtype=np.float64)
             self.keep.append(p)
@@ -267,7 +281,8 @@ class OracleSim:
     def init_fields(self, rho=None, u=None, C_=None, B=None):
         conv = lambda a, k: None if a is None else np.ascontiguousarray(
             np.asarray(a, np.float64).reshape(self.N * k))
-        arrs = [conv(rho, 1), conv(u, 3), conv(C_, 1), conv(B, 3)]
+        ns = self.scene.scalar_ncomp if self.scene.scalar_lattice else 1
+        arrs = [conv(rho, 1), conv(u, 3), conv(C_, ns), conv(B, 3)]
         ptrs = [None if a is None else _ptr(a) for a in arrs]
         self._L.or_init_fields(self._p, *ptrs)
 
@@ -279,20 +294,25 @@ class OracleSim:
         return self._L.or_time(self._p)
 
     def moments(self) -> np.ndarray:
-        """[nz, ny, nx, 8] array of rho, u(3), C, B(3); zeros at solid nodes."""
-        out = np.zeros((self.N, 8))
+        """[nz, ny, nx, W] array of rho, u(3), C_0, B(3), then C_1, C_2 of
+        several scalar components (W = 8 + components - 1); zeros at solid
+        nodes."""
+        W = self._L.or_moment_width(self._p)
+        out = np.zeros((self.N, W))
         self._L.or_moments(self._p, _ptr(out))
-        return out.reshape(self.shape + (8,))
+        return out.reshape(self.shape + (W,))
 
     def populations(self, field: int) -> np.ndarray:
         sc = self.scene
         Q = {0: sc.fluid_lattice, 1: sc.scalar_lattice, 2: sc.mag_lattice}[field]
         q = len(lattice_table(Q)[1])
-        nc = len(sc.mag_comps) if field == 2 else 1
+        nc = len(sc.mag_comps) if field == 2 else (sc.scalar_ncomp if field == 1 else 1)
         out = np.zeros(nc * q * self.N)
         if self._L.or_populations(self._p, field, _ptr(out)) != 0:
             raise ValueError(field)
-        return out.reshape((nc, q) + self.shape) if field == 2 else out.reshape((q,) + self.shape)
+        if field == 2 or (field == 1 and nc > 1):
+            return out.reshape((nc, q) + self.shape)
+        return out.reshape((q,) + self.shape)
 
     def set_populations(self, field: int, arr: np.ndarray):
         a = np.ascontiguousarray(arr, np.float64)
@@ -306,7 +326,7 @@ class OracleSim:
                        ("kind", "i4"), ("bnd", "i4"), ("u_given", "i4"), ("d", "f8"),
                        ("value", "f8"), ("a1", "f8"), ("a3", "f8"), ("weight", "f8"),
                        ("u_w", "f8", 3), ("omega", "f8"), ("compare", "i4"), ("pad", "i4"),
-                       ("quad", "f8")])
+                       ("quad", "f8"), ("partner", "i4"), ("pad2", "i4"), ("cross", "f8")])
         assert dt.itemsize == C.sizeof(Link)
         return np.frombuffer(bytes(out), dtype=dt, count=n).copy()
 

@@ -22,6 +22,11 @@
  *  - if the second fluid node E is not fluid, A stands in for E.
  *  - a link crossing several boundaries: walls win over open boundaries, then
  *    the smaller d, then the lower boundary index.
+ *  - several scalar components C_1 .. C_ns (Section 4.2.2): one convection-
+ *    diffusion lattice each, with its own relaxation time; a flux wall's law
+ *    for component i may also depend on another component j,
+ *    F_i = a1 C_i + quad C_i^2 + cross C_i C_j - a3, with both C_i(X) and
+ *    C_j(X) extrapolated by Eq. 13 (no iteration couples the components).
  */
 #include <math.h>
 #include <stdint.h>
@@ -193,6 +198,9 @@ typedef struct {
     double k;             /* LAW_ROBIN: d phi/dn = k phi; LAW_REACTION: F = -k (phi - phi_eq) */
     double phi_eq;
     double c_w, H;        /* LAW_SHERCLIFF: thin-wall conductance ratio, length scale */
+    int32_t partner;      /* scalar component j of the cross term (LAW_COEF, FLUX); -1: none */
+    int32_t pad;
+    double cross;         /* F_i += cross C_i C_j */
 } or_bc;
 
 typedef struct {
@@ -202,7 +210,7 @@ typedef struct {
     double center[3];
     double radius;
     double u_w[3];
-    or_bc f, h, g[3];
+    or_bc f, h[3], g[3]; /* h: one condition per scalar component */
     double omega; /* the boundary velocity is u_w cos(omega t') (0: steady) */
     double d_used; /* > 0: the links take this d in their update, not the measured one */
     double lo[3], hi[3]; /* box: closed solid block lo <= x <= hi (bounds may be infinite) */
@@ -220,6 +228,9 @@ typedef struct {
     double init_C;
     int32_t nb;
     const or_boundary* b;
+    int32_t ns;          /* scalar components (>= 1 with a scalar lattice) */
+    int32_t pad;
+    double tau_s[3];     /* relaxation time of each scalar component (tau_s[0] = tau_c) */
 } or_scene;
 
 typedef struct {
@@ -236,6 +247,9 @@ typedef struct {
     int32_t compare; /* comparison form of the kind (Section 5) */
     int32_t pad;
     double quad;     /* quadratic term of the flux law */
+    int32_t partner; /* FLUX: scalar component j of the cross term, -1 none */
+    int32_t pad2;
+    double cross;    /* FLUX: F_i += cross C_i(X) C_j(X) */
 } or_link;
 
 /* ------------------------------------------------------------------------- */
@@ -330,7 +344,7 @@ static double cylinder_d(const or_boundary* b, const int* A, const int* e) {
 
 static const or_bc* bc_of(const or_boundary* b, int field, int comp_slot) {
     if (field == 0) return &b->f;
-    if (field == 1) return &b->h;
+    if (field == 1) return &b->h[comp_slot];
     return &b->g[comp_slot];
 }
 
@@ -472,7 +486,7 @@ static void flux_law(const or_scene* s, const or_bc* bc, int field, const or_lat
         if (pos >= bc->profile_len) pos = bc->profile_len - 1;
         prof = bc->profile[pos];
     }
-    double tau = field == 1 ? s->tau_c : s->tau_m;
+    double tau = field == 1 ? s->tau_s[comp] : s->tau_m;
     double kappa = (double)L->c2 * (tau - 0.5);
     lk->a1 = lk->a3 = lk->quad = 0.0;
     if (bc->law == LAW_ROBIN) {
@@ -493,6 +507,12 @@ static void flux_law(const or_scene* s, const or_bc* bc, int field, const or_lat
         lk->a1 = has_prof ? prof : bc->a1;
         lk->a3 = bc->a3;
         lk->quad = bc->quad;
+    }
+    lk->partner = -1;
+    lk->cross = 0.0;
+    if (field == 1 && bc->kind == K_FLUX && bc->law == LAW_COEF && bc->partner >= 0) {
+        lk->partner = bc->partner;
+        lk->cross = bc->cross;
     }
 }
 
@@ -600,7 +620,7 @@ static int build_field_links(or_sim* S, int field, const or_lattice* L, int ncom
 static int build_links(or_sim* S) {
     const or_scene* s = &S->sc;
     int cap = 64;
-    int per_node = S->Lf.Q + (s->sl ? S->Lh.Q : 0) + (s->ml ? S->Lg.Q * s->ncomp : 0);
+    int per_node = S->Lf.Q + (s->sl ? S->Lh.Q * s->ns : 0) + (s->ml ? S->Lg.Q * s->ncomp : 0);
     /* upper bound: every fluid node next to a boundary, every direction */
     long nf = 0;
     for (int n = 0; n < S->N; ++n) nf += S->fluid[n];
@@ -608,7 +628,7 @@ static int build_links(or_sim* S) {
     or_link* L = (or_link*)malloc(sizeof(or_link) * (size_t)cap);
     int cnt = 0;
     cnt = build_field_links(S, 0, &S->Lf, 1, L, cap, cnt);
-    if (cnt >= 0 && s->sl) cnt = build_field_links(S, 1, &S->Lh, 1, L, cap, cnt);
+    if (cnt >= 0 && s->sl) cnt = build_field_links(S, 1, &S->Lh, s->ns, L, cap, cnt);
     if (cnt >= 0 && s->ml) cnt = build_field_links(S, 2, &S->Lg, s->ncomp, L, cap, cnt);
     if (cnt < 0) {
         free(L);
@@ -624,10 +644,14 @@ static int build_links(or_sim* S) {
 /* ------------------------------------------------------------------------- */
 #define IDX(q, n) ((size_t)(q) * (size_t)S->N + (size_t)(n))
 #define GIDX(k, q, n) (((size_t)(k) * (size_t)S->Lg.Q + (size_t)(q)) * (size_t)S->N + (size_t)(n))
+#define HIDX(k, q, n) (((size_t)(k) * (size_t)S->Lh.Q + (size_t)(q)) * (size_t)S->N + (size_t)(n))
+/* moments kept per node: rho, u(3), C_0, B(3), then C_1, C_2 */
+#define MOMW 10
+static int cslot(int k) { return k == 0 ? 4 : 7 + k; }
 
 /* moments at node n from the pre-collision populations: rho, u, C, B.
  * Also returns the total force F (body + Lorentz). */
-static void node_moments(const or_sim* S, int n, real* rho_o, real* u, real* C_o, real* B,
+static void node_moments(const or_sim* S, int n, real* rho_o, real* u, real* C_o /* [ns] */, real* B,
                          real* F) {
     const or_scene* s = &S->sc;
     const or_lattice* Lf = &S->Lf;
@@ -637,9 +661,12 @@ static void node_moments(const or_sim* S, int n, real* rho_o, real* u, real* C_o
         rho += fa;
         for (int k = 0; k < 3; ++k) m[k] += Lf->e[a][k] * fa;
     }
-    real C = 0.0;
     if (s->sl)
-        for (int a = 0; a < S->Lh.Q; ++a) C += S->h[IDX(a, n)];
+        for (int k = 0; k < s->ns; ++k) {
+            real C = 0.0;
+            for (int a = 0; a < S->Lh.Q; ++a) C += S->h[HIDX(k, a, n)];
+            C_o[k] = C;
+        }
     for (int k = 0; k < 3; ++k) B[k] = s->B_ext[k];
     real Fl[3] = {0.0, 0.0, 0.0};
     if (s->ml) {
@@ -678,22 +705,21 @@ static void node_moments(const or_sim* S, int n, real* rho_o, real* u, real* C_o
         u[k] = (m[k] + 0.5 * F[k]) / rho;
     }
     *rho_o = rho;
-    *C_o = C;
 }
 
 static void collide_node(or_sim* S, int n) {
     const or_scene* s = &S->sc;
-    real rho, u[3], C, B[3], F[3];
-    node_moments(S, n, &rho, u, &C, B, F);
-    real* mo = &S->mom[(size_t)n * 8];
+    real rho, u[3], C[3] = {0, 0, 0}, B[3], F[3];
+    node_moments(S, n, &rho, u, C, B, F);
+    real* mo = &S->mom[(size_t)n * MOMW];
     mo[0] = rho;
     mo[1] = u[0];
     mo[2] = u[1];
     mo[3] = u[2];
-    mo[4] = C;
     mo[5] = B[0];
     mo[6] = B[1];
     mo[7] = B[2];
+    for (int k = 0; k < 3; ++k) mo[cslot(k)] = C[k];
     /* Eq. 1 with the Guo source term.  The equilibria conserve the zeroth
      * moments (Section 2.4) and the force adds no mass; with weights rounded
      * to real precision that holds only if the rest entry closes the sum,
@@ -716,14 +742,15 @@ static void collide_node(or_sim* S, int n) {
         real fa = S->f[IDX(a, n)];
         S->fs[IDX(a, n)] = fa + (eqv[a] - fa) / tf + srcv[a];
     }
-    /* Eq. 3 */
-    if (s->sl) {
-        eq_closed_h(&S->Lh, C, u, eqv);
-        for (int a = 0; a < S->Lh.Q; ++a) {
-            real ha = S->h[IDX(a, n)];
-            S->hs[IDX(a, n)] = ha + (eqv[a] - ha) / s->tau_c;
+    /* Eq. 3, for each scalar component */
+    if (s->sl)
+        for (int k = 0; k < s->ns; ++k) {
+            eq_closed_h(&S->Lh, C[k], u, eqv);
+            for (int a = 0; a < S->Lh.Q; ++a) {
+                real ha = S->h[HIDX(k, a, n)];
+                S->hs[HIDX(k, a, n)] = ha + (eqv[a] - ha) / s->tau_s[k];
+            }
         }
-    }
     /* Eq. 5 */
     if (s->ml)
         for (int c = 0; c < s->ncomp; ++c) {
@@ -745,9 +772,12 @@ typedef struct {
     double x_ap_E;  /* post-collision, direction alpha' (towards the wall), at E */
     double x_ap_A;  /* post-collision, direction alpha', at A */
     double x_a_A;   /* post-collision, direction alpha, at A */
-    double mA[8], mE[8]; /* rho, u(3), C, B(3) at A and E at time t */
+    double mA[MOMW], mE[MOMW]; /* rho, u(3), C_0, B(3), C_1, C_2 at A and E at time t */
     int32_t compare;     /* the comparison form of the kind (Section 5) */
     double quad;         /* quadratic term of the flux law */
+    int32_t cslot;       /* FLUX: moment slot of the link's scalar component */
+    int32_t pslot;       /* FLUX: moment slot of the cross term's component, -1: none */
+    double cross;        /* FLUX: coefficient of C_i(X) C_j(X) in F_i */
 } or_link_in;
 
 /* Eq. 13: phi(X) = -d phi(E) + (d+1) phi(A) */
@@ -759,9 +789,11 @@ typedef struct {
     real d, value, a1, a3, weight;
     real u_w[3];
     real x_ap_E, x_ap_A, x_a_A;
-    real mA[8], mE[8];
+    real mA[MOMW], mE[MOMW];
     int32_t compare;
     real quad;
+    int32_t cslot, pslot;
+    real cross;
 } or_link_in_r;
 
 static real link_eval_r(const or_link_in_r* in) {
@@ -806,9 +838,13 @@ static real link_eval_r(const or_link_in_r* in) {
         case K_MAG_THETA: {
             real phiX, dmove;
             real mu_[3] = {-uX[0], -uX[1], -uX[2]};
+            real cross = 0;
             if (in->kind == K_FLUX) {
-                phiX = extrap(d, in->mE[4], in->mA[4]);
+                phiX = extrap(d, in->mE[in->cslot], in->mA[in->cslot]);
                 dmove = heq(&L, ap, phiX, mu_) - heq(&L, a, phiX, mu_); /* Eq. 24 */
+                /* another component's value at X, extrapolated the same way
+                 * (Section 4.2.2): F_i(C_i, C_j) needs no iteration */
+                if (in->pslot >= 0) cross = in->cross * phiX * extrap(d, in->mE[in->pslot], in->mA[in->pslot]);
             } else {
                 phiX = BX[in->comp_axis];
                 dmove = geq(&L, ap, in->comp_axis, BX, mu_) - geq(&L, a, in->comp_axis, BX, mu_);
@@ -822,7 +858,7 @@ static real link_eval_r(const or_link_in_r* in) {
                 return ((2 * d - 1) * in->x_a_A + bounced) / (2 * d);
             }
             /* Eq. 23 with F(phi_X) = a1 phi_X + quad phi_X^2 - a3, Eq. 48 */
-            real dflux = (in->a1 * phiX + in->quad * phiX * phiX - in->a3) * in->weight;
+            real dflux = (in->a1 * phiX + in->quad * phiX * phiX + cross - in->a3) * in->weight;
             if (in->compare) { /* Eq. 33: the flux joins the bounced population at X */
                 if (d < (real)0.5) return xY + dflux + dmove;
                 return ((2 * d - 1) * in->x_a_A + in->x_ap_A + dflux + dmove) / (2 * d);
@@ -853,8 +889,11 @@ double or_link_eval(const or_link_in* in) {
     r.x_a_A = in->x_a_A;
     r.compare = in->compare;
     r.quad = in->quad;
+    r.cslot = in->cslot;
+    r.pslot = in->pslot;
+    r.cross = in->cross;
     for (int k = 0; k < 3; ++k) r.u_w[k] = in->u_w[k];
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < MOMW; ++k) {
         r.mA[k] = in->mA[k];
         r.mE[k] = in->mE[k];
     }
@@ -868,7 +907,7 @@ static void apply_links(or_sim* S) {
         const or_lattice* L = lk->field == 0 ? &S->Lf : (lk->field == 1 ? &S->Lh : &S->Lg);
         const real* xs = lk->field == 0 ? S->fs : (lk->field == 1 ? S->hs : S->gs);
         real* x = lk->field == 0 ? S->f : (lk->field == 1 ? S->h : S->g);
-        size_t base = lk->field == 2 ? (size_t)lk->comp * (size_t)L->Q * (size_t)S->N : 0;
+        size_t base = lk->field != 0 ? (size_t)lk->comp * (size_t)L->Q * (size_t)S->N : 0;
         int a = lk->dir, ap = L->opp[a];
         int E = lk->E >= 0 ? lk->E : lk->A;
         or_link_in_r in;
@@ -880,6 +919,9 @@ static void apply_links(or_sim* S) {
         in.u_given = lk->u_given;
         in.compare = lk->compare;
         in.quad = lk->quad;
+        in.cslot = lk->field == 1 ? cslot(lk->comp) : 4;
+        in.pslot = lk->field == 1 && lk->partner >= 0 ? cslot(lk->partner) : -1;
+        in.cross = lk->cross;
         in.d = lk->d;
         in.value = lk->value;
         in.a1 = lk->a1;
@@ -893,8 +935,8 @@ static void apply_links(or_sim* S) {
         in.x_ap_E = xs[base + (size_t)ap * S->N + E];
         in.x_ap_A = xs[base + (size_t)ap * S->N + lk->A];
         in.x_a_A = xs[base + (size_t)a * S->N + lk->A];
-        for (int k = 0; k < 8; ++k) in.mA[k] = S->mom[(size_t)lk->A * 8 + k];
-        for (int k = 0; k < 8; ++k) in.mE[k] = S->mom[(size_t)E * 8 + k];
+        for (int k = 0; k < MOMW; ++k) in.mA[k] = S->mom[(size_t)lk->A * MOMW + k];
+        for (int k = 0; k < MOMW; ++k) in.mE[k] = S->mom[(size_t)E * MOMW + k];
         x[base + (size_t)a * S->N + lk->A] = link_eval_r(&in);
     }
 }
@@ -931,14 +973,19 @@ or_sim* or_create(const or_scene* sc) {
     S->f = (real*)calloc(N * S->Lf.Q, sizeof(real));
     S->fs = (real*)calloc(N * S->Lf.Q, sizeof(real));
     if (sc->sl) {
-        S->h = (real*)calloc(N * S->Lh.Q, sizeof(real));
-        S->hs = (real*)calloc(N * S->Lh.Q, sizeof(real));
+        if (S->sc.ns < 1) S->sc.ns = 1;
+        if (S->sc.ns > 3) {
+            or_destroy(S);
+            return NULL;
+        }
+        S->h = (real*)calloc(N * S->Lh.Q * S->sc.ns, sizeof(real));
+        S->hs = (real*)calloc(N * S->Lh.Q * S->sc.ns, sizeof(real));
     }
     if (sc->ml) {
         S->g = (real*)calloc(N * S->Lg.Q * sc->ncomp, sizeof(real));
         S->gs = (real*)calloc(N * S->Lg.Q * sc->ncomp, sizeof(real));
     }
-    S->mom = (real*)calloc(N * 8, sizeof(real));
+    S->mom = (real*)calloc(N * MOMW, sizeof(real));
     if (build_links(S) != 0) {
         or_destroy(S);
         return NULL;
@@ -948,7 +995,7 @@ or_sim* or_create(const or_scene* sc) {
 }
 
 /* equilibrium initialisation from (rho, u, C, B) fields; NULL = uniform rest
- * state (rho0, 0, init_C, B_ext).  u, B are [N][3]. */
+ * state (rho0, 0, init_C, B_ext).  u, B are [N][3]; C is [ns][N]. */
 int or_init_fields(or_sim* S, const double* rho, const double* u, const double* C, const double* B) {
     const or_scene* s = &S->sc;
     for (int n = 0; n < S->N; ++n) {
@@ -958,14 +1005,15 @@ int or_init_fields(or_sim* S, const double* rho, const double* u, const double* 
             for (int k = 0; k < 3; ++k) uu[k] = u[3 * (size_t)n + k];
         if (B)
             for (int k = 0; k < 3; ++k) BB[k] = B[3 * (size_t)n + k];
-        real cc = C ? C[n] : s->init_C;
         real eqv[19];
         eq_closed_f(&S->Lf, r, uu, eqv);
         for (int a = 0; a < S->Lf.Q; ++a) S->f[IDX(a, n)] = eqv[a];
-        if (s->sl) {
-            eq_closed_h(&S->Lh, cc, uu, eqv);
-            for (int a = 0; a < S->Lh.Q; ++a) S->h[IDX(a, n)] = eqv[a];
-        }
+        if (s->sl)
+            for (int k = 0; k < s->ns; ++k) {
+                real cc = C ? C[(size_t)k * S->N + n] : s->init_C;
+                eq_closed_h(&S->Lh, cc, uu, eqv);
+                for (int a = 0; a < S->Lh.Q; ++a) S->h[HIDX(k, a, n)] = eqv[a];
+            }
         if (s->ml)
             for (int c = 0; c < s->ncomp; ++c) {
                 eq_closed_g(&S->Lg, s->comps[c], BB, uu, eqv);
@@ -999,7 +1047,8 @@ void or_step(or_sim* S, long nsteps) {
                     int sc_[3] = {c[0] - S->Lh.e[a][0], c[1] - S->Lh.e[a][1], c[2] - S->Lh.e[a][2]};
                     if (!wrap(s, sc_)) continue;
                     int src = node_index(s, sc_);
-                    if (S->fluid[src]) S->h[IDX(a, n)] = S->hs[IDX(a, src)];
+                    if (!S->fluid[src]) continue;
+                    for (int k = 0; k < s->ns; ++k) S->h[HIDX(k, a, n)] = S->hs[HIDX(k, a, src)];
                 }
             if (s->ml)
                 for (int a = 0; a < S->Lg.Q; ++a) {
@@ -1016,28 +1065,34 @@ void or_step(or_sim* S, long nsteps) {
     }
 }
 
-/* moments at the current time: [N][8] rho, u, C, B (zeros at solid nodes) */
+/* columns of or_moments: rho, u, C_0, B, then C_1 .. C_{ns-1} */
+int or_moment_width(const or_sim* S) { return 8 + (S->sc.sl ? S->sc.ns - 1 : 0); }
+
+/* moments at the current time: [N][or_moment_width] rho, u, C_0, B, C_1, ...
+ * (zeros at solid nodes) */
 void or_moments(const or_sim* S, double* out) {
+    const int W = or_moment_width(S);
     for (int n = 0; n < S->N; ++n) {
-        double* o = &out[(size_t)n * 8];
+        double* o = &out[(size_t)n * W];
         if (!S->fluid[n]) {
-            memset(o, 0, sizeof(double) * 8);
+            memset(o, 0, sizeof(double) * W);
             continue;
         }
-        real rho, u[3], C, B[3], F[3];
-        node_moments(S, n, &rho, u, &C, B, F);
+        real rho, u[3], C[3] = {0, 0, 0}, B[3], F[3];
+        node_moments(S, n, &rho, u, C, B, F);
         o[0] = rho;
         o[1] = u[0];
         o[2] = u[1];
         o[3] = u[2];
-        o[4] = C;
+        o[4] = C[0];
         o[5] = B[0];
         o[6] = B[1];
         o[7] = B[2];
+        for (int k = 1; k < W - 7; ++k) o[7 + k] = C[k];
     }
 }
 
-/* populations of one field at the current time, [Q][N] (g: [ncomp][Q][N]) */
+/* populations of one field at the current time, [Q][N] (h: [ns][Q][N], g: [ncomp][Q][N]) */
 static void copy_out(const real* src, double* dst, size_t n) {
     for (size_t i = 0; i < n; ++i) dst[i] = (double)src[i];
 }
@@ -1048,7 +1103,7 @@ static void copy_in(const double* src, real* dst, size_t n) {
 int or_populations(const or_sim* S, int field, double* out) {
     size_t N = (size_t)S->N;
     if (field == 0) copy_out(S->f, out, N * S->Lf.Q);
-    else if (field == 1 && S->sc.sl) copy_out(S->h, out, N * S->Lh.Q);
+    else if (field == 1 && S->sc.sl) copy_out(S->h, out, N * S->Lh.Q * S->sc.ns);
     else if (field == 2 && S->sc.ml) copy_out(S->g, out, N * S->Lg.Q * S->sc.ncomp);
     else return -1;
     return 0;
@@ -1057,7 +1112,7 @@ int or_populations(const or_sim* S, int field, double* out) {
 int or_set_populations(or_sim* S, int field, const double* in) {
     size_t N = (size_t)S->N;
     if (field == 0) copy_in(in, S->f, N * S->Lf.Q);
-    else if (field == 1 && S->sc.sl) copy_in(in, S->h, N * S->Lh.Q);
+    else if (field == 1 && S->sc.sl) copy_in(in, S->h, N * S->Lh.Q * S->sc.ns);
     else if (field == 2 && S->sc.ml) copy_in(in, S->g, N * S->Lg.Q * S->sc.ncomp);
     else return -1;
     return 0;

@@ -26,6 +26,8 @@ assert LINK_DTYPE.itemsize == C.sizeof(L.lbm_link)
 
 
 def params_from_scene(sc) -> L.lbm_params:
+    if sc.scalar_lattice and sc.scalar_ncomp != 1:
+        raise NotImplementedError("several scalar components")
     p = L.lbm_params()
     p.dim = sc.dim
     for k in range(3):
@@ -80,7 +82,7 @@ def boundaries_from_scene(sc):
             d.center[k] = b.center[k]
             d.u_w[k] = b.u_w[k]
         put(d.f, b.f)
-        put(d.h, b.h)
+        put(d.h, b.h_of(0))
         for k in range(3):
             put(d.g[k], b.g[k] if k < len(b.g) else None)
     return arr, len(sc.boundaries), keep

@@ -119,6 +119,10 @@ class BC:
     alt    : the comparison form of Section 5 instead of the method's: VEL
              and PRES extrapolated at every d (Eqs. 15-16), FLUX and MAG_FLUX
              with the flux added at the wall (Eq. 33)
+    partner, cross: a scalar FLUX wall of component i under the "coef" law
+             whose flux also depends on component j = partner:
+             F_i = a1 C_i + quad C_i^2 + cross C_i C_j - a3 (Section 4.2.2,
+             a surface reaction between components); partner -1: none
     """
     kind: str
     value: float = 0.0
@@ -134,6 +138,8 @@ class BC:
     phi_eq: float = 0.0
     c_w: float = 0.0
     H: float = 0.0
+    partner: int = -1
+    cross: float = 0.0
 
 
 @dataclass
@@ -160,8 +166,14 @@ class Boundary:
     lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # box: closed solid block lo <= x <= hi
     hi: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     f: Optional[BC] = None
-    h: Optional[BC] = None
+    h: object = None             # a BC, or one per scalar component (list)
     g: List[Optional[BC]] = field(default_factory=list)   # one per evolved component
+
+    def h_of(self, k: int) -> Optional[BC]:
+        """the condition of scalar component k (a single BC serves all)"""
+        if isinstance(self.h, (list, tuple)):
+            return self.h[k] if k < len(self.h) else None
+        return self.h
 
 
 @dataclass
@@ -187,8 +199,11 @@ class Scene:
     store_scale: Tuple[float, float, float] = (1.0, 1.0, 1.0)
     steps: int = 1000
     wall_omega: float = 0.0               # rad per step of the boundaries with u_osc
-    init_C: float = 0.0                   # initial uniform concentration
-    # optional initial fields (fluid-domain arrays, shape (nz, ny, nx[, 3]))
+    init_C: float = 0.0                   # initial uniform concentration (every scalar component)
+    scalar_ncomp: int = 1                 # scalar components C_0 .. (1..3), one D2Q5/D3Q7 lattice each
+    tau_cs: Tuple[float, ...] = ()        # relaxation times of components 1, 2 (component 0: tau_c)
+    # optional initial fields (fluid-domain arrays, shape (nz, ny, nx[, 3]);
+    # init_Cf of several scalar components: (scalar_ncomp, nz, ny, nx))
     init_rho: Optional[np.ndarray] = None
     init_u: Optional[np.ndarray] = None
     init_Cf: Optional[np.ndarray] = None
@@ -198,6 +213,10 @@ class Scene:
     @property
     def nodes(self) -> int:
         return self.n[0] * self.n[1] * self.n[2]
+
+    def tau_scalar(self, k: int) -> float:
+        """relaxation time of scalar component k"""
+        return self.tau_c if k == 0 else self.tau_cs[k - 1]
 
     def with_(self, **kw) -> "Scene":
         return dataclasses.replace(self, **kw)

@@ -337,6 +337,71 @@ def test_nonlinear_surface_reaction_exact(qb, qt):
     assert np.isclose(quad - base, -k * CX * CX, rtol=1e-12)
 
 
+def _two_species(qb, qt, k, ny=12, tau=(0.8, 0.65), Cb=(1.0, 0.6)):
+    """components A (0) and B (1) given below; above, the reaction A + B ->
+    products consumes both at the rate k C_A C_B (F_i = -k C_A C_B)"""
+    bot = Boundary("plane", axis=1, side=0, q=qb, f=BC("VEL"),
+                   h=[BC("CONC", value=Cb[0]), BC("CONC", value=Cb[1])])
+    top = Boundary("plane", axis=1, side=1, q=qt, f=BC("VEL"),
+                   h=[BC("FLUX", partner=1, cross=-k), BC("FLUX", partner=0, cross=-k)])
+    return Scene(name="ab1d", dim=2, n=(1, ny, 1), periodic=(True, False, True), fluid_lattice="D2Q9",
+                 scalar_lattice="D2Q5", scalar_ncomp=2, tau_c=tau[0], tau_cs=(tau[1],), init_C=0.5,
+                 boundaries=[bot, top])
+
+
+@pytest.mark.parametrize("qb,qt", [(0.5, 0.5), (0.3, 0.8), (0.9, 1.0)])
+def test_two_component_surface_reaction_exact(qb, qt):
+    """Two scalar components reacting at a wall (Section 4.2.2): each
+    component's flux F_i(C_A, C_B) = -k C_A C_B is evaluated explicitly from
+    both extrapolated wall values (Eq. 13), with no iteration coupling the
+    components.  With both given below, the steady profiles are the lines
+    C_i = C_i,b + s_i y with D_i s_i = -phi, phi = k C_A(W) C_B(W), i.e.
+    k (W^2 / (D_A D_B)) phi^2 - (1 + k W (C_A,b / D_B + C_B,b / D_A)) phi
+    + k C_A,b C_B,b = 0, reached to rounding for any d."""
+    ny, k, Cb = 12, 0.01, (1.0, 0.6)
+    DA, DB = (0.8 - 0.5) / 4, (0.65 - 0.5) / 4
+    y = np.arange(ny) + qb
+    W = ny - 1 + qb + qt
+    o = oracle.OracleSim(_two_species(qb, qt, k, ny=ny, Cb=Cb))
+    o.step(120000)
+    a = k * W * W / (DA * DB)
+    b = -(1 + k * W * (Cb[0] / DB + Cb[1] / DA))
+    c = k * Cb[0] * Cb[1]
+    phi = (-b - math.sqrt(b * b - 4 * a * c)) / (2 * a)
+    m = o.moments()
+    assert m.shape[-1] == 9
+    assert np.abs(m[0, :, 0, 4] - (Cb[0] - phi / DA * y)).max() < 1e-11
+    assert np.abs(m[0, :, 0, 8] - (Cb[1] - phi / DB * y)).max() < 1e-11
+    # the cross term enters a link as a linear term with the partner's
+    # extrapolated value as coefficient
+    x = dict(x_ap_E=0.11, x_ap_A=0.13, x_a_A=0.07, d=0.3)
+    mA = [1, 0, 0, 0, 0.9, 0, 0, 0, 0.4, 0]
+    mE = [1, 0, 0, 0, 0.8, 0, 0, 0, 0.7, 0]
+    PX = -0.3 * 0.7 + 1.3 * 0.4
+    cross = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, pslot=8, cross=-k, **x)
+    lin = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, a1=-k * PX, **x)
+    assert np.isclose(cross, lin, rtol=1e-14, atol=1e-16)
+    # the second component's own link reads its value from slot 8
+    own = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, cslot=8, a1=0.05, **x)
+    swap = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=[1, 0, 0, 0, 0.4, 0, 0, 0, 0.9, 0],
+                            mE=[1, 0, 0, 0, 0.7, 0, 0, 0, 0.8, 0], a1=0.05, **x)
+    assert own == swap
+
+
+def test_components_without_coupling_evolve_alone():
+    """Several scalar components share the flow but not their populations:
+    without a cross term each evolves exactly as a single-component run."""
+    sc2 = _two_species(0.3, 0.8, 0.0)
+    sc2.boundaries[1].h = [BC("FLUX", a1=-0.003), BC("FLUX", quad=-0.01)]
+    o2 = oracle.OracleSim(sc2)
+    o2.step(500)
+    for comp, top, tau, Cb in ((0, BC("FLUX", a1=-0.003), 0.8, 1.0), (1, BC("FLUX", quad=-0.01), 0.65, 0.6)):
+        o1 = oracle.OracleSim(_chan_scalar(0.3, 0.8, BC("CONC", value=Cb), top, tau_c=tau).with_(init_C=0.5))
+        o1.step(500)
+        col = 4 if comp == 0 else 8
+        assert np.array_equal(o2.moments()[..., col], o1.moments()[..., 4])
+
+
 @pytest.mark.parametrize("qb,qt", [(0.5, 0.5), (0.25, 1.0)])
 def test_magnetic_linear_profile_exact(qb, qt):
     """Pure magnetic diffusion (u = 0, B2 = 0, Lorentz force switched off by a
