@@ -42,7 +42,7 @@ class _BC(C.Structure):
                 ("profile_len", C.c_int32), ("alt", C.c_int32), ("law", C.c_int32), ("value", C.c_double),
                 ("a1", C.c_double), ("a3", C.c_double), ("quad", C.c_double),
                 ("profile", C.POINTER(C.c_double)), ("k", C.c_double), ("phi_eq", C.c_double),
-                ("c_w", C.c_double), ("H", C.c_double), ("partner", C.c_int32), ("pad", C.c_int32),
+                ("c_w", C.c_double), ("H", C.c_double), ("cj", C.c_int32), ("cl", C.c_int32),
                 ("cross", C.c_double)]
 
 
@@ -73,7 +73,7 @@ class Link(C.Structure):
                 ("u_given", C.c_int32), ("d", C.c_double), ("value", C.c_double),
                 ("a1", C.c_double), ("a3", C.c_double), ("weight", C.c_double),
                 ("u_w", C.c_double * 3), ("omega", C.c_double), ("compare", C.c_int32), ("pad", C.c_int32),
-                ("quad", C.c_double), ("partner", C.c_int32), ("pad2", C.c_int32), ("cross", C.c_double)]
+                ("quad", C.c_double), ("cj", C.c_int32), ("cl", C.c_int32), ("cross", C.c_double)]
 
 
 class LinkIn(C.Structure):
@@ -83,7 +83,8 @@ class LinkIn(C.Structure):
                 ("weight", C.c_double), ("u_w", C.c_double * 3), ("x_ap_E", C.c_double),
                 ("x_ap_A", C.c_double), ("x_a_A", C.c_double), ("mA", C.c_double * 10),
                 ("mE", C.c_double * 10), ("compare", C.c_int32), ("quad", C.c_double),
-                ("cslot", C.c_int32), ("pslot", C.c_int32), ("cross", C.c_double)]
+                ("cslot", C.c_int32), ("jslot", C.c_int32), ("lslot", C.c_int32),
+                ("cross", C.c_double)]
 
 
 _libs = {}
@@ -161,8 +162,8 @@ def link_eval(**kw) -> float:
     Keywords: lattice (name), kind (name), dir, d, x_ap_E, x_ap_A, x_a_A,
     mA, mE (vectors rho, u, C_0, B, C_1, C_2), value, a1, quad, a3, weight,
     u_w, u_given, comp_axis; FLUX of several components: cslot (moment slot
-    of the link's component, 4 by default), pslot (of the cross term's
-    component, -1 none) and cross.
+    of the link's component, 4 by default), jslot, lslot (of the bilinear
+    term's components, -1 none) and cross.
     """
     li = LinkIn()
     li.lattice = S.LATTICE_CODES[kw.get("lattice", "D2Q9")]
@@ -176,7 +177,8 @@ def link_eval(**kw) -> float:
         setattr(li, k, float(kw.get(k, 0.0)))
     li.weight = float(kw.get("weight", 1.0))
     li.cslot = int(kw.get("cslot", 4))
-    li.pslot = int(kw.get("pslot", -1))
+    li.jslot = int(kw.get("jslot", -1))
+    li.lslot = int(kw.get("lslot", -1))
     li.cross = float(kw.get("cross", 0.0))
     for i, v in enumerate(kw.get("u_w", (0.0, 0.0, 0.0))):
         li.u_w[i] = v
@@ -243,7 +245,8 @@ class _SceneHolder:
         dst.value, dst.a1, dst.a3, dst.quad = bc.value, bc.a1, bc.a3, bc.quad
         dst.k, dst.phi_eq, dst.c_w, dst.H = bc.k, bc.phi_eq, bc.c_w, bc.H
         dst.profile_axis = bc.profile_axis
-        dst.partner, dst.cross = bc.partner, bc.cross
+        dst.cj, dst.cl = bc.cross_comps
+        dst.cross = bc.cross
         if bc.profile is not None:
             p = np.ascontiguousarray(bc.profile, dtype=np.float64)
             self.keep.append(p)
@@ -326,7 +329,7 @@ class OracleSim:
                        ("kind", "i4"), ("bnd", "i4"), ("u_given", "i4"), ("d", "f8"),
                        ("value", "f8"), ("a1", "f8"), ("a3", "f8"), ("weight", "f8"),
                        ("u_w", "f8", 3), ("omega", "f8"), ("compare", "i4"), ("pad", "i4"),
-                       ("quad", "f8"), ("partner", "i4"), ("pad2", "i4"), ("cross", "f8")])
+                       ("quad", "f8"), ("cj", "i4"), ("cl", "i4"), ("cross", "f8")])
         assert dt.itemsize == C.sizeof(Link)
         return np.frombuffer(bytes(out), dtype=dt, count=n).copy()
 

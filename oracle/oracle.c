@@ -24,9 +24,11 @@
  *    the smaller d, then the lower boundary index.
  *  - several scalar components C_1 .. C_ns (Section 4.2.2): one convection-
  *    diffusion lattice each, with its own relaxation time; a flux wall's law
- *    for component i may also depend on another component j,
- *    F_i = a1 C_i + quad C_i^2 + cross C_i C_j - a3, with both C_i(X) and
- *    C_j(X) extrapolated by Eq. 13 (no iteration couples the components).
+ *    for component i may also depend on the other components through one
+ *    bilinear term, F_i = a1 C_i + quad C_i^2 + cross C_j C_l - a3 (j, l any
+ *    components, i included: the rate of a reaction A + B -> P consumes A and
+ *    B and produces P), every C(X) extrapolated by Eq. 13 (no iteration
+ *    couples the components).
  */
 #include <math.h>
 #include <stdint.h>
@@ -198,9 +200,8 @@ typedef struct {
     double k;             /* LAW_ROBIN: d phi/dn = k phi; LAW_REACTION: F = -k (phi - phi_eq) */
     double phi_eq;
     double c_w, H;        /* LAW_SHERCLIFF: thin-wall conductance ratio, length scale */
-    int32_t partner;      /* scalar component j of the cross term (LAW_COEF, FLUX); -1: none */
-    int32_t pad;
-    double cross;         /* F_i += cross C_i C_j */
+    int32_t cj, cl;       /* scalar components j, l of the bilinear term (LAW_COEF, FLUX); -1: none */
+    double cross;         /* F_i += cross C_j C_l */
 } or_bc;
 
 typedef struct {
@@ -247,9 +248,8 @@ typedef struct {
     int32_t compare; /* comparison form of the kind (Section 5) */
     int32_t pad;
     double quad;     /* quadratic term of the flux law */
-    int32_t partner; /* FLUX: scalar component j of the cross term, -1 none */
-    int32_t pad2;
-    double cross;    /* FLUX: F_i += cross C_i(X) C_j(X) */
+    int32_t cj, cl;  /* FLUX: scalar components j, l of the bilinear term, -1 none */
+    double cross;    /* FLUX: F_i += cross C_j(X) C_l(X) */
 } or_link;
 
 /* ------------------------------------------------------------------------- */
@@ -508,10 +508,11 @@ static void flux_law(const or_scene* s, const or_bc* bc, int field, const or_lat
         lk->a3 = bc->a3;
         lk->quad = bc->quad;
     }
-    lk->partner = -1;
+    lk->cj = lk->cl = -1;
     lk->cross = 0.0;
-    if (field == 1 && bc->kind == K_FLUX && bc->law == LAW_COEF && bc->partner >= 0) {
-        lk->partner = bc->partner;
+    if (field == 1 && bc->kind == K_FLUX && bc->law == LAW_COEF && bc->cj >= 0 && bc->cl >= 0) {
+        lk->cj = bc->cj;
+        lk->cl = bc->cl;
         lk->cross = bc->cross;
     }
 }
@@ -776,8 +777,8 @@ typedef struct {
     int32_t compare;     /* the comparison form of the kind (Section 5) */
     double quad;         /* quadratic term of the flux law */
     int32_t cslot;       /* FLUX: moment slot of the link's scalar component */
-    int32_t pslot;       /* FLUX: moment slot of the cross term's component, -1: none */
-    double cross;        /* FLUX: coefficient of C_i(X) C_j(X) in F_i */
+    int32_t jslot, lslot; /* FLUX: moment slots of the bilinear term's components, -1: none */
+    double cross;        /* FLUX: coefficient of C_j(X) C_l(X) in F_i */
 } or_link_in;
 
 /* Eq. 13: phi(X) = -d phi(E) + (d+1) phi(A) */
@@ -792,7 +793,7 @@ typedef struct {
     real mA[MOMW], mE[MOMW];
     int32_t compare;
     real quad;
-    int32_t cslot, pslot;
+    int32_t cslot, jslot, lslot;
     real cross;
 } or_link_in_r;
 
@@ -842,9 +843,11 @@ static real link_eval_r(const or_link_in_r* in) {
             if (in->kind == K_FLUX) {
                 phiX = extrap(d, in->mE[in->cslot], in->mA[in->cslot]);
                 dmove = heq(&L, ap, phiX, mu_) - heq(&L, a, phiX, mu_); /* Eq. 24 */
-                /* another component's value at X, extrapolated the same way
-                 * (Section 4.2.2): F_i(C_i, C_j) needs no iteration */
-                if (in->pslot >= 0) cross = in->cross * phiX * extrap(d, in->mE[in->pslot], in->mA[in->pslot]);
+                /* other components' values at X, extrapolated the same way
+                 * (Section 4.2.2): F_i(C_1, C_2, ...) needs no iteration */
+                if (in->jslot >= 0 && in->lslot >= 0)
+                    cross = in->cross * extrap(d, in->mE[in->jslot], in->mA[in->jslot]) *
+                            extrap(d, in->mE[in->lslot], in->mA[in->lslot]);
             } else {
                 phiX = BX[in->comp_axis];
                 dmove = geq(&L, ap, in->comp_axis, BX, mu_) - geq(&L, a, in->comp_axis, BX, mu_);
@@ -890,7 +893,8 @@ double or_link_eval(const or_link_in* in) {
     r.compare = in->compare;
     r.quad = in->quad;
     r.cslot = in->cslot;
-    r.pslot = in->pslot;
+    r.jslot = in->jslot;
+    r.lslot = in->lslot;
     r.cross = in->cross;
     for (int k = 0; k < 3; ++k) r.u_w[k] = in->u_w[k];
     for (int k = 0; k < MOMW; ++k) {
@@ -920,7 +924,8 @@ static void apply_links(or_sim* S) {
         in.compare = lk->compare;
         in.quad = lk->quad;
         in.cslot = lk->field == 1 ? cslot(lk->comp) : 4;
-        in.pslot = lk->field == 1 && lk->partner >= 0 ? cslot(lk->partner) : -1;
+        in.jslot = lk->field == 1 && lk->cj >= 0 ? cslot(lk->cj) : -1;
+        in.lslot = lk->field == 1 && lk->cl >= 0 ? cslot(lk->cl) : -1;
         in.cross = lk->cross;
         in.d = lk->d;
         in.value = lk->value;

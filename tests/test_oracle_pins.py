@@ -337,52 +337,72 @@ def test_nonlinear_surface_reaction_exact(qb, qt):
     assert np.isclose(quad - base, -k * CX * CX, rtol=1e-12)
 
 
-def _two_species(qb, qt, k, ny=12, tau=(0.8, 0.65), Cb=(1.0, 0.6)):
-    """components A (0) and B (1) given below; above, the reaction A + B ->
-    products consumes both at the rate k C_A C_B (F_i = -k C_A C_B)"""
-    bot = Boundary("plane", axis=1, side=0, q=qb, f=BC("VEL"),
-                   h=[BC("CONC", value=Cb[0]), BC("CONC", value=Cb[1])])
+def _two_species(qb, qt, k, ny=12, tau=(0.8, 0.65, 0.7), Cb=(1.0, 0.6, 0.2), product=False):
+    """components A (0) and B (1), and with `product` P (2), given below;
+    above, the reaction A + B -> P at the rate k C_A C_B consumes A and B
+    (F_A = F_B = -k C_A C_B) and produces P (F_P = +k C_A C_B)"""
+    n = 3 if product else 2
+    bot = Boundary("plane", axis=1, side=0, q=qb, f=BC("VEL"), h=[BC("CONC", value=Cb[i]) for i in range(n)])
     top = Boundary("plane", axis=1, side=1, q=qt, f=BC("VEL"),
-                   h=[BC("FLUX", partner=1, cross=-k), BC("FLUX", partner=0, cross=-k)])
+                   h=[BC("FLUX", cross_comps=(0, 1), cross=-k if i < 2 else k) for i in range(n)])
     return Scene(name="ab1d", dim=2, n=(1, ny, 1), periodic=(True, False, True), fluid_lattice="D2Q9",
-                 scalar_lattice="D2Q5", scalar_ncomp=2, tau_c=tau[0], tau_cs=(tau[1],), init_C=0.5,
+                 scalar_lattice="D2Q5", scalar_ncomp=n, tau_c=tau[0], tau_cs=tuple(tau[1:n]), init_C=0.5,
                  boundaries=[bot, top])
 
 
-@pytest.mark.parametrize("qb,qt", [(0.5, 0.5), (0.3, 0.8), (0.9, 1.0)])
-def test_two_component_surface_reaction_exact(qb, qt):
-    """Two scalar components reacting at a wall (Section 4.2.2): each
-    component's flux F_i(C_A, C_B) = -k C_A C_B is evaluated explicitly from
-    both extrapolated wall values (Eq. 13), with no iteration coupling the
-    components.  With both given below, the steady profiles are the lines
-    C_i = C_i,b + s_i y with D_i s_i = -phi, phi = k C_A(W) C_B(W), i.e.
+@pytest.mark.parametrize("qb,qt,product", [(0.5, 0.5, False), (0.3, 0.8, False), (0.9, 1.0, False),
+                                           (0.4, 0.7, True)])
+def test_multi_component_surface_reaction_exact(qb, qt, product):
+    """Scalar components reacting at a wall (Section 4.2.2): each component's
+    flux F_i(C_A, C_B) = -/+ k C_A C_B is evaluated explicitly from the
+    extrapolated wall values (Eq. 13), with no iteration coupling the
+    components.  With all given below, the steady profiles are the lines
+    C_i = C_i,b + s_i y with D_A s_A = D_B s_B = -phi (and D_P s_P = +phi),
+    phi = k C_A(W) C_B(W), i.e.
     k (W^2 / (D_A D_B)) phi^2 - (1 + k W (C_A,b / D_B + C_B,b / D_A)) phi
     + k C_A,b C_B,b = 0, reached to rounding for any d."""
-    ny, k, Cb = 12, 0.01, (1.0, 0.6)
-    DA, DB = (0.8 - 0.5) / 4, (0.65 - 0.5) / 4
+    ny, k, Cb = 12, 0.01, (1.0, 0.6, 0.2)
+    DA, DB, DP = (0.8 - 0.5) / 4, (0.65 - 0.5) / 4, (0.7 - 0.5) / 4
     y = np.arange(ny) + qb
     W = ny - 1 + qb + qt
-    o = oracle.OracleSim(_two_species(qb, qt, k, ny=ny, Cb=Cb))
+    o = oracle.OracleSim(_two_species(qb, qt, k, ny=ny, Cb=Cb, product=product))
     o.step(120000)
     a = k * W * W / (DA * DB)
     b = -(1 + k * W * (Cb[0] / DB + Cb[1] / DA))
     c = k * Cb[0] * Cb[1]
     phi = (-b - math.sqrt(b * b - 4 * a * c)) / (2 * a)
     m = o.moments()
-    assert m.shape[-1] == 9
+    assert m.shape[-1] == (10 if product else 9)
     assert np.abs(m[0, :, 0, 4] - (Cb[0] - phi / DA * y)).max() < 1e-11
     assert np.abs(m[0, :, 0, 8] - (Cb[1] - phi / DB * y)).max() < 1e-11
-    # the cross term enters a link as a linear term with the partner's
-    # extrapolated value as coefficient
+    if product:
+        assert np.abs(m[0, :, 0, 9] - (Cb[2] + phi / DP * y)).max() < 1e-11
+
+
+def test_bilinear_flux_term_is_a_linear_term_with_extrapolated_coefficient():
+    """The bilinear term cross C_j(X) C_l(X) of a FLUX link equals a linear
+    term a1 C_i(X) whose coefficient is cross times the other component's
+    value at X, both extrapolated by Eq. 13; with j = l = i it is the
+    quadratic term."""
+    k = 0.01
     x = dict(x_ap_E=0.11, x_ap_A=0.13, x_a_A=0.07, d=0.3)
-    mA = [1, 0, 0, 0, 0.9, 0, 0, 0, 0.4, 0]
-    mE = [1, 0, 0, 0, 0.8, 0, 0, 0, 0.7, 0]
-    PX = -0.3 * 0.7 + 1.3 * 0.4
-    cross = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, pslot=8, cross=-k, **x)
-    lin = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, a1=-k * PX, **x)
+    mA = [1, 0, 0, 0, 0.9, 0, 0, 0, 0.4, 0.25]
+    mE = [1, 0, 0, 0, 0.8, 0, 0, 0, 0.7, 0.5]
+    BX = -0.3 * 0.7 + 1.3 * 0.4
+    PX = -0.3 * 0.5 + 1.3 * 0.25
+    cross = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, jslot=4, lslot=8, cross=-k, **x)
+    lin = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, a1=-k * BX, **x)
     assert np.isclose(cross, lin, rtol=1e-14, atol=1e-16)
+    # a component's flux driven by two others only: a constant a3 = -cross B_X P_X
+    prod = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, jslot=8, lslot=9, cross=k, **x)
+    const = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, a3=-k * BX * PX, **x)
+    assert np.isclose(prod, const, rtol=1e-14, atol=1e-16)
+    sq = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, jslot=4, lslot=4, cross=-k, **x)
+    quad = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, quad=-k, **x)
+    assert np.isclose(sq, quad, rtol=1e-14, atol=1e-16)
     # the second component's own link reads its value from slot 8
-    own = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA, mE=mE, cslot=8, a1=0.05, **x)
+    own = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=mA[:9] + [0], mE=mE[:9] + [0], cslot=8,
+                           a1=0.05, **x)
     swap = oracle.link_eval(lattice="D2Q5", kind="FLUX", dir=3, mA=[1, 0, 0, 0, 0.4, 0, 0, 0, 0.9, 0],
                             mE=[1, 0, 0, 0, 0.7, 0, 0, 0, 0.8, 0], a1=0.05, **x)
     assert own == swap
