@@ -4,7 +4,9 @@
  * One step advances three coupled lattices on a regular grid:
  *   f  flow, BGK (Eqs. 1-2), D2Q9 or D3Q19, with a body force and the Lorentz
  *      force J x B;
- *   h  convection-diffusion scalar C (Eqs. 3-4), D2Q5 or D3Q7;
+ *   h  convection-diffusion scalar C (Eqs. 3-4), D2Q5 or D3Q7, for one to
+ *      three scalar components C_0, C_1, C_2, one lattice each, whose flux
+ *      walls may react with each other (Section 4.2.2);
  *   g  vector-valued magnetic distributions for B (Eqs. 5-6), D2Q5 or D3Q7,
  *      one distribution per evolved Cartesian component of B;
  * and, in the same sweep, the boundary-link updates of Sections 3-4:
@@ -94,25 +96,30 @@ typedef struct {
     int32_t mag_ncomp;    /* evolved B components: 0 (no magnetic lattice), 1..3 */
     int32_t mag_comp[3];  /* Cartesian axis (0..2) of each evolved component */
     int32_t storage;      /* lbm_storage */
-    int32_t reserved;
+    int32_t scalar_ncomp; /* scalar components (Section 4.2.2), one scalar lattice each: 0 or 1 =
+                             one component C_0; 2 or 3 with a scalar lattice and no magnetic
+                             lattice.  Component k relaxes with tau_c (k = 0) or tau_cs[k - 1];
+                             all share the rest value C0 and the flow field */
     double tau_f, tau_c, tau_m;  /* relaxation times (> 1/2) */
     double rho0, C0, mu;         /* rest density, rest concentration, permeability */
     double B_ext[3];             /* applied field; non-evolved components stay at B_ext */
     double accel[3];             /* body force per unit mass */
     double store_scale[3];       /* F16/BF16: power-of-two scale of f, h, g deviations */
     double wall_omega;           /* angular frequency (rad per step) of oscillating boundary velocities */
+    double tau_cs[2];            /* relaxation times of scalar components 1 and 2 (> 1/2 when present) */
 } lbm_params;
 
 /* One boundary link: the population entering fluid node A along e_alpha, whose
  * source node A - e_alpha lies beyond a boundary.  For a magnetic link, comp is
- * the slot (0..mag_ncomp-1) of the evolved component. */
+ * the slot (0..mag_ncomp-1) of the evolved component; for a scalar link, the
+ * scalar component (0..scalar_ncomp-1). */
 typedef struct {
     uint32_t node;   /* fluid node A (domain linear index) */
     uint32_t enode;  /* second fluid node E = A + e_alpha; ignored when flags bit 1 is set */
     uint8_t field;   /* 0 = f, 1 = h, 2 = g */
     uint8_t dir;     /* unknown direction alpha (lattice numbering, see lbm_lattice_table) */
     uint8_t kind;    /* lbm_link_kind */
-    uint8_t comp;    /* magnetic slot */
+    uint8_t comp;    /* magnetic slot or scalar component */
     uint8_t flags;   /* bit 0: u_w is the boundary velocity (else extrapolated, Eq. 13);
                         bit 1: E is not fluid, A stands in for E;
                         bit 2 (with bit 0): the boundary velocity oscillates,
@@ -127,7 +134,8 @@ typedef struct {
                         FLUX and MAG_FLUX add the flux at X instead of M (Eq. 33,
                         and Y + flux + correction for d < 0.5).  Other kinds:
                         LBM_EINVAL */
-    uint8_t pad[3];
+    uint8_t cross_comp[2]; /* FLUX with cross != 0: the scalar components j, l of the bilinear term */
+    uint8_t pad;
     double d;        /* boundary-to-node distance |AX| / |AE| in (0, 1] */
     double value;    /* PRES: rho_w; CONC: C_w; MAG_DIR: B_k */
     double a1, a3;   /* FLUX / MAG_FLUX: F(phi) = a1 phi_X - a3 (lattice units; Eq. 17 with a2 = D);
@@ -140,6 +148,11 @@ typedef struct {
                         - a3, evaluated explicitly from the extrapolated phi_X (Eq. 13; a nonlinear
                         surface reaction, Section 4.2.2); 0 for the other kinds (else LBM_EINVAL).
                         (Eq. 17's own a2 is the coefficient of the normal derivative, D here.) */
+    double cross;    /* FLUX of one of several scalar components i = comp: F_i gains cross C_j,X C_l,X with
+                        (j, l) = cross_comp (any components, i included), each C_X extrapolated by Eq. 13
+                        like C_i,X: a surface reaction between components (Section 4.2.2; A + B -> P
+                        consumes A and B at the rate k C_A C_B and produces P), with no iteration between
+                        them; 0 for the other kinds and with one scalar component (else LBM_EINVAL) */
 } lbm_link;
 
 /* How a boundary states the flux law of a FLUX or MAG_FLUX condition, or the
@@ -180,6 +193,9 @@ typedef struct {
     double phi_eq;         /* LBM_LAW_REACTION: equilibrium value of the reacting field */
     double c_w, H;         /* LBM_LAW_SHERCLIFF: wall conductance ratio (> 0, may be +inf) and the
                               length scale of Eq. 30 (> 0): the channel half-width or pipe radius */
+    int32_t cross_comp[2]; /* FLUX, LBM_LAW_COEF, several scalar components: the components j, l
+                              (0..scalar_ncomp-1) of the bilinear term */
+    double cross;          /* its coefficient: F_i += cross C_j,X C_l,X (lbm_link.cross); 0 = none */
 } lbm_bc;
 
 typedef struct {
@@ -205,6 +221,8 @@ typedef struct {
                             channel between reservoirs, Section 5.1).  Along a
                             periodic axis a box must be unbounded or stay clear of
                             the domain's ends. */
+    lbm_bc h_more[2]; /* conditions of scalar components 1 and 2 (h is component 0's); each must
+                         have a kind exactly when h has one */
 } lbm_boundary;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -259,8 +277,9 @@ lbm_status lbm_set_geometry(lbm_ctx* ctx, const uint8_t* host_mask);
 lbm_status lbm_set_links(lbm_ctx* ctx, const lbm_link* host_links, size_t n);
 
 /* Equilibrium initialisation (Eqs. 2, 4, 6) from device FP64 fields in domain
- * layout: rho [N], u [3][N], C [N], B [3][N] (N = domain nodes); any may be
- * NULL for the uniform rest value (rho0, 0, C0, B_ext).  Sets time 0. */
+ * layout: rho [N], u [3][N], C [scalar components][N], B [3][N] (N = domain
+ * nodes); any may be NULL for the uniform rest value (rho0, 0, C0, B_ext).
+ * Sets time 0. */
 lbm_status lbm_init(lbm_ctx* ctx, const double* dev_rho, const double* dev_u, const double* dev_C,
                     const double* dev_B);
 
@@ -296,20 +315,24 @@ lbm_status lbm_step_stats(const lbm_ctx* ctx, int64_t out[3]);
 size_t lbm_timing_scratch_bytes(const lbm_ctx* ctx);
 lbm_status lbm_step_timed(lbm_ctx* ctx, int64_t n, void* dev_scratch, size_t scratch_bytes, float ms_out[2]);
 
-/* Moments at the current time into dev_out, SoA [8][N] of rho, u_x, u_y, u_z,
- * C, B_x, B_y, B_z (0 at solid nodes); out_type LBM_F64 or LBM_F32. */
+/* Moments at the current time into dev_out, SoA [7 + m][N] of rho, u_x, u_y,
+ * u_z, C_0, B_x, B_y, B_z, then C_1 .. C_{m-1} of m >= 2 scalar components
+ * (m = max(scalar_ncomp, 1); 0 at solid nodes); out_type LBM_F64 or
+ * LBM_F32. */
 lbm_status lbm_read_moments(lbm_ctx* ctx, void* dev_out, int32_t out_type);
 
 /* Populations of one field at the current time (after the boundary links),
- * FP64 into dev_out as [slots][N]: f: Q planes; h: Q planes; g: ncomp*Q
- * planes (component-major).  Solid nodes hold 0. */
+ * FP64 into dev_out as [slots][N]: f: Q planes; h: m*Q planes of the m
+ * scalar components; g: ncomp*Q planes (component-major).  Solid nodes
+ * hold 0. */
 lbm_status lbm_read_populations(lbm_ctx* ctx, int32_t field, double* dev_out);
 
 /* FP64 reductions at the current time, synchronising the stream:
- * out[0] steady-state residual: max over u, C - C0 and B - B_ext of
+ * out[0] steady-state residual: max over u, C - C0 (all scalar components
+ *        together) and B - B_ext of
  *        ||phi(t) - phi(t0)||_2 / ((t - t0) max(||phi(t)||_2, 1e-30)), where t0
  *        is the time of the previous lbm_reduce (-1 on the first call);
- * out[1] total mass sum(rho); out[2] sum(C); out[3..5] sum(B);
+ * out[1] total mass sum(rho); out[2] sum(C_0); out[3..5] sum(B);
  * out[6] t - t0; out[7] number of non-finite moments.
  * Returns LBM_EUNSTABLE when out[7] > 0. */
 lbm_status lbm_reduce(lbm_ctx* ctx, double out[8]);

@@ -30,17 +30,18 @@ class lbm_params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
                 ("fluid", C.c_int32), ("scalar", C.c_int32), ("magnetic", C.c_int32),
                 ("mag_ncomp", C.c_int32), ("mag_comp", C.c_int32 * 3), ("storage", C.c_int32),
-                ("reserved", C.c_int32), ("tau_f", C.c_double), ("tau_c", C.c_double),
+                ("scalar_ncomp", C.c_int32), ("tau_f", C.c_double), ("tau_c", C.c_double),
                 ("tau_m", C.c_double), ("rho0", C.c_double), ("C0", C.c_double), ("mu", C.c_double),
                 ("B_ext", C.c_double * 3), ("accel", C.c_double * 3), ("store_scale", C.c_double * 3),
-                ("wall_omega", C.c_double)]
+                ("wall_omega", C.c_double), ("tau_cs", C.c_double * 2)]
 
 
 class lbm_link(C.Structure):
     _fields_ = [("node", C.c_uint32), ("enode", C.c_uint32), ("field", C.c_uint8), ("dir", C.c_uint8),
-                ("kind", C.c_uint8), ("comp", C.c_uint8), ("flags", C.c_uint8), ("pad", C.c_uint8 * 3),
-                ("d", C.c_double), ("value", C.c_double), ("a1", C.c_double), ("a3", C.c_double),
-                ("weight", C.c_double), ("u_w", C.c_double * 3), ("quad", C.c_double)]
+                ("kind", C.c_uint8), ("comp", C.c_uint8), ("flags", C.c_uint8),
+                ("cross_comp", C.c_uint8 * 2), ("pad", C.c_uint8), ("d", C.c_double), ("value", C.c_double), ("a1", C.c_double),
+                ("a3", C.c_double), ("weight", C.c_double), ("u_w", C.c_double * 3), ("quad", C.c_double),
+                ("cross", C.c_double)]
 
 
 class lbm_bc(C.Structure):
@@ -48,7 +49,8 @@ class lbm_bc(C.Structure):
                 ("profile_len", C.c_int32), ("alt", C.c_int32), ("law", C.c_int32),
                 ("value", C.c_double), ("a1", C.c_double), ("a3", C.c_double), ("quad", C.c_double),
                 ("profile", C.POINTER(C.c_double)), ("k", C.c_double), ("phi_eq", C.c_double),
-                ("c_w", C.c_double), ("H", C.c_double)]
+                ("c_w", C.c_double), ("H", C.c_double), ("cross_comp", C.c_int32 * 2),
+                ("cross", C.c_double)]
 
 
 class lbm_boundary(C.Structure):
@@ -56,7 +58,7 @@ class lbm_boundary(C.Structure):
                 ("q", C.c_double), ("center", C.c_double * 3), ("radius", C.c_double),
                 ("u_w", C.c_double * 3), ("f", lbm_bc), ("h", lbm_bc), ("g", lbm_bc * 3),
                 ("u_osc", C.c_int32), ("reserved", C.c_int32), ("d_scheme", C.c_double),
-                ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("h_more", lbm_bc * 2)]
 
 
 class lbm_batch_config(C.Structure):

@@ -101,6 +101,10 @@ bool batch_layout(int n, const lbm_params* p, const size_t* nl, BatchLayout* L, 
             if (why) *why = "item " + std::to_string(i) + ": " + w;
             return false;
         }
+        if (p[i].scalar_ncomp > 1) {
+            if (why) *why = "item " + std::to_string(i) + ": several scalar components are not batched";
+            return false;
+        }
         if (!same_combo(p[0], p[i])) {
             if (why) *why = "item " + std::to_string(i) + " differs from item 0 in lattices or storage";
             return false;
@@ -176,7 +180,8 @@ void advance(lbm_batch* b, int64_t k) {
 void aux_of(const lbm_ctx* c, void** snap, double** acc) {
     char* aux = (char*)c->buf[4];
     *snap = aux;
-    *acc = (double*)(aux + round_up(7 * c->pad.plane * compute_bytes(c->p.storage), kAlign));
+    *acc = (double*)(aux + round_up((size_t)(moment_planes(&c->p) - 1) * c->pad.plane * compute_bytes(c->p.storage),
+                                    kAlign));
 }
 
 // item descriptors from the items' current state (links count only for items

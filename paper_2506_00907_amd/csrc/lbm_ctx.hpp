@@ -28,6 +28,8 @@ Pad padding(const lbm_params* p);
 size_t value_bytes(int storage);
 size_t compute_bytes(int storage);
 int total_planes(const lbm_params* p);
+int scalar_comps(const lbm_params* p);   // scalar components (1 without several)
+int moment_planes(const lbm_params* p);  // moment planes per parity: 8 + scalar components - 1
 lbmi::KernelSet kernels_for(const lbm_params* p);
 // device buffer sizes of one context (roles as in lbm.h)
 void layout(const lbm_params* p, size_t n_links, size_t sz[LBM_NBUF]);

@@ -256,7 +256,7 @@ __device__ __forceinline__ void st8(T* p, uint32_t i, const uint32_t w[2]) {
 // ---------------------------------------------------------------------------
 // configuration bundle
 // ---------------------------------------------------------------------------
-template <int FLC, int SLC, int MLC, int NC, class SF>
+template <int FLC, int SLC, int MLC, int NC, class SF, int NSC = 1>
 struct Cfg {
     using FL = typename LatOf<FLC>::T;
     using HL = typename LatOf<SLC>::T;
@@ -268,9 +268,11 @@ struct Cfg {
     static constexpr int QH = HL::Q;
     static constexpr int QG = GL::Q;
     static constexpr int NCOMP = (MLC == 0) ? 0 : NC;
-    static constexpr int QT = QF + QH + NCOMP * QG;
-    static constexpr int H0 = QF;          // first h plane
-    static constexpr int G0 = QF + QH;     // first g plane
+    static constexpr int NS = (SLC == 0) ? 1 : NSC;  // scalar components, one h lattice each
+    static constexpr int QT = QF + NS * QH + NCOMP * QG;
+    static constexpr int H0 = QF;          // first h plane (component k: H0 + k QH)
+    static constexpr int G0 = QF + NS * QH;  // first g plane
+    static constexpr int MW = 8 + NS - 1;  // moment planes: rho, u, C_0, B, then C_1, C_2
     static constexpr bool SCALED = sizeof(T) == 2;  // 16-bit storage carries a power-of-two scale
 };
 
@@ -278,6 +280,7 @@ struct Cfg {
 template <class R>
 struct Phys {
     R omf, omc, omm, guo;          // 1/tau_f, 1/tau_c, 1/tau_m, 1 - 1/(2 tau_f)
+    R omcx[2];                     // 1/tau of scalar components 1, 2
     R rho0, C0, inv_mu, grad_c;    // grad_c = 1/(tau_m c_g^2)
     R Bext[3], acc[3];
     R sc[3], isc[3];               // storage scale and inverse (f, h, g)
@@ -289,6 +292,7 @@ __host__ Phys<R> make_phys(const KArgs& a, double cg2) {
     Phys<R> p;
     p.omf = (R)(1.0 / a.tau_f);
     p.omc = (R)(1.0 / a.tau_c);
+    for (int k = 0; k < 2; ++k) p.omcx[k] = (R)(a.tau_cs[k] > 0.0 ? 1.0 / a.tau_cs[k] : 1.0);
     p.omm = (R)(1.0 / a.tau_m);
     p.guo = (R)(1.0 - 0.5 / a.tau_f);
     p.rho0 = (R)a.rho0;
@@ -344,6 +348,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
 template <class R>
 struct Mom {
     R drho, u[3], dC, dB[3];  // deviations from rho0, C0 and B_ext (all three axes)
+    R dCx[2];                 // deviations of scalar components 1, 2 from C0
 };
 
 // ---------------------------------------------------------------------------
@@ -352,12 +357,15 @@ struct Mom {
 // x_a:   post-collision deviation of A along alpha
 // x_apA: post-collision deviation of A along alpha'
 // x_apE: post-collision deviation of E along alpha' (streamed value)
-// mA, mE: moments at A and E at the previous time (deviations + u)
+// mA, mE: moments at A and E at the previous time (deviations + u); slot 4
+// holds the link's own scalar component, slots 8 and 9 (XS) the components
+// of a bilinear flux term
 // t: time of the value being set (the bounced population meets the boundary
 // at t - d, where an oscillating boundary velocity is evaluated)
 // CMP: the comparison forms (link flag bit 3, kind 8) are compiled in; the
 // method-only instantiation keeps the link kernel of the hot path lean.
-template <class R, bool CMP = true>
+// XS: several scalar components (a FLUX link may carry a cross term).
+template <class R, bool CMP = true, bool XS = false>
 __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R x_a, R x_apA,
                                         R x_apE, const R* mA, const R* mE, R w, R c2, uint32_t t) {
     const R d = L.d;
@@ -429,7 +437,16 @@ __device__ __forceinline__ R link_value(const DevLink<R>& L, const Phys<R>& P, R
                 const R tb = ((th - one) * bx + th * dmove - two * w * Bk) / (th + one);
                 return lo ? tb : ((two * d - one) * x_a + tb) / (two * d);
             }
-            R dflux = ((L.a1 + L.quad * phiX) * phiX - L.a3) * L.weight;  // F(phi_X), explicit
+            // F(phi_X), explicit; a bilinear term in components j, l
+            // (Section 4.2.2) takes their values at X extrapolated the same way
+            R dflux;
+            if (XS && L.pslot) {
+                const R JX = P.C0 + cE * mE[8] + cA * mA[8];
+                const R LX = P.C0 + cE * mE[9] + cA * mA[9];
+                dflux = ((L.a1 + L.quad * phiX) * phiX + L.value * JX * LX - L.a3) * L.weight;
+            } else {
+                dflux = ((L.a1 + L.quad * phiX) * phiX - L.a3) * L.weight;
+            }
             if (alt)  // flux added at X, not at M (Eq. 33 and its d < 0.5 analogue)
                 return lo ? Y + dflux + dmove : ((two * d - one) * x_a + x_apA + dflux + dmove) / (two * d);
             R xM = (half - d) * x_apE + (half + d) * x_apA + dflux + dmove;
@@ -496,18 +513,29 @@ __device__ __forceinline__ typename C::R link_update(const Geo& G, const Phys<ty
         x_apA *= isc;
         xs *= isc;
     }
-    const R* Mp = M + (size_t)(ODD ^ 1) * 8 * PL;  // moments of the previous time
-    // only the moments this link's formula uses are read (the rest stay 0)
-    R mA[8], mE[8];
+    const R* Mp = M + (size_t)(ODD ^ 1) * C::MW * PL;  // moments of the previous time
+    // only the moments this link's formula uses are read (the rest stay 0);
+    // the scalar slot reads the link's own component, slots 8 and 9 the
+    // components of a bilinear term
+    R mA[10], mE[10];
     const uint32_t need = L.need;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         mA[q] = (R)0;
         mE[q] = (R)0;
         if (need & (1u << q)) {
-            mA[q] = Mp[(size_t)q * PL + L.A];
-            mE[q] = Mp[(size_t)q * PL + L.mE];
+            const size_t src = (C::NS > 1 && q == 4) ? (size_t)L.cslot : (size_t)q;
+            mA[q] = Mp[src * PL + L.A];
+            mE[q] = Mp[src * PL + L.mE];
         }
+    }
+    mA[8] = mE[8] = mA[9] = mE[9] = (R)0;
+    if (C::NS > 1 && L.pslot) {
+        const size_t j = L.pslot & 15u, l = L.pslot >> 4;
+        mA[8] = Mp[j * PL + L.A];
+        mE[8] = Mp[j * PL + L.mE];
+        mA[9] = Mp[l * PL + L.A];
+        mE[9] = Mp[l * PL + L.mE];
     }
     const int e2 = L.ex * L.ex + L.ey * L.ey + L.ez * L.ez;
     R w, c2;
@@ -521,7 +549,7 @@ __device__ __forceinline__ typename C::R link_update(const Geo& G, const Phys<ty
         w = (R)0.125;
         c2 = (R)0.25;
     }
-    const R v = link_value<R, CMP>(L, P, x_a, x_apA, xs, mA, mE, w, c2, t);
+    const R v = link_value<R, CMP, (C::NS > 1)>(L, P, x_a, x_apA, xs, mA, mE, w, c2, t);
     if (ODD) st_sr<SF>(Sp, L.B, C::SCALED ? v * sc : v, C::SCALED ? dither(L.B, L.pap, seed) : 0u);
     else st_sr<SF>(Sa, L.A, C::SCALED ? v * sc : v, C::SCALED ? dither(L.A, L.pa, seed) : 0u);
     return v - x_apA;
@@ -561,7 +589,8 @@ __global__ __launch_bounds__(256) void k_flux(Geo G, Phys<typename C::R> P, type
     if (k < nlinks) {
         const DevLink<typename C::R> L = load_link(links + k);
         const double net = (double)link_update<C, ODD>(G, P, S, L, M, tstep);
-        const int slot = L.field == 2 ? 2 + L.caxis : L.field;
+        // solute: component 0 only
+        const int slot = L.field == 2 ? 2 + L.caxis : ((L.field == 1 && C::NS > 1 && L.cslot != 4) ? -1 : L.field);
 #pragma unroll
         for (int q = 0; q < 5; ++q) v[q] = q == slot ? net : 0.0;
     }
@@ -635,11 +664,14 @@ __device__ __forceinline__ void gather(const Geo& G, const Phys<typename C::R>& 
         x_[i] = C::SCALED ? v * P.isc[0] : v;
     }
 #pragma unroll
-    for (int i = 0; i < QH; ++i) {
-        R v = ODD ? ld<SF>(plane(C::H0 + HL::opp(i)), q.at(-HL::ex(i), -HL::ey(i), -HL::ez(i)))
-                  : ld<SF>(plane(C::H0 + i), n);
-        x_[C::H0 + i] = C::SCALED ? v * P.isc[1] : v;
-    }
+    for (int k = 0; k < C::NS; ++k)
+#pragma unroll
+        for (int i = 0; i < QH; ++i) {
+            const int b = C::H0 + k * QH;
+            R v = ODD ? ld<SF>(plane(b + HL::opp(i)), q.at(-HL::ex(i), -HL::ey(i), -HL::ez(i)))
+                      : ld<SF>(plane(b + i), n);
+            x_[b + i] = C::SCALED ? v * P.isc[1] : v;
+        }
 #pragma unroll
     for (int c = 0; c < NCP; ++c)
 #pragma unroll
@@ -679,9 +711,14 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
     }
     const R rho = P.rho0 + drho;
     const R irho = (R)1 / rho;
-    R dC = 0;
+    R dCs[C::NS];
 #pragma unroll
-    for (int i = 0; i < QH; ++i) dC += x_[C::H0 + i];
+    for (int k = 0; k < C::NS; ++k) {
+        dCs[k] = 0;
+#pragma unroll
+        for (int i = 0; i < QH; ++i) dCs[k] += x_[C::H0 + k * QH + i];
+    }
+    const R dC = dCs[0];
     R dB[3] = {0, 0, 0}, B[3] = {P.Bext[0], P.Bext[1], P.Bext[2]};
     R lam[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // lam[c][i] = sum_a e_ai g_a,c
 #pragma unroll
@@ -732,11 +769,13 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
     m.dB[0] = dB[0];
     m.dB[1] = dB[1];
     m.dB[2] = dB[2];
+#pragma unroll
+    for (int k = 1; k < C::NS; ++k) m.dCx[k - 1] = dCs[k];
     if (MODE != 0) return;
 
     // moments of link nodes for the next step's extrapolations (Eq. 13)
     if (fl & NF_MOM) {
-        R* Mc = M + (size_t)ODD * 8 * PL;
+        R* Mc = M + (size_t)ODD * C::MW * PL;
         Mc[0 * (size_t)PL + n] = drho;
         Mc[1 * (size_t)PL + n] = ux;
         Mc[2 * (size_t)PL + n] = uy;
@@ -745,6 +784,8 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
         Mc[5 * (size_t)PL + n] = dB[0];
         Mc[6 * (size_t)PL + n] = dB[1];
         Mc[7 * (size_t)PL + n] = dB[2];
+#pragma unroll
+        for (int k = 1; k < C::NS; ++k) Mc[(size_t)(7 + k) * PL + n] = dCs[k];
     }
 
     // ---- collision (deviation form), opposite directions in pairs: the
@@ -774,19 +815,22 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
         x_[a] = xa + omf * (ev + od - xa) + (evs + ods);
         x_[b] = xb + omf * (ev - od - xb) + (evs - ods);
     }
-    if (QH > 0) {
-        const R Cc = P.C0 + dC, omc = P.omc;
-        x_[C::H0] += omc * ((R)HL::w(0) * dC - x_[C::H0]);
+#pragma unroll
+    for (int k = 0; k < (QH > 0 ? C::NS : 0); ++k) {
+        const int h0 = C::H0 + k * QH;
+        const R dCk = dCs[k];
+        const R Cc = P.C0 + dCk, omc = k == 0 ? P.omc : P.omcx[k - 1];
+        x_[h0] += omc * ((R)HL::w(0) * dCk - x_[h0]);
 #pragma unroll
         for (int a = 1; a < QH; ++a) {
             if (HL::opp(a) < a) continue;
             const int b = HL::opp(a);
             const R w = (R)HL::w(a);
             const R eu = (R)HL::ex(a) * ux + (R)HL::ey(a) * uy + (R)HL::ez(a) * uz;
-            const R ev = w * dC, od = (R)4 * w * Cc * eu;
-            const R xa = x_[C::H0 + a], xb = x_[C::H0 + b];
-            x_[C::H0 + a] = xa + omc * (ev + od - xa);
-            x_[C::H0 + b] = xb + omc * (ev - od - xb);
+            const R ev = w * dCk, od = (R)4 * w * Cc * eu;
+            const R xa = x_[h0 + a], xb = x_[h0 + b];
+            x_[h0 + a] = xa + omc * (ev + od - xa);
+            x_[h0 + b] = xb + omc * (ev - od - xb);
         }
     }
 #pragma unroll
@@ -827,11 +871,14 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
         else put(FL::opp(i), n, v);
     }
 #pragma unroll
-    for (int i = 0; i < QH; ++i) {
-        const R v = C::SCALED ? x_[C::H0 + i] * P.sc[1] : x_[C::H0 + i];
-        if (ODD) put(C::H0 + i, nb(HL::ex(i), HL::ey(i), HL::ez(i)), v);
-        else put(C::H0 + HL::opp(i), n, v);
-    }
+    for (int k = 0; k < C::NS; ++k)
+#pragma unroll
+        for (int i = 0; i < QH; ++i) {
+            const int b = C::H0 + k * QH;
+            const R v = C::SCALED ? x_[b + i] * P.sc[1] : x_[b + i];
+            if (ODD) put(b + i, nb(HL::ex(i), HL::ey(i), HL::ez(i)), v);
+            else put(b + HL::opp(i), n, v);
+        }
 #pragma unroll
     for (int c = 0; c < NCP; ++c)
 #pragma unroll
@@ -894,10 +941,10 @@ __global__ void k_time(uint32_t* tbase, uint32_t t, int add) {
     }
 }
 
-// Per-node terms of the FP64 reductions: sums of rho, C, B (0..4); squared
-// change of u, C - C0, B - B_ext since the snapshot (5..7) and their squared
-// norms (8..10); a non-finite flag (11).  The snapshot is replaced by the
-// current values.
+// Per-node terms of the FP64 reductions: sums of rho, C_0, B (0..4); squared
+// change of u, C - C0 (every scalar component), B - B_ext since the snapshot
+// (5..7) and their squared norms (8..10); a non-finite flag (11).  The
+// snapshot is replaced by the current values.
 template <class C>
 __device__ __forceinline__ void reduce_node(const Phys<typename C::R>& P, const NodeRes<C>& r, bool fluid,
                                             typename C::R* snap, int snap_valid, uint32_t PL, uint32_t n,
@@ -905,21 +952,23 @@ __device__ __forceinline__ void reduce_node(const Phys<typename C::R>& P, const 
     using R = typename C::R;
     for (int q = 0; q < NACC; ++q) v[q] = 0.0;
     if (!fluid) return;
-    double phi[7] = {r.m.u[0], r.m.u[1], r.m.u[2], r.m.dC, r.m.dB[0], r.m.dB[1], r.m.dB[2]};
+    constexpr int NP = C::MW - 1;  // u, C_0, B, C_1, C_2
+    double phi[9] = {r.m.u[0], r.m.u[1], r.m.u[2], r.m.dC, r.m.dB[0], r.m.dB[1], r.m.dB[2], 0.0, 0.0};
+    for (int k = 1; k < C::NS; ++k) phi[6 + k] = r.m.dCx[k - 1];
     v[0] = (double)P.rho0 + (double)r.m.drho;
     v[1] = (double)P.C0 + (double)r.m.dC;
     for (int k = 0; k < 3; ++k) v[2 + k] = (double)P.Bext[k] + (double)r.m.dB[k];
-    for (int q = 0; q < 7; ++q) {
+    for (int q = 0; q < NP; ++q) {
         const double s = snap_valid ? (double)snap[(size_t)q * PL + n] : 0.0;
         const double dd = phi[q] - s;
-        const int fld = q < 3 ? 0 : (q == 3 ? 1 : 2);
+        const int fld = q < 3 ? 0 : ((q == 3 || q > 6) ? 1 : 2);
         v[5 + fld] += dd * dd;
         v[8 + fld] += phi[q] * phi[q];
         snap[(size_t)q * PL + n] = (R)phi[q];
     }
     bool bad = false;
     for (int q = 0; q < 5; ++q) bad = bad || !(v[q] - v[q] == 0.0);
-    for (int q = 0; q < 7; ++q) bad = bad || !(phi[q] - phi[q] == 0.0);
+    for (int q = 0; q < NP; ++q) bad = bad || !(phi[q] - phi[q] == 0.0);
     v[11] = bad ? 1.0 : 0.0;
 }
 
@@ -969,7 +1018,8 @@ __global__ __launch_bounds__(256) void k_observe(Geo G, Phys<typename C::R> P, t
     const size_t N = (size_t)G.n0 * G.n1 * G.n2;
     if (mode == OBS_MOMENTS) {
         if (dom < 0) return;
-        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double v[C::MW];
+        for (int q = 0; q < C::MW; ++q) v[q] = 0.0;
         if (fluid) {
             v[0] = (double)P.rho0 + (double)r.m.drho;
             v[1] = r.m.u[0];
@@ -977,8 +1027,9 @@ __global__ __launch_bounds__(256) void k_observe(Geo G, Phys<typename C::R> P, t
             v[3] = r.m.u[2];
             v[4] = (double)P.C0 + (double)r.m.dC;
             for (int k = 0; k < 3; ++k) v[5 + k] = (double)P.Bext[k] + (double)r.m.dB[k];
+            for (int k = 1; k < C::NS; ++k) v[7 + k] = (double)P.C0 + (double)r.m.dCx[k - 1];
         }
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < C::MW; ++q) {
             if (out_f64) ((double*)out)[(size_t)q * N + dom] = v[q];
             else ((float*)out)[(size_t)q * N + dom] = (float)v[q];
         }
@@ -991,8 +1042,10 @@ __global__ __launch_bounds__(256) void k_observe(Geo G, Phys<typename C::R> P, t
             for (int i = 0; i < C::QF; ++i)
                 o[(size_t)i * N + dom] = fluid ? (double)r.x[i] + C::FL::w(i) * (double)P.rho0 : 0.0;
         } else if (field == 1) {
-            for (int i = 0; i < C::QH; ++i)
-                o[(size_t)i * N + dom] = fluid ? (double)r.x[C::H0 + i] + C::HL::w(i) * (double)P.C0 : 0.0;
+            for (int k = 0; k < C::NS; ++k)
+                for (int i = 0; i < C::QH; ++i)
+                    o[(size_t)(k * C::QH + i) * N + dom] =
+                        fluid ? (double)r.x[C::H0 + k * C::QH + i] + C::HL::w(i) * (double)P.C0 : 0.0;
         } else {
             for (int c = 0; c < C::NCOMP; ++c)
                 for (int i = 0; i < C::QG; ++i)
@@ -1058,8 +1111,6 @@ __global__ __launch_bounds__(256) void k_init(Geo G, Phys<typename C::R> P, type
     R u[3] = {0, 0, 0};
     if (u_in)
         for (int k = 0; k < 3; ++k) u[k] = (R)u_in[(size_t)k * N + dom];
-    const R dC = C_in ? (R)(C_in[dom] - (double)P.C0) : (R)0;
-    const R Cc = P.C0 + dC;
     R B[3] = {P.Bext[0], P.Bext[1], P.Bext[2]}, dB[3] = {0, 0, 0};
     if (B_in)
         for (int k = 0; k < 3; ++k) {
@@ -1077,10 +1128,15 @@ __global__ __launch_bounds__(256) void k_init(Geo G, Phys<typename C::R> P, type
         st<typename C::S>(S + (size_t)i * PL, (uint32_t)n, C::SCALED ? v * P.sc[0] : v);
     }
 #pragma unroll
-    for (int i = 0; i < C::QH; ++i) {
-        const R eu = (R)HL::ex(i) * u[0] + (R)HL::ey(i) * u[1] + (R)HL::ez(i) * u[2];
-        const R v = (R)HL::w(i) * (dC + Cc * eu * (R)4);
-        st<typename C::S>(S + (size_t)(C::H0 + i) * PL, (uint32_t)n, C::SCALED ? v * P.sc[1] : v);
+    for (int k = 0; k < C::NS; ++k) {
+        const R dC = C_in ? (R)(C_in[(size_t)k * N + dom] - (double)P.C0) : (R)0;
+        const R Cc = P.C0 + dC;
+#pragma unroll
+        for (int i = 0; i < C::QH; ++i) {
+            const R eu = (R)HL::ex(i) * u[0] + (R)HL::ey(i) * u[1] + (R)HL::ez(i) * u[2];
+            const R v = (R)HL::w(i) * (dC + Cc * eu * (R)4);
+            st<typename C::S>(S + (size_t)(C::H0 + k * C::QH + i) * PL, (uint32_t)n, C::SCALED ? v * P.sc[1] : v);
+        }
     }
 #pragma unroll
     for (int c = 0; c < C::NCOMP; ++c) {
@@ -1107,7 +1163,7 @@ struct BItem {
     const uint8_t* flags;
     const DevLink<typename C::R>* links;
     typename C::R* M;
-    typename C::R* snap;  // [7][plane] residual snapshot
+    typename C::R* snap;  // [MW - 1][plane] residual snapshot
     double* acc;          // [NACC] FP64 accumulators
     uint32_t* tbase;      // time base word of the item
     uint32_t t0;          // the item's time when the descriptor was written
@@ -1490,16 +1546,26 @@ struct Launch {
         k.observe = &observe;
         k.init = &init;
         k.QT = C::QT;
+        k.MW = C::MW;
         return k;
     }
 };
 
 // the lattice combinations the library instantiates
 template <class SF>
-KernelSet select_kernels(int fl, int sl, int ml, int nc) {
-#define LBM_CASE(F, H, M, N)                                  \
-    if (fl == F && sl == H && ml == M && (M == 0 || nc == N)) \
+KernelSet select_kernels(int fl, int sl, int ml, int nc, int ns) {
+#define LBM_CASE(F, H, M, N)                                                \
+    if (fl == F && sl == H && ml == M && (M == 0 || nc == N) && ns <= 1) \
         return Launch<Cfg<F, H, M, N, SF>>::set();
+    // several scalar components: flow and scalar lattices only
+#define LBM_CASE_NS(F, H, S)                          \
+    if (fl == F && sl == H && ml == 0 && ns == S) \
+        return Launch<Cfg<F, H, 0, 0, SF, S>>::set();
+    LBM_CASE_NS(1, 3, 2)
+    LBM_CASE_NS(1, 3, 3)
+    LBM_CASE_NS(2, 4, 2)
+    LBM_CASE_NS(2, 4, 3)
+#undef LBM_CASE_NS
     LBM_CASE(1, 0, 0, 0)
     LBM_CASE(1, 3, 0, 0)
     LBM_CASE(1, 0, 3, 1)

@@ -89,6 +89,13 @@ bool valid_params(const lbm_params* p, std::string* why) {
         if (p->mag_comp[c] != c) return fail("evolved magnetic component c must be Cartesian axis c");
     if (!(p->tau_f > 0.5) || (p->scalar && !(p->tau_c > 0.5)) || (p->magnetic && !(p->tau_m > 0.5)))
         return fail("relaxation times must exceed 1/2");
+    if (p->scalar_ncomp < 0 || p->scalar_ncomp > 3) return fail("scalar_ncomp must be 0..3");
+    if (p->scalar_ncomp > 1) {
+        if (!p->scalar) return fail("several scalar components need a scalar lattice");
+        if (p->magnetic) return fail("several scalar components: no magnetic lattice");
+        for (int k = 0; k + 1 < p->scalar_ncomp; ++k)
+            if (!(p->tau_cs[k] > 0.5)) return fail("relaxation times must exceed 1/2");
+    }
     if (!(p->rho0 > 0.0)) return fail("rho0 must be positive");
     if (p->magnetic && !(p->mu > 0.0)) return fail("mu must be positive");
     if (p->storage < LBM_F64 || p->storage > LBM_BF16) return fail("unknown storage");
@@ -117,20 +124,24 @@ size_t value_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == LB
 size_t compute_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 size_t link_bytes(int storage) { return storage == LBM_F64 ? sizeof(DevLink<double>) : sizeof(DevLink<float>); }
 
+int scalar_comps(const lbm_params* p) { return p->scalar_ncomp > 1 ? p->scalar_ncomp : 1; }
+
+int moment_planes(const lbm_params* p) { return 8 + scalar_comps(p) - 1; }
+
 int total_planes(const lbm_params* p) {
     int q = lattice_of(p->fluid).Q;
-    if (p->scalar) q += lattice_of(p->scalar).Q;
+    if (p->scalar) q += scalar_comps(p) * lattice_of(p->scalar).Q;
     if (p->magnetic) q += p->mag_ncomp * lattice_of(p->magnetic).Q;
     return q;
 }
 
 lbmi::KernelSet kernels_for(const lbm_params* p) {
-    const int nc = p->magnetic ? p->mag_ncomp : 0;
+    const int nc = p->magnetic ? p->mag_ncomp : 0, ns = scalar_comps(p);
     switch (p->storage) {
-        case LBM_F64: return lbmi::kernels_f64(p->fluid, p->scalar, p->magnetic, nc);
-        case LBM_F32: return lbmi::kernels_f32(p->fluid, p->scalar, p->magnetic, nc);
-        case LBM_F16: return lbmi::kernels_f16(p->fluid, p->scalar, p->magnetic, nc);
-        default: return lbmi::kernels_bf16(p->fluid, p->scalar, p->magnetic, nc);
+        case LBM_F64: return lbmi::kernels_f64(p->fluid, p->scalar, p->magnetic, nc, ns);
+        case LBM_F32: return lbmi::kernels_f32(p->fluid, p->scalar, p->magnetic, nc, ns);
+        case LBM_F16: return lbmi::kernels_f16(p->fluid, p->scalar, p->magnetic, nc, ns);
+        default: return lbmi::kernels_bf16(p->fluid, p->scalar, p->magnetic, nc, ns);
     }
 }
 
@@ -168,7 +179,7 @@ class LinkBuilder {
         for (int field = 0; field < 3; ++field) {
             if (!fields[field]) continue;
             const HostLat L = lattice_of(fields[field]);
-            const int ncomp = field == 2 ? p_.mag_ncomp : 1;
+            const int ncomp = field == 2 ? p_.mag_ncomp : (field == 1 ? scalar_comps(&p_) : 1);
             std::vector<std::vector<double>> segs(b_.size());
             for (int z = 0; z < p_.n[2]; ++z)
                 for (int y = 0; y < p_.n[1]; ++y)
@@ -219,12 +230,17 @@ class LinkBuilder {
                                 lk.field = (uint8_t)field;
                                 lk.dir = (uint8_t)a;
                                 lk.kind = (uint8_t)bc.kind;
-                                lk.comp = (uint8_t)(field == 2 ? c : 0);
+                                lk.comp = (uint8_t)(field == 0 ? 0 : c);
                                 lk.flags = (uint8_t)((bc.u_given ? 1 : 0) | (e_ok ? 0 : 2) |
                                                      (bc.u_given && bd.u_osc ? 4 : 0) | (bc.alt ? 8 : 0));
                                 lk.d = bd.d_scheme > 0.0 ? bd.d_scheme : best.d;
                                 lk.value = bc.value;
                                 law_coefficients(bc, field, c, A, &lk);
+                                if (field == 1 && bc.kind == LBM_LK_FLUX && bc.law == LBM_LAW_COEF && bc.cross != 0.0) {
+                                    lk.cross_comp[0] = (uint8_t)bc.cross_comp[0];
+                                    lk.cross_comp[1] = (uint8_t)bc.cross_comp[1];
+                                    lk.cross = bc.cross;
+                                }
                                 for (int k = 0; k < 3; ++k) lk.u_w[k] = bd.u_w[k];
                                 const bool flux = bc.kind == LBM_LK_FLUX || bc.kind == LBM_LK_MAG_FLUX;
                                 // flat faces: a node's flux split evenly over the
@@ -263,7 +279,7 @@ class LinkBuilder {
         const bool has_prof = bc.profile && bc.profile_len > 0;
         if (has_prof) prof = bc.profile[std::min(A[bc.profile_axis], bc.profile_len - 1)];
         const int code = field == 1 ? p_.scalar : p_.magnetic;
-        const double tau = field == 1 ? p_.tau_c : p_.tau_m;
+        const double tau = field == 1 ? (comp == 0 ? p_.tau_c : p_.tau_cs[comp - 1]) : p_.tau_m;
         const double kappa = field == 0 ? 0.0 : lattice_of(code).c2 * (tau - 0.5);
         switch (bc.law) {
             case LBM_LAW_ROBIN: {
@@ -364,7 +380,7 @@ class LinkBuilder {
     }
 
     static const lbm_bc& bc_of(const lbm_boundary& b, int field, int comp) {
-        return field == 0 ? b.f : (field == 1 ? b.h : b.g[comp]);
+        return field == 0 ? b.f : (field == 1 ? (comp == 0 ? b.h : b.h_more[comp - 1]) : b.g[comp]);
     }
 
     // surface element S_i of every outer-layer solid node of a cylinder in
@@ -505,8 +521,9 @@ void layout(const lbm_params* p, size_t n_links, size_t sz[LBM_NBUF]) {
     sz[0] = round_up((size_t)total_planes(p) * d.plane * vb, kAlign);          // populations
     sz[1] = round_up(d.plane, kAlign) + round_up(d.plane / 64, kAlign);        // node flags, wave summary
     sz[2] = round_up(std::max<size_t>(n_links, 1) * link_bytes(p->storage), kAlign);  // link records
-    sz[3] = round_up(2 * 8 * d.plane * cb, kAlign) + kAlign;                   // moment planes, time base
-    sz[4] = round_up(7 * d.plane * cb, kAlign) + round_up(lbmi::NACC * sizeof(double), kAlign);  // reductions
+    const size_t mw = (size_t)moment_planes(p);
+    sz[3] = round_up(2 * mw * d.plane * cb, kAlign) + kAlign;                  // moment planes, time base
+    sz[4] = round_up((mw - 1) * d.plane * cb, kAlign) + round_up(lbmi::NACC * sizeof(double), kAlign);  // reductions
     sz[5] = sz[6] = sz[7] = 0;
 }
 
@@ -532,6 +549,7 @@ lbmi::KArgs base_args(const lbm_ctx* c) {
     a.cmp_links = c->cmp_links ? 1 : 0;
     a.tau_f = c->p.tau_f;
     a.tau_c = c->p.scalar ? c->p.tau_c : 1.0;
+    for (int k = 0; k < 2; ++k) a.tau_cs[k] = k + 1 < scalar_comps(&c->p) ? c->p.tau_cs[k] : 1.0;
     a.tau_m = c->p.magnetic ? c->p.tau_m : 1.0;
     a.rho0 = c->p.rho0;
     a.wall_omega = c->p.wall_omega;
@@ -553,7 +571,8 @@ lbmi::KArgs base_args(const lbm_ctx* c) {
 }
 
 uint32_t* time_base(const lbm_ctx* c) {
-    return (uint32_t*)((char*)c->buf[3] + round_up(2 * 8 * c->pad.plane * compute_bytes(c->p.storage), kAlign));
+    return (uint32_t*)((char*)c->buf[3] +
+                       round_up(2 * (size_t)moment_planes(&c->p) * c->pad.plane * compute_bytes(c->p.storage), kAlign));
 }
 
 size_t domain_nodes(const lbm_params& p) { return (size_t)p.n[0] * p.n[1] * p.n[2]; }
@@ -587,13 +606,14 @@ void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::
                    const std::vector<uint32_t>& padE, const std::vector<uint32_t>& padB,
                    std::vector<unsigned char>* bytes) {
     const HostLat Lf = lattice_of(c->p.fluid), Lh = lattice_of(c->p.scalar), Lg = lattice_of(c->p.magnetic);
-    const int QF = Lf.Q, QH = c->p.scalar ? Lh.Q : 0, QG = Lg.Q;
+    const int QF = Lf.Q, QH = c->p.scalar ? Lh.Q : 0, QG = Lg.Q, NS = scalar_comps(&c->p);
+    auto cslot = [](int k) { return k == 0 ? 4 : 7 + k; };  // moment plane of scalar component k
     bytes->assign(std::max<size_t>(L.size(), 1) * sizeof(DevLink<R>), 0);
     DevLink<R>* out = (DevLink<R>*)bytes->data();
     for (size_t i = 0; i < L.size(); ++i) {
         const lbm_link& s = L[i];
         const HostLat& lat = s.field == 0 ? Lf : (s.field == 1 ? Lh : Lg);
-        const int base = s.field == 0 ? 0 : (s.field == 1 ? QF : QF + QH + s.comp * QG);
+        const int base = s.field == 0 ? 0 : (s.field == 1 ? QF + s.comp * QH : QF + NS * QH + s.comp * QG);
         DevLink<R> d;
         std::memset(&d, 0, sizeof d);
         d.A = padA[i];
@@ -625,6 +645,11 @@ void fill_devlinks(const lbm_ctx* c, const std::vector<lbm_link>& L, const std::
         d.uw1 = (R)s.u_w[1];
         d.uw2 = (R)s.u_w[2];
         d.need = moments_needed(s, lat.e[s.dir]);
+        d.cslot = (uint8_t)(s.field == 1 ? cslot(s.comp) : 4);
+        if (s.field == 1 && s.kind == LBM_LK_FLUX && s.cross != 0.0) {
+            d.pslot = (uint8_t)(cslot(s.cross_comp[0]) | (cslot(s.cross_comp[1]) << 4));
+            d.value = (R)s.cross;  // a FLUX link has no given value
+        }
         out[i] = d;
     }
 }
@@ -688,7 +713,19 @@ lbm_status lbm_build_links(const lbm_params* p, const lbm_boundary* bnds, int32_
             for (int k = 0; k < 3; ++k)
                 if (!(b.lo[k] <= b.hi[k])) return LBM_EINVAL;
         if (!(b.d_scheme == 0.0 || (b.d_scheme > 0.0 && b.d_scheme <= 1.0))) return LBM_EINVAL;
-        const lbm_bc* bcs[5] = {&b.f, &b.h, &b.g[0], &b.g[1], &b.g[2]};
+        const int ns = scalar_comps(p);
+        for (int k = 1; k < ns; ++k)
+            if ((b.h_more[k - 1].kind != 0) != (b.h.kind != 0)) return LBM_EINVAL;
+        for (int k = 0; k < 3; ++k) {
+            const lbm_bc& bc = k == 0 ? b.h : b.h_more[k - 1];
+            if (!std::isfinite(bc.cross)) return LBM_EINVAL;
+            if (bc.cross == 0.0 || k >= ns) continue;
+            if (bc.kind != LBM_LK_FLUX || bc.law != LBM_LAW_COEF || ns < 2)
+                return LBM_EINVAL;
+            for (int j = 0; j < 2; ++j)
+                if (bc.cross_comp[j] < 0 || bc.cross_comp[j] >= ns) return LBM_EINVAL;
+        }
+        const lbm_bc* bcs[7] = {&b.f, &b.h, &b.g[0], &b.g[1], &b.g[2], &b.h_more[0], &b.h_more[1]};
         for (const lbm_bc* bc : bcs) {
             if (bc->alt && !(bc->kind == LBM_LK_VEL || bc->kind == LBM_LK_PRES || bc->kind == LBM_LK_FLUX ||
                              bc->kind == LBM_LK_MAG_FLUX))
@@ -792,7 +829,11 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
 
     // validate each link; mark the (node, slot) pairs it covers
     const int QF = lats[0].Q, QH = p.scalar ? lats[1].Q : 0, QG = p.magnetic ? lats[2].Q : 0;
-    const int QT = QF + QH + p.mag_ncomp * QG;
+    const int NS = scalar_comps(&p);
+    const int QT = QF + NS * QH + p.mag_ncomp * QG;
+    auto plane_base = [&](int field, int comp) {
+        return field == 0 ? 0 : (field == 1 ? QF + comp * QH : QF + NS * QH + comp * QG);
+    };
     std::vector<uint8_t> covered(N * (size_t)QT, 0);
     std::vector<lbm_link> links(L, L + n);
     for (size_t i = 0; i < n; ++i) {
@@ -806,7 +847,8 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
         if (k.field > 2 || !codes[k.field]) return bad("field has no lattice");
         const HostLat& lat = lats[k.field];
         if (k.dir < 1 || k.dir >= lat.Q) return bad("direction out of range");
-        if (k.field == 2 ? k.comp >= p.mag_ncomp : k.comp != 0) return bad("component out of range");
+        if (k.field == 2 ? k.comp >= p.mag_ncomp : (k.field == 1 ? k.comp >= NS : k.comp != 0))
+            return bad("component out of range");
         const bool okkind = k.field == 0 ? (k.kind == LBM_LK_VEL || k.kind == LBM_LK_PRES)
                             : k.field == 1 ? (k.kind == LBM_LK_CONC || k.kind == LBM_LK_FLUX || k.kind == LBM_LK_BB0)
                                            : (k.kind == LBM_LK_MAG_DIR || k.kind == LBM_LK_MAG_FLUX || k.kind == LBM_LK_BB0 ||
@@ -827,6 +869,10 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
             return bad("non-finite wall data");
         if (k.quad != 0.0 && k.kind != LBM_LK_FLUX && k.kind != LBM_LK_MAG_FLUX)
             return bad("quad (quadratic flux term) needs kind FLUX or MAG_FLUX");
+        if (!std::isfinite(k.cross)) return bad("non-finite cross coefficient");
+        if (k.cross != 0.0 && (k.kind != LBM_LK_FLUX || NS < 2 || k.cross_comp[0] >= NS || k.cross_comp[1] >= NS))
+            return bad("a bilinear flux term needs kind FLUX, several scalar components and components below "
+                       "scalar_ncomp");
         int q[3];
         coords(k.node, q);
         int s[3] = {q[0] - lat.e[k.dir][0], q[1] - lat.e[k.dir][1], q[2] - lat.e[k.dir][2]};
@@ -835,7 +881,7 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
             int e[3] = {q[0] + lat.e[k.dir][0], q[1] + lat.e[k.dir][1], q[2] + lat.e[k.dir][2]};
             if (!wrap(e) || !c->mask[dom(e)] || dom(e) != k.enode) return bad("enode is not the fluid node A + e_alpha");
         }
-        const int base = k.field == 0 ? 0 : (k.field == 1 ? QF : QF + QH + k.comp * QG);
+        const int base = plane_base(k.field, k.comp);
         uint8_t& cov = covered[(size_t)k.node * QT + base + k.dir];
         if (cov) return bad("duplicate link");
         cov = 1;
@@ -848,12 +894,12 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
         for (int f = 0; f < 3; ++f) {
             if (!codes[f]) continue;
             const HostLat& lat = lats[f];
-            const int nc = f == 2 ? p.mag_ncomp : 1;
+            const int nc = f == 2 ? p.mag_ncomp : (f == 1 ? NS : 1);
             for (int a = 1; a < lat.Q; ++a) {
                 int s[3] = {q[0] - lat.e[a][0], q[1] - lat.e[a][1], q[2] - lat.e[a][2]};
                 if (wrap(s) && c->mask[dom(s)]) continue;
                 for (int cc = 0; cc < nc; ++cc) {
-                    const int base = f == 0 ? 0 : (f == 1 ? QF : QF + QH + cc * QG);
+                    const int base = plane_base(f, cc);
                     if (!covered[i * QT + base + a]) {
                         char msg[160];
                         snprintf(msg, sizeof msg, "node %zu field %d dir %d comp %d has no boundary link", i, f, a, cc);
@@ -1223,7 +1269,7 @@ lbm_status lbm_read_normalised(lbm_ctx* c, int32_t axis, double U, double* dev_o
         return set_err(c, LBM_EINVAL, "bad axis, velocity scale or output");
     if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
     const size_t cb = compute_bytes(c->p.storage);
-    double* acc = (double*)((char*)c->buf[4] + round_up(7 * c->pad.plane * cb, kAlign));
+    double* acc = (double*)((char*)c->buf[4] + round_up((size_t)(moment_planes(&c->p) - 1) * c->pad.plane * cb, kAlign));
     lbm_status st;
     if ((st = hip_check(c, hipMemsetAsync(acc, 0, lbmi::NACC * sizeof(double), c->stream), "accumulator clear")))
         return st;
@@ -1259,7 +1305,7 @@ lbm_status lbm_boundary_flux(lbm_ctx* c, double out[5]) {
     if (c->n_links == 0) return LBM_OK;
     const size_t cb = compute_bytes(c->p.storage);
     char* aux = (char*)c->buf[4];
-    double* acc = (double*)(aux + round_up(7 * c->pad.plane * cb, kAlign));  // the reduction accumulators
+    double* acc = (double*)(aux + round_up((size_t)(moment_planes(&c->p) - 1) * c->pad.plane * cb, kAlign));  // the reduction accumulators
     lbm_status st;
     if ((st = hip_check(c, hipMemsetAsync(acc, 0, lbmi::NACC * sizeof(double), c->stream), "accumulator clear")))
         return st;
@@ -1279,7 +1325,7 @@ lbm_status lbm_reduce(lbm_ctx* c, double out[8]) {
     if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
     const size_t cb = compute_bytes(c->p.storage);
     char* aux = (char*)c->buf[4];
-    double* acc = (double*)(aux + round_up(7 * c->pad.plane * cb, kAlign));
+    double* acc = (double*)(aux + round_up((size_t)(moment_planes(&c->p) - 1) * c->pad.plane * cb, kAlign));
     lbm_status st;
     if ((st = hip_check(c, hipMemsetAsync(acc, 0, lbmi::NACC * sizeof(double), c->stream), "accumulator clear")))
         return st;

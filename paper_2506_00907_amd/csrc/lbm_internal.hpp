@@ -32,10 +32,14 @@ struct alignas(16) DevLink {
     uint8_t field;        // 0 f, 1 h, 2 g
     uint8_t caxis;        // Cartesian axis of the magnetic component (g links)
     int8_t ex, ey, ez;    // e_alpha
-    uint8_t need;         // bit q: the link's formula uses moment q (rho, u_x, u_y, u_z, C, B_x, B_y, B_z)
-    uint8_t pad[2];
+    uint8_t need;         // bit q: the link's formula uses moment q (rho, u_x, u_y, u_z, C, B_x, B_y, B_z);
+                          // bit 4 reads the moment plane cslot
+    uint8_t cslot;        // moment plane of the link's scalar component: 4 (C_0), 8 (C_1), 9 (C_2)
+    uint8_t pslot;        // FLUX with a bilinear term: moment planes of its components j (bits 0-3)
+                          // and l (bits 4-7); 0: none
     R d;
-    R value;  // given value minus its rest value (rho0, C0 or B_ext,k)
+    R value;  // given value minus its rest value (rho0, C0 or B_ext,k); FLUX with pslot: the
+              // coefficient of the bilinear term (F_i += value C_j,X C_l,X)
     R a1, a3, weight, uw0, uw1, uw2;
     R quad;   // quadratic coefficient of the flux law (FLUX / MAG_FLUX)
 };
@@ -51,9 +55,10 @@ struct KArgs {
     void* S;               // populations [QT][plane]
     const uint8_t* flags;  // [plane]
     const void* links;     // DevLink<R>[n_links]
-    void* M;               // R[2][8][plane]
+    void* M;               // R[2][MW][plane], MW = 8 + scalar components - 1
     size_t n_links;
     double tau_f, tau_c, tau_m, rho0, C0, mu;
+    double tau_cs[2];      // relaxation times of scalar components 1, 2
     double wall_omega;     // angular frequency of oscillating boundary velocities (link flag bit 2)
     double Bext[3], accel[3], scale[3];
     int comp[3];           // Cartesian axis of each evolved magnetic component
@@ -66,13 +71,13 @@ struct KArgs {
     int mode;              // OBS_*
     int field;             // OBS_POPS: 0 f, 1 h, 2 g; OBS_NORM: Cartesian axis
     double norm_u, norm_b; // scale: u /= norm_u, B - B_ext /= norm_u * norm_b
-    void* out;             // OBS_MOMENTS: [8][N] (out_f64 ? double : float); OBS_POPS: double
+    void* out;             // OBS_MOMENTS: [MW][N] (out_f64 ? double : float); OBS_POPS: double
     int out_f64;
     double* acc;           // OBS_REDUCE: FP64 accumulators [NACC], or with acc_blocks the
                            // per-block records [blocks][NACC]
     int acc_blocks;        // OBS_REDUCE: 1 = each block stores its sums into its own record
                            // of acc (no atomics), 0 = FP64 atomics into acc[0..NACC)
-    void* snap;            // OBS_REDUCE: R[7][plane] snapshot of u, C - C0, B - B_ext
+    void* snap;            // OBS_REDUCE: R[MW - 1][plane] snapshot of u, C_0 - C0, B - B_ext, C_k - C0
     int snap_valid;
     const double *init_rho, *init_u, *init_C, *init_B;
     hipStream_t stream;
@@ -122,6 +127,7 @@ struct KernelSet {
     Launcher set_time = nullptr; // *tbase = tstep
     Launcher tick = nullptr;     // *tbase += tstep
     int QT = 0;                  // population planes
+    int MW = 8;                  // moment planes (8 + scalar components - 1)
     // batched items
     Describer describe = nullptr;  // writes one item descriptor from its launch description
     size_t item_bytes = 0;         // size of one item descriptor
@@ -136,9 +142,9 @@ struct KernelSet {
 };
 
 // storage codes as in lbm.h
-KernelSet kernels_f64(int fl, int sl, int ml, int nc);
-KernelSet kernels_f32(int fl, int sl, int ml, int nc);
-KernelSet kernels_f16(int fl, int sl, int ml, int nc);
-KernelSet kernels_bf16(int fl, int sl, int ml, int nc);
+KernelSet kernels_f64(int fl, int sl, int ml, int nc, int ns);
+KernelSet kernels_f32(int fl, int sl, int ml, int nc, int ns);
+KernelSet kernels_f16(int fl, int sl, int ml, int nc, int ns);
+KernelSet kernels_bf16(int fl, int sl, int ml, int nc, int ns);
 
 }  // namespace lbmi

@@ -2,5 +2,5 @@
 #include "lbm_device.hpp"
 
 namespace lbmi {
-KernelSet kernels_bf16(int fl, int sl, int ml, int nc) { return select_kernels<BF16S>(fl, sl, ml, nc); }
+KernelSet kernels_bf16(int fl, int sl, int ml, int nc, int ns) { return select_kernels<BF16S>(fl, sl, ml, nc, ns); }
 }  // namespace lbmi

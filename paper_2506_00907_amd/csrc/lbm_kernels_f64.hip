@@ -2,5 +2,5 @@
 #include "lbm_device.hpp"
 
 namespace lbmi {
-KernelSet kernels_f64(int fl, int sl, int ml, int nc) { return select_kernels<F64S>(fl, sl, ml, nc); }
+KernelSet kernels_f64(int fl, int sl, int ml, int nc, int ns) { return select_kernels<F64S>(fl, sl, ml, nc, ns); }
 }  // namespace lbmi

@@ -20,14 +20,13 @@ BOUNDARY_TYPES = {"plane": 0, "cylinder": 1, "box": 2}
 STORAGES = {"f64": L.LBM_F64, "f32": L.LBM_F32, "f16": L.LBM_F16, "bf16": L.LBM_BF16}
 
 LINK_DTYPE = np.dtype([("node", "<u4"), ("enode", "<u4"), ("field", "u1"), ("dir", "u1"), ("kind", "u1"),
-                       ("comp", "u1"), ("flags", "u1"), ("pad", "u1", 3), ("d", "<f8"), ("value", "<f8"),
-                       ("a1", "<f8"), ("a3", "<f8"), ("weight", "<f8"), ("u_w", "<f8", 3), ("quad", "<f8")])
+                       ("comp", "u1"), ("flags", "u1"), ("cross_comp", "u1", 2), ("pad", "u1"), ("d", "<f8"),
+                       ("value", "<f8"), ("a1", "<f8"), ("a3", "<f8"), ("weight", "<f8"), ("u_w", "<f8", 3),
+                       ("quad", "<f8"), ("cross", "<f8")])
 assert LINK_DTYPE.itemsize == C.sizeof(L.lbm_link)
 
 
 def params_from_scene(sc) -> L.lbm_params:
-    if sc.scalar_lattice and sc.scalar_ncomp != 1:
-        raise NotImplementedError("several scalar components")
     p = L.lbm_params()
     p.dim = sc.dim
     for k in range(3):
@@ -44,6 +43,9 @@ def params_from_scene(sc) -> L.lbm_params:
         p.mag_comp[i] = c
     p.storage = STORAGES[sc.storage]
     p.tau_f, p.tau_c, p.tau_m = sc.tau_f, sc.tau_c, sc.tau_m
+    p.scalar_ncomp = sc.scalar_ncomp if sc.scalar_lattice else 0
+    for k in range(1, p.scalar_ncomp):
+        p.tau_cs[k - 1] = sc.tau_scalar(k)
     p.rho0, p.C0, p.mu = sc.rho0, sc.C0, sc.mu
     p.wall_omega = sc.wall_omega
     return p
@@ -64,6 +66,8 @@ def boundaries_from_scene(sc):
         dst.value, dst.a1, dst.a3, dst.quad = bc.value, bc.a1, bc.a3, bc.quad
         dst.k, dst.phi_eq, dst.c_w, dst.H = bc.k, bc.phi_eq, bc.c_w, bc.H
         dst.profile_axis = bc.profile_axis
+        dst.cross_comp[0], dst.cross_comp[1] = bc.cross_comps
+        dst.cross = bc.cross
         if bc.profile is not None:
             prof = np.ascontiguousarray(bc.profile, dtype=np.float64)
             keep.append(prof)
@@ -83,6 +87,8 @@ def boundaries_from_scene(sc):
             d.u_w[k] = b.u_w[k]
         put(d.f, b.f)
         put(d.h, b.h_of(0))
+        for k in range(1, max(sc.scalar_ncomp, 1)):
+            put(d.h_more[k - 1], b.h_of(k))
         for k in range(3):
             put(d.g[k], b.g[k] if k < len(b.g) else None)
     return arr, len(sc.boundaries), keep
@@ -183,6 +189,8 @@ class Lattice:
         self._call("lbm_set_links", self.links.ctypes.data_as(C.c_void_p), self.n_links)
         self.N = sc.nodes
         self.shape = (sc.n[2], sc.n[1], sc.n[0])
+        self.n_scalar = max(int(self.params.scalar_ncomp), 1)
+        self.moment_width = 8 + self.n_scalar - 1
         if init:
             self.init(sc.init_rho, sc.init_u, sc.init_Cf, sc.init_B, C_uniform=sc.init_C)
 
@@ -200,7 +208,8 @@ class Lattice:
     # -- ABI calls ----------------------------------------------------------
     def init(self, rho=None, u=None, C_=None, B=None, C_uniform: Optional[float] = None):
         """lbm_init from fields (arrays of the domain shape; u, B with a last
-        axis of 3) or the uniform rest state; C_uniform fills C when given."""
+        axis of 3; C of several scalar components with a first axis of
+        components) or the uniform rest state; C_uniform fills C when given."""
         torch = self.torch
         N = self.N
 
@@ -214,9 +223,11 @@ class Lattice:
                 t = t.reshape(N, 3).t().contiguous()
             return t.to(self.device)
 
-        tr, tu, tC, tB = dev(rho, 1), dev(u, 3), dev(C_, 1), dev(B, 3)
+        ns = self.n_scalar
+        tr, tu, tB = dev(rho, 1), dev(u, 3), dev(B, 3)
+        tC = None if C_ is None else torch.as_tensor(np.asarray(C_, np.float64)).reshape(ns * N).to(self.device)
         if tC is None and C_uniform is not None and C_uniform != self.params.C0:
-            tC = torch.full((N,), float(C_uniform), dtype=torch.float64, device=self.device)
+            tC = torch.full((ns * N,), float(C_uniform), dtype=torch.float64, device=self.device)
         self._keep_init = (tr, tu, tC, tB)
         ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
         self._call("lbm_init", ptr(tr), ptr(tu), ptr(tC), ptr(tB))
@@ -250,11 +261,12 @@ class Lattice:
         return L.lib().lbm_time(self.ctx)
 
     def read_moments(self, dtype: str = "f64", out=None):
-        """[8, nz, ny, nx] tensor of rho, u, C, B at the current time."""
+        """[W, nz, ny, nx] tensor of rho, u, C_0, B, then C_1, C_2 of several
+        scalar components (W = 8 + components - 1), at the current time."""
         torch = self.torch
         td = torch.float64 if dtype == "f64" else torch.float32
         if out is None:
-            out = torch.empty((8,) + self.shape, dtype=td, device=self.device)
+            out = torch.empty((self.moment_width,) + self.shape, dtype=td, device=self.device)
         self._call("lbm_read_moments", C.c_void_p(out.data_ptr()), L.LBM_F64 if dtype == "f64" else L.LBM_F32)
         return out
 
@@ -264,7 +276,7 @@ class Lattice:
         sc = self.scene
         lat = {0: sc.fluid_lattice, 1: sc.scalar_lattice, 2: sc.mag_lattice}[field]
         q = len(lattice_table(LATTICES[lat])[1])
-        nc = len(sc.mag_comps) if field == 2 else 1
+        nc = len(sc.mag_comps) if field == 2 else (self.n_scalar if field == 1 else 1)
         out = torch.empty((nc * q,) + self.shape, dtype=torch.float64, device=self.device)
         self._call("lbm_read_populations", field, C.c_void_p(out.data_ptr()))
         return out

@@ -119,10 +119,11 @@ class BC:
     alt    : the comparison form of Section 5 instead of the method's: VEL
              and PRES extrapolated at every d (Eqs. 15-16), FLUX and MAG_FLUX
              with the flux added at the wall (Eq. 33)
-    partner, cross: a scalar FLUX wall of component i under the "coef" law
-             whose flux also depends on component j = partner:
-             F_i = a1 C_i + quad C_i^2 + cross C_i C_j - a3 (Section 4.2.2,
-             a surface reaction between components); partner -1: none
+    cross_comps, cross: a scalar FLUX wall of component i under the "coef"
+             law whose flux also depends on components (j, l) = cross_comps:
+             F_i = a1 C_i + quad C_i^2 + cross C_j C_l - a3 (Section 4.2.2, a
+             surface reaction between components, e.g. A + B -> P); (-1, -1):
+             none
     """
     kind: str
     value: float = 0.0
@@ -138,7 +139,7 @@ class BC:
     phi_eq: float = 0.0
     c_w: float = 0.0
     H: float = 0.0
-    partner: int = -1
+    cross_comps: Tuple[int, int] = (-1, -1)
     cross: float = 0.0
 
 
@@ -348,6 +349,30 @@ def reactive_channel(nx: int = 512, ny: int = 256, k: float = 1e-2, q: float = 0
     return Scene(name=f"reactive_{nx}x{ny}", dim=2, n=(nx, ny, 1), periodic=(False, False, True),
                  fluid_lattice=D2Q9, scalar_lattice=D2Q5, tau_f=tau_f, tau_c=tau_c,
                  rho0=1.0, C0=0.0, init_C=0.0, boundaries=walls + [inlet, outlet],
+                 storage=storage, store_scale=(1024.0, 1024.0, 1.0), steps=steps)
+
+
+def reactive_species(nx: int = 512, ny: int = 256, k: float = 2e-2, q: float = 0.3, ncomp: int = 3,
+                     C_in: Tuple[float, ...] = (1.0, 0.8, 0.0), taus: Tuple[float, ...] = (0.6, 0.7, 0.65),
+                     rho_in: float = 1.001, rho_out: float = 1.0, tau_f: float = 0.8, storage: str = "f32",
+                     steps: int = 2000, q_io: float = 0.5) -> Scene:
+    """The pressure-driven reactive channel with several scalar components
+    (Section 4.2.2): A (0) and B (1) enter at the inlet and react at both
+    walls, A + B -> P at the rate k C_A C_B, so F_A = F_B = -k C_A C_B; with
+    three components the product P (2) leaves the walls at F_P = +k C_A C_B.
+    Zero flux at the outlet for every component."""
+    if ncomp not in (2, 3):
+        raise ValueError("ncomp must be 2 or 3")
+    walls = [Boundary("plane", axis=1, side=side, q=q, f=BC(VEL),
+                      h=[BC(FLUX, cross_comps=(0, 1), cross=-k if i < 2 else k) for i in range(ncomp)])
+             for side in (0, 1)]
+    inlet = Boundary("plane", axis=0, side=0, q=q_io, is_open=True, f=BC(PRES, value=rho_in),
+                     h=[BC(CONC, value=C_in[i], u_given=False) for i in range(ncomp)])
+    outlet = Boundary("plane", axis=0, side=1, q=q_io, is_open=True, f=BC(PRES, value=rho_out),
+                      h=[BC(FLUX, a1=0.0, a3=0.0, u_given=False) for _ in range(ncomp)])
+    return Scene(name=f"reactive_species{ncomp}_{nx}x{ny}", dim=2, n=(nx, ny, 1), periodic=(False, False, True),
+                 fluid_lattice=D2Q9, scalar_lattice=D2Q5, scalar_ncomp=ncomp, tau_f=tau_f, tau_c=taus[0],
+                 tau_cs=tuple(taus[1:ncomp]), rho0=1.0, C0=0.0, init_C=0.0, boundaries=walls + [inlet, outlet],
                  storage=storage, store_scale=(1024.0, 1024.0, 1.0), steps=steps)
 
 
@@ -624,6 +649,8 @@ def developed(sc: Scene, seed: int = BASE_SEED + 7, u_amp: float = 0.02, b_amp: 
     for c in sc.mag_comps:
         B[..., c] += b_amp * smooth()
     Cf = sc.init_C + C_amp * smooth() if sc.scalar_lattice else None
+    if Cf is not None and sc.scalar_ncomp > 1:
+        Cf = np.stack([Cf] + [sc.init_C + C_amp * smooth() for _ in range(sc.scalar_ncomp - 1)])
     return sc.with_(init_rho=rho, init_u=u, init_B=B if sc.mag_lattice else None, init_Cf=Cf)
 
 

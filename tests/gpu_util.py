@@ -16,7 +16,8 @@ def direction_map(name):
 
 
 def gpu_moments(lat):
-    """[nz, ny, nx, 8] numpy array from the library."""
+    """[nz, ny, nx, W] numpy array from the library (W = 8, plus one column
+    per scalar component beyond the first)."""
     return lat.read_moments("f64").cpu().numpy().transpose(1, 2, 3, 0)
 
 
@@ -32,7 +33,7 @@ def gpu_populations(lat, field):
     for c in range(nc):
         for a in range(q):
             out[c * q + m[a]] = P[c * q + a]
-    return out.reshape((nc, q) + P.shape[1:]) if field == 2 else out
+    return out.reshape((nc, q) + P.shape[1:]) if field == 2 or (field == 1 and nc > 1) else out
 
 
 def rel_l2(a, b, floor=1e-300):

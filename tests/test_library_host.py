@@ -2,6 +2,7 @@
 own geometry / link builder agrees with the oracle's independent builder, and
 invalid inputs are rejected before any device work."""
 import ctypes as C
+import dataclasses
 import math
 import os
 import re
@@ -85,7 +86,19 @@ SCENES = {
     "open_box_alt": lambda: scenes.open_box(nx=6, ny=3, q_in=0.52, q_out=0.7, alt_in=True, alt_out=True),
     "pipe_conducting_q19": lambda: scenes.mhd_pipe(nx=2, side=17, R=6.3, wall="conducting", mag_lattice="D3Q19"),
     "reactive_quadratic": lambda: _quadratic_walls(scenes.reactive_channel(nx=9, ny=6, q=0.3)),
+    "species2": lambda: scenes.reactive_species(nx=11, ny=7, q=0.7, ncomp=2),
+    "species3": lambda: scenes.reactive_species(nx=9, ny=6, q=0.3, ncomp=3),
+    "species3_3d": lambda: _species_3d(),
 }
+
+
+def _species_3d():
+    """three components in a D3Q7 pipe: A + B -> P on the curved wall"""
+    sc = scenes.mhd_pipe(nx=2, side=13, R=5.3, wall="insulating")
+    wall = dataclasses.replace(sc.boundaries[0], g=[], h=[scenes.BC(scenes.FLUX, cross_comps=(0, 1), cross=c)
+                                                          for c in (-0.02, -0.02, 0.02)])
+    return sc.with_(boundaries=[wall], mag_lattice=None, mag_comps=(), scalar_lattice="D3Q7", scalar_ncomp=3,
+                    tau_c=0.6, tau_cs=(0.7, 0.65), B_ext=(0.0, 0.0, 0.0))
 
 
 def _quadratic_walls(sc, k=0.02):
@@ -127,8 +140,10 @@ def compare_link_tables(sc):
         assert bool(r["flags"] & 1) == bool(o_["u_given"])
         assert bool(r["flags"] & 4) == (o_["omega"] != 0.0)
         assert bool(r["flags"] & 8) == bool(o_["compare"])
-        for fld in ("value", "a1", "quad", "a3"):
+        for fld in ("value", "a1", "quad", "a3", "cross"):
             assert r[fld] == o_[fld], (fld, r[fld], o_[fld])
+        if r["cross"] != 0.0:
+            assert (int(r["cross_comp"][0]), int(r["cross_comp"][1])) == (int(o_["cj"]), int(o_["cl"]))
         assert abs(r["weight"] - o_["weight"]) < 1e-12 * max(1.0, abs(o_["weight"]))
         assert np.array_equal(r["u_w"], o_["u_w"])
     return ll
@@ -429,6 +444,105 @@ def test_builder_rejects_uncovered_boundary():
     sc.boundaries[1].f = None
     with pytest.raises(L.LbmError):
         lbm.build_links(sc)
+
+
+# ---------------------------------------------------------------------------
+# several scalar components (Section 4.2.2)
+# ---------------------------------------------------------------------------
+def test_several_components_buffer_layout():
+    """m components: m scalar lattices of populations, 7 + m moment planes
+    per parity, 6 + m snapshot planes"""
+    sc = scenes.reactive_species(nx=64, ny=30, ncomp=3)
+    p = lbm.params_from_scene(sc)
+    sizes = lbm.required_bytes(p, 100)
+    plane = ((66 * 32 + 63) // 64) * 64   # one halo layer on each side of both axes
+    up = lambda x: ((x + 255) // 256) * 256
+    assert sizes[0] == up((9 + 3 * 5) * plane * 4)
+    assert sizes[3] == up(2 * 10 * plane * 4) + 256
+    assert sizes[4] == up(9 * plane * 4) + up(16 * 8)
+
+
+@pytest.mark.parametrize("mut", [
+    dict(scalar_ncomp=4), dict(scalar_ncomp=-1), dict(tau_cs=(0.5, 0.7)), dict(scalar_ncomp=3, tau_cs=(0.7, 0.4)),
+])
+def test_several_components_rejects_bad_params(mut):
+    sc = scenes.reactive_species(nx=6, ny=5, ncomp=2)
+    p = lbm.params_from_scene(sc)
+    for k, v in mut.items():
+        if isinstance(v, tuple):
+            for i, x in enumerate(v):
+                getattr(p, k)[i] = x
+        else:
+            setattr(p, k, v)
+    assert L.lib().lbm_required_bytes(C.byref(p), 10, (C.c_size_t * L.LBM_NBUF)()) == 0
+
+
+def test_several_components_need_a_scalar_lattice_and_no_magnetic_one():
+    for sc in (scenes.poiseuille(nx=4, ny=4), scenes.hartmann_couette(nx=3, ny=7)):
+        p = lbm.params_from_scene(sc)
+        p.scalar_ncomp = 2
+        p.tau_cs[0] = 0.7
+        assert L.lib().lbm_required_bytes(C.byref(p), 10, (C.c_size_t * L.LBM_NBUF)()) == 0
+
+
+def _species_walls(sc, **kw):
+    for b in sc.boundaries[:2]:
+        b.h = [dataclasses.replace(bc, **kw) for bc in b.h]
+    return sc
+
+
+@pytest.mark.parametrize("bad", [
+    dict(cross_comps=(0, 2)),              # a component beyond scalar_ncomp
+    dict(cross_comps=(-1, 1)),
+    dict(law="robin", k=0.1),              # the bilinear term belongs to the given-coefficient law
+    dict(cross=float("nan")),
+])
+def test_several_components_builder_validation(bad):
+    sc = _species_walls(scenes.reactive_species(nx=6, ny=5, ncomp=2), **bad)
+    with pytest.raises(L.LbmError):
+        lbm.build_links(sc)
+
+
+def test_several_components_need_a_condition_for_each():
+    sc = scenes.reactive_species(nx=6, ny=5, ncomp=3)
+    sc.boundaries[0].h = sc.boundaries[0].h[:2]
+    with pytest.raises(L.LbmError):
+        lbm.build_links(sc)
+    # a bilinear term with one component only
+    one = scenes.reactive_channel(nx=6, ny=5)
+    one.boundaries[0].h = scenes.BC(scenes.FLUX, cross_comps=(0, 0), cross=-0.01)
+    with pytest.raises(L.LbmError):
+        lbm.build_links(one)
+
+
+def test_several_components_link_validation():
+    sc = scenes.reactive_species(nx=6, ny=5, ncomp=2)
+    mask, links = lbm.build_links(sc)
+    fc = _FakeCtx(sc, len(links) + 4)
+    assert L.lib().lbm_set_geometry(fc.ctx, mask.ctypes.data_as(C.c_void_p)) == 0
+    flux = np.nonzero(links["cross"] != 0)[0]
+    conc = np.nonzero((links["field"] == 1) & (links["kind"] == lbm.KINDS["CONC"]))[0]
+    assert len(flux) and len(conc)
+    bad = links.copy()
+    bad["cross_comp"][flux[0]] = (0, 2)
+    assert fc.set_links(bad) == -1 and "bilinear" in fc.err()
+    bad = links.copy()
+    bad["cross"][conc[0]] = 0.1
+    assert fc.set_links(bad) == -1 and "bilinear" in fc.err()
+    bad = links.copy()
+    bad["comp"][conc[0]] = 2
+    assert fc.set_links(bad) == -1 and "component" in fc.err()
+    # one component's links missing
+    keep = ~((links["field"] == 1) & (links["comp"] == 1))
+    assert fc.set_links(links[keep]) == -1 and "no boundary link" in fc.err()
+    assert fc.set_links(links) != -1   # valid: only the upload (no device here) fails
+
+
+def test_batch_rejects_several_components():
+    scs = [scenes.reactive_species(nx=6, ny=5, ncomp=2)] * 2
+    params = _batch_params(scs)
+    caps = (C.c_size_t * 2)(*[len(lbm.build_links(sc)[1]) for sc in scs])
+    assert L.lib().lbm_batch_required_bytes(2, params, caps, (C.c_size_t * L.LBM_NBUF)()) == 0
 
 
 # ---------------------------------------------------------------------------
