@@ -140,7 +140,7 @@ def algorithmic_bytes(lat) -> dict:
     links = lat.links
     e_valid = (links["flags"] & 2) == 0
     mom_nodes = np.unique(np.concatenate([links["node"], links["enode"][e_valid]])).size
-    sweep = n_fluid * 2 * QT * s + padded + mom_nodes * 8 * cb
+    sweep = n_fluid * 2 * QT * s + padded + mom_nodes * lat.moment_width * cb
     link = len(links) * (rec + 4 * s) + 2 * cb * int(links_moment_reads(links, sc).sum())
     return dict(sweep=int(sweep), links=int(link), per_fluid_node_populations=2 * QT * s,
                 fluid_nodes=n_fluid, n_links=int(len(links)), moment_nodes=int(mom_nodes), planes=QT)

