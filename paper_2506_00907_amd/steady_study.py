@@ -148,6 +148,23 @@ def equalise(batch, items, masks, ref_m, target, eligible, chunk, max_extra):
     return extra, secs, moms
 
 
+def target_verdict(v, label):
+    """3x plain's time to steady at equal error: the speed-up at the point
+    where the variant's errors are compared (the batch at the residual rule,
+    whose arithmetic is plain's; cold and warm after the equal-error
+    continuation) and the share of reference-converged items within the
+    rule; met when the speed-up is at least 3 with at least 90 % of the
+    items within the rule."""
+    if label == "batch":
+        sp, st = v.get("speedup_vs_plain_at_residual"), v.get("at_residual", {}).get("all", {})
+    else:
+        eq = v.get("equal_error", {})
+        sp, st = eq.get("speedup_vs_plain"), eq.get("all", {})
+    share = st.get("equal")
+    met = sp is not None and share is not None and sp >= 3.0 and share >= 0.9
+    return dict(speedup=sp, share_within_rule=share, met=bool(met))
+
+
 def rule_stats(e, e_plain, sel):
     """share of the selected items within the equal-error rule
     |e - e_plain| <= 0.1 e_plain, and within or below it (e <= 1.1 e_plain)."""
@@ -193,9 +210,13 @@ def plain(items, tol, interval, max_steps, stall=None, chunk=50_000):
     return dict(steps=np.array(steps), seconds=secs, moments=moms, status=status)
 
 
-def inits_from(moms):
-    """(u, B) initial fields from moment arrays [nz, ny, nx, 8]."""
-    return [(m[..., 1:4], m[..., 5:8]) for m in moms]
+def inits_from(moms, items=None, links=None):
+    """(u, B) initial fields from moment arrays [nz, ny, nx, 8]; with items
+    and links, b_x shifted to the thin walls' steady balance
+    (warmstart.thin_wall_shift)."""
+    if items is None:
+        return [(m[..., 1:4], m[..., 5:8]) for m in moms]
+    return [(m[..., 1:4], ws.thin_wall_shift(it, lk, m[..., 5:8])) for m, it, lk in zip(moms, items, links)]
 
 
 def summary(sol, moms, ref_m, items, masks, ref_ok=None):
@@ -218,12 +239,52 @@ def item_table(items, masks):
                  raised=bool(it.raised), fluid=int(np.asarray(mk).sum())) for it, mk in zip(items, masks)]
 
 
+# the variants after the plain run and the FP32 batch: FP16 batch from rest
+# then FP32 polish; the same from the network's start; the network's start
+# straight into the FP32 batch
+VARIANTS = ("cold", "warm", "warm32")
+
+
+def second_reference(a, items, masks, ref_m, ref_ok, e_plain, finals, kw32, res):
+    """How far the reference itself is determined.  The reference continues
+    the rest-start trajectory of the FP32 batch; a second FP64 reference run
+    to the same tolerance from the warm variant's final state shows how much
+    of that start it still carries (slow modes decay over many more steps
+    than the residual rule waits).  Reported: the spread between the two
+    references, the equal-error statistics over the items whose references
+    agree to within a tenth of plain's error (the only items on which a
+    difference of that size can be judged), and every variant's errors
+    against the second reference."""
+    import torch
+    log("[eval] second reference: FP64 from the warm variant's final state")
+    r2 = ws.solve(items, "f64", tol=a.ref_tol, inits=inits_from(finals["warm_eq"]), **kw32)
+    ref2_m = ws.moments_of(r2["batch"])
+    ref2_ok = np.array([st == "steady" for st in r2["status"]])
+    seconds = r2["seconds"]
+    del r2
+    torch.cuda.empty_cache()
+    both = ref_ok & ref2_ok
+    spread = field_error(items, ref2_m, ref_m, masks)
+    resolved = both & (spread <= 0.1 * e_plain)
+    e2 = {k: field_error(items, m, ref2_m, masks) for k, m in finals.items()}
+    out = dict(seconds=seconds, status=ref2_ok.tolist(), spread=spread.tolist(),
+               n_both=int(both.sum()), n_resolved=int(resolved.sum()),
+               spread_median=float(np.median(spread[both])) if both.any() else None,
+               spread_over_plain_median=float(np.median(spread[both] / e_plain[both])) if both.any() else None)
+    e1 = {k: field_error(items, m, ref_m, masks) for k, m in finals.items()}
+    out["resolved"] = {k: rule_stats(e1[k], e_plain, resolved) for k in finals if k != "plain"}
+    out["against_second"] = {k: rule_stats(e2[k], e2["plain"], both) for k in finals if k != "plain"}
+    res["reference2"] = out
+    log(f"[eval] second reference: {seconds:.1f} s, {int(both.sum())} items with both references, "
+        f"{int(resolved.sum())} resolved, spread median {out['spread_median']}")
+
+
 def cmd_eval(a):
     import torch
     from paper_2506_00907_amd import lbm
     items = scenes.batch_items(a.items, seed=EVAL_SEED)
     res = dict(items=a.items, seed=EVAL_SEED, tol=a.tol, tol_fp16=a.tol16, interval=a.interval,
-               ref_tol=a.ref_tol, equal_chunk=a.equal_chunk)
+               ref_tol=a.ref_tol, equal_chunk=a.equal_chunk, wall_shift=a.wall_shift, stall=a.stall)
     kw = dict(interval=a.interval, max_steps=a.max_steps, chunk=a.chunk, log=log)
     kw32 = dict(kw, stall=a.stall)
     raised = np.array([it.raised for it in items])
@@ -232,6 +293,7 @@ def cmd_eval(a):
     bsol = ws.solve(items, "f32", tol=a.tol, **kw32)
     b_m = ws.moments_of(bsol["batch"])
     masks = [lat.mask for lat in bsol["batch"].items]
+    links = [lat.links for lat in bsol["batch"].items]
     res["item_table"] = item_table(items, masks)
     del bsol["batch"]
     torch.cuda.empty_cache()
@@ -257,10 +319,14 @@ def cmd_eval(a):
                             errors_b=eb.tolist(),
                             error_median_ref_steady=float(np.median(e_plain[ref_ok])) if ref_ok.any() else None)
         plain_steps = pl["steps"]
+        finals = {"plain": pl["moments"], "batch": b_m}
         del pl
 
-    for label in ("cold", "warm"):
+    net_inits, net_t = None, 0.0
+    for label in VARIANTS:
         inits, t_inf = None, 0.0
+        if label == "warm32":
+            inits, t_inf = net_inits, net_t
         if label == "warm":
             params = np.load(a.weights)
             torch.cuda.synchronize()
@@ -272,6 +338,8 @@ def cmd_eval(a):
                 X[i] = torch.from_numpy(ws.features(it, masks[i], a.size))
             pred = ws.predict(net, X).cpu().numpy()
             inits = [ws.init_fields(it, masks[i], pred[i]) for i, it in enumerate(items)]
+            if a.wall_shift:
+                inits = [(u, ws.thin_wall_shift(it, links[i], B)) for i, (it, (u, B)) in enumerate(zip(items, inits))]
             torch.cuda.synchronize()
             t_inf = time.perf_counter() - t0
             pe = []
@@ -281,18 +349,30 @@ def cmd_eval(a):
                 pe.append(float(np.linalg.norm((pred[i] - t_ref)[sel]) / max(np.linalg.norm(t_ref[sel]), 1e-30)))
             res["prediction_error"] = dict(median=float(np.median(pe)), max=float(np.max(pe)))
             log(f"[eval] warm: inference {t_inf:.2f} s, prediction error median {np.median(pe):.3f}")
-        log(f"[eval] {label}: FP16 batch, tol {a.tol16:g}")
-        s16 = ws.solve(items, "f16", tol=a.tol16, inits=inits, stall=0.5, **kw)
-        m16 = ws.moments_of(s16["batch"])
-        del s16["batch"]
-        torch.cuda.empty_cache()
-        log(f"[eval] {label}: FP32 polish, tol {a.tol:g}")
-        p = ws.solve(items, "f32", tol=a.tol, inits=inits_from(m16), **kw32)
+            net_inits, net_t = inits, t_inf
+        s16 = None
+        if label != "warm32":
+            log(f"[eval] {label}: FP16 batch, tol {a.tol16:g}")
+            s16 = ws.solve(items, "f16", tol=a.tol16, inits=inits, stall=0.5, **kw)
+            m16 = ws.moments_of(s16["batch"])
+            del s16["batch"]
+            torch.cuda.empty_cache()
+            log(f"[eval] {label}: FP32 polish, tol {a.tol:g}")
+            t0 = time.perf_counter()
+            hand = inits_from(m16, items, links) if a.wall_shift else inits_from(m16)
+            t_hand = time.perf_counter() - t0
+        else:
+            log(f"[eval] {label}: FP32 batch from the network's start, tol {a.tol:g}")
+            hand, t_hand = inits, 0.0
+        p = ws.solve(items, "f32", tol=a.tol, inits=hand, **kw32)
+        p["seconds"] += t_hand
         mp = ws.moments_of(p["batch"])
+        if e_plain is not None:
+            finals[label] = mp
         r = summary(p, mp, ref_m, items, masks, ref_ok)
-        r16 = summary(s16, m16, ref_m, items, masks, ref_ok)
+        r16 = summary(s16, m16, ref_m, items, masks, ref_ok) if s16 is not None else None
         out = dict(inference_seconds=t_inf, fp16=r16, polish=r,
-                   total_seconds=t_inf + s16["seconds"] + p["seconds"],
+                   total_seconds=t_inf + (s16["seconds"] if s16 is not None else 0.0) + p["seconds"],
                    error_median=r["error_median"], error_max=r["error_max"],
                    error_median_ref_steady=r.get("error_median_ref_steady"))
         if e_plain is not None:
@@ -314,23 +394,28 @@ def cmd_eval(a):
                                       raised=rule_stats(e_eq, e_plain, ref_ok & raised),
                                       n_extended=int((extra > 0).sum()))
             log(f"[eval] {label}: {int((extra > 0).sum())} items ran on, {secs:.1f} s more")
+            finals[label + "_eq"] = me
         del p["batch"]
         torch.cuda.empty_cache()
         res[label] = out
         log(f"[eval] {label}: {res[label]['total_seconds']:.1f} s, error median {r['error_median']:.2e}")
+    if a.plain and a.second_reference:
+        second_reference(a, items, masks, ref_m, ref_ok, e_plain, finals, kw32, res)
     if a.plain:
         res["batch"]["at_residual"] = dict(all=rule_stats(np.array(res["batch"]["errors"]), e_plain, ref_ok))
-        for label in ("batch", "cold", "warm"):
+        for label in ("batch",) + VARIANTS:
             tot = res[label]["seconds"] if label == "batch" else res[label]["total_seconds"]
             res[label]["speedup_vs_plain_at_residual"] = res["plain"]["seconds"] / tot
             if label != "batch":
                 eq = res[label]["equal_error"]
                 eq["speedup_vs_plain"] = res["plain"]["seconds"] / eq["total_seconds"]
+        for label in ("batch",) + VARIANTS:
+            res[label]["target_3x_at_equal_error"] = target_verdict(res[label], label)
     os.makedirs(a.out, exist_ok=True)
     json.dump(res, open(os.path.join(a.out, "eval.json"), "w"), indent=1)
     brief = {k: v for k, v in res.items() if k not in ("reference", "item_table")}
     drop = ("steps", "status", "errors", "errors_u", "errors_b", "extra_steps")
-    for k in ("batch", "cold", "warm", "plain"):
+    for k in ("batch", "plain") + VARIANTS:
         if k in brief:
             brief[k] = {kk: vv for kk, vv in brief[k].items() if kk not in drop}
             for sub in ("fp16", "polish", "equal_error"):
@@ -368,7 +453,10 @@ def cmd_report(a):
       f"| — | — | {st.get('equal', float('nan')):.2f} (at the residual rule) | — | — | "
       f"{st.get('median_ratio', float('nan')):.2f} |")
     for label, name in (("cold", "cold: FP16 batch, then FP32 polish"),
-                        ("warm", "warm: network, FP16 batch, then FP32 polish")):
+                        ("warm", "warm: network, FP16 batch, then FP32 polish"),
+                        ("warm32", "warm32: network, then FP32 batch")):
+        if label not in ev:
+            continue
         v = ev[label]
         eq = v.get("equal_error", {})
         if not eq:
@@ -378,20 +466,53 @@ def cmd_report(a):
           f"({eq['all']['not_worse']:.2f} not worse) | {eq['unraised'].get('not_worse', float('nan')):.2f} | "
           f"{eq['raised'].get('not_worse', float('nan')):.2f} | {eq['all']['median_ratio']:.2f} |")
     w("")
-    for label in ("cold", "warm"):
-        v = ev[label]
+    if pl:
+        for label in ("batch",) + VARIANTS:
+            if label not in ev:
+                continue
+            tv = ev[label].get("target_3x_at_equal_error") or target_verdict(ev[label], label)
+            if tv["speedup"] is None:
+                continue
+            w(f"- target (3x plain at equal error, >= 90 % of the items within the rule), {label}: "
+              f"{'met' if tv['met'] else 'not met'} (speed-up {tv['speedup']:.2f}, "
+              f"{tv['share_within_rule']:.2f} within the rule).")
+    for label in VARIANTS:
+        v = ev.get(label, {})
         if "equal_error" not in v:
             continue
         ar = v["at_residual"]
+        fp16 = f"FP16 {v['fp16']['seconds']:.1f} s, " if v.get("fp16") else ""
         w(f"- {label}: at the residual rule {ar['all']['equal']:.2f} of the reference-converged items are within "
           f"|e - e_plain| <= 0.1 e_plain and {ar['all']['not_worse']:.2f} not worse (median ratio "
           f"{ar['all']['median_ratio']:.2f}); {v['equal_error']['n_extended']} items ran on for "
-          f"{v['equal_error']['extra_seconds']:.1f} s. Phases: inference {v['inference_seconds']:.1f} s, FP16 "
-          f"{v['fp16']['seconds']:.1f} s, polish {v['polish']['seconds']:.1f} s.")
+          f"{v['equal_error']['extra_seconds']:.1f} s. Phases: inference {v['inference_seconds']:.1f} s, {fp16}"
+          f"FP32 {v['polish']['seconds']:.1f} s.")
     if "prediction_error" in ev:
         w(f"- network prediction error (relative L2 of the scaled fields): median {ev['prediction_error']['median']:.3f}, "
           f"max {ev['prediction_error']['max']:.3f}.")
     w(f"- reference: {ev['reference']['seconds']:.1f} s.")
+    r2 = ev.get("reference2")
+    if r2:
+        w("")
+        w(f"Second reference (FP64 from the warm variant's final state, same tolerance, {r2['seconds']:.1f} s): "
+          f"{r2['n_both']} items have both references; their spread (relative L2 between the two) has median "
+          f"{r2['spread_median']:.2e}, {r2['spread_over_plain_median']:.2f} times plain's error. "
+          f"{r2['n_resolved']} items have references that agree to within a tenth of plain's error.")
+        w("")
+        w("| Variant | resolved items within the rule | not worse | median error / plain | "
+          "against the second reference: within | not worse | median ratio |")
+        w("|---|---|---|---|---|---|---|")
+        names = dict(batch="batch (at the residual rule)", cold="cold (at the residual rule)",
+                     cold_eq="cold (at equal error)", warm="warm (at the residual rule)",
+                     warm_eq="warm (at equal error)", warm32="warm32 (at the residual rule)",
+                     warm32_eq="warm32 (at equal error)")
+        for k, name in names.items():
+            rs, ag = r2["resolved"].get(k, {}), r2["against_second"].get(k, {})
+            if not rs:
+                continue
+            f = lambda d, key: f"{d[key]:.2f}" if key in d else "—"
+            w(f"| {name} | {f(rs, 'equal')} (n = {rs.get('n', 0)}) | {f(rs, 'not_worse')} | {f(rs, 'median_ratio')} "
+              f"| {f(ag, 'equal')} (n = {ag.get('n', 0)}) | {f(ag, 'not_worse')} | {f(ag, 'median_ratio')} |")
     if tr:
         w(f"- training: {tr['items']} items (seed {tr['seed']}), {tr['epochs']} epochs in {tr['train_seconds']:.1f} s, "
           f"loss {tr['loss'][0]:.3e} -> {tr['loss'][-1]:.3e}.")
@@ -427,11 +548,16 @@ def main(argv=None):
             p.add_argument("--ref-tol", type=float, default=1e-10)
             p.add_argument("--tol16", type=float, default=1e-6)
             p.add_argument("--plain", action="store_true")
+            p.add_argument("--no-wall-shift", dest="wall_shift", action="store_false",
+                           help="start the warm and polish phases without the thin-wall offset correction")
             p.add_argument("--stall", type=float, default=0.95,
                            help="FP32/FP64 runs: an item stops when its residual fell by less than this "
                                 "factor over a chunk (mass-drift floors of interpolated walls)")
             p.add_argument("--equal-chunk", type=int, default=2000,
                            help="steps per round of the equal-error continuation")
+            p.add_argument("--second-reference", action="store_true",
+                           help="also run an FP64 reference from the warm variant's final state and report "
+                                "how far the reference is determined")
     a = ap.parse_args(argv)
     if a.cmd == "report":
         cmd_report(a)

@@ -58,3 +58,42 @@ def test_scales_follow_the_hartmann_limit():
     L = ws.half_width(it)
     assert math.isclose(U, it.scene.accel[0] * L * L / (nu * (2.0 + it.Ha)))
     assert math.isclose(Bs, U)  # nu = eta and rho0 = mu = 1 for these items
+
+
+def test_thin_wall_shift_balances_the_wall_fluxes():
+    """The offset of b_x that thin_wall_shift adds makes the flux-weighted sum
+    of the extrapolated wall values vanish, the balance the steady state of
+    the thin walls satisfies (the FP64 oracle's steady state shows it)."""
+    import oracle
+    kw = dict(side_lo=14, side_hi=20, c_lo=0.3, c_hi=3.0, Ha_hi=10.0, storage="f64")
+    duct = scenes.batch_items(1, ducts_only=True, q_duct=0.5, **kw)[0]
+    pipe = next(it for it in scenes.batch_items(6, **kw) if it.shape == "pipe")
+    for it in (duct, pipe):
+        mask, links = lbm.build_links(it.scene)
+        sel = (links["field"] == 2) & (links["kind"] == 7)
+        w = links["weight"][sel]
+        A = links["node"][sel].astype(np.int64)
+        E = np.where((links["flags"][sel] & 2) != 0, A, links["enode"][sel].astype(np.int64))
+        d = links["d"][sel]
+
+        def balance(B):
+            b = (B[..., 0] - it.scene.B_ext[0]).reshape(-1)
+            bX = -d * b[E] + (1 + d) * b[A]
+            return np.sum(w * bX), np.sum(w * np.abs(bX))
+
+        rng = np.random.default_rng(3)
+        B = np.zeros((it.nz, it.ny, 1, 3)) + np.asarray(it.scene.B_ext)
+        B[..., 0] += 1e-3 * rng.standard_normal(B.shape[:3]) + 2e-3
+        s0, _ = balance(B)
+        B2 = ws.thin_wall_shift(it, links, B)
+        s1, m1 = balance(B2)
+        assert abs(s0) > 1e-3 * np.sum(w) and abs(s1) < 1e-12 * m1
+        assert np.allclose(B2[..., 1:], B[..., 1:]) and np.ptp((B2 - B)[..., 0]) < 1e-15
+        # the oracle's steady state of the same section satisfies the balance
+        # (to round-off on half-way duct walls and on pipe walls; duct walls
+        # at other distances leave an imbalance of ~1e-3 of sum |w b_X| from
+        # their interpolated bounce-back)
+        o = oracle.OracleSim(it.scene)
+        o.step(10000)
+        s, m = balance(o.moments()[..., 5:8])
+        assert abs(s) < 1e-12 * m, (s, m)
