@@ -210,13 +210,24 @@ def plain(items, tol, interval, max_steps, stall=None, chunk=50_000):
     return dict(steps=np.array(steps), seconds=secs, moments=moms, status=status)
 
 
-def inits_from(moms, items=None, links=None):
+def axial(u):
+    """the axial velocity only: the steady flow of a straight section has no
+    in-plane velocity, and equilibria of in-plane velocities excite a
+    row-alternating mode the update keeps"""
+    v = np.zeros_like(u)
+    v[..., 0] = u[..., 0]
+    return v
+
+
+def inits_from(moms, items=None, links=None, shift=True):
     """(u, B) initial fields from moment arrays [nz, ny, nx, 8]; with items
-    and links, b_x shifted to the thin walls' steady balance
+    and links (a handover between phases), the axial velocity only and, with
+    shift, b_x shifted to the thin walls' steady balance
     (warmstart.thin_wall_shift)."""
     if items is None:
         return [(m[..., 1:4], m[..., 5:8]) for m in moms]
-    return [(m[..., 1:4], ws.thin_wall_shift(it, lk, m[..., 5:8])) for m, it, lk in zip(moms, items, links)]
+    return [(axial(m[..., 1:4]), ws.thin_wall_shift(it, lk, m[..., 5:8]) if shift else m[..., 5:8])
+            for m, it, lk in zip(moms, items, links)]
 
 
 def summary(sol, moms, ref_m, items, masks, ref_ok=None):
@@ -241,8 +252,9 @@ def item_table(items, masks):
 
 # the variants after the plain run and the FP32 batch: FP16 batch from rest
 # then FP32 polish; the same from the network's start; the network's start
-# straight into the FP32 batch
-VARIANTS = ("cold", "warm", "warm32")
+# straight into the FP32 batch; its velocity only (the induced field from
+# rest, as in the plain run) straight into the FP32 batch
+VARIANTS = ("cold", "warm", "warm32", "warm32u")
 
 
 def second_reference(a, items, masks, ref_m, ref_ok, e_plain, finals, kw32, res):
@@ -327,6 +339,10 @@ def cmd_eval(a):
         inits, t_inf = None, 0.0
         if label == "warm32":
             inits, t_inf = net_inits, net_t
+        if label == "warm32u":
+            inits = [(u, np.zeros_like(B) + np.asarray(it.scene.B_ext, float))
+                     for it, (u, B) in zip(items, net_inits)]
+            t_inf = net_t
         if label == "warm":
             params = np.load(a.weights)
             torch.cuda.synchronize()
@@ -351,7 +367,7 @@ def cmd_eval(a):
             log(f"[eval] warm: inference {t_inf:.2f} s, prediction error median {np.median(pe):.3f}")
             net_inits, net_t = inits, t_inf
         s16 = None
-        if label != "warm32":
+        if label not in ("warm32", "warm32u"):
             log(f"[eval] {label}: FP16 batch, tol {a.tol16:g}")
             s16 = ws.solve(items, "f16", tol=a.tol16, inits=inits, stall=0.5, **kw)
             m16 = ws.moments_of(s16["batch"])
@@ -359,7 +375,7 @@ def cmd_eval(a):
             torch.cuda.empty_cache()
             log(f"[eval] {label}: FP32 polish, tol {a.tol:g}")
             t0 = time.perf_counter()
-            hand = inits_from(m16, items, links) if a.wall_shift else inits_from(m16)
+            hand = inits_from(m16, items, links, shift=a.wall_shift)
             t_hand = time.perf_counter() - t0
         else:
             log(f"[eval] {label}: FP32 batch from the network's start, tol {a.tol:g}")
@@ -419,7 +435,7 @@ def cmd_eval(a):
         if k in brief:
             brief[k] = {kk: vv for kk, vv in brief[k].items() if kk not in drop}
             for sub in ("fp16", "polish", "equal_error"):
-                if sub in brief[k]:
+                if brief[k].get(sub):
                     brief[k][sub] = {kk: vv for kk, vv in brief[k][sub].items() if kk not in drop}
     log(json.dumps(brief, default=str))
 
@@ -454,7 +470,8 @@ def cmd_report(a):
       f"{st.get('median_ratio', float('nan')):.2f} |")
     for label, name in (("cold", "cold: FP16 batch, then FP32 polish"),
                         ("warm", "warm: network, FP16 batch, then FP32 polish"),
-                        ("warm32", "warm32: network, then FP32 batch")):
+                        ("warm32", "warm32: network, then FP32 batch"),
+                        ("warm32u", "warm32u: network velocity, induced field from rest, then FP32 batch")):
         if label not in ev:
             continue
         v = ev[label]
@@ -505,7 +522,8 @@ def cmd_report(a):
         names = dict(batch="batch (at the residual rule)", cold="cold (at the residual rule)",
                      cold_eq="cold (at equal error)", warm="warm (at the residual rule)",
                      warm_eq="warm (at equal error)", warm32="warm32 (at the residual rule)",
-                     warm32_eq="warm32 (at equal error)")
+                     warm32_eq="warm32 (at equal error)", warm32u="warm32u (at the residual rule)",
+                     warm32u_eq="warm32u (at equal error)")
         for k, name in names.items():
             rs, ag = r2["resolved"].get(k, {}), r2["against_second"].get(k, {})
             if not rs:
