@@ -151,16 +151,19 @@ STEADY = {
 
 @pytest.mark.parametrize("key", sorted(STEADY))
 def test_fp32_parity_at_steady_state(key):
-    """FP32 storage against the FP64 oracle at the steady state.
+    """FP32 storage against the FP64 oracle at the steady state, compared at
+    the same time (the transpiring channel's total mass keeps varying slowly
+    in both).
 
     At a fixed point the FP32 rounding of every stored population repeats
-    identically each step, acting as a constant forcing that the slowest
-    relaxation mode (decay rate ~ nu pi^2 / (2H)^2) amplifies by its inverse;
-    the FP32 residual also stalls near 1e-8.  The stated 1e-5 bar applies to
-    rho, u, C and B.  The induced field b = B - B_ext is a small sum of g
-    populations that carry large +-4 w (e.B) u_k terms when B_ext >> b, so its
-    relative FP32 error is larger by about |g|/|b|; it is reported and only
-    held to a sanity bound."""
+    identically each step, acting as a constant forcing that the slow modes
+    amplify by their inverse decay rates; the FP32 residual also stalls near
+    1e-8.  The 1e-5 bar holds for rho, u, C and B.  The induced field b =
+    B - B_ext does not meet it: its FP32 fixed point is displaced by a
+    constant offset (pipe: 4.7e-5 to 5.4e-5 of |b| over a further 6e4 steps,
+    while the FP64 path stays within 1e-13 of the oracle), a displacement of
+    the FP32 fixed point, not a residual that more steps would remove.  It is
+    held to 1e-4."""
     _case("fp32 steady " + key)
     mk, steps = STEADY[key]
     sc = mk()
@@ -180,7 +183,7 @@ def test_fp32_parity_at_steady_state(key):
     print(key, {k: f"{v:.1e}" for k, v in errs.items()}, f"B {errB:.1e}", f"residual {r:.1e}", flush=True)
     for f in ("rho", "u", "C"):
         assert errs[f] < 1e-5, (f, errs[f])
-    assert errB < 1e-5 and errs["b"] < 1e-3, (errB, errs["b"])
+    assert errB < 1e-5 and errs["b"] < 1e-4, (errB, errs["b"])
 
 
 @pytest.mark.parametrize("storage,bound", [("f16", 2e-2), ("bf16", 1e-1)])
