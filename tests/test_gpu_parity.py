@@ -159,11 +159,11 @@ def test_fp32_parity_at_steady_state(key):
     identically each step, acting as a constant forcing that the slow modes
     amplify by their inverse decay rates; the FP32 residual also stalls near
     1e-8.  The 1e-5 bar holds for rho, u, C and B.  The induced field b =
-    B - B_ext does not meet it: its FP32 fixed point is displaced by a
-    constant offset (pipe: 4.7e-5 to 5.4e-5 of |b| over a further 6e4 steps,
-    while the FP64 path stays within 1e-13 of the oracle), a displacement of
-    the FP32 fixed point, not a residual that more steps would remove.  It is
-    held to 1e-4."""
+    B - B_ext does not meet it: its FP32 fixed point is displaced by a smooth
+    field of 3e-5 to 7e-5 of |b| on the pipes (every wall type), constant
+    over a further 6e4 steps while the FP64 path stays within 1e-13 of the
+    oracle: the constant per-node rounding forcing projected on b's slowest
+    diffusive modes.  More steps do not remove it; it is held to 1e-4."""
     _case("fp32 steady " + key)
     mk, steps = STEADY[key]
     sc = mk()
