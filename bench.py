@@ -76,6 +76,9 @@ def make_scene(name: str, storage: str):
         return (scenes.config(4, storage=storage, wall="shercliff"),
                 "MHD pipe 128x128 cross-section x 64 periodic, R = 60, Ha = 10, Shercliff c_w = 0.05 "
                 "(D3Q19 + D3Q7)")
+    if name == "species":
+        return (scenes.reactive_species(ncomp=3, storage=storage),
+                "reactive channel 512x256, A + B -> P at both walls (D2Q9 + 3 x D2Q5)")
     if name == "poiseuille":
         return scenes.config(1, storage=storage), "plane Poiseuille 64x32 (D2Q9)"
     if name == "hartmann_wide":
@@ -95,7 +98,8 @@ ROOFLINE_VARIANT = {"pipe": "pipe_long", "hartmann": "hartmann_wide"}
 def links_moment_reads(links, sc) -> np.ndarray:
     """Moments per node (at A, and again at E) each link's formula reads:
     u at X when extrapolated (3), rho_X for a velocity link moving along
-    e_alpha (1), C_X (1) or B_X (1, or 3 with a moving wall)."""
+    e_alpha (1), C_X (1, and 2 more for a bilinear term in two components)
+    or B_X (1, or 3 with a moving wall)."""
     from paper_2506_00907_amd import lbm
     kind, flags, comp = links["kind"], links["flags"], links["comp"]
     u_given = (flags & 1) != 0
@@ -113,7 +117,7 @@ def links_moment_reads(links, sc) -> np.ndarray:
     n = np.zeros(len(links), int)
     n = np.where(kind == 1, np.where(u_given & (eu == 0), 0, 1) + u3, n)
     n = np.where(kind == 2, 3, n)
-    n = np.where(kind == 4, 1 + u3, n)
+    n = np.where(kind == 4, 1 + u3 + np.where(links["cross"] != 0, 2, 0), n)
     n = np.where(kind == 7, np.where(uw_zero, 1, 3 + u3), n)
     return n
 
@@ -123,7 +127,8 @@ def algorithmic_bytes(lat) -> dict:
 
     sweep (the fused stream-collide kernel): every population of every fluid
     node read once and written once, one flag byte per padded node, and the
-    eight moments stored for each node a link extrapolates from.
+    moments (eight, one more per extra scalar component) stored for each
+    node a link extrapolates from.
     links: per link its record, three population reads and one write, and
     the moments of A and of E its formula uses."""
     sc = lat.scene
@@ -131,7 +136,7 @@ def algorithmic_bytes(lat) -> dict:
     cb = 8 if sc.storage == "f64" else 4
     rec = 96 if sc.storage == "f64" else 64
     q = {"D2Q9": 9, "D3Q19": 19, "D2Q5": 5, "D3Q7": 7}
-    QT = q[sc.fluid_lattice] + (q[sc.scalar_lattice] if sc.scalar_lattice else 0) + \
+    QT = q[sc.fluid_lattice] + (lat.n_scalar * q[sc.scalar_lattice] if sc.scalar_lattice else 0) + \
         (len(sc.mag_comps) * q[sc.mag_lattice] if sc.mag_lattice else 0)
     n_fluid = int(lat.mask.sum())
     padded = 1
@@ -387,7 +392,8 @@ def main():
         for w, st in (("reactive", "f32"), ("reactive", "f16"), ("reactive", "bf16"), ("hartmann", "f32"),
                       ("hartmann", "f16"),
                       ("pipe", "f32"), ("pipe", "bf16"), ("hartmann_wide", "f32"), ("hartmann_wide", "f16"),
-                      ("pipe_long", "f32"), ("pipe_long", "f16"), ("pipe_long", "bf16"), ("pipe_long", "f64")):
+                      ("pipe_long", "f32"), ("pipe_long", "f16"), ("pipe_long", "bf16"), ("pipe_long", "f64"),
+                      ("species", "f32")):
             s2, d2 = make_scene(w, st)
             l2 = lbm.Lattice(s2)
             a2 = algorithmic_bytes(l2)
