@@ -44,9 +44,9 @@ KERNEL_SOURCES = ("paper_2506_00907_amd/csrc/lbm_device.hpp", "paper_2506_00907_
                   "paper_2506_00907_amd/build.py")
 MEASURED_TRAFFIC = {
     # (workload, storage): (kernel source digest, bytes per launch)
-    ("pipe_long", "f32"): ("c3c3694375a963d6", 2463564148.0),
-    ("pipe", "f32"): ("c3c3694375a963d6", 153618635.0),
-    ("hartmann_wide", "f32"): ("c3c3694375a963d6", 2578222379.0),
+    ("pipe_long", "f32"): ("c2c6a23ec2822772", 2463564148.0),
+    ("pipe", "f32"): ("c2c6a23ec2822772", 153618635.0),
+    ("hartmann_wide", "f32"): ("c2c6a23ec2822772", 2578222379.0),
 }
 
 

@@ -231,40 +231,6 @@ template <> __device__ __forceinline__ float from_store<BF16S>(uint16_t t) {
     return __builtin_bit_cast(float, (uint32_t)t << 16);
 }
 
-// 8 bytes of consecutive elements of a plane, as two 32-bit words, at the
-// alignment of one element (the odd-step gathers and scatters of the K-node
-// sweep are shifted by one element along x)
-typedef uint32_t u32x2_a2 __attribute__((ext_vector_type(2), aligned(2)));
-typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
-template <class T>
-__device__ __forceinline__ void ld8(const T* p, uint32_t i, uint32_t w[2]) {
-    const char* a = reinterpret_cast<const char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T));
-    if (sizeof(T) == 2) {
-        const u32x2_a2 v = *reinterpret_cast<const u32x2_a2*>(a);
-        w[0] = v.x;
-        w[1] = v.y;
-    } else {
-        const u32x2_a4 v = *reinterpret_cast<const u32x2_a4*>(a);
-        w[0] = v.x;
-        w[1] = v.y;
-    }
-}
-template <class T>
-__device__ __forceinline__ void st8(T* p, uint32_t i, const uint32_t w[2]) {
-    char* a = reinterpret_cast<char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T));
-    if (sizeof(T) == 2) {
-        u32x2_a2 v;
-        v.x = w[0];
-        v.y = w[1];
-        *reinterpret_cast<u32x2_a2*>(a) = v;
-    } else {
-        u32x2_a4 v;
-        v.x = w[0];
-        v.y = w[1];
-        *reinterpret_cast<u32x2_a4*>(a) = v;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // configuration bundle
 // ---------------------------------------------------------------------------
