@@ -304,6 +304,45 @@ def cpu_baseline(sc, budget_s: float = 12.0, single_budget_s: float = 4.0):
     return out
 
 
+def cfg1_time_to_steady(steps: int = 20000):
+    """The plane Poiseuille channel (64 x 32, FP64) from rest for `steps`
+    steps, after which its slowest mode has decayed to ~4e-9: wall time on
+    the GPU (graph replays, capture excluded) and of the FP64 oracle on the
+    host cores and on one thread, the steady residual the GPU reaches, and
+    the largest difference of u between the two at the end."""
+    import torch
+    import oracle
+    from paper_2506_00907_amd import lbm
+    sc, desc = make_scene("poiseuille", "f64")
+    lat = lbm.Lattice(sc)
+    lat.step(1)
+    lat.step_prepare(steps - 1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lat.step(steps - 1)
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t
+    lat.reduce()
+    lat.step(1000)
+    resid = float(lat.reduce()[0])
+    u_gpu = lat.read_moments("f64").cpu().numpy()[1]
+    out = dict(workload=desc, steps=steps, gpu_seconds=gpu_s, residual_after=resid)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    for label, threads in (("oracle_seconds", cores), ("oracle_seconds_one_thread", 1)):
+        if not _omp_threads(threads):
+            continue
+        o = oracle.OracleSim(sc)
+        t = time.perf_counter()
+        o.step(steps)
+        out[label] = time.perf_counter() - t
+        if threads == cores:
+            o.step(1000)
+            out["max_u_difference"] = float(np.abs(o.moments()[..., 1] - u_gpu).max())
+    _omp_threads(cores)
+    out["cores"] = cores
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -405,6 +444,7 @@ def main():
             del l2
             torch.cuda.empty_cache()
         out["extra"] = extra
+        out["cfg1_time_to_steady"] = cfg1_time_to_steady()
     if args.batch:
         out["batch"] = bench_batch(args.batch, 1000)
     if not args.no_cpu:
