@@ -360,8 +360,8 @@ def main():
                     help="add the batch of N duct/pipe cross-sections (autotuned)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sweep shards by "
-              "slab or by item; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the sweep would shard "
+              "by slab or by batch item). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

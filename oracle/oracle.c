@@ -11,7 +11,7 @@
  * one node at a time, in the order the method states it:
  *   moments -> collision (Eqs. 1-6) -> propagation -> boundary links (Secs. 3-4).
  *
- * Readings where the paper is silent (each listed in the design notes):
+ * Readings where the paper is silent:
  *  - body force: Guo-Zheng-Shi forcing; u includes half the force.
  *  - Lorentz force: J x B with J = curl(B)/mu, the gradient of B taken from the
  *    local non-equilibrium first moment of g, evaluated with the velocity that

@@ -441,7 +441,7 @@ def cmd_eval(a):
 
 
 def cmd_report(a):
-    """Markdown summary of eval.json (and train.json) for the design notes."""
+    """Markdown summary of eval.json (and train.json)."""
     ev = json.load(open(a.eval))
     tr = json.load(open(a.train)) if a.train else None
     ref_ok = np.array([st == "steady" for st in ev["reference"]["status"]])

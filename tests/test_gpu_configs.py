@@ -1,6 +1,7 @@
-"""The survey's workloads at their full sizes against the FP64 oracle,
-through the C ABI, element by element.  Each comparison gives the relative
-L2 error of rho, u, C and b = B - B_ext over the fluid nodes and the largest
+"""The reactive-channel, Hartmann-Couette and MHD-pipe workloads at their
+full sizes against the FP64 oracle, through the C ABI, element by element.
+Each comparison gives the relative L2 error of rho, u, C and b = B - B_ext
+over the fluid nodes and the largest
 error at a node that a boundary link enters, relative to the field's
 largest value.  Bars:
 
