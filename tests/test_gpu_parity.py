@@ -42,6 +42,9 @@ def _thin(ny, storage="f64"):
 FP64_CASES = {
     "poiseuille_d05": lambda: scenes.poiseuille(nx=16, ny=12, storage="f64"),
     "couette_d03": lambda: scenes.poiseuille(nx=7, ny=13, q=0.3, u_top=0.01, g=1e-6, storage="f64"),
+    # walls almost on the outer node layers (d = 0.02): the d < 0.5 forms with
+    # interpolation weights near (1, 0)
+    "couette_d002": lambda: scenes.poiseuille(nx=7, ny=13, q=0.02, u_top=0.01, g=1e-6, storage="f64"),
     "periodic_box": _periodic_box,
     "thin_ny1": lambda: _thin(1),
     "thin_ny2": lambda: _thin(2),

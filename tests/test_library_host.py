@@ -247,6 +247,8 @@ def test_too_many_links_and_order(small):
 @pytest.mark.parametrize("mut", [
     dict(dim=4), dict(tau_f=0.5), dict(fluid=2), dict(storage=9), dict(mag_ncomp=2),
     dict(n=(0, 4, 1)), dict(store_scale=(0.0, 1.0, 1.0)),
+    # padded node indices must fit 32 bits (2e9 padded nodes at most)
+    dict(dim=3, fluid=2, n=(2000, 2000, 600), periodic=(0, 0, 0)),
 ])
 def test_rejects_bad_params(mut):
     sc = scenes.poiseuille(nx=4, ny=4)
