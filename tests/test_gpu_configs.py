@@ -96,10 +96,11 @@ WORKLOADS = {
     "cfg2": (lambda st: scenes.config(2, storage=st, k_range=(1e-3, 1e-1)), 2000),
     # Hartmann-Couette 1024 x 512 (Ha 5, c 0.1, moving transpiring walls, q_b, q_t seeded)
     "cfg3": (lambda st: scenes.config(3, storage=st), 2000),
-    # MHD pipe 128 x 128 x 64, R = 60, Ha = 10: the three wall types
+    # MHD pipe 128 x 128 x 64, R = 60, Ha = 10: the three wall types (the
+    # Shercliff wall, the bench workload, over 2000 steps)
     "cfg4_insulating": (lambda st: scenes.config(4, storage=st, wall="insulating"), 200),
     "cfg4_conducting": (lambda st: scenes.config(4, storage=st, wall="conducting"), 200),
-    "cfg4_shercliff": (lambda st: scenes.config(4, storage=st, wall="shercliff"), 200),
+    "cfg4_shercliff": (lambda st: scenes.config(4, storage=st, wall="shercliff"), 2000),
 }
 
 # FP16 / BF16: reported, with loose bounds (relative L2 over the fluid nodes)
