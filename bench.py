@@ -39,14 +39,15 @@ HBM_PEAK = 8.0e12  # bytes/s, MI355X
 # profiles/, scaled by the same counters of a 1 GiB device copy (FETCH_SIZE
 # reports half of the bytes read, WRITE_SIZE all bytes written): 2 x FETCH +
 # WRITE.  Valid only for the kernel sources and build flags they were taken
-# with.
+# with (the digest follows a source change only when the sweep kernels'
+# gfx950 instructions are unchanged by it).
 KERNEL_SOURCES = ("paper_2506_00907_amd/csrc/lbm_device.hpp", "paper_2506_00907_amd/csrc/lbm_internal.hpp",
                   "paper_2506_00907_amd/build.py")
 MEASURED_TRAFFIC = {
     # (workload, storage): (kernel source digest, bytes per launch)
-    ("pipe_long", "f32"): ("c2c6a23ec2822772", 2463564148.0),
-    ("pipe", "f32"): ("c2c6a23ec2822772", 153618635.0),
-    ("hartmann_wide", "f32"): ("c2c6a23ec2822772", 2578222379.0),
+    ("pipe_long", "f32"): ("3edc7cb72c2a2bf3", 2463564148.0),
+    ("pipe", "f32"): ("3edc7cb72c2a2bf3", 153618635.0),
+    ("hartmann_wide", "f32"): ("3edc7cb72c2a2bf3", 2578222379.0),
 }
 
 

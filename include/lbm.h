@@ -365,7 +365,7 @@ lbm_status lbm_reduce_static(lbm_ctx* ctx, double out[8]);
 lbm_status lbm_read_normalised(lbm_ctx* ctx, int32_t axis, double U, double* dev_out);
 
 /* FP64 net inflow through the boundary links over the last step, by field:
- * out[0] f (mass), out[1] h (solute), out[2..4] g (B_x, B_y, B_z).  A link
+ * out[0] f (mass), out[1] h (solute C_0), out[2..4] g (B_x, B_y, B_z).  A link
  * (A, alpha) adds the value it sets, f_alpha(A) at the current time (the
  * link updates of Sections 3-4), minus the post-collision population that A
  * sent toward the wall in the step before, f*_alpha'(A).  Collision and
@@ -375,6 +375,14 @@ lbm_status lbm_read_normalised(lbm_ctx* ctx, int32_t axis, double U, double* dev
  * (the state is otherwise unchanged).  Synchronises the stream.
  * LBM_ESTATE before the first step. */
 lbm_status lbm_boundary_flux(lbm_ctx* ctx, double out[5]);
+
+/* lbm_boundary_flux for every scalar component (Section 4.2.2): out[k] is the
+ * net inflow of C_k through the h links over the last step, k < m (the
+ * scalar components; out[k] = 0 beyond).  out[0] equals lbm_boundary_flux's
+ * out[1].  Collision and streaming conserve each component's total, so the
+ * change of sum(C_k) over a step equals out[k], up to rounding.  Same
+ * conditions and side effects as lbm_boundary_flux. */
+lbm_status lbm_boundary_flux_scalar(lbm_ctx* ctx, double out[3]);
 
 /* Checkpoint: lbm_state_bytes() bytes of host memory hold the populations,
  * moment planes and time.  lbm_save synchronises the stream. */

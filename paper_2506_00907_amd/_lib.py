@@ -98,6 +98,7 @@ SIGNATURES = {
     "lbm_reduce": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "lbm_reduce_static": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "lbm_boundary_flux": (C.c_int, [_VP, C.POINTER(C.c_double)]),
+    "lbm_boundary_flux_scalar": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "lbm_read_normalised": (C.c_int, [_VP, C.c_int32, C.c_double, _VP]),
     "lbm_state_bytes": (C.c_size_t, [_VP]),
     "lbm_save": (C.c_int, [_VP, _VP]),

@@ -554,33 +554,36 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // The links of the current step as k_links, plus the FP64 sums of their net
-// inflows by field slot: 0 f (mass), 1 h (solute), 2 + axis g (B_x, B_y,
-// B_z), one FP64 atomic per slot and block.
+// inflows by field slot: 0 f (mass), 1 h (solute C_0), 2 + axis g (B_x, B_y,
+// B_z), 5 and 6 the scalar components C_1 and C_2; one FP64 atomic per slot
+// and block.
 template <class C, int ODD>
 __global__ __launch_bounds__(256) void k_flux(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
                                               const DevLink<typename C::R>* __restrict__ links,
                                               const typename C::R* __restrict__ M, uint32_t nlinks, uint32_t tstep,
                                               double* __restrict__ acc) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    double v[5] = {0, 0, 0, 0, 0};
+    constexpr int NV = 7;
+    double v[NV] = {0, 0, 0, 0, 0, 0, 0};
     if (k < nlinks) {
         const DevLink<typename C::R> L = load_link(links + k);
         const double net = (double)link_update<C, ODD>(G, P, S, L, M, tstep);
-        // solute: component 0 only
-        const int slot = L.field == 2 ? 2 + L.caxis : ((L.field == 1 && C::NS > 1 && L.cslot != 4) ? -1 : L.field);
+        // scalar component k's moment plane is 4 (k = 0) or 7 + k
+        int slot = L.field == 2 ? 2 + L.caxis : L.field;
+        if (C::NS > 1 && L.field == 1 && L.cslot != 4) slot = L.cslot - 3;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) v[q] = q == slot ? net : 0.0;
+        for (int q = 0; q < NV; ++q) v[q] = q == slot ? net : 0.0;
     }
-    __shared__ double red[5][4];
+    __shared__ double red[NV][4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
+    for (int q = 0; q < NV; ++q) {
         const double sum = wave_sum(v[q]);
         if (lane == 0) red[q][wv] = sum;
     }
     __syncthreads();
-    if (threadIdx.x < 5) atomicAdd(&acc[threadIdx.x], red[threadIdx.x][0] + red[threadIdx.x][1] +
-                                                          red[threadIdx.x][2] + red[threadIdx.x][3]);
+    if (threadIdx.x < NV) atomicAdd(&acc[threadIdx.x], red[threadIdx.x][0] + red[threadIdx.x][1] +
+                                                           red[threadIdx.x][2] + red[threadIdx.x][3]);
 }
 
 // ---------------------------------------------------------------------------

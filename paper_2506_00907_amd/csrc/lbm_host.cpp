@@ -1297,11 +1297,14 @@ lbm_status lbm_read_normalised(lbm_ctx* c, int32_t axis, double U, double* dev_o
     return hip_check(c, c->ks.scale(a), "normalisation launch");
 }
 
-lbm_status lbm_boundary_flux(lbm_ctx* c, double out[5]) {
-    if (!c || !out) return LBM_EINVAL;
+namespace {
+
+// the link kernel of the current step with its net inflows by slot: 0 f,
+// 1 h (C_0), 2..4 g (B_x, B_y, B_z), 5..6 C_1, C_2
+lbm_status run_flux(lbm_ctx* c, double h[7]) {
+    for (int q = 0; q < 7; ++q) h[q] = 0.0;
     if (!c->initialized) return set_err(c, LBM_ESTATE, "lbm_init must come first");
     if (c->t == 0) return set_err(c, LBM_ESTATE, "no step has been taken");
-    for (int q = 0; q < 5; ++q) out[q] = 0.0;
     if (c->n_links == 0) return LBM_OK;
     const size_t cb = compute_bytes(c->p.storage);
     char* aux = (char*)c->buf[4];
@@ -1312,12 +1315,30 @@ lbm_status lbm_boundary_flux(lbm_ctx* c, double out[5]) {
     lbmi::KArgs a = base_args(c);
     a.acc = acc;
     if ((st = hip_check(c, c->ks.flux(a), "flux launch"))) return st;
-    double h[5];
-    if ((st = hip_check(c, hipMemcpyAsync(h, acc, sizeof h, hipMemcpyDeviceToHost, c->stream), "flux copy")))
+    if ((st = hip_check(c, hipMemcpyAsync(h, acc, 7 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                        "flux copy")))
         return st;
-    if ((st = hip_check(c, hipStreamSynchronize(c->stream), "flux sync"))) return st;
-    for (int q = 0; q < 5; ++q) out[q] = h[q];
-    return LBM_OK;
+    return hip_check(c, hipStreamSynchronize(c->stream), "flux sync");
+}
+
+}  // namespace
+
+lbm_status lbm_boundary_flux(lbm_ctx* c, double out[5]) {
+    if (!c || !out) return LBM_EINVAL;
+    double h[7];
+    const lbm_status st = run_flux(c, h);
+    for (int q = 0; q < 5; ++q) out[q] = st ? 0.0 : h[q];
+    return st;
+}
+
+lbm_status lbm_boundary_flux_scalar(lbm_ctx* c, double out[3]) {
+    if (!c || !out) return LBM_EINVAL;
+    double h[7];
+    const lbm_status st = run_flux(c, h);
+    out[0] = st ? 0.0 : h[1];
+    out[1] = st ? 0.0 : h[5];
+    out[2] = st ? 0.0 : h[6];
+    return st;
 }
 
 lbm_status lbm_reduce(lbm_ctx* c, double out[8]) {

@@ -308,6 +308,13 @@ class Lattice:
         self._call("lbm_boundary_flux", out)
         return np.array(out[:])
 
+    def scalar_flux(self) -> np.ndarray:
+        """lbm_boundary_flux_scalar: net inflow of each scalar component
+        through the boundary links over the last step."""
+        out = (C.c_double * 3)()
+        self._call("lbm_boundary_flux_scalar", out)
+        return np.array(out[:self.n_scalar])
+
     def save(self) -> bytes:
         nb = L.lib().lbm_state_bytes(self.ctx)
         buf = (C.c_char * nb)()

@@ -148,3 +148,32 @@ def test_full_size_channel_three_components_every_storage():
         assert max(wall.values()) < bar, (st, wall)
         del lat
         torch.cuda.empty_cache()
+
+
+def test_every_component_total_changes_by_its_boundary_inflow():
+    """Collision and streaming conserve each component's total, so over a
+    step sum(C_k) changes by exactly the net inflow its links report
+    (lbm_boundary_flux_scalar; FP64 storage, rounding aside): every
+    component's wall reaction and inlet are accounted for, and component 0's
+    figure is lbm_boundary_flux's solute inflow."""
+    _case("component inflows, 3-component channel, fp64")
+    sc = scenes.developed(scenes.reactive_species(nx=48, ny=23, q=0.3, ncomp=3, k=5e-2, storage="f64"))
+    lat = lbm.Lattice(sc)
+    sel = lat.mask.reshape(lat.shape).astype(bool)
+
+    def totals():
+        m = lat.read_moments("f64").cpu().numpy()
+        return np.array([m[c][sel].sum() for c in (4, 8, 9)])
+
+    lat.step(9)
+    for _ in range(3):
+        before = totals()
+        lat.step(1)
+        flux = lat.scalar_flux()
+        after = totals()
+        assert flux.shape == (3,)
+        for k in range(3):
+            assert abs((after[k] - before[k]) - flux[k]) < 1e-11 * max(abs(before[k]), 1.0), (k, after - before, flux)
+        assert flux[0] == pytest.approx(lat.boundary_flux()[1], rel=1e-12, abs=1e-15)
+    # every component crosses the boundary (inlet, outlet and both reacting walls)
+    assert np.all(np.abs(flux) > 1e-8), flux
