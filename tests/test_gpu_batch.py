@@ -193,19 +193,24 @@ def test_tuner_candidates_and_real_steps():
     assert_items_equal_alone(B, scs, t)
 
 
-def test_full_size_fp16_items_against_fp32_batch():
+def test_full_size_fp16_items_against_the_oracle():
+    """Eight full-size CFG5 items (sides 64-256) in one FP16 batch, 258 steps
+    from a developed state, each against the FP64 oracle run of the same
+    item (FP16 storage has no parity bound; the error is reported and held to
+    loose bounds)."""
     its = scenes.batch_items(8)
     s16 = [scenes.developed(it.scene, seed=3000 + i, u_amp=0.005) for i, it in enumerate(its)]
-    s32 = [sc.with_(storage="f32") for sc in s16]
-    B16, B32 = lbm.Batch(s16), lbm.Batch(s32)
+    B16 = lbm.Batch(s16)
     B16.configure("resident", 512, 32, 64)
     B16.step(258)
-    B32.step(258)
     for i in range(len(its)):
-        m16, m32 = gpu_moments(B16.items[i]), gpu_moments(B32.items[i])
-        err = field_errors(m16, m32, B16.items[i].mask.reshape(m16.shape[:3]), s16[i].B_ext)
+        o = oracle.OracleSim(s16[i].with_(storage="f64"), "f64")
+        o.step(258)
+        m16 = gpu_moments(B16.items[i])
+        err = field_errors(m16, o.moments(), o.mask(), s16[i].B_ext)
+        print(i, its[i].shape, its[i].ny, its[i].nz, {k: f"{v:.1e}" for k, v in err.items()}, flush=True)
         assert np.isfinite(m16).all()
-        assert err["rho"] < 1e-3 and err["u"] < 3e-2 and err["b"] < 3e-2, (i, err)
+        assert err["rho"] < 1e-3 and err["u"] < 2e-2 and err["b"] < 2e-2, (i, err)
     # one item of the FP16 batch against the same item alone
     alone = lbm.Lattice(s16[0])
     alone.step(258)
