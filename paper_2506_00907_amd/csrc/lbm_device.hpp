@@ -602,6 +602,16 @@ struct NodeRes {
     Mom<typename C::R> m;
 };
 
+// e . v for a lattice vector e whose components (-1, 0 or 1) are known at
+// compile time: a zero component contributes -0.0, which the compiler drops
+// exactly, so only the nonzero terms are formed (0 * v would have to be
+// computed, since it is not exactly zero for every v)
+template <class R>
+__device__ __forceinline__ R edot(int ex, int ey, int ez, R x, R y, R z) {
+    auto t = [](int e, R v) -> R { return e == 0 ? (R)-0.0 : (e > 0 ? v : -v); };
+    return t(ex, x) + t(ey, y) + t(ez, z);
+}
+
 // Padded node and its wrapped neighbour offsets (fluid nodes never touch a
 // non-periodic edge of the padded grid, so wrapping only ever applies on
 // periodic axes).
@@ -773,7 +783,12 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
 
     // ---- collision (deviation form), opposite directions in pairs: the
     // equilibrium and the Guo source split into a part even in e (shared by
-    // the pair) and a part odd in e (opposite signs) ----
+    // the pair) and a part odd in e (opposite signs).  Per pair of the fluid
+    // and magnetic lattices,
+    //   x_a' = (1 - om) x_a + S + D,   x_b' = (1 - om) x_b + S - D,
+    // with S = om ev + evs and D = om od + ods gathered into per-node factors
+    // that only the lattice weight w multiplies (fewer instructions, and in
+    // FP32 closer to the oracle than x + om (x_eq - x) after long runs) ----
     const R usq = ux * ux + uy * uy + uz * uz;
     const R uF = ux * F[0] + uy * F[1] + uz * F[2];
     const R omf = P.omf, guo = P.guo;
@@ -782,21 +797,25 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
         const R feq = w0 * (drho - (R)1.5 * rho * usq);
         x_[0] += omf * (feq - x_[0]) - (R)3 * guo * w0 * uF;
     }
+    {
+        // om ev + evs = w (s0 + eu (s2 eu + s1 eF)), om od + ods = w (d1 eu + d2 eF)
+        const R om1 = (R)1 - omf;
+        const R s0 = omf * (drho - (R)1.5 * rho * usq) - (R)3 * guo * uF;
+        const R s2 = (R)4.5 * omf * rho, s1 = (R)9 * guo;
+        const R d1 = (R)3 * omf * rho, d2 = (R)3 * guo;
 #pragma unroll
-    for (int a = 1; a < QF; ++a) {
-        if (FL::opp(a) < a) continue;
-        const int b = FL::opp(a);
-        const R ex = (R)FL::ex(a), ey = (R)FL::ey(a), ez = (R)FL::ez(a);
-        const R w = (R)FL::w(a);
-        const R eu = ex * ux + ey * uy + ez * uz;
-        const R eF = ex * F[0] + ey * F[1] + ez * F[2];
-        const R ev = w * (drho + rho * ((R)4.5 * eu * eu - (R)1.5 * usq)) ;
-        const R od = (R)3 * w * rho * eu;
-        const R evs = guo * w * ((R)9 * eu * eF - (R)3 * uF);
-        const R ods = (R)3 * guo * w * eF;
-        const R xa = x_[a], xb = x_[b];
-        x_[a] = xa + omf * (ev + od - xa) + (evs + ods);
-        x_[b] = xb + omf * (ev - od - xb) + (evs - ods);
+        for (int a = 1; a < QF; ++a) {
+            if (FL::opp(a) < a) continue;
+            const int b = FL::opp(a);
+            const R w = (R)FL::w(a);
+            const R eu = edot(FL::ex(a), FL::ey(a), FL::ez(a), ux, uy, uz);
+            const R eF = edot(FL::ex(a), FL::ey(a), FL::ez(a), F[0], F[1], F[2]);
+            const R S = w * s0 + eu * ((w * s2) * eu + (w * s1) * eF);
+            const R D = (w * d1) * eu + (w * d2) * eF;
+            const R xa = x_[a], xb = x_[b];
+            x_[a] = om1 * xa + (S + D);
+            x_[b] = om1 * xb + (S - D);
+        }
     }
 #pragma unroll
     for (int k = 0; k < (QH > 0 ? C::NS : 0); ++k) {
@@ -804,12 +823,15 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
         const R dCk = dCs[k];
         const R Cc = P.C0 + dCk, omc = k == 0 ? P.omc : P.omcx[k - 1];
         x_[h0] += omc * ((R)HL::w(0) * dCk - x_[h0]);
+        // relaxed toward the pair's equilibrium directly: in FP32 this kept
+        // the steady solute field of the reactive channel 3 times closer to
+        // the oracle's than the (1 - om) x + S + D form of f and g
 #pragma unroll
         for (int a = 1; a < QH; ++a) {
             if (HL::opp(a) < a) continue;
             const int b = HL::opp(a);
             const R w = (R)HL::w(a);
-            const R eu = (R)HL::ex(a) * ux + (R)HL::ey(a) * uy + (R)HL::ez(a) * uz;
+            const R eu = edot(HL::ex(a), HL::ey(a), HL::ez(a), ux, uy, uz);
             const R ev = w * dCk, od = (R)4 * w * Cc * eu;
             const R xa = x_[h0 + a], xb = x_[h0 + b];
             x_[h0 + a] = xa + omc * (ev + od - xa);
@@ -823,17 +845,19 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
         const R omm = P.omm;
         const int p0 = C::G0 + c * QG;
         x_[p0] += omm * ((R)GL::w(0) * dB[c] - x_[p0]);
+        // om ev = w om dB_k, om od = w (om / c2) (e.u B_k - e.B u_k)
+        const R om1 = (R)1 - omm, sg = omm * dB[c], dg = (R)(1.0 / GL::c2) * omm;
 #pragma unroll
         for (int a = 1; a < QG; ++a) {
             if (GL::opp(a) < a) continue;
             const int b = GL::opp(a);
-            const R ex = (R)GL::ex(a), ey = (R)GL::ey(a), ez = (R)GL::ez(a);
             const R w = (R)GL::w(a);
-            const R s = (ex * ux + ey * uy + ez * uz) * Bk - (ex * B[0] + ey * B[1] + ez * B[2]) * uk;
-            const R ev = w * dB[c], od = (R)(1.0 / GL::c2) * w * s;
+            const R s = edot(GL::ex(a), GL::ey(a), GL::ez(a), ux, uy, uz) * Bk -
+                        edot(GL::ex(a), GL::ey(a), GL::ez(a), B[0], B[1], B[2]) * uk;
+            const R S = w * sg, D = (w * dg) * s;
             const R xa = x_[p0 + a], xb = x_[p0 + b];
-            x_[p0 + a] = xa + omm * (ev + od - xa);
-            x_[p0 + b] = xb + omm * (ev - od - xb);
+            x_[p0 + a] = om1 * xa + (S + D);
+            x_[p0 + b] = om1 * xb + (S - D);
         }
     }
 
