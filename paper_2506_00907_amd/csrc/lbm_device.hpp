@@ -861,16 +861,7 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
         }
     }
 
-    // 16-bit storage: the scatter forms its addresses again from an opaque
-    // copy of the node index, so the gather's addresses (one 64-bit pointer
-    // per neighbour) are not held through the collision.  The odd step then
-    // needs about 65 registers instead of 95-110, so 7-8 waves per SIMD fit
-    // instead of 4-5, and the FP16 sweeps run 3-5 % faster.  FP32 sweeps
-    // keep the gather's addresses: there the extra address arithmetic cost
-    // more than the added waves gained.
-    Nbr qs = q;
-    if (C::SCALED) __asm__ volatile("" : "+v"(qs.n));
-    auto nb = [&](int ex, int ey, int ez) -> uint32_t { return qs.at(ex, ey, ez); };
+    auto nb = [&](int ex, int ey, int ez) -> uint32_t { return q.at(ex, ey, ez); };
 
     // ---- scatter (streaming); 16-bit formats round stochastically with a
     // dither of (writing node, time), then the slot ----
@@ -884,7 +875,7 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
     for (int i = 0; i < QF; ++i) {
         const R v = C::SCALED ? x_[i] * P.sc[0] : x_[i];
         if (ODD) put(i, nb(FL::ex(i), FL::ey(i), FL::ez(i)), v);
-        else put(FL::opp(i), qs.n, v);
+        else put(FL::opp(i), n, v);
     }
 #pragma unroll
     for (int k = 0; k < C::NS; ++k)
@@ -893,7 +884,7 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
             const int b = C::H0 + k * QH;
             const R v = C::SCALED ? x_[b + i] * P.sc[1] : x_[b + i];
             if (ODD) put(b + i, nb(HL::ex(i), HL::ey(i), HL::ez(i)), v);
-            else put(b + HL::opp(i), qs.n, v);
+            else put(b + HL::opp(i), n, v);
         }
 #pragma unroll
     for (int c = 0; c < NCP; ++c)
@@ -902,7 +893,7 @@ __device__ __forceinline__ void finish(const Geo& G, const Phys<typename C::R>& 
             const int b = C::G0 + c * QG;
             const R v = C::SCALED ? x_[b + i] * P.sc[2] : x_[b + i];
             if (ODD) put(b + i, nb(GL::ex(i), GL::ey(i), GL::ez(i)), v);
-            else put(b + GL::opp(i), qs.n, v);
+            else put(b + GL::opp(i), n, v);
         }
 }
 
