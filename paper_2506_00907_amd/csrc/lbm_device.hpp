@@ -161,14 +161,14 @@ template <> __device__ __forceinline__ void st<BF16S>(uint16_t* p, uint32_t i, f
     at(p, i) = (uint16_t)(b >> 16);
 }
 
-// Stores with stochastic rounding for the 16-bit formats: a dither is added
-// below the last kept mantissa bit before truncation, so increments smaller
-// than half a unit in the last place survive on average instead of being
-// rounded away.  The dither is a counter-based hash (the 32-bit finaliser of
-// MurmurHash3): a link store hashes (slot, node, time); the sweep hashes
-// (writing node, time) once per node and mixes in each slot with one more
-// multiply-xorshift round.  Either way a slot written at a given time gets the
-// same rounding on every path.
+// Stores with stochastic rounding for the 16-bit formats: a value rounds up
+// with probability equal to its distance from the lower neighbour, in units
+// of the last place, so increments smaller than half a unit survive on
+// average instead of being rounded away.  The random bits come from a
+// counter-based hash (the 32-bit finaliser of MurmurHash3): a link store
+// hashes (slot, node, time); the sweep hashes (writing node, time) once per
+// node and mixes in each slot with one more multiply-xorshift round.  Either
+// way a slot written at a given time gets the same rounding on every path.
 __device__ __forceinline__ uint32_t dither(uint32_t node, uint32_t slot, uint32_t t) {
     uint32_t h = node * 0x9E3779B1u + slot * 0x85EBCA77u + t * 0xC2B2AE3Du;
     h ^= h >> 16;
@@ -193,17 +193,19 @@ template <class SF>
 __device__ __forceinline__ typename SF::T to_store(typename SF::R v, uint32_t r) {
     return v;
 }
+// gfx950 converts with stochastic rounding in one instruction
+// (v_cvt_sr_f16_f32, v_cvt_sr_bf16_f32), taking its random bits from r
+typedef _Float16 lbm_half2 __attribute__((ext_vector_type(2)));
+typedef __bf16 lbm_bf162 __attribute__((ext_vector_type(2)));
 template <> __device__ __forceinline__ uint16_t to_store<F16S>(float v, uint32_t r) {
-    uint32_t b = __builtin_bit_cast(uint32_t, v);
-    const uint32_t e = (b >> 23) & 0xFFu;
-    // normal FP16 range below the largest binade: dither the 13 dropped bits
-    if (e >= 113u && e < 142u) b = (b + (r & 0x1FFFu)) & ~0x1FFFu;
-    return __builtin_bit_cast(uint16_t, (_Float16)__builtin_bit_cast(float, b));
+    lbm_half2 h = {0, 0};
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, v, r, false);
+    return __builtin_bit_cast(uint16_t, h[0]);
 }
 template <> __device__ __forceinline__ uint16_t to_store<BF16S>(float v, uint32_t r) {
-    uint32_t b = __builtin_bit_cast(uint32_t, v);
-    if (((b >> 23) & 0xFFu) < 0xFEu) b += r & 0xFFFFu;  // finite and not next to overflow
-    return (uint16_t)(b >> 16);
+    lbm_bf162 h = {0, 0};
+    h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, r, false);
+    return __builtin_bit_cast(uint16_t, h[0]);
 }
 template <class SF>
 __device__ __forceinline__ void st_sr(typename SF::T* p, uint32_t i, typename SF::R v, uint32_t r) {
