@@ -45,9 +45,9 @@ KERNEL_SOURCES = ("paper_2506_00907_amd/csrc/lbm_device.hpp", "paper_2506_00907_
                   "paper_2506_00907_amd/build.py")
 MEASURED_TRAFFIC = {
     # (workload, storage): (kernel source digest, bytes per launch)
-    ("pipe_long", "f32"): ("6e6ab00588d294e5", 2463098929.0),
-    ("pipe", "f32"): ("6e6ab00588d294e5", 153594184.0),
-    ("hartmann_wide", "f32"): ("6e6ab00588d294e5", 2585135750.0),
+    ("pipe_long", "f32"): ("ce1e15573a42445e", 2463098929.0),
+    ("pipe", "f32"): ("ce1e15573a42445e", 153594184.0),
+    ("hartmann_wide", "f32"): ("ce1e15573a42445e", 2585135750.0),
 }
 
 

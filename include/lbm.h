@@ -301,6 +301,20 @@ lbm_status lbm_step_prepare(lbm_ctx* ctx, int64_t n);
  * replays, out[1] steps run inside them, out[2] steps launched singly. */
 lbm_status lbm_step_stats(const lbm_ctx* ctx, int64_t out[3]);
 
+/* How a captured run orders the kernels of its steps.  mode 0 (the
+ * default): the link kernel, then the whole sweep, per step.  mode 1
+ * (overlap): the sweep of each step runs as two launches, first over the
+ * 64-node waves that hold a link node A or its partner E = A + e_alpha, then
+ * over the other waves with fluid nodes, and the link kernel of the next step
+ * runs on a second captured stream beside the second launch.  It reads only
+ * slots that threads of A and E write and writes only slots no sweep thread
+ * touches (Section 3's link updates read the post-collision populations of A
+ * and E and set the one that enters A), so the states are those of mode 0.
+ * Mode 1 pays on lattices with millions of links and costs time on small
+ * ones (the graph's cross-stream dependencies).  Drops captured runs.
+ * Errors: LBM_EINVAL for another mode. */
+lbm_status lbm_set_step_overlap(lbm_ctx* ctx, int32_t mode);
+
 /* Durations of the two kernels of a step, for measurement: n (even, 2 to
  * 4096) launches of the boundary-link kernel back to back, captured in one
  * HIP graph and timed with HIP events on the context's stream, then n

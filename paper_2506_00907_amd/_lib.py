@@ -91,6 +91,7 @@ SIGNATURES = {
     "lbm_step": (C.c_int, [_VP, C.c_int64]),
     "lbm_step_prepare": (C.c_int, [_VP, C.c_int64]),
     "lbm_step_stats": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    "lbm_set_step_overlap": (C.c_int, [_VP, C.c_int32]),
     "lbm_timing_scratch_bytes": (C.c_size_t, [_VP]),
     "lbm_step_timed": (C.c_int, [_VP, C.c_int64, _VP, C.c_size_t, C.POINTER(C.c_float)]),
     "lbm_read_moments": (C.c_int, [_VP, _VP, C.c_int32]),

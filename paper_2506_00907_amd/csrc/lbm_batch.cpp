@@ -706,7 +706,7 @@ void lbm_batch_destroy(lbm_batch* b) {
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     for (auto* c : b->items) {
         drop_graph(c);
-        if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+        release_capture(c);
         delete c;
     }
     delete b;

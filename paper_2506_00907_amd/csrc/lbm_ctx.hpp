@@ -61,6 +61,15 @@ struct lbm_ctx {
     StepGraph run[2];
     StepGraph tail;
     hipStream_t capture_stream = nullptr;
+    // lbm_set_step_overlap mode 1: a captured run overlaps each step's link
+    // kernel with the previous sweep: the sweep runs as two launches over
+    // 64-node waves (those that hold a link node A or its partner E, then the
+    // rest) and the links of the next step, on a second stream, wait only
+    // for the first
+    hipStream_t capture_stream2 = nullptr;
+    hipEvent_t ev_links = nullptr, ev_bnd = nullptr, ev_fork = nullptr, ev_join = nullptr;
+    size_t n_wave_bnd = 0, n_wave_int = 0;  // wave lists after the flags (buffer 1)
+    int overlap_mode = 0;                    // lbm_set_step_overlap
     bool graph_failed = false;
     int graph_steps = 64;
     // what lbm_step ran (lbm_step_stats): graph replays, steps inside them,
@@ -73,6 +82,8 @@ struct lbm_ctx {
 namespace lbmh {
 
 void drop_graph(lbm_ctx* c);
+// destroys the capture streams and events of a context
+void release_capture(lbm_ctx* c);
 lbm_status set_err(lbm_ctx* c, lbm_status s, const std::string& m);
 lbm_status hip_check(lbm_ctx* c, hipError_t e, const char* what);
 lbmi::KArgs base_args(const lbm_ctx* c);

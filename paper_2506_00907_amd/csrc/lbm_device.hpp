@@ -940,6 +940,24 @@ __global__ __launch_bounds__(256) void k_step(Geo G, Phys<typename C::R> P, type
     node_update<C, ODD, 0>(G, P, S, flags, M, n, r, C::SCALED ? step_time(tbase, tstep) : 0u);
 }
 
+// The same update over a list of 64-node waves (four per block): a step's
+// sweep split into the waves that hold link nodes or their partners and the
+// rest, so that the link kernel of the next step can run beside the rest.
+template <class C, int ODD>
+__global__ __launch_bounds__(256) void k_step_waves(Geo G, Phys<typename C::R> P, typename C::T* __restrict__ S,
+                                                    const uint8_t* __restrict__ flags,
+                                                    typename C::R* __restrict__ M, uint32_t nnodes,
+                                                    const uint32_t* __restrict__ waves, uint32_t nwaves,
+                                                    const uint32_t* __restrict__ tbase, uint32_t tstep) {
+    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t w = b * 4u + (threadIdx.x >> 6);
+    if (w >= nwaves) return;
+    const uint32_t n = waves[w] * 64u + (threadIdx.x & 63u);
+    if (n >= nnodes) return;
+    NodeRes<C> r;
+    node_update<C, ODD, 0>(G, P, S, flags, M, n, r, C::SCALED ? step_time(tbase, tstep) : 0u);
+}
+
 // time base of a captured run: *tbase = t (set) or *tbase += t (tick); one
 // lane, through a vector-memory atomic
 template <class C>
@@ -1414,6 +1432,20 @@ struct Launch {
                                (R*)a.M, nn, a.tbase, a.tstep);
         return hipGetLastError();
     }
+    static hipError_t sweep_waves(const KArgs& a) {
+        if (a.n_waves == 0) return hipSuccess;
+        const uint32_t nn = (uint32_t)((size_t)a.NX * a.NY * a.NZ);
+        dim3 grid((a.n_waves + 3) / 4);
+        const Phys<R> P = make_phys<R>(a, cg2());
+        const Geo G = make_geo(a);
+        if (a.parity)
+            hipLaunchKernelGGL((k_step_waves<C, 1>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S,
+                               a.flags, (R*)a.M, nn, a.waves, a.n_waves, a.tbase, a.tstep);
+        else
+            hipLaunchKernelGGL((k_step_waves<C, 0>), grid, dim3(256), 0, a.stream, G, P, (typename C::T*)a.S,
+                               a.flags, (R*)a.M, nn, a.waves, a.n_waves, a.tbase, a.tstep);
+        return hipGetLastError();
+    }
     static hipError_t set_time(const KArgs& a) {
         hipLaunchKernelGGL((k_time<C>), dim3(1), dim3(64), 0, a.stream, a.tbase, a.tstep, 0);
         return hipGetLastError();
@@ -1550,6 +1582,7 @@ struct Launch {
         k.b_clear = &b_clear;
         k.links = &links_only;
         k.sweep = &sweep;
+        k.sweep_waves = &sweep_waves;
         k.step = &step;
         k.flux = &flux;
         k.scale = &scale;

@@ -480,6 +480,21 @@ void drop_graph(lbm_ctx* c) {
     }
 }
 
+void release_capture(lbm_ctx* c) {
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->capture_stream2) (void)hipStreamDestroy(c->capture_stream2);
+    for (hipEvent_t e : {c->ev_links, c->ev_bnd, c->ev_fork, c->ev_join})
+        if (e) (void)hipEventDestroy(e);
+    c->capture_stream = c->capture_stream2 = nullptr;
+    c->ev_links = c->ev_bnd = c->ev_fork = c->ev_join = nullptr;
+}
+
+// first element of the wave lists in buffer 1 (after the flags and the wave
+// summary): the boundary waves, then the interior ones
+uint32_t* wave_lists(const lbm_ctx* c) {
+    return (uint32_t*)((char*)c->buf[1] + round_up(c->pad.plane, kAlign) + round_up(c->pad.plane / 64, kAlign));
+}
+
 lbm_status finish_reduce(lbm_ctx* c, const double h[12], double out[8]) {
     const double dt = (double)(c->t - c->t_snap);
     double res = -1.0;
@@ -519,7 +534,8 @@ void layout(const lbm_params* p, size_t n_links, size_t sz[LBM_NBUF]) {
     const Pad d = padding(p);
     const size_t vb = value_bytes(p->storage), cb = compute_bytes(p->storage);
     sz[0] = round_up((size_t)total_planes(p) * d.plane * vb, kAlign);          // populations
-    sz[1] = round_up(d.plane, kAlign) + round_up(d.plane / 64, kAlign);        // node flags, wave summary
+    sz[1] = round_up(d.plane, kAlign) + round_up(d.plane / 64, kAlign) +       // node flags, wave summary,
+            round_up(d.plane / 64 * 4, kAlign);                                 // wave lists
     sz[2] = round_up(std::max<size_t>(n_links, 1) * link_bytes(p->storage), kAlign);  // link records
     const size_t mw = (size_t)moment_planes(p);
     sz[3] = round_up(2 * mw * d.plane * cb, kAlign) + kAlign;                  // moment planes, time base
@@ -975,6 +991,26 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
         for (size_t k = 64 * g; k < 64 * g + 64 && all; ++k) all = k < d.nodes && (flags[k] & lbmi::NF_FLUID);
         flags[wf0 + g] = all ? 1 : 0;
     }
+    // waves of the link nodes A and their partners E (their slots carry the
+    // link kernel's inputs and its result), then every other wave with a
+    // fluid node; the two lists are swept as separate launches in captured runs
+    const size_t nw = d.plane / 64;
+    std::vector<uint8_t> bnd(nw, 0);
+    for (size_t i = 0; i < n; ++i) {
+        bnd[sA[i] / 64] = 1;
+        bnd[sE[i] / 64] = 1;
+    }
+    std::vector<uint32_t> wl;
+    wl.reserve(nw);
+    for (size_t g = 0; g < nw; ++g)
+        if (bnd[g]) wl.push_back((uint32_t)g);
+    const size_t n_bnd = wl.size();
+    for (size_t g = 0; g < nw; ++g) {
+        if (bnd[g]) continue;
+        bool any = false;
+        for (size_t k = 64 * g; k < 64 * g + 64 && !any; ++k) any = k < d.nodes && (flags[k] & lbmi::NF_FLUID);
+        if (any) wl.push_back((uint32_t)g);
+    }
 
     std::vector<unsigned char> dl;
     if (p.storage == LBM_F64) fill_devlinks<double>(c, sl, sA, sE, sB, &dl);
@@ -985,9 +1021,14 @@ lbm_status lbm_set_links(lbm_ctx* c, const lbm_link* L, size_t n) {
         return st;
     if ((st = hip_check(c, hipMemcpyAsync(c->buf[2], dl.data(), dl.size(), hipMemcpyHostToDevice, c->stream), "links upload")))
         return st;
+    if (!wl.empty() && (st = hip_check(c, hipMemcpyAsync(wave_lists(c), wl.data(), wl.size() * 4,
+                                                          hipMemcpyHostToDevice, c->stream), "wave list upload")))
+        return st;
     if ((st = hip_check(c, hipMemsetAsync(c->buf[3], 0, c->size[3], c->stream), "moment clear"))) return st;
     if ((st = hip_check(c, hipStreamSynchronize(c->stream), "link upload sync"))) return st;
     c->n_links = n;
+    c->n_wave_bnd = n_bnd;
+    c->n_wave_int = wl.size() - n_bnd;
     c->cmp_links = false;
     for (size_t i = 0; i < n; ++i)
         if ((L[i].flags & 8) || L[i].kind == LBM_LK_MAG_THETA) c->cmp_links = true;
@@ -1036,12 +1077,58 @@ lbm_status make_graph(lbm_ctx* c, int parity, int64_t steps, lbm_ctx::StepGraph*
     a.stream = c->capture_stream;
     a.links_ready = 1;
     a.tbase = time_base(c);
+    const bool split = c->n_links > 0 && c->n_wave_bnd > 0 && c->overlap_mode == 1;
+    if (split && !c->capture_stream2) {
+        if (hipStreamCreateWithFlags(&c->capture_stream2, hipStreamNonBlocking) != hipSuccess) {
+            c->capture_stream2 = nullptr;
+            return LBM_EDEVICE;
+        }
+        for (hipEvent_t* e : {&c->ev_links, &c->ev_bnd, &c->ev_fork, &c->ev_join})
+            if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+                *e = nullptr;
+                return LBM_EDEVICE;
+            }
+    }
     if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_EDEVICE;
     hipError_t le = hipSuccess;
-    for (int64_t i = 0; i < steps && le == hipSuccess; ++i) {
-        a.parity = (int)((parity + i) & 1);
-        a.tstep = (uint32_t)i;
-        le = c->ks.step(a);
+    if (!split) {
+        for (int64_t i = 0; i < steps && le == hipSuccess; ++i) {
+            a.parity = (int)((parity + i) & 1);
+            a.tstep = (uint32_t)i;
+            le = c->ks.step(a);
+        }
+    } else {
+        // Step i: links(i) on the second stream; then, on the first, the
+        // sweep of the boundary waves (after links(i)) and of the interior
+        // waves.  links(i + 1) waits for the boundary sweep of step i only:
+        // it reads slots that only threads of A and E nodes write, and writes
+        // slots no thread of either sweep touches, so it overlaps the
+        // interior sweep of step i.
+        const hipStream_t s0 = c->capture_stream, s1 = c->capture_stream2;
+        uint32_t* wl = wave_lists(c);
+        auto ok = [&](hipError_t e) { if (le == hipSuccess) le = e; return le == hipSuccess; };
+        ok(hipEventRecord(c->ev_fork, s0));
+        ok(hipStreamWaitEvent(s1, c->ev_fork, 0));
+        for (int64_t i = 0; i < steps && le == hipSuccess; ++i) {
+            a.parity = (int)((parity + i) & 1);
+            a.tstep = (uint32_t)i;
+            a.stream = s1;
+            if (!ok(c->ks.links(a)) || !ok(hipEventRecord(c->ev_links, s1))) break;
+            a.stream = s0;
+            if (!ok(hipStreamWaitEvent(s0, c->ev_links, 0))) break;
+            a.waves = wl;
+            a.n_waves = (uint32_t)c->n_wave_bnd;
+            if (!ok(c->ks.sweep_waves(a)) || !ok(hipEventRecord(c->ev_bnd, s0))) break;
+            a.waves = wl + c->n_wave_bnd;
+            a.n_waves = (uint32_t)c->n_wave_int;
+            if (!ok(c->ks.sweep_waves(a)) || !ok(hipStreamWaitEvent(s1, c->ev_bnd, 0))) break;
+        }
+        // the second stream joins the first before the capture ends
+        ok(hipEventRecord(c->ev_join, s1));
+        ok(hipStreamWaitEvent(s0, c->ev_join, 0));
+        a.stream = s0;
+        a.waves = nullptr;
+        a.n_waves = 0;
     }
     if (le == hipSuccess) {
         // the time base follows the run
@@ -1142,6 +1229,14 @@ lbm_status lbm_step_prepare(lbm_ctx* c, int64_t n) {
     if (n >= c->graph_steps && !run_for(c, (int)(t & 1), n)) return set_err(c, LBM_EDEVICE, "graph capture");
     const int64_t r = n % c->graph_steps;
     if (r >= 2 && !run_for(c, (int)((t + n - r) & 1), r)) return set_err(c, LBM_EDEVICE, "graph capture");
+    return LBM_OK;
+}
+
+lbm_status lbm_set_step_overlap(lbm_ctx* c, int32_t mode) {
+    if (!c) return LBM_EINVAL;
+    if (mode < 0 || mode > 1) return set_err(c, LBM_EINVAL, "overlap mode must be 0 or 1");
+    if (mode != c->overlap_mode) drop_graph(c);
+    c->overlap_mode = mode;
     return LBM_OK;
 }
 
@@ -1427,7 +1522,7 @@ const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null
 void lbm_destroy(lbm_ctx* c) {
     if (!c || c->batch_owned) return;
     drop_graph(c);
-    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    release_capture(c);
     delete c;
 }
 

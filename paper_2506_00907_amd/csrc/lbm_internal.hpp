@@ -52,6 +52,8 @@ struct KArgs {
     int n0, n1, n2;        // domain extents
     size_t plane;          // padded node count rounded up (population plane stride)
     size_t wave_fluid;     // offset in flags of one byte per 64 nodes (1 = all fluid)
+    const uint32_t* waves; // sweep over a list of 64-node waves (sweep_waves): their indices
+    uint32_t n_waves;
     void* S;               // populations [QT][plane]
     const uint8_t* flags;  // [plane]
     const void* links;     // DevLink<R>[n_links]
@@ -119,6 +121,7 @@ using Describer = size_t (*)(const KArgs&, void* out);
 struct KernelSet {
     Launcher links = nullptr;    // the boundary-link kernel of a step (no-op at t = 0)
     Launcher sweep = nullptr;    // the fused sweep of a step
+    Launcher sweep_waves = nullptr;  // the fused sweep over the waves listed in KArgs::waves
     Launcher step = nullptr;     // links then sweep
     Launcher observe = nullptr;  // moments / populations / reductions at the current time
     Launcher flux = nullptr;     // links of the current step with their FP64 net inflows by field

@@ -239,6 +239,11 @@ class Lattice:
         """lbm_step_prepare: capture the graphs a later step(n) replays."""
         self._call("lbm_step_prepare", int(n))
 
+    def set_step_overlap(self, mode: int):
+        """lbm_set_step_overlap: 0 links then the whole sweep (default), 1 the
+        next step's link kernel beside the sweep of the waves without links."""
+        self._call("lbm_set_step_overlap", int(mode))
+
     def step_stats(self):
         """lbm_step_stats: (graph replays, steps inside them, single steps)."""
         out = (C.c_int64 * 3)()
